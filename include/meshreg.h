@@ -1,0 +1,193 @@
+/*
+ * meshreg.h -- C ABI of the MI355X (gfx950) mesh-based image registration library.
+ *
+ * The library implements the per-iteration hot path of triangular-mesh image
+ * registration (Baghaie, Yu, D'souza, "Fast Mesh-Based Medical Image
+ * Registration", arXiv:1411.2141).  The objective is eq. 1,
+ *     E[u] = D[Re, Te o u] + alpha S[u],
+ * with the nodal SSD data term of eq. 4 (template sampled at the displaced
+ * nodes, eq. 3) and the P1 diffusion energy S[u] = 1/2 sum_c u_c^T K u_c as the
+ * regulariser (the mesh Laplacian of Section 2.3 in symmetric form).  One
+ * iteration follows Algorithm 1 (update, then smoothing) in semi-implicit form:
+ *
+ *   t_i, g_i = s_Te(V_i - 1/2 + u_i), grad s_Te(...)      cubic B-spline (abstract)
+ *   r_i = t_i - s_Re(V_i - 1/2),  h_i = r_i g_i          eq. 4, eq. 6
+ *   f = (M h) / m                                        eq. 10 applied to the P1 load
+ *   b = u - tau f                                        eq. 5
+ *   (I + tau alpha K) u+ = b  for x and y                eq. 7-8 made implicit; solved
+ *                                                        directly (abstract) with a
+ *                                                        sparse Cholesky factor
+ *
+ * and the result is judged by the MSD of the piecewise-linearly warped template
+ * against Re (Section 1; Fig. 3; Table 1).
+ *
+ * Conventions
+ *   - Pixel (row i, col j) is the unit square [j, j+1) x [i, i+1); the mesh covers
+ *     [0, W] x [0, H] (Section 2.1); nodes sit on integer pixel corners (x, y).
+ *   - Spline coordinate = image coordinate - 1/2, so sample [i][j] sits at (j, i).
+ *     Boundary: half-sample symmetric.  Coefficients are FP32.
+ *   - Displacements u are FP64, packed pair-major in the order of the pairs given
+ *     to mesh_reg_init; within a pair node-major with (x, y) interleaved:
+ *     u[2 * (node_offset(p) + i) + c].
+ *   - Images and image gradients are FP32, packed pair-major, each pair row-major.
+ *   - Every call enqueues work on the given HIP stream (NULL = default stream) and
+ *     returns without synchronising; outputs land in device memory.
+ *
+ * Ownership
+ *   - The caller owns every DEVICE buffer passed in; the library never frees them.
+ *   - mesh_reg_init copies the mesh and builds its own coefficient images, so te/re
+ *     may be released after init returns (init synchronises its stream).
+ *   - The context owns its tables, factor, schedules and scratch; mesh_reg_destroy
+ *     frees them.  A context must not be used from two threads at once.
+ *
+ * Errors
+ *   - Every call returns an MR_* status; nothing is thrown across the ABI.
+ *   - On error mesh_reg_init sets *out = NULL; other calls leave the state as it was
+ *     before the call when they fail during validation.
+ *   - mesh_reg_last_error() returns a thread-local message for the last failure.
+ *   - Non-finite displacements met by a kernel raise a sticky device flag that the
+ *     next call reports as MR_ENONFINITE (the offending coordinates are clamped
+ *     so no access leaves the images).
+ */
+#ifndef MESHREG_H
+#define MESHREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mr_ctx mr_ctx;
+
+enum {
+  MR_OK = 0,
+  MR_EINVAL = -1,      /* invalid argument or mesh */
+  MR_ENOMEM = -2,      /* host or device allocation failed */
+  MR_EHIP = -3,        /* a HIP runtime call failed */
+  MR_ENOTSPD = -4,     /* (I + tau alpha K) not positive definite (non-positive pivot) */
+  MR_ESTATE = -5,      /* call not valid in the context's state (e.g. host-only) */
+  MR_ENONFINITE = -6   /* a kernel met a non-finite displacement */
+};
+
+enum { MR_FORCE_P1 = 0, MR_FORCE_NODAL = 1 };
+
+enum {
+  MR_FLAG_HOST_ONLY = 1 /* build tables, operators and the factor only; no device work */
+};
+
+/* One registration pair (Algorithm 1, "Inputs"; Section 2.1 for (V, T)). */
+typedef struct {
+  int32_t height, width;       /* image rows, columns (>= 1) */
+  int32_t n_nodes, n_tris;     /* >= 3 and >= 1 */
+  const int32_t *node_xy;      /* HOST [n_nodes][2] integer corners (x, y) in [0,W]x[0,H]; copied */
+  const int32_t *tris;         /* HOST [n_tris][3] node indices, positive signed area
+                                  (b - a) x (c - a) > 0 in (x, y); copied */
+  const float *te;             /* DEVICE [H][W] template; read during init only */
+  const float *re;             /* DEVICE [H][W] reference; read during init only */
+  double alpha;                /* regularisation weight of eq. 1, >= 0 */
+} mr_pair;
+
+typedef struct {
+  double tau;                  /* step size of eq. 5, > 0 */
+  int32_t force_mode;          /* MR_FORCE_P1 (default) or MR_FORCE_NODAL (f = h, eq. 6 literally) */
+  int32_t flags;               /* MR_FLAG_* */
+} mr_params;
+
+/* Pre-computation (Algorithm 1): validates every mesh, builds tables T1-T6
+ * (node->triangle slots, 1-ring, operator pattern, doubled areas, lumped-mass
+ * weights, pixel->triangle map), the P1 stiffness and mass, a nested-dissection
+ * ordering, the FP64 Cholesky factor of (I + tau alpha K) per pair and its block
+ * solve schedule, then (unless MR_FLAG_HOST_ONLY) uploads everything, computes
+ * the B-spline coefficients of te and re and the reference samples at the
+ * undisplaced nodes on the device.  Synchronises `stream` before returning.
+ * Errors: MR_EINVAL (bad argument or mesh: index out of range, non-positive area,
+ * unreferenced node, node outside the image, uncovered pixel, tau <= 0, alpha < 0,
+ * NaN), MR_ENOTSPD, MR_ENOMEM, MR_EHIP. */
+int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
+                  void *stream, mr_ctx **out);
+
+/* n_iter >= 0 iterations of Algorithm 1 (semi-implicit) on every pair, in place.
+ * u: DEVICE [sum n][2] FP64, in/out.  msd_trace: DEVICE [n_iter][n_pairs] FP64 or
+ * NULL; when given, MSD(u^{k+1}) of every pair is written after iteration k (the
+ * full-pixel warp runs every iteration).  Errors: MR_EINVAL, MR_ESTATE, MR_EHIP,
+ * MR_ENONFINITE (reported by the call after the one that met it). */
+int mesh_reg_step(mr_ctx *ctx, double *u, int32_t n_iter, double *msd_trace, void *stream);
+
+/* Warp and MSD (Section 1; Fig. 3): every pixel takes the piecewise-linear
+ * displacement of its triangle (T6), the template spline is sampled at the
+ * displaced pixel centre and msd[p] = mean over pixels of (W - Re)^2 (FP64,
+ * deterministic order).  u: DEVICE [sum n][2]; msd: DEVICE [n_pairs];
+ * warped: DEVICE [sum H*W] FP32 or NULL. */
+int mesh_reg_warp_msd(mr_ctx *ctx, const double *u, double *msd, float *warped, void *stream);
+
+/* The force of one iteration (eq. 4-6 and eq. 10) for the given u:
+ * h: DEVICE [sum n][2] FP32 or NULL (h_i = r_i g_i); b: DEVICE [sum n][2] FP64 or
+ * NULL (b = u - tau f, natural node order). */
+int mesh_reg_force(mr_ctx *ctx, const double *u, float *h, double *b, void *stream);
+
+/* x = (I + tau alpha K)^-1 b per pair and component, by the FP64 triangular
+ * solves of the Cholesky factor.  b, x: DEVICE [sum n][2]; may alias. */
+int mesh_reg_solve(mr_ctx *ctx, const double *b, double *x, void *stream);
+
+/* Reverse mode through n_iter iterations from u0 followed by the warp + MSD:
+ * with L = sum_p g_msd[p] * MSD_p(u^N), writes dL/du0 (DEVICE [sum n][2] FP64 or
+ * NULL), dL/dalpha_p (DEVICE [n_pairs] FP64 or NULL), dL/dTe (DEVICE [sum H*W]
+ * FP32 or NULL) and the forward MSDs (DEVICE [n_pairs] FP64 or NULL).
+ * Iterates u^k are recomputed from checkpoints every ckpt_every (>= 1) iterations;
+ * the adjoint solves reuse each pair's factor.  g_msd: DEVICE [n_pairs] FP64. */
+int mesh_reg_backward(mr_ctx *ctx, const double *u0, int32_t n_iter, int32_t ckpt_every,
+                      const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
+                      double *msd, void *stream);
+
+/* Replace pair `pair`'s alpha: numeric re-factorisation of (I + tau alpha K) with
+ * the symbolic analysis reused, then upload.  Synchronises `stream`. */
+int mesh_reg_set_alpha(mr_ctx *ctx, int32_t pair, double alpha, void *stream);
+
+/* Replace pair `pair`'s template (DEVICE [H][W] FP32): recomputes its spline
+ * coefficients.  Enqueued on `stream`. */
+int mesh_reg_set_template(mr_ctx *ctx, int32_t pair, const float *te, void *stream);
+
+/* Table export for tests.  Copies table `table_id` (MR_TAB_*) of `pair` into
+ * host_out (if not NULL) and writes its element count to *len.  Element types:
+ * int64 for every table except MR_TAB_T6 (int32 [H][W]) and MR_TAB_PERM (int32). */
+enum {
+  MR_TAB_T1_PTR = 10, MR_TAB_T1_SLOT = 11,   /* slot = 3 * triangle + corner */
+  MR_TAB_T2_PTR = 20, MR_TAB_T2_IDX = 21,
+  MR_TAB_T3_PTR = 30, MR_TAB_T3_IDX = 31,
+  MR_TAB_T4 = 40, MR_TAB_T5 = 50, MR_TAB_T6 = 60,
+  MR_TAB_PERM = 70                           /* elimination order: perm[k] = node */
+};
+int mesh_reg_get_tables(mr_ctx *ctx, int32_t pair, int32_t table_id, void *host_out,
+                        int64_t *len);
+
+/* Scalar facts about a pair or the context (MR_INFO_*), written to *value. */
+enum {
+  MR_INFO_N_NODES = 1, MR_INFO_N_TRIS = 2, MR_INFO_NNZ_L = 3, MR_INFO_N_BLOCKS = 4,
+  MR_INFO_FWD_LEVELS = 5, MR_INFO_BWD_LEVELS = 6, MR_INFO_NODE_OFFSET = 7,
+  MR_INFO_PIXEL_OFFSET = 8, MR_INFO_N_PAIRS = 9, MR_INFO_DEVICE_BYTES = 10,
+  MR_INFO_SOLVE_OFFBLOCK = 11,  /* off-block factor entries per direction */
+  MR_INFO_SOLVE_DENSE = 12,     /* packed dense-inverse entries per direction */
+  MR_INFO_MASS_NNZ = 13         /* entries of the force operator rows */
+};
+int mesh_reg_get_info(mr_ctx *ctx, int32_t pair, int32_t key, int64_t *value);
+
+/* Per-kernel timing: when enabled, HIP events are recorded around every launch
+ * of each kernel family on the launch stream; mesh_reg_kernel_times returns,
+ * per family (MR_KF_*), the summed milliseconds and the launch count, and resets
+ * them.  Synchronises the stream of the last launch. */
+enum { MR_KF_SAMPLE = 0, MR_KF_ASSEMBLE = 1, MR_KF_SOLVE = 2, MR_KF_WARP = 3, MR_KF_COUNT = 4 };
+int mesh_reg_enable_timing(mr_ctx *ctx, int32_t enable);
+int mesh_reg_kernel_times(mr_ctx *ctx, double *ms, int64_t *launches);
+
+void mesh_reg_destroy(mr_ctx *ctx);
+
+/* Thread-local text of the last failure on this thread; valid until the next
+ * call on that thread. */
+const char *mesh_reg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESHREG_H */

@@ -1,0 +1,15 @@
+"""MI355X-native mesh-based image registration (arXiv:1411.2141).
+
+The hot path lives in ``libmeshreg.so`` (HIP kernels for gfx950 plus the host
+pre-computation behind the C ABI of ``include/meshreg.h``).  Importing this
+package loads that library and fails if it has not been built
+(``python -m paper_1411_2141_amd.build``); there is no fallback path.
+"""
+from . import binding
+from .binding import MeshRegError, load_library
+
+load_library()
+
+from .registration import MeshReg  # noqa: E402
+
+__all__ = ["binding", "MeshReg", "MeshRegError", "load_library"]

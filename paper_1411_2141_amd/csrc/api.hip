@@ -1,0 +1,626 @@
+// C ABI of the registration library: context set-up (Algorithm 1's
+// pre-computation), the iteration loop, warp + MSD, and table export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/meshreg.h"
+#include "device.h"
+#include "host.h"
+#include "kernels.h"
+#include "ctx.h"
+
+using namespace mr;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(MR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+namespace mr {
+
+template <typename T>
+static hipError_t upload(DevArray<T> &dst, const std::vector<T> &src, hipStream_t s) {
+  hipError_t e = dst.alloc(src.size());
+  if (e != hipSuccess || src.empty()) return e;
+  return hipMemcpyAsync(dst.ptr, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+static std::vector<double> thomas_cp(int N) {
+  std::vector<double> cp(std::max(N, 1), 0.0);
+  if (N <= 1) return cp;
+  const double off = 1.0 / 6.0;
+  cp[0] = off / (5.0 / 6.0);
+  for (int k = 1; k < N; ++k) {
+    const double diag = (k == N - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
+    cp[k] = off / (diag - off * cp[k - 1]);
+  }
+  return cp;
+}
+
+}  // namespace mr
+
+void mr_ctx::timed_begin(int fam, hipStream_t s) {
+  if (!timing) return;
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  hipEventRecord(a, s);
+  pending.push_back({fam, a, b});
+}
+
+void mr_ctx::timed_end(hipStream_t s) {
+  if (!timing || pending.empty()) return;
+  hipEventRecord(pending.back().stop, s);
+}
+
+// Launches the two triangular solves on x (solve order, in place).  When `out`
+// is given, the backward pass also scatters the result to natural order there.
+hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int lev = 0; lev < (int)fwd_ptr.size() - 1; ++lev) {
+    const int cnt = fwd_ptr[lev + 1] - fwd_ptr[lev];
+    if (!cnt) continue;
+    timed_begin(MR_KF_SOLVE, s);
+    e = launch_solve_fwd_level(d_blocks.ptr, d_fwd_list.ptr + fwd_ptr[lev], cnt, d_fptr.ptr,
+                               d_fidx.ptr, d_fval.ptr, d_dcol.ptr, x, s);
+    timed_end(s);
+    if (e != hipSuccess) return e;
+  }
+  for (int lev = 0; lev < (int)bwd_ptr.size() - 1; ++lev) {
+    const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
+    if (!cnt) continue;
+    timed_begin(MR_KF_SOLVE, s);
+    e = launch_solve_bwd_level(d_blocks.ptr, d_bwd_list.ptr + bwd_ptr[lev], cnt, d_bptr.ptr,
+                               d_bidx.ptr, d_bval.ptr, d_drow.ptr, x, d_perm.ptr, out, s);
+    timed_end(s);
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
+  timed_begin(MR_KF_SAMPLE, s);
+  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr,
+                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, s);
+  timed_end(s);
+  if (e != hipSuccess) return e;
+  timed_begin(MR_KF_ASSEMBLE, s);
+  e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u, d_iperm.ptr,
+                      d_x.ptr, params.tau, s);
+  timed_end(s);
+  return e;
+}
+
+hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_t s) {
+  timed_begin(MR_KF_WARP, s);
+  hipError_t e = launch_warp_msd(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr,
+                                 d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
+                                 d_partials.ptr, d_counter.ptr, msd, d_flags.ptr, s);
+  timed_end(s);
+  return e;
+}
+
+int mr_ctx::check_flags() {
+  if (host_flags && *host_flags) {
+    const unsigned f = *host_flags;
+    *host_flags = 0;
+    hipMemsetAsync(d_flags.ptr, 0, sizeof(unsigned), nullptr);
+    return fail(MR_ENONFINITE, f & kFlagNonFiniteNode
+                                   ? "a non-finite or out-of-range node displacement was met"
+                                   : "a non-finite or out-of-range pixel displacement was met");
+  }
+  return MR_OK;
+}
+
+void mr_ctx::post_flags(hipStream_t s) {
+  if (host_flags) hipMemcpyAsync(host_flags, d_flags.ptr, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+}
+
+mr_ctx::~mr_ctx() {
+  for (auto &p : pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  if (host_flags) hipHostFree(host_flags);
+}
+
+// Uploads tables, operators and the factor of every pair into packed device
+// arrays, and builds the work lists.
+int mr_ctx::upload_all(hipStream_t s) {
+  n_nodes = n_tris = n_pix = 0;
+  dpairs.resize(n_pairs);
+  std::vector<NodeItem> items;
+  std::vector<TileItem> tiles;
+  for (int p = 0; p < n_pairs; ++p) {
+    const PairHost &h = host[p];
+    DevPair &d = dpairs[p];
+    d.height = h.height;
+    d.width = h.width;
+    d.pix_off = n_pix;
+    d.node_off = (int32_t)n_nodes;
+    d.n = h.n;
+    d.tri_off = (int32_t)n_tris;
+    d.nt = h.nt;
+    d.tile_off = (int32_t)tiles.size();
+    d.tiles_x = (h.width + kTile - 1) / kTile;
+    const int ty = (h.height + kTile - 1) / kTile;
+    d.n_tiles = d.tiles_x * ty;
+    d.pad0 = 0;
+    for (int y = 0; y < ty; ++y)
+      for (int x = 0; x < d.tiles_x; ++x) tiles.push_back({p, y * kTile, x * kTile, 0});
+    for (int b = 0; b < h.n; b += kNodeChunk)
+      items.push_back({p, d.node_off + b, d.node_off + std::min(h.n, b + kNodeChunk), 0});
+    n_nodes += h.n;
+    n_tris += h.nt;
+    n_pix += (int64_t)h.height * h.width;
+  }
+  if (n_nodes >= INT32_MAX / 2 || n_tris >= INT32_MAX / 2)
+    return fail(MR_EINVAL, "too many nodes or triangles in one context");
+  n_node_items = (int)items.size();
+  n_tiles = (int)tiles.size();
+  // packed node and triangle data
+  std::vector<int2> xy(n_nodes);
+  std::vector<int4> tri(n_tris);
+  std::vector<int32_t> t6(n_pix), iperm(n_nodes), perm(n_nodes);
+  std::vector<int32_t> mptr(n_nodes + 1, 0), mcol;
+  std::vector<float> mwt;
+  std::vector<DevBlock> blocks;
+  std::vector<int64_t> fptr(n_nodes + 1, 0), bptr(n_nodes + 1, 0);
+  std::vector<int32_t> fidx, bidx;
+  std::vector<double> fval, bval, dcol, drow;
+  int max_fl = 0, max_bl = 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    max_fl = std::max(max_fl, host[p].plan.n_fwd_levels);
+    max_bl = std::max(max_bl, host[p].plan.n_bwd_levels);
+  }
+  std::vector<std::vector<int32_t>> fwd_lv(max_fl), bwd_lv(max_bl);
+  for (int p = 0; p < n_pairs; ++p) {
+    const PairHost &h = host[p];
+    const DevPair &d = dpairs[p];
+    const int32_t no = d.node_off;
+    for (int i = 0; i < h.n; ++i) xy[no + i] = make_int2(h.xy[2 * i], h.xy[2 * i + 1]);
+    for (int t = 0; t < h.nt; ++t)
+      tri[d.tri_off + t] = make_int4(no + h.tri[3 * t], no + h.tri[3 * t + 1], no + h.tri[3 * t + 2], 0);
+    std::copy(h.tab.t6.begin(), h.tab.t6.end(), t6.begin() + d.pix_off);
+    for (int i = 0; i < h.n; ++i) {
+      iperm[no + i] = no + h.iperm[i];
+      perm[no + i] = no + h.perm[i];
+    }
+    // force operator rows: f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j, i.e. the
+    // mass row divided by the lumped mass, with 6 m_i = t5_i
+    for (int i = 0; i < h.n; ++i) {
+      if (params.force_mode == MR_FORCE_NODAL) {
+        mcol.push_back(no + i);
+        mwt.push_back(1.0f);
+      } else {
+        const double den = 4.0 * (double)h.tab.t5[i];
+        for (int64_t q = h.tab.t3_ptr[i]; q < h.tab.t3_ptr[i + 1]; ++q) {
+          mcol.push_back(no + (int32_t)h.tab.t3_idx[q]);
+          mwt.push_back((float)((double)h.mval[q] / den));
+        }
+      }
+      mptr[no + i + 1] = (int32_t)mcol.size();
+    }
+    // solve plan, shifted to global rows
+    const SolvePlan &pl = h.plan;
+    const int64_t doff = (int64_t)dcol.size();
+    fval_off.push_back((int64_t)fval.size());
+    bval_off.push_back((int64_t)bval.size());
+    dense_off.push_back(doff);
+    const int32_t boff = (int32_t)blocks.size();
+    for (size_t k = 0; k < pl.blocks.size(); ++k) {
+      const SolveBlock &B = pl.blocks[k];
+      blocks.push_back({no + B.r0, no + B.r1, B.fwd_group, B.bwd_group, doff + pl.dense_off[k]});
+      fwd_lv[B.fwd_level].push_back(boff + (int32_t)k);
+      bwd_lv[B.bwd_level].push_back(boff + (int32_t)k);
+    }
+    dcol.insert(dcol.end(), pl.dinv_col.begin(), pl.dinv_col.end());
+    drow.insert(drow.end(), pl.dinv_row.begin(), pl.dinv_row.end());
+    const int64_t fo = (int64_t)fidx.size(), bo = (int64_t)bidx.size();
+    for (int r = 0; r < h.n; ++r) {
+      fptr[no + r + 1] = fo + pl.fptr[r + 1];
+      bptr[no + r + 1] = bo + pl.bptr[r + 1];
+    }
+    for (int32_t k : pl.fidx) fidx.push_back(no + k);
+    for (int32_t k : pl.bidx) bidx.push_back(no + k);
+    fval.insert(fval.end(), pl.fval.begin(), pl.fval.end());
+    bval.insert(bval.end(), pl.bval.begin(), pl.bval.end());
+  }
+  if (mcol.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "operator too large");
+  std::vector<int32_t> fwd_list, bwd_list;
+  fwd_ptr.assign(1, 0);
+  bwd_ptr.assign(1, 0);
+  for (auto &lv : fwd_lv) {
+    fwd_list.insert(fwd_list.end(), lv.begin(), lv.end());
+    fwd_ptr.push_back((int32_t)fwd_list.size());
+  }
+  for (auto &lv : bwd_lv) {
+    bwd_list.insert(bwd_list.end(), lv.begin(), lv.end());
+    bwd_ptr.push_back((int32_t)bwd_list.size());
+  }
+  nnz_factor = (int64_t)fidx.size() + (int64_t)dcol.size();
+  HIP_TRY(upload(d_pairs, dpairs, s));
+  HIP_TRY(upload(d_node_items, items, s));
+  HIP_TRY(upload(d_tiles, tiles, s));
+  HIP_TRY(upload(d_xy, xy, s));
+  HIP_TRY(upload(d_tri, tri, s));
+  HIP_TRY(upload(d_t6, t6, s));
+  HIP_TRY(upload(d_iperm, iperm, s));
+  HIP_TRY(upload(d_perm, perm, s));
+  HIP_TRY(upload(d_mptr, mptr, s));
+  HIP_TRY(upload(d_mcol, mcol, s));
+  HIP_TRY(upload(d_mwt, mwt, s));
+  HIP_TRY(upload(d_blocks, blocks, s));
+  HIP_TRY(upload(d_fwd_list, fwd_list, s));
+  HIP_TRY(upload(d_bwd_list, bwd_list, s));
+  HIP_TRY(upload(d_fptr, fptr, s));
+  HIP_TRY(upload(d_fidx, fidx, s));
+  HIP_TRY(upload(d_fval, fval, s));
+  HIP_TRY(upload(d_bptr, bptr, s));
+  HIP_TRY(upload(d_bidx, bidx, s));
+  HIP_TRY(upload(d_bval, bval, s));
+  HIP_TRY(upload(d_dcol, dcol, s));
+  HIP_TRY(upload(d_drow, drow, s));
+  HIP_TRY(d_coef.alloc(n_pix));
+  HIP_TRY(d_re.alloc(n_pix));
+  HIP_TRY(d_rho.alloc(n_nodes));
+  HIP_TRY(d_h.alloc(n_nodes));
+  HIP_TRY(d_x.alloc(n_nodes));
+  HIP_TRY(d_partials.alloc(std::max(n_tiles, 1)));
+  HIP_TRY(d_counter.alloc(1));
+  HIP_TRY(d_flags.alloc(1));
+  HIP_TRY(d_msd_tmp.alloc(n_pairs));
+  HIP_TRY(hipMemsetAsync(d_counter.ptr, 0, sizeof(unsigned), s));
+  HIP_TRY(hipMemsetAsync(d_flags.ptr, 0, sizeof(unsigned), s));
+  HIP_TRY(hipHostMalloc((void **)&host_flags, sizeof(unsigned), hipHostMallocDefault));
+  *host_flags = 0;
+  return MR_OK;
+}
+
+// Re-uploads the numeric values of one pair's factor (same structure).
+int mr_ctx::upload_factor(int p, hipStream_t s) {
+  const SolvePlan &pl = host[p].plan;
+  auto put = [&](double *dst, const std::vector<double> &v) {
+    return v.empty() ? hipSuccess
+                     : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  };
+  HIP_TRY(put(d_fval.ptr + fval_off[p], pl.fval));
+  HIP_TRY(put(d_bval.ptr + bval_off[p], pl.bval));
+  HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
+  HIP_TRY(put(d_drow.ptr + dense_off[p], pl.dinv_row));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MR_OK;
+}
+
+int64_t mr_ctx::device_bytes() const {
+  return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
+                   d_tri.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
+                   d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_mptr.bytes() +
+                   d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
+                   d_blocks.bytes() + d_fwd_list.bytes() + d_bwd_list.bytes() + d_fptr.bytes() +
+                   d_bptr.bytes() + d_fidx.bytes() + d_bidx.bytes() + d_fval.bytes() +
+                   d_bval.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
+                   d_msd_tmp.bytes() + d_counter.bytes() + d_flags.bytes());
+}
+
+// B-spline coefficients of one pair's image (FP32 device input).
+int mr_ctx::prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s) {
+  const DevPair &d = dpairs[p];
+  DevArray<double> tmp, cpw, cph;
+  HIP_TRY(tmp.alloc((size_t)d.height * d.width));
+  HIP_TRY(upload(cpw, thomas_cp(d.width), s));
+  HIP_TRY(upload(cph, thomas_cp(d.height), s));
+  HIP_TRY(launch_prefilter(img, nullptr, tmp.ptr, coef_out, d.height, d.width, cpw.ptr, cph.ptr, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" const char *mesh_reg_last_error(void) { return g_last_error.c_str(); }
+
+static int check_ctx(mr_ctx *c, bool need_device) {
+  if (!c) return fail(MR_EINVAL, "null context");
+  if (need_device && c->host_only) return fail(MR_ESTATE, "context was built host-only");
+  return MR_OK;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
+                             void *stream, mr_ctx **out) {
+  if (!out) return fail(MR_EINVAL, "out is null");
+  *out = nullptr;
+  if (!pairs || n_pairs < 1 || !params) return fail(MR_EINVAL, "need pairs, n_pairs >= 1 and params");
+  if (!(params->tau > 0.0) || !std::isfinite(params->tau)) return fail(MR_EINVAL, "tau must be finite and > 0");
+  if (params->force_mode != MR_FORCE_P1 && params->force_mode != MR_FORCE_NODAL)
+    return fail(MR_EINVAL, "unknown force_mode");
+  const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    const mr_pair &q = pairs[p];
+    if (!(q.alpha >= 0.0) || !std::isfinite(q.alpha))
+      return fail(MR_EINVAL, "pair " + std::to_string(p) + ": alpha must be finite and >= 0");
+    if (!q.node_xy || !q.tris) return fail(MR_EINVAL, "pair " + std::to_string(p) + ": null mesh");
+    if (q.n_nodes < 3 || q.n_tris < 1 || q.height < 1 || q.width < 1)
+      return fail(MR_EINVAL, "pair " + std::to_string(p) + ": empty mesh or image");
+    if (!host_only && (!q.te || !q.re))
+      return fail(MR_EINVAL, "pair " + std::to_string(p) + ": null te/re");
+  }
+  mr_ctx *c = new (std::nothrow) mr_ctx();
+  if (!c) return fail(MR_ENOMEM, "context allocation failed");
+  c->params = *params;
+  c->n_pairs = n_pairs;
+  c->host_only = host_only;
+  c->host.resize(n_pairs);
+  OrderOptions opt;
+  for (int p = 0; p < n_pairs; ++p) {
+    const mr_pair &q = pairs[p];
+    PairHost &h = c->host[p];
+    h.height = q.height;
+    h.width = q.width;
+    h.n = q.n_nodes;
+    h.nt = q.n_tris;
+    h.alpha = q.alpha;
+    h.xy.assign(q.node_xy, q.node_xy + 2 * (size_t)q.n_nodes);
+    h.tri.assign(q.tris, q.tris + 3 * (size_t)q.n_tris);
+    bool not_spd = false;
+    std::string e = prepare_pair(h, params->tau, opt, &not_spd);
+    if (!e.empty()) {
+      delete c;
+      return fail(not_spd ? MR_ENOTSPD : MR_EINVAL, "pair " + std::to_string(p) + ": " + e);
+    }
+  }
+  if (host_only) {
+    *out = c;
+    return MR_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(MR_EHIP, "no HIP device available");
+  }
+  if ((rc = c->upload_all(s)) != MR_OK) {
+    delete c;
+    return rc;
+  }
+  for (int p = 0; p < n_pairs; ++p) {
+    const DevPair &d = c->dpairs[p];
+    float *coef_re = c->d_re.ptr + d.pix_off;  // temporarily holds Re's coefficients
+    if ((rc = c->prefilter_pair(p, pairs[p].te, c->d_coef.ptr + d.pix_off, s)) != MR_OK ||
+        (rc = c->prefilter_pair(p, pairs[p].re, coef_re, s)) != MR_OK) {
+      delete c;
+      return rc;
+    }
+  }
+  hipError_t e = launch_sample_rho(c->d_node_items.ptr, c->n_node_items, c->d_pairs.ptr,
+                                   c->d_xy.ptr, c->d_re.ptr, c->d_rho.ptr, s);
+  // the reference pixels themselves replace its coefficients
+  for (int p = 0; p < n_pairs && e == hipSuccess; ++p) {
+    const DevPair &d = c->dpairs[p];
+    e = hipMemcpyAsync(c->d_re.ptr + d.pix_off, pairs[p].re,
+                       sizeof(float) * (size_t)d.height * d.width, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(MR_EHIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace,
+                             void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || n_iter < 0) return fail(MR_EINVAL, "u must be a 16-byte aligned device pointer; n_iter >= 0");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  double2 *u2 = reinterpret_cast<double2 *>(u);
+  for (int k = 0; k < n_iter; ++k) {
+    HIP_TRY(c->force(u2, s));
+    HIP_TRY(c->solve(c->d_x.ptr, u2, s));
+    if (msd_trace) HIP_TRY(c->warp(u2, msd_trace + (size_t)k * c->n_pairs, nullptr, s));
+  }
+  c->post_flags(s);
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_warp_msd(mr_ctx *c, const double *u, double *msd, float *warped,
+                                 void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || !msd) return fail(MR_EINVAL, "need aligned u and msd");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c->warp(reinterpret_cast<const double2 *>(u), msd, warped, s));
+  c->post_flags(s);
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_force(mr_ctx *c, const double *u, float *h, double *b, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || (b && !aligned16(b)) || (h && ((uintptr_t)h & 7u)))
+    return fail(MR_EINVAL, "need aligned u (and h, b)");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c->force(reinterpret_cast<const double2 *>(u), s));
+  if (h) HIP_TRY(hipMemcpyAsync(h, c->d_h.ptr, sizeof(float2) * c->n_nodes, hipMemcpyDeviceToDevice, s));
+  if (b) HIP_TRY(launch_from_solve_order((int)c->n_nodes, c->d_x.ptr, c->d_iperm.ptr,
+                                         reinterpret_cast<double2 *>(b), s));
+  c->post_flags(s);
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_solve(mr_ctx *c, const double *b, double *x, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!b || !x || !aligned16(b) || !aligned16(x)) return fail(MR_EINVAL, "need aligned b and x");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_to_solve_order((int)c->n_nodes, reinterpret_cast<const double2 *>(b),
+                                c->d_iperm.ptr, c->d_x.ptr, s));
+  HIP_TRY(c->solve(c->d_x.ptr, reinterpret_cast<double2 *>(x), s));
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *stream) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (pair < 0 || pair >= c->n_pairs) return fail(MR_EINVAL, "pair out of range");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MR_EINVAL, "alpha must be finite and >= 0");
+  PairHost &h = c->host[pair];
+  const double old = h.alpha;
+  h.alpha = alpha;
+  bool not_spd = false;
+  std::string e = refactor(h, c->params.tau, &not_spd);
+  if (!e.empty()) {
+    h.alpha = old;
+    bool dummy;
+    refactor(h, c->params.tau, &dummy);
+    return fail(not_spd ? MR_ENOTSPD : MR_EINVAL, e);
+  }
+  fill_dense_inverses(h);
+  fill_offblock_values(h);
+  if (c->host_only) return MR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  return c->upload_factor(pair, s);
+}
+
+extern "C" int mesh_reg_set_template(mr_ctx *c, int32_t pair, const float *te, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (pair < 0 || pair >= c->n_pairs || !te) return fail(MR_EINVAL, "bad pair or null te");
+  hipStream_t s = (hipStream_t)stream;
+  return c->prefilter_pair(pair, te, c->d_coef.ptr + c->dpairs[pair].pix_off, s);
+}
+
+extern "C" int mesh_reg_get_tables(mr_ctx *c, int32_t pair, int32_t table_id, void *host_out,
+                                   int64_t *len) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (pair < 0 || pair >= c->n_pairs || !len) return fail(MR_EINVAL, "bad pair or null len");
+  const PairHost &h = c->host[pair];
+  const std::vector<int64_t> *v64 = nullptr;
+  const std::vector<int32_t> *v32 = nullptr;
+  switch (table_id) {
+    case MR_TAB_T1_PTR: v64 = &h.tab.t1_ptr; break;
+    case MR_TAB_T1_SLOT: v64 = &h.tab.t1_slot; break;
+    case MR_TAB_T2_PTR: v64 = &h.tab.t2_ptr; break;
+    case MR_TAB_T2_IDX: v64 = &h.tab.t2_idx; break;
+    case MR_TAB_T3_PTR: v64 = &h.tab.t3_ptr; break;
+    case MR_TAB_T3_IDX: v64 = &h.tab.t3_idx; break;
+    case MR_TAB_T4: v64 = &h.tab.t4; break;
+    case MR_TAB_T5: v64 = &h.tab.t5; break;
+    case MR_TAB_T6: v32 = &h.tab.t6; break;
+    case MR_TAB_PERM: v32 = &h.perm; break;
+    default: return fail(MR_EINVAL, "unknown table id");
+  }
+  if (v64) {
+    *len = (int64_t)v64->size();
+    if (host_out) std::memcpy(host_out, v64->data(), v64->size() * sizeof(int64_t));
+  } else {
+    *len = (int64_t)v32->size();
+    if (host_out) std::memcpy(host_out, v32->data(), v32->size() * sizeof(int32_t));
+  }
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *value) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (!value) return fail(MR_EINVAL, "null value");
+  if (key == MR_INFO_N_PAIRS) {
+    *value = c->n_pairs;
+    return MR_OK;
+  }
+  if (key == MR_INFO_DEVICE_BYTES) {
+    *value = c->device_bytes();
+    return MR_OK;
+  }
+  if (pair < 0 || pair >= c->n_pairs) return fail(MR_EINVAL, "pair out of range");
+  const PairHost &h = c->host[pair];
+  switch (key) {
+    case MR_INFO_N_NODES: *value = h.n; break;
+    case MR_INFO_N_TRIS: *value = h.nt; break;
+    case MR_INFO_NNZ_L: *value = h.L.colptr.empty() ? 0 : h.L.colptr[h.n]; break;
+    case MR_INFO_N_BLOCKS: *value = (int64_t)h.plan.blocks.size(); break;
+    case MR_INFO_SOLVE_OFFBLOCK: *value = (int64_t)h.plan.fidx.size(); break;
+    case MR_INFO_SOLVE_DENSE: *value = (int64_t)h.plan.dinv_col.size(); break;
+    case MR_INFO_MASS_NNZ:
+      *value = c->params.force_mode == MR_FORCE_NODAL ? h.n : (int64_t)h.tab.t3_idx.size();
+      break;
+    case MR_INFO_FWD_LEVELS: *value = h.plan.n_fwd_levels; break;
+    case MR_INFO_BWD_LEVELS: *value = h.plan.n_bwd_levels; break;
+    case MR_INFO_NODE_OFFSET: {
+      int64_t o = 0;
+      for (int p = 0; p < pair; ++p) o += c->host[p].n;
+      *value = o;
+      break;
+    }
+    case MR_INFO_PIXEL_OFFSET: {
+      int64_t o = 0;
+      for (int p = 0; p < pair; ++p) o += (int64_t)c->host[p].height * c->host[p].width;
+      *value = o;
+      break;
+    }
+    default: return fail(MR_EINVAL, "unknown info key");
+  }
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_enable_timing(mr_ctx *c, int32_t enable) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  c->timing = enable != 0;
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_kernel_times(mr_ctx *c, double *ms, int64_t *launches) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!ms || !launches) return fail(MR_EINVAL, "null output");
+  for (int f = 0; f < MR_KF_COUNT; ++f) {
+    ms[f] = 0.0;
+    launches[f] = 0;
+  }
+  for (auto &p : c->pending) {
+    HIP_TRY(hipEventSynchronize(p.stop));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, p.start, p.stop));
+    ms[p.family] += t;
+    launches[p.family] += 1;
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  c->pending.clear();
+  return MR_OK;
+}
+
+extern "C" void mesh_reg_destroy(mr_ctx *c) { delete c; }
+
+extern "C" int mesh_reg_backward(mr_ctx *c, const double *u0, int32_t n_iter, int32_t ckpt_every,
+                                 const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
+                                 double *msd, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  return c->backward(u0, n_iter, ckpt_every, g_msd, g_u0, g_alpha, g_te, msd, (hipStream_t)stream);
+}

@@ -1,0 +1,99 @@
+// The library context: host pre-computation of every pair plus the packed
+// device arrays the kernels read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/meshreg.h"
+#include "device.h"
+#include "host.h"
+
+namespace mr {
+
+template <typename T>
+struct DevArray {
+  T *ptr = nullptr;
+  size_t count = 0;
+  DevArray() = default;
+  DevArray(const DevArray &) = delete;
+  DevArray &operator=(const DevArray &) = delete;
+  ~DevArray() { release(); }
+  hipError_t alloc(size_t n) {
+    release();
+    count = n;
+    if (n == 0) return hipSuccess;
+    return hipMalloc((void **)&ptr, n * sizeof(T));
+  }
+  void release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    count = 0;
+  }
+  size_t bytes() const { return count * sizeof(T); }
+};
+
+struct TimedLaunch {
+  int family;
+  hipEvent_t start, stop;
+};
+
+}  // namespace mr
+
+struct mr_ctx {
+  int device = 0;
+  mr_params params{};
+  int32_t n_pairs = 0;
+  bool host_only = false;
+  std::vector<mr::PairHost> host;
+  std::vector<mr::DevPair> dpairs;
+  int64_t n_nodes = 0, n_tris = 0, n_pix = 0, nnz_factor = 0;
+  int n_node_items = 0, n_tiles = 0;
+  // per pair offsets into the packed factor arrays (for re-factorisation)
+  std::vector<int64_t> fval_off, bval_off, dense_off;
+
+  mr::DevArray<mr::DevPair> d_pairs;
+  mr::DevArray<mr::NodeItem> d_node_items;
+  mr::DevArray<mr::TileItem> d_tiles;
+  mr::DevArray<int2> d_xy;
+  mr::DevArray<int4> d_tri;
+  mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
+  mr::DevArray<float> d_coef, d_re, d_rho;
+  mr::DevArray<int32_t> d_mptr, d_mcol;
+  mr::DevArray<float> d_mwt;
+  mr::DevArray<float2> d_h;
+  mr::DevArray<double2> d_x;
+  mr::DevArray<mr::DevBlock> d_blocks;
+  mr::DevArray<int32_t> d_fwd_list, d_bwd_list;
+  std::vector<int32_t> fwd_ptr, bwd_ptr;     // level -> range of the level lists (host)
+  mr::DevArray<int64_t> d_fptr, d_bptr;
+  mr::DevArray<int32_t> d_fidx, d_bidx;
+  mr::DevArray<double> d_fval, d_bval, d_dcol, d_drow;
+  mr::DevArray<double> d_partials, d_msd_tmp;
+  mr::DevArray<unsigned> d_counter, d_flags;
+  unsigned *host_flags = nullptr;            // pinned copy of d_flags
+
+  bool timing = false;
+  std::vector<mr::TimedLaunch> pending;
+
+  ~mr_ctx();
+  int upload_all(hipStream_t s);
+  int upload_factor(int pair, hipStream_t s);
+  int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
+  hipError_t force(const double2 *u, hipStream_t s);
+  hipError_t solve(double2 *x, double2 *out, hipStream_t s);
+  hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
+  int check_flags();
+  void post_flags(hipStream_t s);
+  void timed_begin(int family, hipStream_t s);
+  void timed_end(hipStream_t s);
+  int64_t device_bytes() const;
+  int backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
+               double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s);
+};
+
+namespace mr {
+using Ctx = ::mr_ctx;
+}

@@ -1,0 +1,101 @@
+// Host-side (CPU) pre-computation of one registration pair: mesh tables,
+// P1 operators, nested-dissection ordering, FP64 Cholesky factor and the
+// block schedule of the triangular solves.  Plain C++17, no HIP: this part is
+// built with g++ (and sanitizers) as well as hipcc.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mr {
+
+// Tables T1-T6 of the pre-computation step of Algorithm 1.
+struct MeshTables {
+  std::vector<int64_t> t1_ptr, t1_slot;   // node -> slots 3*tri+corner, slots in triangle order
+  std::vector<int64_t> t2_ptr, t2_idx;    // 1-ring, ascending
+  std::vector<int64_t> t3_ptr, t3_idx;    // operator pattern = 1-ring + diagonal, ascending
+  std::vector<int64_t> t4;                // twice the signed area per triangle
+  std::vector<int64_t> t5;                // per node: sum of t4 over its triangles
+  std::vector<int32_t> t6;                // per pixel: lowest-id triangle holding its centre
+};
+
+// Cholesky factor L of P S P^T stored by columns (CSC), rows ascending, with the
+// diagonal first in every column.
+struct Factor {
+  int32_t n = 0;
+  std::vector<int64_t> colptr;
+  std::vector<int32_t> rowidx;
+  std::vector<double> val;
+  std::vector<int32_t> parent;            // elimination tree
+};
+
+// A block of consecutive rows [r0, r1) of the permuted system, solved as one
+// unit: its dense diagonal block of L is inverted, its coupling to other
+// blocks is applied by sparse dot products.
+struct SolveBlock {
+  int32_t r0, r1;
+  int32_t parent;                          // block id, -1 for a root
+  int32_t fwd_level, bwd_level;
+  int32_t fwd_group, bwd_group;            // lanes per row for the off-block dot products
+};
+
+struct SolvePlan {
+  std::vector<SolveBlock> blocks;
+  // dense inverses of the diagonal blocks, packed lower triangles:
+  // column-major (forward) and row-major (backward), both b(b+1)/2 per block
+  std::vector<int64_t> dense_off;          // per block, same offset in both arrays
+  std::vector<double> dinv_col, dinv_row;
+  // forward off-block entries by row: L(i, k) with k < r0(block(i))
+  std::vector<int64_t> fptr;
+  std::vector<int32_t> fidx;
+  std::vector<double> fval;
+  // backward off-block entries by column: L(r, j) with r >= r1(block(j))
+  std::vector<int64_t> bptr;
+  std::vector<int32_t> bidx;
+  std::vector<double> bval;
+  int32_t n_fwd_levels = 0, n_bwd_levels = 0;
+};
+
+struct PairHost {
+  int32_t height = 0, width = 0, n = 0, nt = 0;
+  double alpha = 0.0;
+  std::vector<int32_t> xy;                 // [n][2]
+  std::vector<int32_t> tri;                // [nt][3]
+  MeshTables tab;
+  std::vector<double> kval;                // stiffness on the t3 pattern
+  std::vector<int64_t> mval;               // 24 * mass on the t3 pattern (integer)
+  std::vector<int32_t> perm, iperm;        // perm[k] = node eliminated k-th
+  Factor L;
+  std::vector<int64_t> L_rowptr;           // strict lower pattern of L by rows,
+  std::vector<int32_t> L_rowcol;           // columns ascending (from the symbolic phase)
+  SolvePlan plan;
+};
+
+struct OrderOptions {
+  int32_t leaf_max = 32;                   // nested-dissection leaf size
+  int32_t block_max = 128;                 // largest dense diagonal block
+};
+
+// Each returns an empty string on success, else the reason.
+std::string validate_mesh(const PairHost &p);
+std::string build_tables(PairHost &p);
+void build_operators(PairHost &p);
+std::string nested_dissection(PairHost &p, const OrderOptions &opt,
+                              std::vector<std::pair<int32_t, int32_t>> &ranges,
+                              std::vector<int32_t> &range_parent);
+// Symbolic + numeric factorisation of P (I + tau alpha K) P^T.  Returns "" or
+// a message; sets *not_spd when a pivot is not positive.
+std::string cholesky(PairHost &p, double tau, bool *not_spd);
+// Numeric refactorisation with the symbolic structure of p.L reused.
+std::string refactor(PairHost &p, double tau, bool *not_spd);
+std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, int32_t>> &ranges,
+                             const std::vector<int32_t> &range_parent, const OrderOptions &opt);
+// Dense inverses only (after a refactor with unchanged structure).
+void fill_dense_inverses(PairHost &p);
+void fill_offblock_values(PairHost &p);
+
+// Everything above in order.
+std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd);
+
+}  // namespace mr

@@ -1,0 +1,427 @@
+// Ordering, FP64 sparse Cholesky factorisation of S = I + tau alpha K and the
+// block schedule of its triangular solves.
+//
+// The paper solves its sparse mesh system directly (abstract; Section 3.3);
+// here the system is the implicit diffusion step (eq. 7-8 taken implicitly
+// with the symmetric P1 stiffness).  The factor is computed once per mesh and
+// alpha on the host; the GPU only runs the two triangular solves per iteration.
+//
+// Ordering: geometric nested dissection on the node coordinates.  A node set is
+// split at the median coordinate of its wider axis; the separator is the
+// smaller of the two one-sided boundary sets; the halves are ordered first,
+// the separator last.  Small sets become leaf blocks, separators become one or
+// more chained blocks.  Every block is a contiguous row range of P S P^T and
+// the block tree contains the elimination tree, which is what lets the solve
+// run block-parallel level by level.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+
+#include "host.h"
+
+namespace mr {
+
+namespace {
+
+struct NDState {
+  const PairHost &p;
+  const OrderOptions &opt;
+  std::vector<int32_t> order;
+  std::vector<std::pair<int32_t, int32_t>> ranges;
+  std::vector<int32_t> parent;
+  std::vector<int8_t> side;   // -1 outside the current set, 0 left, 1 right
+  NDState(const PairHost &pp, const OrderOptions &o) : p(pp), opt(o), side(pp.n, -1) {}
+
+  int32_t emit(const std::vector<int32_t> &nodes) {
+    const int32_t r0 = (int32_t)order.size();
+    order.insert(order.end(), nodes.begin(), nodes.end());
+    ranges.emplace_back(r0, (int32_t)order.size());
+    parent.push_back(-1);
+    return (int32_t)ranges.size() - 1;
+  }
+
+  // Orders `S` (consumed) and returns the block id of its subtree root.
+  int32_t run(std::vector<int32_t> S) {
+    if ((int32_t)S.size() <= opt.leaf_max) {
+      std::sort(S.begin(), S.end());
+      return emit(S);
+    }
+    int32_t lo[2] = {INT32_MAX, INT32_MAX}, hi[2] = {INT32_MIN, INT32_MIN};
+    for (int32_t v : S)
+      for (int a = 0; a < 2; ++a) {
+        lo[a] = std::min(lo[a], p.xy[2 * v + a]);
+        hi[a] = std::max(hi[a], p.xy[2 * v + a]);
+      }
+    int axis = (hi[0] - lo[0] >= hi[1] - lo[1]) ? 0 : 1;
+    if (hi[axis] == lo[axis]) axis ^= 1;
+    // split value: the median coordinate, moved up if nothing lies below it
+    std::vector<int32_t> coord(S.size());
+    for (size_t k = 0; k < S.size(); ++k) coord[k] = p.xy[2 * S[k] + axis];
+    std::vector<int32_t> tmp = coord;
+    std::nth_element(tmp.begin(), tmp.begin() + tmp.size() / 2, tmp.end());
+    int32_t c = tmp[tmp.size() / 2];
+    if (c == lo[axis]) {
+      int32_t nxt = INT32_MAX;
+      for (int32_t v : coord)
+        if (v > lo[axis]) nxt = std::min(nxt, v);
+      c = nxt;
+    }
+    for (size_t k = 0; k < S.size(); ++k) side[S[k]] = coord[k] < c ? 0 : 1;
+    std::vector<int32_t> sepL, sepR;
+    const auto &ptr = p.tab.t2_ptr;
+    const auto &idx = p.tab.t2_idx;
+    for (int32_t v : S) {
+      const int8_t sv = side[v];
+      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        const int8_t sw = side[idx[k]];
+        if (sw >= 0 && sw != sv) {
+          (sv == 0 ? sepL : sepR).push_back(v);
+          break;
+        }
+      }
+    }
+    const bool useR = sepR.size() <= sepL.size();
+    std::vector<int32_t> &sep = useR ? sepR : sepL;
+    for (int32_t v : sep) side[v] = 2;
+    std::vector<int32_t> A, B;
+    for (int32_t v : S) {
+      if (side[v] == 0) A.push_back(v);
+      else if (side[v] == 1) B.push_back(v);
+    }
+    for (int32_t v : S) side[v] = -1;
+    std::vector<int32_t>().swap(S);
+    const int32_t a = A.empty() ? -1 : run(std::move(A));
+    const int32_t b = B.empty() ? -1 : run(std::move(B));
+    // separator nodes along the cut, then chunked into chained blocks
+    const int other = axis ^ 1;
+    std::sort(sep.begin(), sep.end(), [&](int32_t u, int32_t v) {
+      const int32_t cu = p.xy[2 * u + other], cv = p.xy[2 * v + other];
+      return cu != cv ? cu < cv : u < v;
+    });
+    const int32_t ns = (int32_t)sep.size();
+    const int32_t nchunk = std::max<int32_t>(1, (ns + opt.block_max - 1) / opt.block_max);
+    int32_t prev = -1, first = -1;
+    for (int32_t q = 0; q < nchunk; ++q) {
+      const int32_t s0 = (int32_t)((int64_t)ns * q / nchunk), s1 = (int32_t)((int64_t)ns * (q + 1) / nchunk);
+      std::vector<int32_t> part(sep.begin() + s0, sep.begin() + s1);
+      const int32_t id = emit(part);
+      if (prev >= 0) parent[prev] = id;
+      if (first < 0) first = id;
+      prev = id;
+    }
+    if (a >= 0) parent[a] = first;
+    if (b >= 0) parent[b] = first;
+    return prev;
+  }
+};
+
+inline int32_t next_pow2_clamped(double x, int32_t lo, int32_t hi) {
+  int32_t g = lo;
+  while (g < hi && g < x) g *= 2;
+  return g;
+}
+
+}  // namespace
+
+std::string nested_dissection(PairHost &p, const OrderOptions &opt,
+                              std::vector<std::pair<int32_t, int32_t>> &ranges,
+                              std::vector<int32_t> &range_parent) {
+  NDState st(p, opt);
+  std::vector<int32_t> all(p.n);
+  for (int32_t i = 0; i < p.n; ++i) all[i] = i;
+  st.run(std::move(all));
+  if ((int32_t)st.order.size() != p.n) return "nested dissection lost nodes";
+  p.perm = st.order;
+  p.iperm.assign(p.n, -1);
+  for (int32_t k = 0; k < p.n; ++k) p.iperm[p.perm[k]] = k;
+  for (int32_t i = 0; i < p.n; ++i)
+    if (p.iperm[i] < 0) return "nested dissection produced a non-permutation";
+  ranges = std::move(st.ranges);
+  range_parent = std::move(st.parent);
+  return "";
+}
+
+// Permuted matrix A = P S P^T: row k holds entries (iperm[j], S[perm[k], j]).
+static void permuted_rows(const PairHost &p, double tau,
+                          std::vector<std::vector<std::pair<int32_t, double>>> &rows) {
+  rows.assign(p.n, {});
+  const auto &ptr = p.tab.t3_ptr;
+  const auto &idx = p.tab.t3_idx;
+  const double ta = tau * p.alpha;
+  for (int32_t k = 0; k < p.n; ++k) {
+    const int32_t v = p.perm[k];
+    for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q) {
+      const int32_t j = (int32_t)idx[q];
+      const double s = (j == v ? 1.0 : 0.0) + ta * p.kval[q];
+      rows[k].emplace_back(p.iperm[j], s);
+    }
+    std::sort(rows[k].begin(), rows[k].end());
+  }
+}
+
+// Up-looking numeric factorisation over the stored row patterns.
+static std::string numeric(PairHost &p, double tau, bool *not_spd) {
+  Factor &L = p.L;
+  const int32_t n = L.n;
+  std::vector<std::vector<std::pair<int32_t, double>>> A;
+  permuted_rows(p, tau, A);
+  std::vector<double> x(n, 0.0);
+  std::vector<int64_t> next(n);
+  for (int32_t j = 0; j < n; ++j) next[j] = L.colptr[j] + 1;
+  for (int32_t i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (auto &e : A[i]) {
+      if (e.first < i) x[e.first] = e.second;
+      else if (e.first == i) d = e.second;
+    }
+    for (int64_t q = p.L_rowptr[i]; q < p.L_rowptr[i + 1]; ++q) {
+      const int32_t j = p.L_rowcol[q];
+      const double lij = x[j] / L.val[L.colptr[j]];
+      x[j] = 0.0;
+      for (int64_t r = L.colptr[j] + 1; r < next[j]; ++r) x[L.rowidx[r]] -= L.val[r] * lij;
+      d -= lij * lij;
+      L.rowidx[next[j]] = i;
+      L.val[next[j]] = lij;
+      ++next[j];
+    }
+    if (!(d > 0.0) || !std::isfinite(d)) {
+      *not_spd = true;
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "non-positive pivot %.3e at elimination step %d", d, i);
+      return buf;
+    }
+    L.rowidx[L.colptr[i]] = i;
+    L.val[L.colptr[i]] = std::sqrt(d);
+  }
+  for (int32_t j = 0; j < n; ++j)
+    if (next[j] != L.colptr[j + 1]) return "factor structure mismatch";
+  return "";
+}
+
+std::string cholesky(PairHost &p, double tau, bool *not_spd) {
+  *not_spd = false;
+  const int32_t n = p.n;
+  Factor &L = p.L;
+  L.n = n;
+  // permuted lower pattern
+  std::vector<std::vector<std::pair<int32_t, double>>> A;
+  permuted_rows(p, tau, A);
+  // elimination tree (with path-compressed ancestors)
+  L.parent.assign(n, -1);
+  std::vector<int32_t> anc(n, -1);
+  for (int32_t i = 0; i < n; ++i)
+    for (auto &e : A[i]) {
+      int32_t k = e.first;
+      if (k >= i) continue;
+      while (k != -1 && k != i) {
+        const int32_t nk = anc[k];
+        anc[k] = i;
+        if (nk == -1) L.parent[k] = i;
+        k = nk;
+      }
+    }
+  // row patterns: walk up the tree from each entry of row i until a marked node
+  std::vector<int32_t> mark(n, -1), count(n, 1);
+  p.L_rowptr.assign(n + 1, 0);
+  p.L_rowcol.clear();
+  std::vector<int32_t> rowbuf;
+  for (int32_t i = 0; i < n; ++i) {
+    rowbuf.clear();
+    mark[i] = i;
+    for (auto &e : A[i]) {
+      int32_t k = e.first;
+      if (k >= i) continue;
+      while (k != -1 && mark[k] != i) {
+        mark[k] = i;
+        rowbuf.push_back(k);
+        k = L.parent[k];
+      }
+    }
+    std::sort(rowbuf.begin(), rowbuf.end());
+    for (int32_t j : rowbuf) ++count[j];
+    p.L_rowcol.insert(p.L_rowcol.end(), rowbuf.begin(), rowbuf.end());
+    p.L_rowptr[i + 1] = (int64_t)p.L_rowcol.size();
+  }
+  L.colptr.assign(n + 1, 0);
+  for (int32_t j = 0; j < n; ++j) L.colptr[j + 1] = L.colptr[j] + count[j];
+  L.rowidx.assign(L.colptr[n], 0);
+  L.val.assign(L.colptr[n], 0.0);
+  return numeric(p, tau, not_spd);
+}
+
+std::string refactor(PairHost &p, double tau, bool *not_spd) {
+  *not_spd = false;
+  return numeric(p, tau, not_spd);
+}
+
+void fill_dense_inverses(PairHost &p) {
+  SolvePlan &pl = p.plan;
+  const Factor &L = p.L;
+  std::vector<double> D, X;
+  for (size_t s = 0; s < pl.blocks.size(); ++s) {
+    const int32_t r0 = pl.blocks[s].r0, r1 = pl.blocks[s].r1, b = r1 - r0;
+    if (b == 0) continue;
+    D.assign((size_t)b * b, 0.0);
+    X.assign((size_t)b * b, 0.0);
+    for (int32_t j = r0; j < r1; ++j)
+      for (int64_t q = L.colptr[j]; q < L.colptr[j + 1]; ++q) {
+        const int32_t i = L.rowidx[q];
+        if (i >= r1) break;
+        D[(size_t)(i - r0) * b + (j - r0)] = L.val[q];
+      }
+    // X = D^-1 (lower triangular), column by column
+    for (int32_t c = 0; c < b; ++c) {
+      X[(size_t)c * b + c] = 1.0 / D[(size_t)c * b + c];
+      for (int32_t i = c + 1; i < b; ++i) {
+        double acc = 0.0;
+        for (int32_t k = c; k < i; ++k) acc += D[(size_t)i * b + k] * X[(size_t)k * b + c];
+        X[(size_t)i * b + c] = -acc / D[(size_t)i * b + i];
+      }
+    }
+    const int64_t off = pl.dense_off[s];
+    for (int32_t j = 0; j < b; ++j) {
+      const int64_t oc = off + (int64_t)j * b - (int64_t)j * (j - 1) / 2;
+      for (int32_t i = j; i < b; ++i) pl.dinv_col[oc + (i - j)] = X[(size_t)i * b + j];
+    }
+    for (int32_t i = 0; i < b; ++i) {
+      const int64_t orow = off + (int64_t)i * (i + 1) / 2;
+      for (int32_t j = 0; j <= i; ++j) pl.dinv_row[orow + j] = X[(size_t)i * b + j];
+    }
+  }
+}
+
+void fill_offblock_values(PairHost &p) {
+  SolvePlan &pl = p.plan;
+  const Factor &L = p.L;
+  const int32_t n = L.n;
+  std::vector<int32_t> blk_of(n);
+  for (size_t s = 0; s < pl.blocks.size(); ++s)
+    for (int32_t r = pl.blocks[s].r0; r < pl.blocks[s].r1; ++r) blk_of[r] = (int32_t)s;
+  std::vector<int64_t> fnext(pl.fptr.begin(), pl.fptr.end() - 1);
+  for (int32_t k = 0; k < n; ++k)
+    for (int64_t q = L.colptr[k] + 1; q < L.colptr[k + 1]; ++q) {
+      const int32_t i = L.rowidx[q];
+      if (k < pl.blocks[blk_of[i]].r0) {
+        pl.fidx[fnext[i]] = k;
+        pl.fval[fnext[i]++] = L.val[q];
+      }
+    }
+  for (int32_t j = 0; j < n; ++j) {
+    int64_t w = pl.bptr[j];
+    const int32_t r1 = pl.blocks[blk_of[j]].r1;
+    for (int64_t q = L.colptr[j] + 1; q < L.colptr[j + 1]; ++q)
+      if (L.rowidx[q] >= r1) {
+        pl.bidx[w] = L.rowidx[q];
+        pl.bval[w++] = L.val[q];
+      }
+  }
+}
+
+std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, int32_t>> &ranges,
+                             const std::vector<int32_t> &range_parent, const OrderOptions &opt) {
+  SolvePlan &pl = p.plan;
+  const Factor &L = p.L;
+  const int32_t n = L.n;
+  const int32_t nb = (int32_t)ranges.size();
+  pl.blocks.assign(nb, SolveBlock{});
+  std::vector<int32_t> blk_of(n, -1);
+  for (int32_t s = 0; s < nb; ++s) {
+    SolveBlock &B = pl.blocks[s];
+    B.r0 = ranges[s].first;
+    B.r1 = ranges[s].second;
+    B.parent = range_parent[s];
+    if (B.r1 - B.r0 > opt.block_max) return "block larger than block_max";
+    if (B.parent >= 0 && B.parent <= s) return "block tree not in postorder";
+    for (int32_t r = B.r0; r < B.r1; ++r) blk_of[r] = s;
+  }
+  for (int32_t r = 0; r < n; ++r)
+    if (blk_of[r] < 0) return "row not covered by a block";
+  // descendants of block s are the contiguous ids [desc_lo[s], s] (postorder)
+  std::vector<int32_t> desc_lo(nb);
+  for (int32_t s = 0; s < nb; ++s) desc_lo[s] = s;
+  for (int32_t s = 0; s < nb; ++s)
+    if (pl.blocks[s].parent >= 0)
+      desc_lo[pl.blocks[s].parent] = std::min(desc_lo[pl.blocks[s].parent], desc_lo[s]);
+  // every factor entry must couple a block to itself or to an ancestor
+  for (int32_t k = 0; k < n; ++k)
+    for (int64_t q = L.colptr[k] + 1; q < L.colptr[k + 1]; ++q) {
+      const int32_t bi = blk_of[L.rowidx[q]], bk = blk_of[k];
+      if (bk < desc_lo[bi] || bk > bi) return "factor entry outside the block tree";
+    }
+  // levels
+  for (int32_t s = 0; s < nb; ++s) pl.blocks[s].fwd_level = 0;
+  for (int32_t s = 0; s < nb; ++s) {
+    const int32_t par = pl.blocks[s].parent;
+    if (par >= 0) pl.blocks[par].fwd_level = std::max(pl.blocks[par].fwd_level, pl.blocks[s].fwd_level + 1);
+  }
+  for (int32_t s = nb - 1; s >= 0; --s) {
+    const int32_t par = pl.blocks[s].parent;
+    pl.blocks[s].bwd_level = par >= 0 ? pl.blocks[par].bwd_level + 1 : 0;
+  }
+  pl.n_fwd_levels = pl.n_bwd_levels = 0;
+  for (auto &B : pl.blocks) {
+    pl.n_fwd_levels = std::max(pl.n_fwd_levels, B.fwd_level + 1);
+    pl.n_bwd_levels = std::max(pl.n_bwd_levels, B.bwd_level + 1);
+  }
+  // dense storage
+  pl.dense_off.assign(nb, 0);
+  int64_t tot = 0;
+  for (int32_t s = 0; s < nb; ++s) {
+    const int64_t b = pl.blocks[s].r1 - pl.blocks[s].r0;
+    pl.dense_off[s] = tot;
+    tot += b * (b + 1) / 2;
+  }
+  pl.dinv_col.assign(tot, 0.0);
+  pl.dinv_row.assign(tot, 0.0);
+  // off-block counts
+  pl.fptr.assign(n + 1, 0);
+  pl.bptr.assign(n + 1, 0);
+  for (int32_t k = 0; k < n; ++k)
+    for (int64_t q = L.colptr[k] + 1; q < L.colptr[k + 1]; ++q) {
+      const int32_t i = L.rowidx[q];
+      if (k < pl.blocks[blk_of[i]].r0) pl.fptr[i + 1]++;
+      if (i >= pl.blocks[blk_of[k]].r1) pl.bptr[k + 1]++;
+    }
+  for (int32_t r = 0; r < n; ++r) {
+    pl.fptr[r + 1] += pl.fptr[r];
+    pl.bptr[r + 1] += pl.bptr[r];
+  }
+  pl.fidx.assign(pl.fptr[n], 0);
+  pl.fval.assign(pl.fptr[n], 0.0);
+  pl.bidx.assign(pl.bptr[n], 0);
+  pl.bval.assign(pl.bptr[n], 0.0);
+  // lanes per row for the off-block dot products
+  for (auto &B : pl.blocks) {
+    const int32_t b = B.r1 - B.r0;
+    int64_t fl = 0, bl = 0;
+    for (int32_t r = B.r0; r < B.r1; ++r) {
+      fl += pl.fptr[r + 1] - pl.fptr[r];
+      bl += pl.bptr[r + 1] - pl.bptr[r];
+    }
+    const double fa = b ? (double)fl / b : 0.0, ba = b ? (double)bl / b : 0.0;
+    B.fwd_group = next_pow2_clamped(fa, 1, 64);
+    B.bwd_group = next_pow2_clamped(ba, 1, 64);
+  }
+  fill_dense_inverses(p);
+  fill_offblock_values(p);
+  return "";
+}
+
+std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd) {
+  *not_spd = false;
+  std::string e = validate_mesh(p);
+  if (!e.empty()) return e;
+  e = build_tables(p);
+  if (!e.empty()) return e;
+  build_operators(p);
+  std::vector<std::pair<int32_t, int32_t>> ranges;
+  std::vector<int32_t> rparent;
+  e = nested_dissection(p, opt, ranges, rparent);
+  if (!e.empty()) return e;
+  e = cholesky(p, tau, not_spd);
+  if (!e.empty()) return e;
+  return build_solve_plan(p, ranges, rparent, opt);
+}
+
+}  // namespace mr

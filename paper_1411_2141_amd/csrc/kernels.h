@@ -1,0 +1,36 @@
+// Launch wrappers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mr {
+
+hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp, float *out,
+                            int H, int W, const double *cp_w, const double *cp_h, hipStream_t s);
+hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
+                             const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
+                         const double2 *u, const int2 *xy, const float *coef, const float *rho,
+                         float2 *h, unsigned *flags, hipStream_t s);
+hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
+                           const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
+                           double tau, hipStream_t s);
+hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
+                                  const int64_t *fptr, const int32_t *fidx, const double *fval,
+                                  const double *dcol, double2 *x, hipStream_t s);
+hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
+                                  const int64_t *bptr, const int32_t *bidx, const double *bval,
+                                  const double *drow, double2 *x, const int32_t *perm,
+                                  double2 *out, hipStream_t s);
+hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
+                           const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
+                           const float *coef, const float *re, float *warped, double *partials,
+                           unsigned *counter, double *msd, unsigned *flags, hipStream_t s);
+hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
+                                 hipStream_t s);
+hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,
+                                   hipStream_t s);
+
+}  // namespace mr

@@ -1,0 +1,550 @@
+// HIP kernels of the registration hot path for gfx950 (CDNA4, wave64).
+//
+// Per iteration (Algorithm 1, semi-implicit form):
+//   k_sample    node-parallel: template B-spline value and gradient at the
+//               displaced node (eq. 3), residual against the reference sample
+//               (eq. 4), force density h = r g (eq. 6)
+//   k_assemble  node-parallel gather over the mass-matrix row: the
+//               area-weighted triangle-to-node average of eq. 10 applied to the
+//               P1 load, then b = u - tau f (eq. 5), written in solve order
+//   k_solve_fwd / k_solve_bwd
+//               block-level-scheduled FP64 triangular solves with the Cholesky
+//               factor of I + tau alpha K (eq. 7-8 made implicit, solved directly)
+//   k_warp_msd  pixel-tile-parallel: piecewise-linear displacement of each
+//               pixel's triangle, template sample at the displaced pixel centre,
+//               squared error, deterministic FP64 reduction to the MSD
+// All node-, tile- and block-parallel launches cover every pair of a batch
+// through work lists, so one launch per kernel family advances all pairs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace mr {
+
+// ---------------------------------------------------------------------------
+// Cubic B-spline pieces.  For a point at integer cell `c` plus fraction t in
+// [0, 1), the taps are c-1 .. c+2 and their weights are beta(t+1), beta(t),
+// beta(t-1), beta(t-2) of the centred cubic B-spline, with the derivatives
+// below.  Index folding is half-sample symmetric with period 2N.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int fold_index(int n, int N) {
+  if ((unsigned)n < (unsigned)N) return n;
+  const int P = 2 * N;
+  int m = n % P;
+  if (m < 0) m += P;
+  return m >= N ? P - 1 - m : m;
+}
+
+__device__ __forceinline__ void bs_weights(float t, float w[4]) {
+  const float s = 1.0f - t, t2 = t * t, t3 = t2 * t;
+  w[0] = s * s * s * (1.0f / 6.0f);
+  w[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+  w[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+  w[3] = t3 * (1.0f / 6.0f);
+}
+
+// FP64 weights for the pixel warp: the MSD is a mean of squared differences
+// of nearly equal numbers, so a systematic FP32 weight rounding (at t = 0 the
+// FP32 weights sum to 1 + 3e-8 per axis) would bias it by ~1e-6 relative.
+__device__ __forceinline__ void bs_weights_d(double t, double w[4]) {
+  const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
+  w[0] = s * s * s * (1.0 / 6.0);
+  w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) * (1.0 / 6.0);
+  w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) * (1.0 / 6.0);
+  w[3] = t3 * (1.0 / 6.0);
+}
+
+__device__ __forceinline__ void bs_deriv(float t, float d[4]) {
+  const float s = 1.0f - t, t2 = t * t;
+  d[0] = -0.5f * s * s;
+  d[1] = 1.5f * t2 - 2.0f * t;
+  d[2] = -1.5f * t2 + t + 0.5f;
+  d[3] = 0.5f * t2;
+}
+
+__device__ __forceinline__ void bs_deriv2(float t, float e[4]) {
+  e[0] = 1.0f - t;
+  e[1] = 3.0f * t - 2.0f;
+  e[2] = 1.0f - 3.0f * t;
+  e[3] = t;
+}
+
+// Integer cell and fraction of base + off.  Non-finite or absurd offsets are
+// replaced by 0 (so no tap leaves the image) and reported through the result.
+__device__ __forceinline__ bool split_coord(int base, double off, int &cell, float &frac) {
+  const bool ok = (off == off) && fabs(off) < 1.0e6;
+  if (!ok) off = 0.0;
+  const double fl = floor(off);
+  cell = base + (int)fl;
+  frac = (float)(off - fl);
+  return ok;
+}
+
+// Same split, keeping the fraction in FP64.
+__device__ __forceinline__ bool split_coord_d(int base, double off, int &cell, double &frac) {
+  const bool ok = (off == off) && fabs(off) < 1.0e6;
+  if (!ok) off = 0.0;
+  const double fl = floor(off);
+  cell = base + (int)fl;
+  frac = off - fl;
+  return ok;
+}
+
+struct Taps {
+  int col[4];
+  const float *row[4];
+};
+
+__device__ __forceinline__ void make_taps(const float *__restrict__ c, int H, int W, int cx,
+                                          int cy, Taps &tp) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    tp.col[k] = fold_index(cx - 1 + k, W);
+    tp.row[k] = c + (size_t)fold_index(cy - 1 + k, H) * W;
+  }
+}
+
+__device__ __forceinline__ float spline_value(const float *__restrict__ c, int H, int W, int cx,
+                                              float fx, int cy, float fy) {
+  float wx[4], wy[4];
+  bs_weights(fx, wx);
+  bs_weights(fy, wy);
+  Taps tp;
+  make_taps(c, H, W, cx, cy, tp);
+  float v = 0.0f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float *r = tp.row[m];
+    const float rv = r[tp.col[0]] * wx[0] + r[tp.col[1]] * wx[1] + r[tp.col[2]] * wx[2] +
+                     r[tp.col[3]] * wx[3];
+    v += wy[m] * rv;
+  }
+  return v;
+}
+
+// Value with FP32 coefficients, FP64 weights and FP64 accumulation.
+__device__ __forceinline__ double spline_value_d(const float *__restrict__ c, int H, int W,
+                                                 int cx, double fx, int cy, double fy) {
+  double wx[4], wy[4];
+  bs_weights_d(fx, wx);
+  bs_weights_d(fy, wy);
+  Taps tp;
+  make_taps(c, H, W, cx, cy, tp);
+  double v = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float *r = tp.row[m];
+    const double rv = (double)r[tp.col[0]] * wx[0] + (double)r[tp.col[1]] * wx[1] +
+                      (double)r[tp.col[2]] * wx[2] + (double)r[tp.col[3]] * wx[3];
+    v += wy[m] * rv;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void spline_value_grad(const float *__restrict__ c, int H, int W,
+                                                  int cx, float fx, int cy, float fy, float &val,
+                                                  float &gx, float &gy) {
+  float wx[4], dx[4], wy[4], dy[4];
+  bs_weights(fx, wx);
+  bs_deriv(fx, dx);
+  bs_weights(fy, wy);
+  bs_deriv(fy, dy);
+  Taps tp;
+  make_taps(c, H, W, cx, cy, tp);
+  val = gx = gy = 0.0f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float *r = tp.row[m];
+    const float c0 = r[tp.col[0]], c1 = r[tp.col[1]], c2 = r[tp.col[2]], c3 = r[tp.col[3]];
+    const float rv = c0 * wx[0] + c1 * wx[1] + c2 * wx[2] + c3 * wx[3];
+    const float rd = c0 * dx[0] + c1 * dx[1] + c2 * dx[2] + c3 * dx[3];
+    val += wy[m] * rv;
+    gx += wy[m] * rd;
+    gy += dy[m] * rv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-computation kernels (run once per pair, and for the template adjoint)
+// ---------------------------------------------------------------------------
+
+// Solve B c = s along each row (thread per row) with the Thomas algorithm;
+// `cp` holds the eliminated super-diagonal, which depends only on the length.
+template <typename Tin>
+__global__ void k_prefilter_rows(const Tin *__restrict__ src, double *__restrict__ dst, int H,
+                                 int W, const double *__restrict__ cp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= H) return;
+  const Tin *s = src + (size_t)r * W;
+  double *d = dst + (size_t)r * W;
+  if (W == 1) {
+    d[0] = (double)s[0];
+    return;
+  }
+  const double off = 1.0 / 6.0;
+  double prev = (double)s[0] / (5.0 / 6.0);
+  d[0] = prev;
+  for (int k = 1; k < W; ++k) {
+    const double diag = (k == W - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
+    const double den = diag - off * cp[k - 1];
+    prev = ((double)s[k] - off * prev) / den;
+    d[k] = prev;
+  }
+  for (int k = W - 2; k >= 0; --k) {
+    prev = d[k] - cp[k] * prev;
+    d[k] = prev;
+  }
+}
+
+// Column pass (thread per column, coalesced across threads), in place on
+// `tmp`, writing the FP32 coefficients.
+__global__ void k_prefilter_cols(double *__restrict__ tmp, float *__restrict__ out, int H, int W,
+                                 const double *__restrict__ cp) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= W) return;
+  double *d = tmp + col;
+  if (H == 1) {
+    out[col] = (float)d[0];
+    return;
+  }
+  const double off = 1.0 / 6.0;
+  double prev = d[0] / (5.0 / 6.0);
+  d[0] = prev;
+  for (int k = 1; k < H; ++k) {
+    const double diag = (k == H - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
+    const double den = diag - off * cp[k - 1];
+    prev = (d[(size_t)k * W] - off * prev) / den;
+    d[(size_t)k * W] = prev;
+  }
+  out[(size_t)(H - 1) * W + col] = (float)prev;
+  for (int k = H - 2; k >= 0; --k) {
+    prev = d[(size_t)k * W] - cp[k] * prev;
+    out[(size_t)k * W + col] = (float)prev;
+  }
+}
+
+// Reference spline at the undisplaced nodes: rho_i = s_Re(V_i - 1/2).
+__global__ __launch_bounds__(256) void k_sample_rho(const NodeItem *__restrict__ items,
+                                                    const DevPair *__restrict__ pairs,
+                                                    const int2 *__restrict__ xy,
+                                                    const float *__restrict__ coef_re,
+                                                    float *__restrict__ rho) {
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + threadIdx.x;
+  if (i >= it.end) return;
+  const DevPair P = pairs[it.pair];
+  const int2 v = xy[i];
+  rho[i] = spline_value(coef_re + P.pix_off, P.height, P.width, v.x - 1, 0.5f, v.y - 1, 0.5f);
+}
+
+// ---------------------------------------------------------------------------
+// Hot path
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items,
+                                                const DevPair *__restrict__ pairs,
+                                                const double2 *__restrict__ u,
+                                                const int2 *__restrict__ xy,
+                                                const float *__restrict__ coef,
+                                                const float *__restrict__ rho,
+                                                float2 *__restrict__ h, unsigned *flags) {
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + threadIdx.x;
+  if (i >= it.end) return;
+  const DevPair P = pairs[it.pair];
+  const double2 ui = u[i];
+  const int2 v = xy[i];
+  int cx, cy;
+  float fx, fy;
+  const bool ok = split_coord(v.x, ui.x - 0.5, cx, fx) & split_coord(v.y, ui.y - 0.5, cy, fy);
+  if (!ok) atomicOr(flags, kFlagNonFiniteNode);
+  float val, gx, gy;
+  spline_value_grad(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy, val, gx, gy);
+  const float r = val - rho[i];
+  h[i] = make_float2(r * gx, r * gy);
+}
+
+__global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
+                                                  const int32_t *__restrict__ mcol,
+                                                  const float *__restrict__ mwt,
+                                                  const float2 *__restrict__ h,
+                                                  const double2 *__restrict__ u,
+                                                  const int32_t *__restrict__ iperm,
+                                                  double2 *__restrict__ x, double tau) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float fx = 0.0f, fy = 0.0f;
+  const int q1 = mptr[i + 1];
+  for (int q = mptr[i]; q < q1; ++q) {
+    const float w = mwt[q];
+    const float2 hj = h[mcol[q]];
+    fx += w * hj.x;
+    fy += w * hj.y;
+  }
+  const double2 ui = u[i];
+  x[iperm[i]] = make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
+}
+
+// Forward solve of one block level: for each block, t = b - L_off y (sparse,
+// rows of the block against already-solved rows), then y = D^-1 t with the
+// block's dense inverse (column-major packed lower triangle).  In place on x.
+__global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
+    const DevBlock *__restrict__ blocks, const int32_t *__restrict__ level_list,
+    const int64_t *__restrict__ fptr, const int32_t *__restrict__ fidx,
+    const double *__restrict__ fval, const double *__restrict__ dcol, double2 *x) {
+  __shared__ double2 t[kBlockMax];
+  const DevBlock B = blocks[level_list[blockIdx.x]];
+  const int b = B.r1 - B.r0;
+  const int tid = threadIdx.x;
+  const int G = B.fgroup;
+  const int sub = tid & (G - 1);
+  const int ngroups = kSolveThreads / G;
+  for (int r = tid / G; r < b; r += ngroups) {
+    const int row = B.r0 + r;
+    double ax = 0.0, ay = 0.0;
+    const int64_t q1 = fptr[row + 1];
+    for (int64_t q = fptr[row] + sub; q < q1; q += G) {
+      const double v = fval[q];
+      const double2 yk = x[fidx[q]];
+      ax += v * yk.x;
+      ay += v * yk.y;
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) {
+      ax += __shfl_xor(ax, off);
+      ay += __shfl_xor(ay, off);
+    }
+    if (sub == 0) {
+      const double2 bb = x[row];
+      t[r] = make_double2(bb.x - ax, bb.y - ay);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += kSolveThreads) {
+    double ax = 0.0, ay = 0.0;
+    const double *d = dcol + B.doff + i;
+    for (int j = 0; j <= i; ++j) {
+      // element (i, j) of the packed column-major lower triangle
+      const double v = d[(int64_t)j * b - (int64_t)j * (j - 1) / 2 - j];
+      ax += v * t[j].x;
+      ay += v * t[j].y;
+    }
+    x[B.r0 + i] = make_double2(ax, ay);
+  }
+}
+
+// Backward solve of one block level: t = y - L_off^T z (columns of the block
+// against already-solved later rows), then z = D^-T t with the row-major packed
+// inverse.  In place on x; the last level pass also scatters z to `out` in the
+// natural node order when `out` is not null.
+__global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
+    const DevBlock *__restrict__ blocks, const int32_t *__restrict__ level_list,
+    const int64_t *__restrict__ bptr, const int32_t *__restrict__ bidx,
+    const double *__restrict__ bval, const double *__restrict__ drow, double2 *x,
+    const int32_t *__restrict__ perm, double2 *__restrict__ out) {
+  __shared__ double2 t[kBlockMax];
+  const DevBlock B = blocks[level_list[blockIdx.x]];
+  const int b = B.r1 - B.r0;
+  const int tid = threadIdx.x;
+  const int G = B.bgroup;
+  const int sub = tid & (G - 1);
+  const int ngroups = kSolveThreads / G;
+  for (int r = tid / G; r < b; r += ngroups) {
+    const int col = B.r0 + r;
+    double ax = 0.0, ay = 0.0;
+    const int64_t q1 = bptr[col + 1];
+    for (int64_t q = bptr[col] + sub; q < q1; q += G) {
+      const double v = bval[q];
+      const double2 zk = x[bidx[q]];
+      ax += v * zk.x;
+      ay += v * zk.y;
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) {
+      ax += __shfl_xor(ax, off);
+      ay += __shfl_xor(ay, off);
+    }
+    if (sub == 0) {
+      const double2 yy = x[col];
+      t[r] = make_double2(yy.x - ax, yy.y - ay);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < b; j += kSolveThreads) {
+    double ax = 0.0, ay = 0.0;
+    const double *d = drow + B.doff + j;
+    for (int i = j; i < b; ++i) {
+      // element (i, j) of the packed row-major lower triangle
+      const double v = d[(int64_t)i * (i + 1) / 2];
+      ax += v * t[i].x;
+      ay += v * t[i].y;
+    }
+    const double2 z = make_double2(ax, ay);
+    x[B.r0 + j] = z;
+    if (out) out[perm[B.r0 + j]] = z;
+  }
+}
+
+// Warp + MSD over kTile x kTile pixel tiles.  Each workgroup writes its FP64
+// partial sum; the last workgroup to finish sums every pair's partials in a
+// fixed order (deterministic) and resets the counter for the next launch.
+__global__ __launch_bounds__(256) void k_warp_msd(
+    const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, int n_pairs,
+    const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
+    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
+    float *__restrict__ warped, double *partials, unsigned *counter, double *__restrict__ msd,
+    unsigned *flags) {
+  const TileItem it = tiles[blockIdx.x];
+  const DevPair P = pairs[it.pair];
+  const int i = it.y0 + (int)(threadIdx.x / kTile);
+  const int j = it.x0 + (int)(threadIdx.x % kTile);
+  double acc = 0.0;
+  if (i < P.height && j < P.width) {
+    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
+    const int4 nd = tri[P.tri_off + t6[pix]];
+    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
+    // barycentric weights in doubled coordinates (exact integer cross products)
+    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
+    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+    const double inv = 1.0 / (ca + cb + cc);
+    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
+    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
+    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
+    int qx, qy;
+    double fx, fy;
+    const bool ok = split_coord_d(j, dx, qx, fx) & split_coord_d(i, dy, qy, fy);
+    if (!ok) atomicOr(flags, kFlagNonFinitePixel);
+    const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
+    if (warped) warped[pix] = (float)w;
+    const double e = w - (double)re[pix];
+    acc = e * e;
+  }
+  __shared__ double red[4];
+  __shared__ int last;
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int p = wave; p < n_pairs; p += 4) {
+    const DevPair Q = pairs[p];
+    double s = 0.0;
+    for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
+    s = wave_sum(s);
+    if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
+  }
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+}
+
+// Gather / scatter between the natural node order and the solve order.
+__global__ void k_to_solve_order(int n, const double2 *__restrict__ src,
+                                 const int32_t *__restrict__ iperm, double2 *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[iperm[i]] = src[i];
+}
+
+__global__ void k_from_solve_order(int n, const double2 *__restrict__ x,
+                                   const int32_t *__restrict__ iperm, double2 *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = x[iperm[i]];
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp, float *out,
+                            int H, int W, const double *cp_w, const double *cp_h,
+                            hipStream_t s) {
+  const int tb = 64;
+  if (src_f)
+    k_prefilter_rows<float><<<(H + tb - 1) / tb, tb, 0, s>>>(src_f, tmp, H, W, cp_w);
+  else
+    k_prefilter_rows<double><<<(H + tb - 1) / tb, tb, 0, s>>>(src_d, tmp, H, W, cp_w);
+  k_prefilter_cols<<<(W + tb - 1) / tb, tb, 0, s>>>(tmp, out, H, W, cp_h);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
+                             const int2 *xy, const float *coef_re, float *rho, hipStream_t s) {
+  k_sample_rho<<<n_items, kNodeChunk, 0, s>>>(items, pairs, xy, coef_re, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
+                         const double2 *u, const int2 *xy, const float *coef, const float *rho,
+                         float2 *h, unsigned *flags, hipStream_t s) {
+  k_sample<<<n_items, kNodeChunk, 0, s>>>(items, pairs, u, xy, coef, rho, h, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
+                           const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
+                           double tau, hipStream_t s) {
+  k_assemble<<<(n + 255) / 256, 256, 0, s>>>(n, mptr, mcol, mwt, h, u, iperm, x, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
+                                  const int64_t *fptr, const int32_t *fidx, const double *fval,
+                                  const double *dcol, double2 *x, hipStream_t s) {
+  k_solve_fwd<<<count, kSolveThreads, 0, s>>>(blocks, level_list, fptr, fidx, fval, dcol, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
+                                  const int64_t *bptr, const int32_t *bidx, const double *bval,
+                                  const double *drow, double2 *x, const int32_t *perm,
+                                  double2 *out, hipStream_t s) {
+  k_solve_bwd<<<count, kSolveThreads, 0, s>>>(blocks, level_list, bptr, bidx, bval, drow, x, perm,
+                                             out);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
+                           const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
+                           const float *coef, const float *re, float *warped, double *partials,
+                           unsigned *counter, double *msd, unsigned *flags, hipStream_t s) {
+  k_warp_msd<<<n_tiles, kTile * kTile, 0, s>>>(tiles, pairs, n_pairs, u, xy, tri, t6, coef, re,
+                                               warped, partials, counter, msd, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
+                                 hipStream_t s) {
+  k_to_solve_order<<<(n + 255) / 256, 256, 0, s>>>(n, src, iperm, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,
+                                   hipStream_t s) {
+  k_from_solve_order<<<(n + 255) / 256, 256, 0, s>>>(n, x, iperm, dst);
+  return hipGetLastError();
+}
+
+}  // namespace mr

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical seeded
+inputs, through the C ABI.
+
+Tolerances (from the arithmetic): node and pixel sampling use FP32 B-spline
+coefficients and FP32 tap sums, so a sample carries an absolute error of a
+few 1e-7; the force density h and the right-hand side inherit it (normwise
+relative <= 2e-5 allows a 10x margin over the measured ~2e-6).  The
+triangular solves are FP64 (relative 1e-12).  Displacements after N
+iterations: normwise relative 1e-5 per pair; MSD of ``warp_msd`` at an
+identical u: relative 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import registration as reg
+from synth import make_pair, uniform_mesh
+from tests._problems import small_pair, translation_pair
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-5
+MSD_TOL = 1e-6
+H_TOL = 2e-5
+SOLVE_TOL = 1e-12
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1411_2141_amd  # noqa: F401  (loads the library)
+
+
+def lib():
+    import paper_1411_2141_amd as pkg
+    return pkg
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def gpu_ctx(pairs, tau, force_mode=0):
+    return lib().MeshReg(pairs, tau=tau, force_mode=force_mode)
+
+
+def as_dict(p):
+    return dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=p.alpha)
+
+
+def oracle_problem(d, tau, force_mode=0):
+    return reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau, force_mode=force_mode)
+
+
+def to_dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+CASES = {
+    "c1_128": lambda: as_dict(make_pair(1)),
+    "adaptive_48": lambda: dict(zip(("te", "re", "V", "T"), small_pair(seed=1, side=48, s_min=1, s_max=16)[:4]), alpha=0.2),
+    "ragged_40x24": lambda: (lambda V, T: dict(
+        te=small_pair(seed=2, side=48)[0][:24, :40].copy(), re=small_pair(seed=2, side=48)[1][:24, :40].copy(),
+        V=V, T=T, alpha=0.1))(*uniform_mesh(24, 40, 4)[:2]),
+    "one_leaf_4": lambda: (lambda V, T: dict(
+        te=np.arange(16, dtype=np.float32).reshape(4, 4) / 16, re=np.ones((4, 4), np.float32) * 0.3,
+        V=V, T=T, alpha=0.5))(*uniform_mesh(4, 4, 4)[:2]),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("force_mode", [0, 1])
+def test_force_parity(case, force_mode):
+    say(f"force parity {case} mode={force_mode}")
+    d = CASES[case]()
+    tau = 0.5
+    pb = oracle_problem(d, tau, force_mode)
+    ctx = gpu_ctx([d], tau, force_mode)
+    rng = np.random.default_rng(3)
+    for scale in (0.0, 0.7, 25.0):
+        u = rng.normal(scale=scale, size=(d["V"].shape[0], 2))
+        h, b = ctx.force(to_dev(u))
+        torch.cuda.synchronize()
+        h_or, f_or = reg.force(pb, u)
+        b_or = u - tau * f_or
+        # absolute floor: FP32 samples carry ~1e-7 absolute error per node, which
+        # dominates where h vanishes (e.g. boundary nodes, whose mirrored normal
+        # derivative is exactly 0)
+        floor = 1e-6 * np.sqrt(h_or.size)
+        hg = h.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(hg - h_or) <= H_TOL * np.linalg.norm(h_or) + floor, scale
+        f_gpu = (u - b.cpu().numpy()) / tau
+        assert np.linalg.norm(f_gpu - f_or) <= H_TOL * np.linalg.norm(f_or) + floor, scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_solve_parity(case):
+    say(f"solve parity {case}")
+    d = CASES[case]()
+    tau = 0.5
+    pb = oracle_problem(d, tau)
+    ctx = gpu_ctx([d], tau)
+    b = np.random.default_rng(4).normal(size=(d["V"].shape[0], 2))
+    x = ctx.solve(to_dev(b))
+    torch.cuda.synchronize()
+    x_or = reg.solve(pb, b)
+    assert rel(x.cpu().numpy(), x_or) < SOLVE_TOL
+    # in place (b and x alias)
+    bd = to_dev(b)
+    lib().binding.mesh_reg_solve(ctx.ctx, bd, bd, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rel(bd.cpu().numpy(), x_or) < SOLVE_TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_warp_msd_parity(case):
+    say(f"warp/msd parity {case}")
+    d = CASES[case]()
+    pb = oracle_problem(d, 0.5)
+    ctx = gpu_ctx([d], 0.5)
+    rng = np.random.default_rng(5)
+    for scale in (0.0, 0.8, 40.0):
+        u = rng.normal(scale=scale, size=(d["V"].shape[0], 2))
+        msd, warped = ctx.warp_msd(to_dev(u), return_warped=True)
+        torch.cuda.synchronize()
+        W_or = reg.warp(pb, u)
+        m_or = reg.msd(pb, u)
+        assert abs(msd.item() - m_or) <= MSD_TOL * m_or + 1e-14, (scale, msd.item(), m_or)
+        H, W = d["te"].shape
+        assert np.abs(warped.cpu().numpy().reshape(H, W) - W_or).max() < 2e-6 * max(1.0, np.abs(W_or).max())
+    ctx.close()
+
+
+def _run_parity(d, tau, n_iter, force_mode=0, check_trace_every=0):
+    pb = oracle_problem(d, tau, force_mode)
+    ctx = gpu_ctx([d], tau, force_mode)
+    u = ctx.zeros_u()
+    trace = ctx.step(u, n_iter, record_msd=check_trace_every > 0)
+    torch.cuda.synchronize()
+    u_or = np.zeros((d["V"].shape[0], 2))
+    msd_or = []
+    for k in range(n_iter):
+        u_or = reg.step(pb, u_or)
+        if check_trace_every and (k % check_trace_every == 0 or k == n_iter - 1):
+            msd_or.append((k, reg.msd(pb, u_or)))
+    ug = u.cpu().numpy()
+    err = rel(ug, u_or)
+    # MSD at the identical (oracle) displacement
+    m_gpu = ctx.warp_msd(to_dev(u_or)).item()
+    m_or = reg.msd(pb, u_or)
+    ctx_trace = trace.cpu().numpy()[:, 0] if trace is not None else None
+    ctx.close()
+    return err, m_gpu, m_or, ctx_trace, msd_or
+
+
+def test_run_parity_c1_50_iterations():
+    say("run parity c1 (128^2, 50 iterations)")
+    p = make_pair(1)
+    err, m_gpu, m_or, trace, msd_or = _run_parity(as_dict(p), 0.5, 50, check_trace_every=10)
+    assert err < U_TOL, err
+    assert abs(m_gpu - m_or) <= MSD_TOL * m_or
+    for k, m in msd_or:   # end-to-end MSD gap: reported through the displacement bound
+        assert abs(trace[k] - m) <= 1e-4 * m
+
+
+def test_run_parity_c1_nodal_force():
+    say("run parity c1 nodal force (20 iterations)")
+    p = make_pair(1)
+    err, m_gpu, m_or, _, _ = _run_parity(as_dict(p), 0.5, 20, force_mode=1)
+    assert err < U_TOL, err
+    assert abs(m_gpu - m_or) <= MSD_TOL * m_or
+
+
+def test_run_parity_c2_200_iterations():
+    say("run parity c2 (512^2 12-bit, 200 iterations, MSD every iteration)")
+    p = make_pair(2)
+    err, m_gpu, m_or, trace, msd_or = _run_parity(as_dict(p), 0.5, 200, check_trace_every=50)
+    assert err < U_TOL, err
+    assert abs(m_gpu - m_or) <= MSD_TOL * m_or
+    assert np.all(np.isfinite(trace)) and trace.shape == (200,)
+    for k, m in msd_or:
+        assert abs(trace[k] - m) <= 1e-4 * m
+
+
+def test_translation_recovered_on_gpu():
+    say("translation recovery (128^2, tau=20, alpha=1, 200 iterations)")
+    te, re_, V, T, _ = translation_pair(side=128, shift=(1.0, -2.0))
+    ctx = gpu_ctx([dict(te=te, re=re_, V=V, T=T, alpha=1.0)], 20.0)
+    u = ctx.zeros_u()
+    m0 = ctx.warp_msd(u).item()
+    ctx.step(u, 200)
+    m1 = ctx.warp_msd(u).item()
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - np.array([1.0, -2.0])).max() < 0.01
+    assert m1 < 1e-4 * m0
+    ctx.close()
+
+
+def test_batched_pairs_match_single_pair_oracle():
+    say("batched: 3 ragged pairs in one context, 8 iterations")
+    ds = [as_dict(make_pair(1)), CASES["adaptive_48"](), CASES["ragged_40x24"]()]
+    tau = 0.5
+    ctx = gpu_ctx(ds, tau)
+    u = ctx.zeros_u()
+    trace = ctx.step(u, 8, record_msd=True)
+    torch.cuda.synchronize()
+    ug = u.cpu().numpy()
+    for k, d in enumerate(ds):
+        pb = oracle_problem(d, tau)
+        u_or, msds, _ = reg.run(pb, None, 8, record_msd=True)
+        assert rel(ug[ctx.node_offsets[k]:ctx.node_offsets[k + 1]], u_or) < U_TOL, k
+        assert abs(trace[-1, k].item() - msds[-1]) <= 1e-4 * msds[-1]
+    ctx.close()
+
+
+def test_set_alpha_refactors():
+    say("set_alpha re-factorisation")
+    d = CASES["adaptive_48"]()
+    ctx = gpu_ctx([d], 0.5)
+    ctx.set_alpha(0, 2.5)
+    d2 = dict(d, alpha=2.5)
+    pb = oracle_problem(d2, 0.5)
+    b = np.random.default_rng(6).normal(size=(d["V"].shape[0], 2))
+    x = ctx.solve(to_dev(b))
+    torch.cuda.synchronize()
+    assert rel(x.cpu().numpy(), reg.solve(pb, b)) < SOLVE_TOL
+    ctx.close()
+
+
+def test_non_finite_displacement_is_reported():
+    say("non-finite displacement flag")
+    d = CASES["one_leaf_4"]()
+    ctx = gpu_ctx([d], 0.5)
+    u = ctx.zeros_u()
+    u[0, 0] = float("nan")
+    ctx.step(u, 1)              # the kernels clamp and flag; no fault
+    torch.cuda.synchronize()
+    with pytest.raises(lib().MeshRegError) as ei:
+        ctx.step(ctx.zeros_u(), 1)
+    assert ei.value.code == lib().binding.MR_ENONFINITE
+    v = ctx.zeros_u()
+    ctx.step(v, 2)              # the flag was cleared
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_zero_iterations_is_a_no_op():
+    say("n_iter = 0")
+    d = CASES["adaptive_48"]()
+    ctx = gpu_ctx([d], 0.5)
+    u = to_dev(np.random.default_rng(7).normal(size=(d["V"].shape[0], 2)))
+    u0 = u.clone()
+    ctx.step(u, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u0)
+    ctx.close()

@@ -1,0 +1,141 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+declared symbol, tables T1-T6 equal the oracle's bit for bit, the ordering is
+a permutation, and invalid inputs are rejected with the documented codes.
+No GPU work is launched (contexts are built host-only)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh
+from synth import make_pair, uniform_mesh
+from tests._problems import small_pair
+
+import paper_1411_2141_amd as pkg
+from paper_1411_2141_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "meshreg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mesh_reg_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTED) == names
+
+
+def host_ctx(pairs, tau=0.5, force_mode=0):
+    return pkg.MeshReg(pairs, tau=tau, force_mode=force_mode, host_only=True)
+
+
+def _pairs_for_tables():
+    out = []
+    te, re_, V, T, _ = small_pair(seed=1, side=48, s_min=1, s_max=16)
+    out.append(dict(te=te, re=re_, V=V, T=T, alpha=0.1))
+    p = make_pair(1)
+    out.append(dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=p.alpha))
+    V, T, _ = uniform_mesh(24, 40, 4)     # ragged, non-square
+    out.append(dict(te=np.zeros((24, 40), np.float32), re=np.zeros((24, 40), np.float32),
+                    V=V, T=T, alpha=0.3))
+    return out
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_tables_bit_exact_with_oracle(k):
+    pair = _pairs_for_tables()[k]
+    H, W = pair["te"].shape
+    ctx = host_ctx([pair])
+    want = omesh.tables(pair["V"], pair["T"], H, W)
+    for name in ("t1_ptr", "t1_slot", "t2_ptr", "t2_idx", "t3_ptr", "t3_idx", "t4", "t5"):
+        got = ctx.table(0, name)
+        assert got.dtype == np.int64
+        assert np.array_equal(got, want[name]), name
+    assert np.array_equal(ctx.table(0, "t6").reshape(H, W), want["t6"])
+    perm = ctx.table(0, "perm")
+    assert np.array_equal(np.sort(perm), np.arange(pair["V"].shape[0]))
+    assert ctx.info(0, "nnz_l") >= pair["V"].shape[0]
+    assert ctx.info(0, "fwd_levels") >= 1 and ctx.info(0, "bwd_levels") >= 1
+    ctx.close()
+
+
+def test_batched_tables_per_pair():
+    pairs = _pairs_for_tables()
+    ctx = host_ctx(pairs)
+    assert ctx.info(0, "n_pairs") == 3
+    for k, pair in enumerate(pairs):
+        H, W = pair["te"].shape
+        want = omesh.tables(pair["V"], pair["T"], H, W)
+        assert np.array_equal(ctx.table(k, "t1_slot"), want["t1_slot"])
+        assert np.array_equal(ctx.table(k, "t6").reshape(H, W), want["t6"])
+        assert ctx.info(k, "node_offset") == sum(p["V"].shape[0] for p in pairs[:k])
+    ctx.close()
+
+
+def _one_leaf():
+    V, T, _ = uniform_mesh(4, 4, 4)
+    z = np.zeros((4, 4), np.float32)
+    return dict(te=z, re=z, V=V, T=T, alpha=0.1)
+
+
+def _expect(code, pair=None, **kw):
+    pair = pair or _one_leaf()
+    with pytest.raises(B.MeshRegError) as ei:
+        host_ctx([pair], **kw)
+    assert ei.value.code == code
+    return str(ei.value)
+
+
+def test_invalid_inputs_are_rejected():
+    p = _one_leaf()
+    host_ctx([p]).close()
+    bad = dict(p, T=p["T"].copy())
+    bad["T"][0, 0] = 99
+    assert "out of range" in _expect(B.MR_EINVAL, bad)
+    bad = dict(p, T=p["T"][:, [0, 2, 1]].copy())
+    assert "area" in _expect(B.MR_EINVAL, bad)
+    bad = dict(p, V=np.vstack([p["V"], [[1, 1]]]))
+    assert "not used" in _expect(B.MR_EINVAL, bad)
+    bad = dict(p, T=p["T"][:1].copy())                   # half the square uncovered
+    bad["V"] = p["V"]
+    msg = _expect(B.MR_EINVAL, bad)
+    assert "not used" in msg or "not covered" in msg
+    bad = dict(p, V=p["V"] * 2)                         # outside the image
+    assert "outside" in _expect(B.MR_EINVAL, bad)
+    _expect(B.MR_EINVAL, tau=0.0)
+    _expect(B.MR_EINVAL, tau=float("nan"))
+    _expect(B.MR_EINVAL, dict(p, alpha=-1.0))
+    _expect(B.MR_EINVAL, dict(p, alpha=float("inf")))
+
+
+def test_uncovered_pixel_is_rejected():
+    # two triangles of a 4x4 leaf inside an 8x4 image: the right half is uncovered
+    V, T, _ = uniform_mesh(4, 4, 4)
+    z = np.zeros((4, 8), np.float32)
+    assert "not covered" in _expect(B.MR_EINVAL, dict(te=z, re=z, V=V, T=T, alpha=0.1))
+
+
+def test_host_only_context_refuses_device_calls():
+    ctx = host_ctx([_one_leaf()])
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_step(ctx.ctx, None, 1)
+    assert ei.value.code in (B.MR_ESTATE, B.MR_EINVAL)
+    ctx.close()
+
+
+def test_set_alpha_host_only_and_rejects_negative():
+    te, re_, V, T, _ = small_pair(seed=2, side=32)
+    ctx = host_ctx([dict(te=te, re=re_, V=V, T=T, alpha=0.1)])
+    ctx.set_alpha(0, 0.7)
+    with pytest.raises(B.MeshRegError) as ei:
+        ctx.set_alpha(0, -0.5)
+    assert ei.value.code == B.MR_EINVAL
+    ctx.close()
