@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -76,8 +77,8 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
     const int cnt = fwd_ptr[lev + 1] - fwd_ptr[lev];
     if (!cnt) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = launch_solve_fwd_level(d_blocks.ptr, d_fwd_list.ptr + fwd_ptr[lev], cnt, d_fptr.ptr,
-                               d_fidx.ptr, d_fval.ptr, d_dcol.ptr, x, s);
+    e = launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt, fwd_lds[lev],
+                               d_cptr.ptr, d_cidx.ptr, d_dcol.ptr, d_prow.ptr, x, d_upd.ptr, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
@@ -85,8 +86,9 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
     const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
     if (!cnt) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = launch_solve_bwd_level(d_blocks.ptr, d_bwd_list.ptr + bwd_ptr[lev], cnt, d_bptr.ptr,
-                               d_bidx.ptr, d_bval.ptr, d_drow.ptr, x, d_perm.ptr, out, s);
+    e = launch_solve_bwd_level(d_blocks.ptr, d_bwd_items.ptr + bwd_ptr[lev], cnt, bwd_lds[lev],
+                               d_below.ptr, d_drow.ptr, d_prow.ptr, x, d_perm.ptr, out,
+                               d_partials2.ptr, d_blk_counters.ptr, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
@@ -110,7 +112,7 @@ hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_
   timed_begin(MR_KF_WARP, s);
   hipError_t e = launch_warp_msd(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr,
                                  d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
-                                 d_partials.ptr, d_counter.ptr, msd, d_flags.ptr, s);
+                                 d_partials.ptr, msd, d_flags.ptr, s);
   timed_end(s);
   return e;
 }
@@ -180,15 +182,18 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> mptr(n_nodes + 1, 0), mcol;
   std::vector<float> mwt;
   std::vector<DevBlock> blocks;
-  std::vector<int64_t> fptr(n_nodes + 1, 0), bptr(n_nodes + 1, 0);
-  std::vector<int32_t> fidx, bidx;
-  std::vector<double> fval, bval, dcol, drow;
+  std::vector<int64_t> cptr(n_nodes + 1, 0);
+  std::vector<int32_t> cidx, below;
+  std::vector<double> dcol, drow, prow;
   int max_fl = 0, max_bl = 0;
   for (int p = 0; p < n_pairs; ++p) {
     max_fl = std::max(max_fl, host[p].plan.n_fwd_levels);
     max_bl = std::max(max_bl, host[p].plan.n_bwd_levels);
   }
-  std::vector<std::vector<int32_t>> fwd_lv(max_fl), bwd_lv(max_bl);
+  std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
+  std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
+  int32_t n_partials = 0, n_counters = 0;
+  if (const char *env = std::getenv("MESHREG_BWD_SPLIT_ROWS")) bwd_split_rows = std::max(8, std::atoi(env));
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
     const DevPair &d = dpairs[p];
@@ -219,41 +224,65 @@ int mr_ctx::upload_all(hipStream_t s) {
     // solve plan, shifted to global rows
     const SolvePlan &pl = h.plan;
     const int64_t doff = (int64_t)dcol.size();
-    fval_off.push_back((int64_t)fval.size());
-    bval_off.push_back((int64_t)bval.size());
+    const int64_t poff = (int64_t)prow.size();
+    const int64_t uoff = (int64_t)below.size();
     dense_off.push_back(doff);
+    panel_off.push_back(poff);
     const int32_t boff = (int32_t)blocks.size();
     for (size_t k = 0; k < pl.blocks.size(); ++k) {
       const SolveBlock &B = pl.blocks[k];
-      blocks.push_back({no + B.r0, no + B.r1, B.fwd_group, B.bwd_group, doff + pl.dense_off[k]});
-      fwd_lv[B.fwd_level].push_back(boff + (int32_t)k);
-      bwd_lv[B.bwd_level].push_back(boff + (int32_t)k);
+      const int32_t m = (int32_t)(pl.below_ptr[k + 1] - pl.below_ptr[k]);
+      const int32_t b = B.r1 - B.r0;
+      if (b > kBlockMax) return fail(MR_EINVAL, "solve block larger than the kernel limit");
+      // panel rows per slice / chunk so that one work item fits the LDS budget
+      const int64_t nd = (int64_t)b * (b + 1) / 2;
+      const int64_t fixed = 8 * nd + 16 * (2 * (int64_t)b + 256) + 16;
+      int32_t rs = b ? (int32_t)((kSolveLdsBudget - fixed) / (8 * (int64_t)b + 16)) : 64;
+      rs = std::max(8, std::min(64, rs));
+      const int32_t ns = std::max<int32_t>(1, (m + rs - 1) / rs);
+      const int32_t bs = std::max<int32_t>(1, (m + bwd_split_rows - 1) / bwd_split_rows);
+      DevBlock db{no + B.r0, no + B.r1, m, B.fwd_group, doff + pl.dense_off[k],
+                  poff + pl.panel_off[k], uoff + pl.below_ptr[k], ns, rs, bs, 0, 0, 0};
+      if (bs > 1) {
+        db.part_off = n_partials;
+        db.cnt_idx = n_counters++;
+        n_partials += bs * b;
+      }
+      const int32_t kn = std::min(rs, m);
+      const int64_t lf = solve_fwd_lds_bytes(b, kn), lb = solve_bwd_lds_bytes(b, kn);
+      if (lf > kSolveLdsBudget || lb > kSolveLdsBudget)
+        return fail(MR_EINVAL, "solve block does not fit the LDS budget");
+      const int32_t id = boff + (int32_t)k;
+      for (int32_t q = 0; q < ns; ++q) fwd_lv[B.fwd_level].push_back(make_int2(id, q));
+      for (int32_t q = 0; q < bs; ++q) bwd_lv[B.bwd_level].push_back(make_int2(id, q));
+      fwd_lds_v[B.fwd_level] = std::max<int32_t>(fwd_lds_v[B.fwd_level], (int32_t)lf);
+      bwd_lds_v[B.bwd_level] = std::max<int32_t>(bwd_lds_v[B.bwd_level], (int32_t)lb);
+      blocks.push_back(db);
     }
     dcol.insert(dcol.end(), pl.dinv_col.begin(), pl.dinv_col.end());
     drow.insert(drow.end(), pl.dinv_row.begin(), pl.dinv_row.end());
-    const int64_t fo = (int64_t)fidx.size(), bo = (int64_t)bidx.size();
-    for (int r = 0; r < h.n; ++r) {
-      fptr[no + r + 1] = fo + pl.fptr[r + 1];
-      bptr[no + r + 1] = bo + pl.bptr[r + 1];
-    }
-    for (int32_t k : pl.fidx) fidx.push_back(no + k);
-    for (int32_t k : pl.bidx) bidx.push_back(no + k);
-    fval.insert(fval.end(), pl.fval.begin(), pl.fval.end());
-    bval.insert(bval.end(), pl.bval.begin(), pl.bval.end());
+    prow.insert(prow.end(), pl.panel_row.begin(), pl.panel_row.end());
+    for (int32_t r : pl.below_idx) below.push_back(no + r);
+    const int64_t co = (int64_t)cidx.size();
+    for (int r = 0; r < h.n; ++r) cptr[no + r + 1] = co + pl.cptr[r + 1];
+    for (int32_t k : pl.cidx) cidx.push_back((int32_t)(uoff + k));
   }
   if (mcol.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "operator too large");
-  std::vector<int32_t> fwd_list, bwd_list;
+  std::vector<int2> fwd_items, bwd_items;
   fwd_ptr.assign(1, 0);
   bwd_ptr.assign(1, 0);
   for (auto &lv : fwd_lv) {
-    fwd_list.insert(fwd_list.end(), lv.begin(), lv.end());
-    fwd_ptr.push_back((int32_t)fwd_list.size());
+    fwd_items.insert(fwd_items.end(), lv.begin(), lv.end());
+    fwd_ptr.push_back((int32_t)fwd_items.size());
   }
   for (auto &lv : bwd_lv) {
-    bwd_list.insert(bwd_list.end(), lv.begin(), lv.end());
-    bwd_ptr.push_back((int32_t)bwd_list.size());
+    bwd_items.insert(bwd_items.end(), lv.begin(), lv.end());
+    bwd_ptr.push_back((int32_t)bwd_items.size());
   }
-  nnz_factor = (int64_t)fidx.size() + (int64_t)dcol.size();
+  fwd_lds = fwd_lds_v;
+  bwd_lds = bwd_lds_v;
+  if (below.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "solve update buffer too large");
+  nnz_factor = (int64_t)prow.size() + (int64_t)dcol.size();
   HIP_TRY(upload(d_pairs, dpairs, s));
   HIP_TRY(upload(d_node_items, items, s));
   HIP_TRY(upload(d_tiles, tiles, s));
@@ -266,14 +295,16 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_mcol, mcol, s));
   HIP_TRY(upload(d_mwt, mwt, s));
   HIP_TRY(upload(d_blocks, blocks, s));
-  HIP_TRY(upload(d_fwd_list, fwd_list, s));
-  HIP_TRY(upload(d_bwd_list, bwd_list, s));
-  HIP_TRY(upload(d_fptr, fptr, s));
-  HIP_TRY(upload(d_fidx, fidx, s));
-  HIP_TRY(upload(d_fval, fval, s));
-  HIP_TRY(upload(d_bptr, bptr, s));
-  HIP_TRY(upload(d_bidx, bidx, s));
-  HIP_TRY(upload(d_bval, bval, s));
+  HIP_TRY(upload(d_fwd_items, fwd_items, s));
+  HIP_TRY(upload(d_bwd_items, bwd_items, s));
+  HIP_TRY(d_partials2.alloc(std::max(n_partials, 1)));
+  HIP_TRY(d_blk_counters.alloc(std::max(n_counters, 1)));
+  HIP_TRY(hipMemsetAsync(d_blk_counters.ptr, 0, sizeof(unsigned) * std::max(n_counters, 1), s));
+  HIP_TRY(upload(d_cptr, cptr, s));
+  HIP_TRY(upload(d_cidx, cidx, s));
+  HIP_TRY(upload(d_below, below, s));
+  HIP_TRY(upload(d_prow, prow, s));
+  HIP_TRY(d_upd.alloc(std::max<size_t>(below.size(), 1)));
   HIP_TRY(upload(d_dcol, dcol, s));
   HIP_TRY(upload(d_drow, drow, s));
   HIP_TRY(d_coef.alloc(n_pix));
@@ -299,8 +330,7 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
     return v.empty() ? hipSuccess
                      : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
   };
-  HIP_TRY(put(d_fval.ptr + fval_off[p], pl.fval));
-  HIP_TRY(put(d_bval.ptr + bval_off[p], pl.bval));
+  HIP_TRY(put(d_prow.ptr + panel_off[p], pl.panel_row));
   HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
   HIP_TRY(put(d_drow.ptr + dense_off[p], pl.dinv_row));
   HIP_TRY(hipStreamSynchronize(s));
@@ -312,9 +342,9 @@ int64_t mr_ctx::device_bytes() const {
                    d_tri.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
-                   d_blocks.bytes() + d_fwd_list.bytes() + d_bwd_list.bytes() + d_fptr.bytes() +
-                   d_bptr.bytes() + d_fidx.bytes() + d_bidx.bytes() + d_fval.bytes() +
-                   d_bval.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
+                   d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
+                   d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
+                   d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
                    d_msd_tmp.bytes() + d_counter.bytes() + d_flags.bytes());
 }
 
@@ -499,7 +529,7 @@ extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *s
     return fail(not_spd ? MR_ENOTSPD : MR_EINVAL, e);
   }
   fill_dense_inverses(h);
-  fill_offblock_values(h);
+  fill_panels(h);
   if (c->host_only) return MR_OK;
   hipStream_t s = (hipStream_t)stream;
   return c->upload_factor(pair, s);
@@ -563,7 +593,7 @@ extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *
     case MR_INFO_N_TRIS: *value = h.nt; break;
     case MR_INFO_NNZ_L: *value = h.L.colptr.empty() ? 0 : h.L.colptr[h.n]; break;
     case MR_INFO_N_BLOCKS: *value = (int64_t)h.plan.blocks.size(); break;
-    case MR_INFO_SOLVE_OFFBLOCK: *value = (int64_t)h.plan.fidx.size(); break;
+    case MR_INFO_SOLVE_OFFBLOCK: *value = (int64_t)h.plan.panel_row.size(); break;
     case MR_INFO_SOLVE_DENSE: *value = (int64_t)h.plan.dinv_col.size(); break;
     case MR_INFO_MASS_NNZ:
       *value = c->params.force_mode == MR_FORCE_NODAL ? h.n : (int64_t)h.tab.t3_idx.size();

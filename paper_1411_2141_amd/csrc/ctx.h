@@ -52,7 +52,7 @@ struct mr_ctx {
   int64_t n_nodes = 0, n_tris = 0, n_pix = 0, nnz_factor = 0;
   int n_node_items = 0, n_tiles = 0;
   // per pair offsets into the packed factor arrays (for re-factorisation)
-  std::vector<int64_t> fval_off, bval_off, dense_off;
+  std::vector<int64_t> dense_off, panel_off;
 
   mr::DevArray<mr::DevPair> d_pairs;
   mr::DevArray<mr::NodeItem> d_node_items;
@@ -66,11 +66,16 @@ struct mr_ctx {
   mr::DevArray<float2> d_h;
   mr::DevArray<double2> d_x;
   mr::DevArray<mr::DevBlock> d_blocks;
-  mr::DevArray<int32_t> d_fwd_list, d_bwd_list;
-  std::vector<int32_t> fwd_ptr, bwd_ptr;     // level -> range of the level lists (host)
-  mr::DevArray<int64_t> d_fptr, d_bptr;
-  mr::DevArray<int32_t> d_fidx, d_bidx;
-  mr::DevArray<double> d_fval, d_bval, d_dcol, d_drow;
+  mr::DevArray<int2> d_fwd_items, d_bwd_items;   // (block, slice) per level
+  std::vector<int32_t> fwd_ptr, bwd_ptr;     // level -> range of the item lists (host)
+  std::vector<int32_t> fwd_lds, bwd_lds;     // level -> dynamic LDS bytes
+  mr::DevArray<double2> d_partials2;         // backward slice partial sums
+  int32_t bwd_split_rows = 1 << 30;          // panel rows per backward workgroup
+  mr::DevArray<unsigned> d_blk_counters;
+  mr::DevArray<int64_t> d_cptr;
+  mr::DevArray<int32_t> d_cidx, d_below;
+  mr::DevArray<double> d_dcol, d_drow, d_prow;
+  mr::DevArray<double2> d_upd;
   mr::DevArray<double> d_partials, d_msd_tmp;
   mr::DevArray<unsigned> d_counter, d_flags;
   unsigned *host_flags = nullptr;            // pinned copy of d_flags

@@ -6,7 +6,8 @@
 
 namespace mr {
 
-constexpr int kBlockMax = 128;     // largest dense diagonal block of the solve
+constexpr int kBlockMax = 96;      // largest dense diagonal block of the solve
+constexpr int kSolveLdsBudget = 64 * 1024 - 512;  // dynamic LDS per solve workgroup (static use < 512 B)
 constexpr int kSolveThreads = 256;
 constexpr int kTile = 16;          // warp tiles are kTile x kTile pixels
 constexpr int kNodeChunk = 256;    // nodes per sample work item
@@ -26,9 +27,29 @@ struct DevPair {
 
 struct DevBlock {
   int32_t r0, r1;         // global rows of the packed permuted system
-  int32_t fgroup, bgroup; // lanes per row of the off-block dot products
+  int32_t m, fgroup;      // rows below the block; lanes per row of the forward gathers
   int64_t doff;           // offset of the packed dense inverse
+  int64_t poff;           // offset of the dense row-major panel (m x b)
+  int64_t boff;           // offset of the below-rows list == update-buffer offset
+  int32_t nslice, rslice; // forward: nslice workgroups of rslice panel rows each
+  int32_t bslice;         // backward: workgroups per block (each walks its rows in
+                          // LDS chunks of rslice)
+  int32_t part_off;       // backward partial sums: [bslice][b] double2 from here
+  int32_t cnt_idx;        // backward arrival counter of the block
+  int32_t pad;
 };
+
+// LDS bytes a forward work item of block size b with kn panel rows needs,
+// and a backward work item with panel chunks of rs rows; the launch of a
+// level uses the maximum over its items.
+inline int64_t solve_fwd_lds_bytes(int b, int kn) {
+  const int64_t nd = (int64_t)b * (b + 1) / 2;
+  return 8 * ((nd + (int64_t)kn * b + 1) / 2 * 2) + 16 * (2 * (int64_t)b + 256);
+}
+inline int64_t solve_bwd_lds_bytes(int b, int rs) {
+  const int64_t nd = (int64_t)b * (b + 1) / 2;
+  return 8 * (((int64_t)rs * b + 1) / 2 * 2) + 16 * ((int64_t)rs + 256 + b) + 8 * nd;
+}
 
 // Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`.
 struct NodeItem {

@@ -31,13 +31,13 @@ struct Factor {
 };
 
 // A block of consecutive rows [r0, r1) of the permuted system, solved as one
-// unit: its dense diagonal block of L is inverted, its coupling to other
-// blocks is applied by sparse dot products.
+// unit (a supernode): its dense diagonal block of L is inverted, and the rows
+// of L below it that its columns touch form a dense panel.
 struct SolveBlock {
   int32_t r0, r1;
   int32_t parent;                          // block id, -1 for a root
   int32_t fwd_level, bwd_level;
-  int32_t fwd_group, bwd_group;            // lanes per row for the off-block dot products
+  int32_t fwd_group;                       // lanes per row for the forward gathers
 };
 
 struct SolvePlan {
@@ -46,15 +46,18 @@ struct SolvePlan {
   // column-major (forward) and row-major (backward), both b(b+1)/2 per block
   std::vector<int64_t> dense_off;          // per block, same offset in both arrays
   std::vector<double> dinv_col, dinv_row;
-  // forward off-block entries by row: L(i, k) with k < r0(block(i))
-  std::vector<int64_t> fptr;
-  std::vector<int32_t> fidx;
-  std::vector<double> fval;
-  // backward off-block entries by column: L(r, j) with r >= r1(block(j))
-  std::vector<int64_t> bptr;
-  std::vector<int32_t> bidx;
-  std::vector<double> bval;
+  // rows below each block touched by its columns, ascending; the positions
+  // below_ptr[s] + k also index the forward update buffer
+  std::vector<int64_t> below_ptr;          // nb + 1
+  std::vector<int32_t> below_idx;
+  // dense panels L(below(s), r0:r1): m x b, row-major, at panel_off[s]
+  std::vector<int64_t> panel_off;
+  std::vector<double> panel_row;
+  // per row: update-buffer positions that contribute to it (ascending block)
+  std::vector<int64_t> cptr;               // n + 1
+  std::vector<int32_t> cidx;
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
+  int32_t max_below = 0;
 };
 
 struct PairHost {
@@ -74,7 +77,7 @@ struct PairHost {
 
 struct OrderOptions {
   int32_t leaf_max = 32;                   // nested-dissection leaf size
-  int32_t block_max = 128;                 // largest dense diagonal block
+  int32_t block_max = 96;                  // largest dense diagonal block
 };
 
 // Each returns an empty string on success, else the reason.
@@ -91,9 +94,9 @@ std::string cholesky(PairHost &p, double tau, bool *not_spd);
 std::string refactor(PairHost &p, double tau, bool *not_spd);
 std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, int32_t>> &ranges,
                              const std::vector<int32_t> &range_parent, const OrderOptions &opt);
-// Dense inverses only (after a refactor with unchanged structure).
+// Numeric parts of the plan (after a refactor with unchanged structure).
 void fill_dense_inverses(PairHost &p);
-void fill_offblock_values(PairHost &p);
+void fill_panels(PairHost &p);
 
 // Everything above in order.
 std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd);

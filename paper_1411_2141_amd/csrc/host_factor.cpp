@@ -291,30 +291,24 @@ void fill_dense_inverses(PairHost &p) {
   }
 }
 
-void fill_offblock_values(PairHost &p) {
+void fill_panels(PairHost &p) {
   SolvePlan &pl = p.plan;
   const Factor &L = p.L;
-  const int32_t n = L.n;
-  std::vector<int32_t> blk_of(n);
-  for (size_t s = 0; s < pl.blocks.size(); ++s)
-    for (int32_t r = pl.blocks[s].r0; r < pl.blocks[s].r1; ++r) blk_of[r] = (int32_t)s;
-  std::vector<int64_t> fnext(pl.fptr.begin(), pl.fptr.end() - 1);
-  for (int32_t k = 0; k < n; ++k)
-    for (int64_t q = L.colptr[k] + 1; q < L.colptr[k + 1]; ++q) {
-      const int32_t i = L.rowidx[q];
-      if (k < pl.blocks[blk_of[i]].r0) {
-        pl.fidx[fnext[i]] = k;
-        pl.fval[fnext[i]++] = L.val[q];
+  std::vector<int32_t> pos(L.n, -1);
+  for (size_t s = 0; s < pl.blocks.size(); ++s) {
+    const int32_t r0 = pl.blocks[s].r0, r1 = pl.blocks[s].r1, b = r1 - r0;
+    const int64_t k0 = pl.below_ptr[s], m = pl.below_ptr[s + 1] - k0;
+    for (int64_t k = 0; k < m; ++k) pos[pl.below_idx[k0 + k]] = (int32_t)k;
+    const int64_t off = pl.panel_off[s];
+    std::fill(pl.panel_row.begin() + off, pl.panel_row.begin() + off + m * b, 0.0);
+    for (int32_t j = r0; j < r1; ++j)
+      for (int64_t q = L.colptr[j] + 1; q < L.colptr[j + 1]; ++q) {
+        const int32_t r = L.rowidx[q];
+        if (r < r1) continue;
+        const int64_t k = pos[r];
+        pl.panel_row[off + k * b + (j - r0)] = L.val[q];
       }
-    }
-  for (int32_t j = 0; j < n; ++j) {
-    int64_t w = pl.bptr[j];
-    const int32_t r1 = pl.blocks[blk_of[j]].r1;
-    for (int64_t q = L.colptr[j] + 1; q < L.colptr[j + 1]; ++q)
-      if (L.rowidx[q] >= r1) {
-        pl.bidx[w] = L.rowidx[q];
-        pl.bval[w++] = L.val[q];
-      }
+    for (int64_t k = 0; k < m; ++k) pos[pl.below_idx[k0 + k]] = -1;
   }
 }
 
@@ -374,37 +368,56 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
   }
   pl.dinv_col.assign(tot, 0.0);
   pl.dinv_row.assign(tot, 0.0);
-  // off-block counts
-  pl.fptr.assign(n + 1, 0);
-  pl.bptr.assign(n + 1, 0);
-  for (int32_t k = 0; k < n; ++k)
-    for (int64_t q = L.colptr[k] + 1; q < L.colptr[k + 1]; ++q) {
-      const int32_t i = L.rowidx[q];
-      if (k < pl.blocks[blk_of[i]].r0) pl.fptr[i + 1]++;
-      if (i >= pl.blocks[blk_of[k]].r1) pl.bptr[k + 1]++;
-    }
-  for (int32_t r = 0; r < n; ++r) {
-    pl.fptr[r + 1] += pl.fptr[r];
-    pl.bptr[r + 1] += pl.bptr[r];
+  // below-sets (union of the column structures under each block)
+  pl.below_ptr.assign(nb + 1, 0);
+  pl.below_idx.clear();
+  std::vector<int32_t> mark(n, -1), rows;
+  for (int32_t s = 0; s < nb; ++s) {
+    const SolveBlock &B = pl.blocks[s];
+    rows.clear();
+    for (int32_t j = B.r0; j < B.r1; ++j)
+      for (int64_t q = L.colptr[j] + 1; q < L.colptr[j + 1]; ++q) {
+        const int32_t r = L.rowidx[q];
+        if (r >= B.r1 && mark[r] != s) {
+          mark[r] = s;
+          rows.push_back(r);
+        }
+      }
+    std::sort(rows.begin(), rows.end());
+    pl.below_idx.insert(pl.below_idx.end(), rows.begin(), rows.end());
+    pl.below_ptr[s + 1] = (int64_t)pl.below_idx.size();
   }
-  pl.fidx.assign(pl.fptr[n], 0);
-  pl.fval.assign(pl.fptr[n], 0.0);
-  pl.bidx.assign(pl.bptr[n], 0);
-  pl.bval.assign(pl.bptr[n], 0.0);
-  // lanes per row for the off-block dot products
+  if (pl.below_idx.size() >= (size_t)INT32_MAX) return "update buffer too large";
+  pl.max_below = 0;
+  pl.panel_off.assign(nb, 0);
+  int64_t ptot = 0;
+  for (int32_t s = 0; s < nb; ++s) {
+    const int64_t m = pl.below_ptr[s + 1] - pl.below_ptr[s];
+    pl.max_below = std::max<int32_t>(pl.max_below, (int32_t)m);
+    pl.panel_off[s] = ptot;
+    ptot += m * (pl.blocks[s].r1 - pl.blocks[s].r0);
+  }
+  pl.panel_row.assign(ptot, 0.0);
+  // contributors of each row, in increasing block order
+  pl.cptr.assign(n + 1, 0);
+  for (int32_t r : pl.below_idx) pl.cptr[r + 1]++;
+  for (int32_t r = 0; r < n; ++r) pl.cptr[r + 1] += pl.cptr[r];
+  pl.cidx.assign(pl.cptr[n], 0);
+  {
+    std::vector<int64_t> next(pl.cptr.begin(), pl.cptr.end() - 1);
+    for (int32_t s = 0; s < nb; ++s)
+      for (int64_t k = pl.below_ptr[s]; k < pl.below_ptr[s + 1]; ++k)
+        pl.cidx[next[pl.below_idx[k]]++] = (int32_t)k;
+  }
+  // lanes per row of the forward contributor gathers
   for (auto &B : pl.blocks) {
     const int32_t b = B.r1 - B.r0;
-    int64_t fl = 0, bl = 0;
-    for (int32_t r = B.r0; r < B.r1; ++r) {
-      fl += pl.fptr[r + 1] - pl.fptr[r];
-      bl += pl.bptr[r + 1] - pl.bptr[r];
-    }
-    const double fa = b ? (double)fl / b : 0.0, ba = b ? (double)bl / b : 0.0;
-    B.fwd_group = next_pow2_clamped(fa, 1, 64);
-    B.bwd_group = next_pow2_clamped(ba, 1, 64);
+    int64_t cnt = 0;
+    for (int32_t r = B.r0; r < B.r1; ++r) cnt += pl.cptr[r + 1] - pl.cptr[r];
+    B.fwd_group = next_pow2_clamped(b ? (double)cnt / b : 0.0, 1, 64);
   }
   fill_dense_inverses(p);
-  fill_offblock_values(p);
+  fill_panels(p);
   return "";
 }
 

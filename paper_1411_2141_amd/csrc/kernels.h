@@ -17,17 +17,19 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
                            double tau, hipStream_t s);
-hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
-                                  const int64_t *fptr, const int32_t *fidx, const double *fval,
-                                  const double *dcol, double2 *x, hipStream_t s);
-hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
-                                  const int64_t *bptr, const int32_t *bidx, const double *bval,
-                                  const double *drow, double2 *x, const int32_t *perm,
-                                  double2 *out, hipStream_t s);
+hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
+                                  int lds_bytes, const int64_t *cptr, const int32_t *cidx,
+                                  const double *dcol, const double *prow, double2 *x,
+                                  double2 *upd, hipStream_t s);
+hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
+                                  int lds_bytes, const int32_t *below_idx, const double *drow,
+                                  const double *prow, double2 *x, const int32_t *perm,
+                                  double2 *out, double2 *partials, unsigned *counters,
+                                  hipStream_t s);
 hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
                            const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
                            const float *coef, const float *re, float *warped, double *partials,
-                           unsigned *counter, double *msd, unsigned *flags, hipStream_t s);
+                           double *msd, unsigned *flags, hipStream_t s);
 hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
                                  hipStream_t s);
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,

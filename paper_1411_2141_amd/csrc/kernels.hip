@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdint>
 
 #include "device.h"
@@ -300,99 +301,250 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
   x[iperm[i]] = make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
 }
 
-// Forward solve of one block level: for each block, t = b - L_off y (sparse,
-// rows of the block against already-solved rows), then y = D^-1 t with the
-// block's dense inverse (column-major packed lower triangle).  In place on x.
-__global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
-    const DevBlock *__restrict__ blocks, const int32_t *__restrict__ level_list,
-    const int64_t *__restrict__ fptr, const int32_t *__restrict__ fidx,
-    const double *__restrict__ fval, const double *__restrict__ dcol, double2 *x) {
-  __shared__ double2 t[kBlockMax];
-  const DevBlock B = blocks[level_list[blockIdx.x]];
-  const int b = B.r1 - B.r0;
-  const int tid = threadIdx.x;
-  const int G = B.fgroup;
-  const int sub = tid & (G - 1);
-  const int ngroups = kSolveThreads / G;
-  for (int r = tid / G; r < b; r += ngroups) {
-    const int row = B.r0 + r;
-    double ax = 0.0, ay = 0.0;
-    const int64_t q1 = fptr[row + 1];
-    for (int64_t q = fptr[row] + sub; q < q1; q += G) {
-      const double v = fval[q];
-      const double2 yk = x[fidx[q]];
-      ax += v * yk.x;
-      ay += v * yk.y;
+// Copies n doubles from global memory to LDS with all of a thread's loads of
+// a batch in flight before the first LDS store (predicated, no serial tail).
+__device__ __forceinline__ void stage_to_lds(double *__restrict__ dst, const double *__restrict__ src,
+                                             int n) {
+  constexpr int U = 16;
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * kSolveThreads) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kSolveThreads;
+      v[u] = e < n ? src[e] : 0.0;
     }
-    for (int off = G >> 1; off > 0; off >>= 1) {
-      ax += __shfl_xor(ax, off);
-      ay += __shfl_xor(ay, off);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kSolveThreads;
+      if (e < n) dst[e] = v[u];
     }
-    if (sub == 0) {
-      const double2 bb = x[row];
-      t[r] = make_double2(bb.x - ax, bb.y - ay);
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < b; i += kSolveThreads) {
-    double ax = 0.0, ay = 0.0;
-    const double *d = dcol + B.doff + i;
-    for (int j = 0; j <= i; ++j) {
-      // element (i, j) of the packed column-major lower triangle
-      const double v = d[(int64_t)j * b - (int64_t)j * (j - 1) / 2 - j];
-      ax += v * t[j].x;
-      ay += v * t[j].y;
-    }
-    x[B.r0 + i] = make_double2(ax, ay);
   }
 }
 
-// Backward solve of one block level: t = y - L_off^T z (columns of the block
-// against already-solved later rows), then z = D^-T t with the row-major packed
-// inverse.  In place on x; the last level pass also scatters z to `out` in the
-// natural node order when `out` is not null.
-__global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
-    const DevBlock *__restrict__ blocks, const int32_t *__restrict__ level_list,
-    const int64_t *__restrict__ bptr, const int32_t *__restrict__ bidx,
-    const double *__restrict__ bval, const double *__restrict__ drow, double2 *x,
-    const int32_t *__restrict__ perm, double2 *__restrict__ out) {
-  __shared__ double2 t[kBlockMax];
-  const DevBlock B = blocks[level_list[blockIdx.x]];
+// Smallest power of two >= b (b <= kBlockMax).
+__device__ __forceinline__ int pow2_at_least(int b) {
+  int p = 1;
+  while (p < b) p <<= 1;
+  return p;
+}
+
+// Sums red[o + q * stride] for q < nparts in order (deterministic combine).
+__device__ __forceinline__ double2 combine_parts(const double2 *red, int o, int stride,
+                                                 int nparts) {
+  double sx = 0.0, sy = 0.0;
+  for (int q = 0; q < nparts; ++q) {
+    sx += red[o + q * stride].x;
+    sy += red[o + q * stride].y;
+  }
+  return make_double2(sx, sy);
+}
+
+// Forward solve, one level of the block tree (supernodal, push form).  Work
+// item = (block, slice).  Every slice of a block computes
+//   t = b_rows - (update entries that descendant blocks wrote for these rows)
+//   y = D^-1 t              (dense inverse, column-major packed, staged in LDS)
+// and then its slice of the block's own update entries
+//   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block)).
+// Slice 0 also writes y to x (in place).  Each phase spreads its sums over all
+// threads and combines the partial sums in a fixed order (deterministic).
+__global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
+    const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
+    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *upd) {
+  extern __shared__ double smem[];
+  const int2 it = items[blockIdx.x];
+  const DevBlock B = blocks[it.x];
   const int b = B.r1 - B.r0;
+  if (b == 0) return;
   const int tid = threadIdx.x;
-  const int G = B.bgroup;
-  const int sub = tid & (G - 1);
-  const int ngroups = kSolveThreads / G;
-  for (int r = tid / G; r < b; r += ngroups) {
-    const int col = B.r0 + r;
+  const int nd = b * (b + 1) / 2;
+  const int k0 = it.y * B.rslice;
+  const int kn = max(0, min(B.rslice, B.m - k0));
+  double *D = smem;
+  double *Ps = D + nd;
+  double2 *t = reinterpret_cast<double2 *>(smem + (nd + kn * b + 1) / 2 * 2);
+  double2 *yv = t + b;
+  double2 *red = yv + b;
+  stage_to_lds(D, dcol + B.doff, nd);
+  stage_to_lds(Ps, prow + B.poff + (int64_t)k0 * b, kn * b);
+  const int bp = pow2_at_least(b);
+  const int np = kSolveThreads / bp;          // threads per row
+  const int r = tid & (bp - 1), part = tid / bp;
+  // phase 1: gathers of the contributions, all loads of a thread in flight
+  {
     double ax = 0.0, ay = 0.0;
-    const int64_t q1 = bptr[col + 1];
-    for (int64_t q = bptr[col] + sub; q < q1; q += G) {
-      const double v = bval[q];
-      const double2 zk = x[bidx[q]];
-      ax += v * zk.x;
-      ay += v * zk.y;
+    if (r < b) {
+      const int row = B.r0 + r;
+      const int64_t q1 = cptr[row + 1];
+      constexpr int U = 8;
+      for (int64_t q = cptr[row] + part; q < q1; q += (int64_t)np * U) {
+        int idx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t qq = q + (int64_t)u * np;
+          idx[u] = qq < q1 ? cidx[qq] : -1;
+        }
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = idx[u] >= 0 ? upd[idx[u]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          ax += v[u].x;
+          ay += v[u].y;
+        }
+      }
     }
-    for (int off = G >> 1; off > 0; off >>= 1) {
-      ax += __shfl_xor(ax, off);
-      ay += __shfl_xor(ay, off);
-    }
-    if (sub == 0) {
-      const double2 yy = x[col];
-      t[r] = make_double2(yy.x - ax, yy.y - ay);
-    }
+    red[tid] = make_double2(ax, ay);
   }
   __syncthreads();
-  for (int j = tid; j < b; j += kSolveThreads) {
+  if (part == 0 && r < b) {
+    const double2 c = combine_parts(red, r, bp, np);
+    const double2 bb = x[B.r0 + r];
+    t[r] = make_double2(bb.x - c.x, bb.y - c.y);
+  }
+  __syncthreads();
+  // phase 2: y_i = sum_{j <= i} D(i, j) t_j, j split over the row's threads
+  {
     double ax = 0.0, ay = 0.0;
-    const double *d = drow + B.doff + j;
-    for (int i = j; i < b; ++i) {
-      // element (i, j) of the packed row-major lower triangle
-      const double v = d[(int64_t)i * (i + 1) / 2];
-      ax += v * t[i].x;
-      ay += v * t[i].y;
+    if (r < b) {
+#pragma unroll 8
+      for (int j = part; j <= r; j += np) {
+        // element (r, j) of the packed column-major lower triangle
+        const double v = D[j * b - j * (j - 1) / 2 + (r - j)];
+        ax += v * t[j].x;
+        ay += v * t[j].y;
+      }
     }
-    const double2 z = make_double2(ax, ay);
+    red[tid] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  if (part == 0 && r < b) {
+    const double2 y = combine_parts(red, r, bp, np);
+    yv[r] = y;
+    if (it.y == 0) x[B.r0 + r] = y;
+  }
+  __syncthreads();
+  // phase 3: the slice's update entries, 4 partial sums per panel row
+  constexpr int kParts = 4;
+  constexpr int kRows = kSolveThreads / kParts;
+  for (int base = 0; base < kn; base += kRows) {
+    const int kk = base + tid % kRows;
+    const int pp = tid / kRows;
+    double ax = 0.0, ay = 0.0;
+    if (kk < kn) {
+      const double *Pr = Ps + kk * b;
+#pragma unroll 8
+      for (int j = pp; j < b; j += kParts) {
+        const double v = Pr[j];
+        ax += v * yv[j].x;
+        ay += v * yv[j].y;
+      }
+    }
+    red[tid] = make_double2(ax, ay);
+    __syncthreads();
+    if (pp == 0 && kk < kn) upd[B.boff + k0 + kk] = combine_parts(red, tid, kRows, kParts);
+    __syncthreads();
+  }
+}
+
+// Backward solve, one level of the block tree.  Work item = (block, slice);
+// a block is split into B.bslice workgroups, each covering a contiguous run of
+// panel rows that it walks in LDS chunks of B.rslice rows, forming the partial
+// sums s_j = sum_k P[k][j] z(below_k).  A block with one workgroup finishes at
+// once; otherwise each workgroup writes its partials, and the last to arrive
+// (device-scope counter) adds them in slice order.  The finishing workgroup
+// forms t = y_block - s and z = D^-T t (row-major packed inverse in LDS),
+// writes z in place and, when `out` is given, scatters it to natural order.
+// The finisher resets the counter.
+__global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
+    const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
+    const double *__restrict__ prow, double2 *x, const int32_t *__restrict__ perm,
+    double2 *__restrict__ out, double2 *partials, unsigned *counters) {
+  extern __shared__ double smem[];
+  __shared__ int last;
+  const int2 it = items[blockIdx.x];
+  const DevBlock B = blocks[it.x];
+  const int b = B.r1 - B.r0;
+  if (b == 0) return;
+  const int tid = threadIdx.x;
+  const int nd = b * (b + 1) / 2;
+  const int rs = B.rslice;
+  // panel rows [kb, ke) of this workgroup
+  const int per = (B.m + B.bslice - 1) / B.bslice;
+  const int kb = min(B.m, it.y * per), ke = min(B.m, kb + per);
+  const int cap = min(rs, B.m);   // LDS chunk capacity in panel rows
+  double *Ps = smem;
+  double2 *zb = reinterpret_cast<double2 *>(smem + (cap * b + 1) / 2 * 2);
+  double2 *red = zb + cap;
+  double2 *t = red + kSolveThreads;
+  double *D = reinterpret_cast<double *>(t + b);
+  if (B.bslice == 1) stage_to_lds(D, drow + B.doff, nd);
+  const int bp = pow2_at_least(b);
+  const int np = kSolveThreads / bp;
+  const int j = tid & (bp - 1), g = tid / bp;
+  double ax = 0.0, ay = 0.0;
+  for (int c0 = kb; c0 < ke; c0 += cap) {
+    const int kn = min(cap, ke - c0);
+    stage_to_lds(Ps, prow + B.poff + (int64_t)c0 * b, kn * b);
+    for (int k = tid; k < kn; k += kSolveThreads) zb[k] = x[below_idx[B.boff + c0 + k]];
+    __syncthreads();
+    if (j < b) {
+#pragma unroll 8
+      for (int k = g; k < kn; k += np) {
+        const double v = Ps[k * b + j];
+        ax += v * zb[k].x;
+        ay += v * zb[k].y;
+      }
+    }
+    __syncthreads();
+  }
+  red[tid] = make_double2(ax, ay);
+  __syncthreads();
+  double2 sum = make_double2(0.0, 0.0);
+  if (g == 0 && j < b) sum = combine_parts(red, j, bp, np);
+  if (B.bslice > 1) {
+    if (g == 0 && j < b) partials[B.part_off + it.y * b + j] = sum;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = (atomicAdd(&counters[B.cnt_idx], 1u) == (unsigned)(B.bslice - 1));
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    stage_to_lds(D, drow + B.doff, nd);
+    if (g == 0 && j < b) {
+      double sx = 0.0, sy = 0.0;
+      for (int q = 0; q < B.bslice; ++q) {
+        const double2 pq = partials[B.part_off + q * b + j];
+        sx += pq.x;
+        sy += pq.y;
+      }
+      sum = make_double2(sx, sy);
+    }
+    if (tid == 0) atomicExch(&counters[B.cnt_idx], 0u);
+  }
+  if (g == 0 && j < b) {
+    const double2 yy = x[B.r0 + j];
+    t[j] = make_double2(yy.x - sum.x, yy.y - sum.y);
+  }
+  __syncthreads();
+  // z_j = sum_{i >= j} D(i, j) t_i, i split over the column's threads
+  {
+    double zx = 0.0, zy = 0.0;
+    if (j < b) {
+#pragma unroll 8
+      for (int i = j + g; i < b; i += np) {
+        // element (i, j) of the packed row-major lower triangle
+        const double v = D[i * (i + 1) / 2 + j];
+        zx += v * t[i].x;
+        zy += v * t[i].y;
+      }
+    }
+    red[tid] = make_double2(zx, zy);
+  }
+  __syncthreads();
+  if (g == 0 && j < b) {
+    const double2 z = combine_parts(red, j, bp, np);
     x[B.r0 + j] = z;
     if (out) out[perm[B.r0 + j]] = z;
   }
@@ -405,8 +557,7 @@ __global__ __launch_bounds__(256) void k_warp_msd(
     const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, int n_pairs,
     const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
     const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
-    float *__restrict__ warped, double *partials, unsigned *counter, double *__restrict__ msd,
-    unsigned *flags) {
+    float *__restrict__ warped, double *__restrict__ partials, unsigned *flags) {
   const TileItem it = tiles[blockIdx.x];
   const DevPair P = pairs[it.pair];
   const int i = it.y0 + (int)(threadIdx.x / kTile);
@@ -437,28 +588,27 @@ __global__ __launch_bounds__(256) void k_warp_msd(
     acc = e * e;
   }
   __shared__ double red[4];
-  __shared__ int last;
   acc = wave_sum(acc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int p = wave; p < n_pairs; p += 4) {
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Second pass of the MSD: per pair, the tile partials summed in tile order by
+// one wavefront (deterministic), divided by the pixel count.
+__global__ __launch_bounds__(256) void k_msd_finish(const DevPair *__restrict__ pairs, int n_pairs,
+                                                    const double *__restrict__ partials,
+                                                    double *__restrict__ msd) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  for (int p = wave; p < n_pairs; p += gridDim.x * 4) {
     const DevPair Q = pairs[p];
     double s = 0.0;
     for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
     s = wave_sum(s);
     if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
   }
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 // Gather / scatter between the natural node order and the solve order.
@@ -510,28 +660,32 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
   return hipGetLastError();
 }
 
-hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
-                                  const int64_t *fptr, const int32_t *fidx, const double *fval,
-                                  const double *dcol, double2 *x, hipStream_t s) {
-  k_solve_fwd<<<count, kSolveThreads, 0, s>>>(blocks, level_list, fptr, fidx, fval, dcol, x);
+hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
+                                  int lds_bytes, const int64_t *cptr, const int32_t *cidx,
+                                  const double *dcol, const double *prow, double2 *x,
+                                  double2 *upd, hipStream_t s) {
+  k_solve_fwd<<<count, kSolveThreads, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x,
+                                                      upd);
   return hipGetLastError();
 }
 
-hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int32_t *level_list, int count,
-                                  const int64_t *bptr, const int32_t *bidx, const double *bval,
-                                  const double *drow, double2 *x, const int32_t *perm,
-                                  double2 *out, hipStream_t s) {
-  k_solve_bwd<<<count, kSolveThreads, 0, s>>>(blocks, level_list, bptr, bidx, bval, drow, x, perm,
-                                             out);
+hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
+                                  int lds_bytes, const int32_t *below_idx, const double *drow,
+                                  const double *prow, double2 *x, const int32_t *perm,
+                                  double2 *out, double2 *partials, unsigned *counters,
+                                  hipStream_t s) {
+  k_solve_bwd<<<count, kSolveThreads, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x,
+                                                      perm, out, partials, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
                            const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
                            const float *coef, const float *re, float *warped, double *partials,
-                           unsigned *counter, double *msd, unsigned *flags, hipStream_t s) {
+                           double *msd, unsigned *flags, hipStream_t s) {
   k_warp_msd<<<n_tiles, kTile * kTile, 0, s>>>(tiles, pairs, n_pairs, u, xy, tri, t6, coef, re,
-                                               warped, partials, counter, msd, flags);
+                                               warped, partials, flags);
+  k_msd_finish<<<std::min((n_pairs + 3) / 4, 64), 256, 0, s>>>(pairs, n_pairs, partials, msd);
   return hipGetLastError();
 }
 
