@@ -82,6 +82,19 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
     timed_end(s);
     if (e != hipSuccess) return e;
   }
+  if (n_apex_rows) {
+    timed_begin(MR_KF_SOLVE, s);
+    e = launch_apex_fwd((int)n_apex_rows, d_apex_rows.ptr, d_apex_cptr.ptr, d_apex_cidx.ptr,
+                        d_upd.ptr, x, d_apex_t.ptr, d_apex_fitems.ptr, (int)d_apex_fitems.count,
+                        apex_lds, d_apex.ptr, d_apex_inv_row.ptr, d_apex_y.ptr, s);
+    timed_end(s);
+    if (e != hipSuccess) return e;
+    timed_begin(MR_KF_SOLVE, s);
+    e = launch_apex_bwd(d_apex_bitems.ptr, (int)d_apex_bitems.count, apex_lds, d_apex.ptr,
+                        d_apex_inv_col.ptr, d_apex_rows.ptr, d_apex_y.ptr, x, d_perm.ptr, out, s);
+    timed_end(s);
+    if (e != hipSuccess) return e;
+  }
   for (int lev = 0; lev < (int)bwd_ptr.size() - 1; ++lev) {
     const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
     if (!cnt) continue;
@@ -95,11 +108,17 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
   return e;
 }
 
-hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
+hipError_t mr_ctx::sample(const double2 *u, double *finish_msd, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
-  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr,
-                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, s);
+  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u, d_xy.ptr,
+                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, d_partials.ptr,
+                               finish_msd, s);
   timed_end(s);
+  return e;
+}
+
+hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
+  hipError_t e = sample(u, nullptr, s);
   if (e != hipSuccess) return e;
   timed_begin(MR_KF_ASSEMBLE, s);
   e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u, d_iperm.ptr,
@@ -108,11 +127,35 @@ hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
   return e;
 }
 
+// One iteration: sample, force assembly (right-hand side in solve order), the
+// forward and backward solves (the latter writing u), and (if msd_out) the
+// warp partials, whose final sum is left pending for the next sample launch
+// or a finish launch.
+hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, hipStream_t s) {
+  hipError_t e = sample(u, *pending, s);
+  *pending = nullptr;
+  if (e != hipSuccess) return e;
+  timed_begin(MR_KF_ASSEMBLE, s);
+  e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u, d_iperm.ptr,
+                      d_x.ptr, params.tau, s);
+  timed_end(s);
+  if (e != hipSuccess) return e;
+  e = solve(d_x.ptr, u, s);
+  if (e != hipSuccess || !msd_out) return e;
+  timed_begin(MR_KF_WARP, s);
+  e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr, d_tri.ptr,
+                           d_t6.ptr, d_coef.ptr, d_re.ptr, nullptr, d_partials.ptr, d_flags.ptr, s);
+  timed_end(s);
+  *pending = msd_out;
+  return e;
+}
+
 hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_t s) {
   timed_begin(MR_KF_WARP, s);
-  hipError_t e = launch_warp_msd(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr,
-                                 d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
-                                 d_partials.ptr, msd, d_flags.ptr, s);
+  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr,
+                                      d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
+                                      d_partials.ptr, d_flags.ptr, s);
+  if (e == hipSuccess) e = launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s);
   timed_end(s);
   return e;
 }
@@ -187,9 +230,16 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<double> dcol, drow, prow;
   int max_fl = 0, max_bl = 0;
   for (int p = 0; p < n_pairs; ++p) {
-    max_fl = std::max(max_fl, host[p].plan.n_fwd_levels);
-    max_bl = std::max(max_bl, host[p].plan.n_bwd_levels);
+    max_fl = std::max(max_fl, host[p].plan.apex_level);
+    max_bl = std::max(max_bl, host[p].plan.n_rel_bwd_levels);
   }
+  std::vector<int32_t> apex_rows_g;
+  std::vector<int64_t> apex_cptr_g(1, 0);
+  std::vector<int32_t> apex_cidx_g;
+  std::vector<double> apex_inv_row_g, apex_inv_col_g;
+  std::vector<ApexDesc> apex_desc;
+  std::vector<int2> apex_fitems, apex_bitems;
+  int32_t apex_nmax = 0;
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
   int32_t n_partials = 0, n_counters = 0;
@@ -253,16 +303,39 @@ int mr_ctx::upload_all(hipStream_t s) {
       if (lf > kSolveLdsBudget || lb > kSolveLdsBudget)
         return fail(MR_EINVAL, "solve block does not fit the LDS budget");
       const int32_t id = boff + (int32_t)k;
-      for (int32_t q = 0; q < ns; ++q) fwd_lv[B.fwd_level].push_back(make_int2(id, q));
-      for (int32_t q = 0; q < bs; ++q) bwd_lv[B.bwd_level].push_back(make_int2(id, q));
-      fwd_lds_v[B.fwd_level] = std::max<int32_t>(fwd_lds_v[B.fwd_level], (int32_t)lf);
-      bwd_lds_v[B.bwd_level] = std::max<int32_t>(bwd_lds_v[B.bwd_level], (int32_t)lb);
+      if (!pl.is_apex[k]) {
+        const int32_t bl = pl.rel_bwd_level[k];
+        for (int32_t q = 0; q < ns; ++q) fwd_lv[B.fwd_level].push_back(make_int2(id, q));
+        for (int32_t q = 0; q < bs; ++q) bwd_lv[bl].push_back(make_int2(id, q));
+        fwd_lds_v[B.fwd_level] = std::max<int32_t>(fwd_lds_v[B.fwd_level], (int32_t)lf);
+        bwd_lds_v[bl] = std::max<int32_t>(bwd_lds_v[bl], (int32_t)lb);
+      }
       blocks.push_back(db);
     }
     dcol.insert(dcol.end(), pl.dinv_col.begin(), pl.dinv_col.end());
     drow.insert(drow.end(), pl.dinv_row.begin(), pl.dinv_row.end());
     prow.insert(prow.end(), pl.panel_row.begin(), pl.panel_row.end());
     for (int32_t r : pl.below_idx) below.push_back(no + r);
+    // apex of this pair
+    {
+      const int32_t na = (int32_t)pl.apex_rows.size();
+      ApexDesc ad{na, 0, (int64_t)apex_rows_g.size(), (int64_t)apex_inv_row_g.size()};
+      apex_desc.push_back(ad);
+      apex_off.push_back(ad.inv_off);
+      apex_nmax = std::max(apex_nmax, na);
+      for (int32_t i = 0; i < na; ++i) {
+        apex_rows_g.push_back(no + pl.apex_rows[i]);
+        for (int64_t q = pl.apex_cptr[i]; q < pl.apex_cptr[i + 1]; ++q)
+          apex_cidx_g.push_back((int32_t)(uoff + pl.apex_cidx[q]));
+        apex_cptr_g.push_back((int64_t)apex_cidx_g.size());
+      }
+      apex_inv_row_g.insert(apex_inv_row_g.end(), pl.apex_inv_row.begin(), pl.apex_inv_row.end());
+      apex_inv_col_g.insert(apex_inv_col_g.end(), pl.apex_inv_col.begin(), pl.apex_inv_col.end());
+      for (int32_t i = 0; i < na; i += kApexRowsPerGroup) {
+        apex_fitems.push_back(make_int2(p, i));
+        apex_bitems.push_back(make_int2(p, i));
+      }
+    }
     const int64_t co = (int64_t)cidx.size();
     for (int r = 0; r < h.n; ++r) cptr[no + r + 1] = co + pl.cptr[r + 1];
     for (int32_t k : pl.cidx) cidx.push_back((int32_t)(uoff + k));
@@ -295,6 +368,19 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_mcol, mcol, s));
   HIP_TRY(upload(d_mwt, mwt, s));
   HIP_TRY(upload(d_blocks, blocks, s));
+  n_apex_rows = (int64_t)apex_rows_g.size();
+  apex_lds = 16 * std::max(apex_nmax, 1);
+  if (apex_lds > 64 * 1024) return fail(MR_EINVAL, "apex larger than the LDS limit");
+  HIP_TRY(upload(d_apex, apex_desc, s));
+  HIP_TRY(upload(d_apex_rows, apex_rows_g, s));
+  HIP_TRY(upload(d_apex_cptr, apex_cptr_g, s));
+  HIP_TRY(upload(d_apex_cidx, apex_cidx_g, s));
+  HIP_TRY(upload(d_apex_inv_row, apex_inv_row_g, s));
+  HIP_TRY(upload(d_apex_inv_col, apex_inv_col_g, s));
+  HIP_TRY(upload(d_apex_fitems, apex_fitems, s));
+  HIP_TRY(upload(d_apex_bitems, apex_bitems, s));
+  HIP_TRY(d_apex_t.alloc(std::max<int64_t>(n_apex_rows, 1)));
+  HIP_TRY(d_apex_y.alloc(std::max<int64_t>(n_apex_rows, 1)));
   HIP_TRY(upload(d_fwd_items, fwd_items, s));
   HIP_TRY(upload(d_bwd_items, bwd_items, s));
   HIP_TRY(d_partials2.alloc(std::max(n_partials, 1)));
@@ -313,10 +399,8 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(d_h.alloc(n_nodes));
   HIP_TRY(d_x.alloc(n_nodes));
   HIP_TRY(d_partials.alloc(std::max(n_tiles, 1)));
-  HIP_TRY(d_counter.alloc(1));
   HIP_TRY(d_flags.alloc(1));
   HIP_TRY(d_msd_tmp.alloc(n_pairs));
-  HIP_TRY(hipMemsetAsync(d_counter.ptr, 0, sizeof(unsigned), s));
   HIP_TRY(hipMemsetAsync(d_flags.ptr, 0, sizeof(unsigned), s));
   HIP_TRY(hipHostMalloc((void **)&host_flags, sizeof(unsigned), hipHostMallocDefault));
   *host_flags = 0;
@@ -331,6 +415,8 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
                      : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
   };
   HIP_TRY(put(d_prow.ptr + panel_off[p], pl.panel_row));
+  HIP_TRY(put(d_apex_inv_row.ptr + apex_off[p], pl.apex_inv_row));
+  HIP_TRY(put(d_apex_inv_col.ptr + apex_off[p], pl.apex_inv_col));
   HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
   HIP_TRY(put(d_drow.ptr + dense_off[p], pl.dinv_row));
   HIP_TRY(hipStreamSynchronize(s));
@@ -345,7 +431,8 @@ int64_t mr_ctx::device_bytes() const {
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
                    d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
-                   d_msd_tmp.bytes() + d_counter.bytes() + d_flags.bytes());
+                   d_apex_inv_row.bytes() + d_apex_inv_col.bytes() + d_apex_cidx.bytes() +
+                   d_msd_tmp.bytes() + d_flags.bytes());
 }
 
 // B-spline coefficients of one pair's image (FP32 device input).
@@ -465,11 +552,10 @@ extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_t
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
   double2 *u2 = reinterpret_cast<double2 *>(u);
-  for (int k = 0; k < n_iter; ++k) {
-    HIP_TRY(c->force(u2, s));
-    HIP_TRY(c->solve(c->d_x.ptr, u2, s));
-    if (msd_trace) HIP_TRY(c->warp(u2, msd_trace + (size_t)k * c->n_pairs, nullptr, s));
-  }
+  double *pending = nullptr;
+  for (int k = 0; k < n_iter; ++k)
+    HIP_TRY(c->iterate(u2, msd_trace ? msd_trace + (size_t)k * c->n_pairs : nullptr, &pending, s));
+  if (pending) HIP_TRY(launch_msd_finish(c->d_pairs.ptr, c->n_pairs, c->d_partials.ptr, pending, s));
   c->post_flags(s);
   return MR_OK;
 }
@@ -530,6 +616,7 @@ extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *s
   }
   fill_dense_inverses(h);
   fill_panels(h);
+  fill_apex_inverse(h);
   if (c->host_only) return MR_OK;
   hipStream_t s = (hipStream_t)stream;
   return c->upload_factor(pair, s);

@@ -52,7 +52,7 @@ struct mr_ctx {
   int64_t n_nodes = 0, n_tris = 0, n_pix = 0, nnz_factor = 0;
   int n_node_items = 0, n_tiles = 0;
   // per pair offsets into the packed factor arrays (for re-factorisation)
-  std::vector<int64_t> dense_off, panel_off;
+  std::vector<int64_t> dense_off, panel_off, apex_off;
 
   mr::DevArray<mr::DevPair> d_pairs;
   mr::DevArray<mr::NodeItem> d_node_items;
@@ -70,6 +70,15 @@ struct mr_ctx {
   std::vector<int32_t> fwd_ptr, bwd_ptr;     // level -> range of the item lists (host)
   std::vector<int32_t> fwd_lds, bwd_lds;     // level -> dynamic LDS bytes
   mr::DevArray<double2> d_partials2;         // backward slice partial sums
+  // apex (dense top of every pair's block tree)
+  int64_t n_apex_rows = 0;
+  int32_t apex_lds = 0;
+  mr::DevArray<mr::ApexDesc> d_apex;
+  mr::DevArray<int32_t> d_apex_rows, d_apex_cidx;
+  mr::DevArray<int64_t> d_apex_cptr;
+  mr::DevArray<double> d_apex_inv_row, d_apex_inv_col;
+  mr::DevArray<int2> d_apex_fitems, d_apex_bitems;
+  mr::DevArray<double2> d_apex_t, d_apex_y;
   int32_t bwd_split_rows = 1 << 30;          // panel rows per backward workgroup
   mr::DevArray<unsigned> d_blk_counters;
   mr::DevArray<int64_t> d_cptr;
@@ -77,7 +86,7 @@ struct mr_ctx {
   mr::DevArray<double> d_dcol, d_drow, d_prow;
   mr::DevArray<double2> d_upd;
   mr::DevArray<double> d_partials, d_msd_tmp;
-  mr::DevArray<unsigned> d_counter, d_flags;
+  mr::DevArray<unsigned> d_flags;
   unsigned *host_flags = nullptr;            // pinned copy of d_flags
 
   bool timing = false;
@@ -87,8 +96,10 @@ struct mr_ctx {
   int upload_all(hipStream_t s);
   int upload_factor(int pair, hipStream_t s);
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
+  hipError_t sample(const double2 *u, double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
   hipError_t solve(double2 *x, double2 *out, hipStream_t s);
+  hipError_t iterate(double2 *u, double *msd_out, double **pending, hipStream_t s);
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
   void post_flags(hipStream_t s);

@@ -51,6 +51,16 @@ inline int64_t solve_bwd_lds_bytes(int b, int rs) {
   return 8 * (((int64_t)rs * b + 1) / 2 * 2) + 16 * ((int64_t)rs + 256 + b) + 8 * nd;
 }
 
+// Apex (dense top of the block tree) of one pair.
+struct ApexDesc {
+  int32_t n;              // apex rows
+  int32_t pad;
+  int64_t rows_off;       // offset into the apex row list, contribution CSR and t/y buffers
+  int64_t inv_off;        // offset of the packed inverse triangles
+};
+
+constexpr int kApexRowsPerGroup = 4;   // one wavefront per apex row / column
+
 // Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`.
 struct NodeItem {
   int32_t pair, begin, end, pad;

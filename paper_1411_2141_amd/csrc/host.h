@@ -58,6 +58,18 @@ struct SolvePlan {
   std::vector<int32_t> cidx;
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
   int32_t max_below = 0;
+  // Apex: the top of the block tree (blocks with fwd_level >= apex_level)
+  // solved as one dense unit: rows ascending, the packed lower triangle of
+  // L(apex, apex)^-1 row-major (forward) and column-major (backward), and per
+  // apex row the update-buffer positions written by non-apex blocks.
+  int32_t apex_level = 0;                  // == n_fwd_levels when there is no apex
+  std::vector<uint8_t> is_apex;            // per block
+  std::vector<int32_t> apex_rows;
+  std::vector<double> apex_inv_row, apex_inv_col;
+  std::vector<int64_t> apex_cptr;          // apex rows + 1
+  std::vector<int32_t> apex_cidx;
+  std::vector<int32_t> rel_bwd_level;      // backward level of non-apex blocks below the apex
+  int32_t n_rel_bwd_levels = 0;
 };
 
 struct PairHost {
@@ -78,6 +90,7 @@ struct PairHost {
 struct OrderOptions {
   int32_t leaf_max = 32;                   // nested-dissection leaf size
   int32_t block_max = 96;                  // largest dense diagonal block
+  int32_t apex_max = 1536;                 // largest apex (0: none)
 };
 
 // Each returns an empty string on success, else the reason.
@@ -97,6 +110,10 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
 // Numeric parts of the plan (after a refactor with unchanged structure).
 void fill_dense_inverses(PairHost &p);
 void fill_panels(PairHost &p);
+// Chooses the apex (largest top set of levels within opt.apex_max rows) and
+// builds its structure; fill_apex_inverse computes the dense inverse.
+void build_apex(PairHost &p, const OrderOptions &opt);
+void fill_apex_inverse(PairHost &p);
 
 // Everything above in order.
 std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd);

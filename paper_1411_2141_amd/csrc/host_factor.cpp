@@ -421,6 +421,90 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
   return "";
 }
 
+void build_apex(PairHost &p, const OrderOptions &opt) {
+  SolvePlan &pl = p.plan;
+  const int32_t nb = (int32_t)pl.blocks.size();
+  // rows per forward level; the apex is the highest run of levels that fits
+  std::vector<int64_t> rows_at(pl.n_fwd_levels, 0);
+  for (auto &B : pl.blocks) rows_at[B.fwd_level] += B.r1 - B.r0;
+  int32_t cut = pl.n_fwd_levels;
+  int64_t acc = 0;
+  for (int32_t l = pl.n_fwd_levels - 1; l >= 1 && opt.apex_max > 0; --l) {
+    if (acc + rows_at[l] > opt.apex_max) break;
+    acc += rows_at[l];
+    cut = l;
+  }
+  if (cut > pl.n_fwd_levels - 2) cut = pl.n_fwd_levels;   // fewer than two levels: no apex
+  pl.apex_level = cut;
+  pl.is_apex.assign(nb, 0);
+  pl.apex_rows.clear();
+  for (int32_t s = 0; s < nb; ++s)
+    if (pl.blocks[s].fwd_level >= cut) {
+      pl.is_apex[s] = 1;
+      for (int32_t r = pl.blocks[s].r0; r < pl.blocks[s].r1; ++r) pl.apex_rows.push_back(r);
+    }
+  std::sort(pl.apex_rows.begin(), pl.apex_rows.end());
+  // contributions to apex rows from non-apex blocks only
+  std::vector<int32_t> blk_of_upd(pl.below_idx.size());
+  for (int32_t s = 0; s < nb; ++s)
+    for (int64_t k = pl.below_ptr[s]; k < pl.below_ptr[s + 1]; ++k) blk_of_upd[k] = s;
+  pl.apex_cptr.assign(pl.apex_rows.size() + 1, 0);
+  pl.apex_cidx.clear();
+  for (size_t i = 0; i < pl.apex_rows.size(); ++i) {
+    const int32_t r = pl.apex_rows[i];
+    for (int64_t q = pl.cptr[r]; q < pl.cptr[r + 1]; ++q)
+      if (!pl.is_apex[blk_of_upd[pl.cidx[q]]]) pl.apex_cidx.push_back(pl.cidx[q]);
+    pl.apex_cptr[i + 1] = (int64_t)pl.apex_cidx.size();
+  }
+  // backward levels of the non-apex blocks, counted from the apex down
+  pl.rel_bwd_level.assign(nb, -1);
+  pl.n_rel_bwd_levels = 0;
+  for (int32_t s = nb - 1; s >= 0; --s) {
+    if (pl.is_apex[s]) continue;
+    const int32_t par = pl.blocks[s].parent;
+    pl.rel_bwd_level[s] = (par < 0 || pl.is_apex[par]) ? 0 : pl.rel_bwd_level[par] + 1;
+    pl.n_rel_bwd_levels = std::max(pl.n_rel_bwd_levels, pl.rel_bwd_level[s] + 1);
+  }
+  fill_apex_inverse(p);
+}
+
+void fill_apex_inverse(PairHost &p) {
+  SolvePlan &pl = p.plan;
+  const Factor &L = p.L;
+  const int64_t nt = (int64_t)pl.apex_rows.size();
+  pl.apex_inv_row.assign(nt * (nt + 1) / 2, 0.0);
+  pl.apex_inv_col.assign(nt * (nt + 1) / 2, 0.0);
+  if (nt == 0) return;
+  // sparse L(apex, apex) by columns, in apex positions
+  std::vector<int32_t> pos(L.n, -1);
+  for (int64_t i = 0; i < nt; ++i) pos[pl.apex_rows[i]] = (int32_t)i;
+  std::vector<std::vector<std::pair<int32_t, double>>> col(nt);
+  std::vector<double> diag(nt);
+  for (int64_t j = 0; j < nt; ++j) {
+    const int32_t c = pl.apex_rows[j];
+    diag[j] = L.val[L.colptr[c]];
+    for (int64_t q = L.colptr[c] + 1; q < L.colptr[c + 1]; ++q)
+      if (pos[L.rowidx[q]] >= 0) col[j].emplace_back(pos[L.rowidx[q]], L.val[q]);
+  }
+  // column c of the inverse: forward substitution of e_c (column-oriented)
+  std::vector<double> x(nt);
+  for (int64_t c = 0; c < nt; ++c) {
+    std::fill(x.begin() + c, x.end(), 0.0);
+    x[c] = 1.0;
+    for (int64_t j = c; j < nt; ++j) {
+      if (x[j] == 0.0) continue;
+      x[j] /= diag[j];
+      const double xj = x[j];
+      for (auto &e : col[j]) x[e.first] -= e.second * xj;
+    }
+    const int64_t oc = c * nt - c * (c - 1) / 2;
+    for (int64_t i = c; i < nt; ++i) {
+      pl.apex_inv_col[oc + (i - c)] = x[i];
+      pl.apex_inv_row[i * (i + 1) / 2 + c] = x[i];
+    }
+  }
+}
+
 std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd) {
   *not_spd = false;
   std::string e = validate_mesh(p);
@@ -434,7 +518,10 @@ std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool 
   if (!e.empty()) return e;
   e = cholesky(p, tau, not_spd);
   if (!e.empty()) return e;
-  return build_solve_plan(p, ranges, rparent, opt);
+  e = build_solve_plan(p, ranges, rparent, opt);
+  if (!e.empty()) return e;
+  build_apex(p, opt);
+  return "";
 }
 
 }  // namespace mr

@@ -11,9 +11,10 @@ hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp
                             int H, int W, const double *cp_w, const double *cp_h, hipStream_t s);
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
-hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs, int n_pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
-                         float2 *h, unsigned *flags, hipStream_t s);
+                         float2 *h, unsigned *flags, const double *partials, double *finish_msd,
+                         hipStream_t s);
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
                            double tau, hipStream_t s);
@@ -26,10 +27,20 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
                                   const double *prow, double2 *x, const int32_t *perm,
                                   double2 *out, double2 *partials, unsigned *counters,
                                   hipStream_t s);
-hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
-                           const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
-                           const float *coef, const float *re, float *warped, double *partials,
-                           double *msd, unsigned *flags, hipStream_t s);
+hipError_t launch_apex_fwd(int n_rows, const int32_t *rows, const int64_t *acptr,
+                           const int32_t *acidx, const double2 *upd, const double2 *x,
+                           double2 *tbuf, const int2 *items, int n_items, int lds_bytes,
+                           const ApexDesc *apex, const double *inv_row, double2 *ybuf,
+                           hipStream_t s);
+hipError_t launch_apex_bwd(const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
+                           const double *inv_col, const int32_t *rows, const double2 *ybuf,
+                           double2 *x, const int32_t *perm, double2 *out, hipStream_t s);
+hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
+                                int n_pairs, const double2 *u, const int2 *xy, const int4 *tri,
+                                const int32_t *t6, const float *coef, const float *re,
+                                float *warped, double *partials, unsigned *flags, hipStream_t s);
+hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
+                             double *msd, hipStream_t s);
 hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
                                  hipStream_t s);
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,

@@ -257,13 +257,37 @@ __global__ __launch_bounds__(256) void k_sample_rho(const NodeItem *__restrict__
 // Hot path
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items,
-                                                const DevPair *__restrict__ pairs,
+// Second pass of the MSD, run by one workgroup: per pair, the tile partials
+// summed in tile order by one wavefront (deterministic) over the pixel count.
+__device__ __forceinline__ void msd_finish_block(const DevPair *__restrict__ pairs, int n_pairs,
+                                                 const double *__restrict__ partials,
+                                                 double *__restrict__ msd) {
+  const int lane = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < n_pairs; p += blockDim.x >> 6) {
+    const DevPair Q = pairs[p];
+    double s = 0.0;
+    for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
+    s = wave_sum(s);
+    if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
+  }
+}
+
+
+// Node sampling.  When `finish_msd` is set, one extra workgroup (the last)
+// completes the MSD of the previous warp instead (saves a launch per iteration).
+__global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items, int n_items,
+                                                const DevPair *__restrict__ pairs, int n_pairs,
                                                 const double2 *__restrict__ u,
                                                 const int2 *__restrict__ xy,
                                                 const float *__restrict__ coef,
                                                 const float *__restrict__ rho,
-                                                float2 *__restrict__ h, unsigned *flags) {
+                                                float2 *__restrict__ h, unsigned *flags,
+                                                const double *__restrict__ partials,
+                                                double *__restrict__ finish_msd) {
+  if ((int)blockIdx.x == n_items) {
+    msd_finish_block(pairs, n_pairs, partials, finish_msd);
+    return;
+  }
   const NodeItem it = items[blockIdx.x];
   const int i = it.begin + threadIdx.x;
   if (i >= it.end) return;
@@ -272,7 +296,8 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
   const int2 v = xy[i];
   int cx, cy;
   float fx, fy;
-  const bool ok = split_coord(v.x, ui.x - 0.5, cx, fx) & split_coord(v.y, ui.y - 0.5, cy, fy);
+  const bool okx = split_coord(v.x, ui.x - 0.5, cx, fx);
+  const bool ok = split_coord(v.y, ui.y - 0.5, cy, fy) && okx;
   if (!ok) atomicOr(flags, kFlagNonFiniteNode);
   float val, gx, gy;
   spline_value_grad(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy, val, gx, gy);
@@ -550,6 +575,107 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
   }
 }
 
+// Apex of the forward solve, step 1: t = b - (update entries of the non-apex
+// blocks) for every apex row of every pair (thread per row, global list).
+__global__ __launch_bounds__(256) void k_apex_rhs(int n_rows, const int32_t *__restrict__ rows,
+                                                  const int64_t *__restrict__ acptr,
+                                                  const int32_t *__restrict__ acidx,
+                                                  const double2 *__restrict__ upd,
+                                                  const double2 *__restrict__ x,
+                                                  double2 *__restrict__ tbuf) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_rows) return;
+  const int64_t q1 = acptr[g + 1];
+  double ax = 0.0, ay = 0.0;
+  constexpr int U = 8;
+  for (int64_t q = acptr[g]; q < q1; q += U) {
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) idx[u] = q + u < q1 ? acidx[q + u] : -1;
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = idx[u] >= 0 ? upd[idx[u]] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ax += v[u].x;
+      ay += v[u].y;
+    }
+  }
+  const double2 bb = x[rows[g]];
+  tbuf[g] = make_double2(bb.x - ax, bb.y - ay);
+}
+
+// Apex of the forward solve, step 2: y = L(apex, apex)^-1 t, one wavefront per
+// row over the row-major packed inverse (t staged in LDS).  Work item =
+// (pair, first row).
+__global__ __launch_bounds__(256) void k_apex_fwd(const int2 *__restrict__ items,
+                                                  const ApexDesc *__restrict__ apex,
+                                                  const double *__restrict__ inv_row,
+                                                  const double2 *__restrict__ tbuf,
+                                                  double2 *__restrict__ ybuf) {
+  extern __shared__ double smem[];
+  double2 *tl = reinterpret_cast<double2 *>(smem);
+  const int2 it = items[blockIdx.x];
+  const ApexDesc A = apex[it.x];
+  const int last = min(A.n - 1, it.y + kApexRowsPerGroup - 1);
+  for (int j = threadIdx.x; j <= last; j += blockDim.x) tl[j] = tbuf[A.rows_off + j];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int i = it.y + (threadIdx.x >> 6);
+  if (i > last) return;
+  const double *row = inv_row + A.inv_off + (int64_t)i * (i + 1) / 2;
+  double ax = 0.0, ay = 0.0;
+#pragma unroll 8
+  for (int j = lane; j <= i; j += 64) {
+    const double v = row[j];
+    ax += v * tl[j].x;
+    ay += v * tl[j].y;
+  }
+  ax = wave_sum(ax);
+  ay = wave_sum(ay);
+  if (lane == 0) ybuf[A.rows_off + i] = make_double2(ax, ay);
+}
+
+// Apex of the backward solve: z = L(apex, apex)^-T y, one wavefront per
+// column over the column-major packed inverse (y staged in LDS); z goes to x
+// and, when `out` is given, to natural node order.  Work item = (pair, first
+// column).
+__global__ __launch_bounds__(256) void k_apex_bwd(const int2 *__restrict__ items,
+                                                  const ApexDesc *__restrict__ apex,
+                                                  const double *__restrict__ inv_col,
+                                                  const int32_t *__restrict__ rows,
+                                                  const double2 *__restrict__ ybuf, double2 *x,
+                                                  const int32_t *__restrict__ perm,
+                                                  double2 *__restrict__ out) {
+  extern __shared__ double smem[];
+  double2 *yl = reinterpret_cast<double2 *>(smem);
+  const int2 it = items[blockIdx.x];
+  const ApexDesc A = apex[it.x];
+  const int first = it.y;
+  for (int i = first + (int)threadIdx.x; i < A.n; i += blockDim.x) yl[i - first] = ybuf[A.rows_off + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int j = first + (threadIdx.x >> 6);
+  if (j >= A.n) return;
+  const int64_t n = A.n;
+  const double *col = inv_col + A.inv_off + (int64_t)j * n - (int64_t)j * (j - 1) / 2 - j;
+  double zx = 0.0, zy = 0.0;
+#pragma unroll 8
+  for (int i = j + lane; i < A.n; i += 64) {
+    const double v = col[i];
+    zx += v * yl[i - first].x;
+    zy += v * yl[i - first].y;
+  }
+  zx = wave_sum(zx);
+  zy = wave_sum(zy);
+  if (lane == 0) {
+    const double2 z = make_double2(zx, zy);
+    const int row = rows[A.rows_off + j];
+    x[row] = z;
+    if (out) out[perm[row]] = z;
+  }
+}
+
 // Warp + MSD over kTile x kTile pixel tiles.  Each workgroup writes its FP64
 // partial sum; the last workgroup to finish sums every pair's partials in a
 // fixed order (deterministic) and resets the counter for the next launch.
@@ -580,7 +706,8 @@ __global__ __launch_bounds__(256) void k_warp_msd(
     const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
     int qx, qy;
     double fx, fy;
-    const bool ok = split_coord_d(j, dx, qx, fx) & split_coord_d(i, dy, qy, fy);
+    const bool okx = split_coord_d(j, dx, qx, fx);
+    const bool ok = split_coord_d(i, dy, qy, fy) && okx;
     if (!ok) atomicOr(flags, kFlagNonFinitePixel);
     const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
     if (warped) warped[pix] = (float)w;
@@ -595,20 +722,10 @@ __global__ __launch_bounds__(256) void k_warp_msd(
   if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Second pass of the MSD: per pair, the tile partials summed in tile order by
-// one wavefront (deterministic), divided by the pixel count.
 __global__ __launch_bounds__(256) void k_msd_finish(const DevPair *__restrict__ pairs, int n_pairs,
                                                     const double *__restrict__ partials,
                                                     double *__restrict__ msd) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  for (int p = wave; p < n_pairs; p += gridDim.x * 4) {
-    const DevPair Q = pairs[p];
-    double s = 0.0;
-    for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
-    s = wave_sum(s);
-    if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
-  }
+  msd_finish_block(pairs, n_pairs, partials, msd);
 }
 
 // Gather / scatter between the natural node order and the solve order.
@@ -646,10 +763,12 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
   return hipGetLastError();
 }
 
-hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs, int n_pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
-                         float2 *h, unsigned *flags, hipStream_t s) {
-  k_sample<<<n_items, kNodeChunk, 0, s>>>(items, pairs, u, xy, coef, rho, h, flags);
+                         float2 *h, unsigned *flags, const double *partials, double *finish_msd,
+                         hipStream_t s) {
+  k_sample<<<n_items + (finish_msd ? 1 : 0), kNodeChunk, 0, s>>>(
+      items, n_items, pairs, n_pairs, u, xy, coef, rho, h, flags, partials, finish_msd);
   return hipGetLastError();
 }
 
@@ -679,13 +798,38 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   return hipGetLastError();
 }
 
-hipError_t launch_warp_msd(const TileItem *tiles, int n_tiles, const DevPair *pairs, int n_pairs,
-                           const double2 *u, const int2 *xy, const int4 *tri, const int32_t *t6,
-                           const float *coef, const float *re, float *warped, double *partials,
-                           double *msd, unsigned *flags, hipStream_t s) {
+hipError_t launch_apex_fwd(int n_rows, const int32_t *rows, const int64_t *acptr,
+                           const int32_t *acidx, const double2 *upd, const double2 *x,
+                           double2 *tbuf, const int2 *items, int n_items, int lds_bytes,
+                           const ApexDesc *apex, const double *inv_row, double2 *ybuf,
+                           hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  k_apex_rhs<<<(n_rows + 255) / 256, 256, 0, s>>>(n_rows, rows, acptr, acidx, upd, x, tbuf);
+  k_apex_fwd<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, inv_row, tbuf, ybuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_apex_bwd(const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
+                           const double *inv_col, const int32_t *rows, const double2 *ybuf,
+                           double2 *x, const int32_t *perm, double2 *out, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  k_apex_bwd<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, inv_col, rows, ybuf,
+                                                                x, perm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
+                                int n_pairs, const double2 *u, const int2 *xy, const int4 *tri,
+                                const int32_t *t6, const float *coef, const float *re,
+                                float *warped, double *partials, unsigned *flags, hipStream_t s) {
   k_warp_msd<<<n_tiles, kTile * kTile, 0, s>>>(tiles, pairs, n_pairs, u, xy, tri, t6, coef, re,
                                                warped, partials, flags);
-  k_msd_finish<<<std::min((n_pairs + 3) / 4, 64), 256, 0, s>>>(pairs, n_pairs, partials, msd);
+  return hipGetLastError();
+}
+
+hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
+                             double *msd, hipStream_t s) {
+  k_msd_finish<<<1, 256, 0, s>>>(pairs, n_pairs, partials, msd);
   return hipGetLastError();
 }
 
