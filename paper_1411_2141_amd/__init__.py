@@ -11,5 +11,7 @@ from .binding import MeshRegError, load_library
 load_library()
 
 from .registration import MeshReg  # noqa: E402
+from .autograd import MeshRegUnrolled, unrolled_msd  # noqa: E402
 
-__all__ = ["binding", "MeshReg", "MeshRegError", "load_library"]
+__all__ = ["binding", "MeshReg", "MeshRegError", "MeshRegUnrolled", "load_library",
+           "unrolled_msd"]

@@ -1,0 +1,68 @@
+"""``torch.autograd.Function`` around the library's unrolled registration.
+
+``msd = MeshRegUnrolled.apply(reg, u0, alpha, te, n_iter, ckpt_every)`` runs
+``n_iter`` iterations from ``u0`` on every pair of ``reg`` and returns the
+per-pair MSD of the final warp.  Its backward calls the library's adjoint
+(``mesh_reg_backward``), which recomputes the iterates from checkpoints every
+``ckpt_every`` iterations and reuses each pair's Cholesky factor, and returns
+the gradients with respect to ``u0`` (``[sum n][2]`` FP64), ``alpha``
+(``[n_pairs]`` FP64) and ``te`` (``[sum H*W]`` FP32, pair-major).
+
+``alpha`` and ``te`` are pushed into the library before the forward pass
+(``mesh_reg_set_alpha`` re-factorises a pair whose alpha changed;
+``mesh_reg_set_template`` re-computes the spline coefficients), so they must
+not be changed between a forward and its backward.
+"""
+from __future__ import annotations
+
+import torch
+
+from .registration import MeshReg
+
+
+def push_parameters(reg: MeshReg, alpha: torch.Tensor | None, te: torch.Tensor | None) -> None:
+    if alpha is not None:
+        vals = alpha.detach().to("cpu", torch.float64).tolist()
+        cache = getattr(reg, "_alpha_cache", [None] * reg.n_pairs)
+        for p, a in enumerate(vals):
+            if cache[p] != a:
+                reg.set_alpha(p, a)
+                cache[p] = a
+        reg._alpha_cache = cache
+    if te is not None:
+        flat = te.detach().to(device=reg.device, dtype=torch.float32).contiguous().view(-1)
+        for p in range(reg.n_pairs):
+            reg.set_template(p, reg.pixel_slice(flat, p).contiguous())
+
+
+class MeshRegUnrolled(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, reg: MeshReg, u0, alpha, te, n_iter: int, ckpt_every: int = 10):
+        push_parameters(reg, alpha, te)
+        u = u0.detach().to(torch.float64).contiguous().clone()
+        reg.step(u, n_iter)
+        msd = reg.warp_msd(u)
+        ctx.reg = reg
+        ctx.n_iter = int(n_iter)
+        ctx.ckpt_every = int(ckpt_every)
+        ctx.alpha_meta = (alpha.device, alpha.dtype) if alpha is not None else None
+        ctx.te_meta = (te.device, te.dtype, te.shape) if te is not None else None
+        ctx.save_for_backward(u0.detach().to(torch.float64).contiguous())
+        return msd
+
+    @staticmethod
+    def backward(ctx, grad_msd):
+        (u0,) = ctx.saved_tensors
+        g = grad_msd.detach().to(device=u0.device, dtype=torch.float64).contiguous()
+        _, g_u0, g_alpha, g_te = ctx.reg.backward(u0, ctx.n_iter, ctx.ckpt_every, g_msd=g)
+        ga = gt = None
+        if ctx.alpha_meta is not None:
+            ga = g_alpha.to(device=ctx.alpha_meta[0], dtype=ctx.alpha_meta[1])
+        if ctx.te_meta is not None:
+            gt = g_te.to(device=ctx.te_meta[0], dtype=ctx.te_meta[1]).view(ctx.te_meta[2])
+        return None, g_u0, ga, gt, None, None
+
+
+def unrolled_msd(reg: MeshReg, u0, alpha=None, te=None, n_iter: int = 10, ckpt_every: int = 10):
+    """Convenience wrapper of ``MeshRegUnrolled.apply``."""
+    return MeshRegUnrolled.apply(reg, u0, alpha, te, n_iter, ckpt_every)

@@ -1,10 +1,368 @@
-// Reverse mode of the unrolled registration (gradient of the final MSD).
+// Reverse mode of the unrolled registration: gradient of
+//   L = sum_p g_msd[p] * MSD_p(u^N)
+// with respect to the initial displacements, each pair's alpha and the
+// template intensities (the objective of eq. 1 unrolled by Algorithm 1 in its
+// semi-implicit form).  With S = I + tau alpha K, u^{k+1} = S^-1 b^k and
+// b^k = u^k - tau (M h(u^k)) / m, h_i = r_i g_i:
+//
+//   warp:   lambda^N_v += (2 g/P) e_p w_v(p) grad s(q_p),  cbar += (2 g/P) e_p beta(x) beta(y)
+//   step k: mu = S^-1 lambda^{k+1}                        (same factor, same kernels)
+//           gbar_alpha -= tau mu^T K u^{k+1}
+//           eta = -tau M (mu / m)                        (-tau mu in the nodal mode)
+//           lambda^k_i = mu_i + (g_i . eta_i) g_i + r_i H_i eta_i
+//           cbar += (eta_i . g_i) beta beta + r_i (eta_x beta' beta + eta_y beta beta')
+//   end:    gbar_Te = B^-1 cbar                           (the prefilter is symmetric)
+//
+// The iterates are recomputed from checkpoints every `ckpt_every` iterations
+// with the forward kernels, so they equal the forward pass bit for bit.  The
+// adjoint arithmetic is FP64; the scatters into lambda^N and cbar use FP64
+// atomic adds (their summation order is not fixed).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
 
 #include "../../include/meshreg.h"
 #include "ctx.h"
+#include "kernels.h"
+#include "spline.h"
 
-int mr_ctx::backward(const double *, int32_t, int32_t, const double *, double *, double *, float *,
-                     double *, hipStream_t) {
-  return MR_ESTATE;
+namespace mr {
+
+// FP64 spline value and gradient with FP32 coefficients.
+__device__ __forceinline__ void spline_vg_d(const float *__restrict__ c, int H, int W, int cx,
+                                            double fx, int cy, double fy, double &val, double &gx,
+                                            double &gy) {
+  double wx[4], dx[4], wy[4], dy[4];
+  bs_weights_d(fx, wx);
+  bs_deriv_d(fx, dx);
+  bs_weights_d(fy, wy);
+  bs_deriv_d(fy, dy);
+  Taps tp;
+  make_taps(c, H, W, cx, cy, tp);
+  val = gx = gy = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float *r = tp.row[m];
+    double rv = 0.0, rd = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const double cv = (double)r[tp.col[n]];
+      rv += cv * wx[n];
+      rd += cv * dx[n];
+    }
+    val += wy[m] * rv;
+    gx += wy[m] * rd;
+    gy += dy[m] * rv;
+  }
+}
+
+// Adds cv beta(x) beta(y) + cgx beta'(x) beta(y) + cgy beta(x) beta'(y) to the
+// 16 taps of the point in cbar (one pair's [H][W] FP64 array).
+__device__ __forceinline__ void scatter_taps(double *__restrict__ cbar, int H, int W, int cx,
+                                             double fx, int cy, double fy, double cv, double cgx,
+                                             double cgy) {
+  double wx[4], dx[4], wy[4], dy[4];
+  bs_weights_d(fx, wx);
+  bs_deriv_d(fx, dx);
+  bs_weights_d(fy, wy);
+  bs_deriv_d(fy, dy);
+  int col[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) col[n] = fold_index(cx - 1 + n, W);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double *row = cbar + (size_t)fold_index(cy - 1 + m, H) * W;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const double v = cv * wy[m] * wx[n] + cgx * wy[m] * dx[n] + cgy * dy[m] * wx[n];
+      unsafeAtomicAdd(row + col[n], v);
+    }
+  }
+}
+
+// Warp adjoint (and the forward MSD partials of the same pixels).
+__global__ __launch_bounds__(256) void k_warp_adjoint(
+    const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs,
+    const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
+    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
+    const double *__restrict__ g_msd, double2 *lam, double *cbar, double *__restrict__ partials) {
+  const TileItem it = tiles[blockIdx.x];
+  const DevPair P = pairs[it.pair];
+  const int i = it.y0 + (int)(threadIdx.x / kTile);
+  const int j = it.x0 + (int)(threadIdx.x % kTile);
+  double acc = 0.0;
+  if (i < P.height && j < P.width) {
+    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
+    const int4 nd = tri[P.tri_off + t6[pix]];
+    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
+    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
+    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+    const double inv = 1.0 / (ca + cb + cc);
+    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
+    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
+    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
+    int qx, qy;
+    double fx, fy;
+    split_coord_d(j, dx, qx, fx);
+    split_coord_d(i, dy, qy, fy);
+    const float *cp = coef + P.pix_off;
+    double val, gx, gy;
+    spline_vg_d(cp, P.height, P.width, qx, fx, qy, fy, val, gx, gy);
+    const double e = val - (double)re[pix];
+    acc = e * e;
+    const double s = 2.0 * g_msd[it.pair] / ((double)P.height * (double)P.width) * e;
+    unsafeAtomicAdd(&lam[nd.x].x, s * wa * gx);
+    unsafeAtomicAdd(&lam[nd.x].y, s * wa * gy);
+    unsafeAtomicAdd(&lam[nd.y].x, s * wb * gx);
+    unsafeAtomicAdd(&lam[nd.y].y, s * wb * gy);
+    unsafeAtomicAdd(&lam[nd.z].x, s * wc * gx);
+    unsafeAtomicAdd(&lam[nd.z].y, s * wc * gy);
+    scatter_taps(cbar + P.pix_off, P.height, P.width, qx, fx, qy, fy, s, 0.0, 0.0);
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Per node: (K u^{k+1})_i . mu_i accumulated into the node item's alpha partial
+// (fixed order), and eta_i = -tau (M (mu / m))_i.
+__global__ __launch_bounds__(256) void k_adjoint_alpha_eta(
+    const NodeItem *__restrict__ items, const int32_t *__restrict__ kptr,
+    const int32_t *__restrict__ kcol, const double *__restrict__ kval,
+    const double *__restrict__ mwt_t, const double2 *__restrict__ mu,
+    const double2 *__restrict__ u1, double2 *__restrict__ eta, double *__restrict__ alpha_part,
+    double tau, int nodal) {
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + threadIdx.x;
+  double da = 0.0;
+  if (i < it.end) {
+    double kx = 0.0, ky = 0.0, ex = 0.0, ey = 0.0;
+    for (int q = kptr[i]; q < kptr[i + 1]; ++q) {
+      const int jn = kcol[q];
+      const double2 uj = u1[jn];
+      kx += kval[q] * uj.x;
+      ky += kval[q] * uj.y;
+      if (!nodal) {
+        const double2 mj = mu[jn];
+        ex += mwt_t[q] * mj.x;
+        ey += mwt_t[q] * mj.y;
+      }
+    }
+    const double2 mi = mu[i];
+    da = mi.x * kx + mi.y * ky;
+    eta[i] = nodal ? make_double2(-tau * mi.x, -tau * mi.y) : make_double2(-tau * ex, -tau * ey);
+  }
+  __shared__ double red[4];
+  da = wave_sum(da);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = da;
+  __syncthreads();
+  if (threadIdx.x == 0) alpha_part[blockIdx.x] += -tau * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// Per node at u^k: lambda^k = mu + (g . eta) g + r H eta, and the coefficient
+// adjoint of the force density scattered into cbar.
+__global__ __launch_bounds__(256) void k_node_adjoint(
+    const NodeItem *__restrict__ items, const DevPair *__restrict__ pairs,
+    const double2 *__restrict__ u, const int2 *__restrict__ xy, const float *__restrict__ coef,
+    const float *__restrict__ rho, const double2 *__restrict__ mu,
+    const double2 *__restrict__ eta, double2 *__restrict__ lam, double *cbar) {
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + threadIdx.x;
+  if (i >= it.end) return;
+  const DevPair P = pairs[it.pair];
+  const double2 ui = u[i];
+  const int2 v = xy[i];
+  int cx, cy;
+  double fx, fy;
+  split_coord_d(v.x, ui.x - 0.5, cx, fx);
+  split_coord_d(v.y, ui.y - 0.5, cy, fy);
+  double wx[4], dx[4], ex[4], wy[4], dy[4], ey[4];
+  bs_weights_d(fx, wx);
+  bs_deriv_d(fx, dx);
+  bs_deriv2_d(fx, ex);
+  bs_weights_d(fy, wy);
+  bs_deriv_d(fy, dy);
+  bs_deriv2_d(fy, ey);
+  const float *c = coef + P.pix_off;
+  Taps tp;
+  make_taps(c, P.height, P.width, cx, cy, tp);
+  double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float *r = tp.row[m];
+    double rv = 0.0, rd = 0.0, re2 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const double cv = (double)r[tp.col[n]];
+      rv += cv * wx[n];
+      rd += cv * dx[n];
+      re2 += cv * ex[n];
+    }
+    val += wy[m] * rv;
+    gx += wy[m] * rd;
+    gy += dy[m] * rv;
+    hxx += wy[m] * re2;
+    hxy += dy[m] * rd;
+    hyy += ey[m] * rv;
+  }
+  const double r = val - (double)rho[i];
+  const double2 et = eta[i];
+  const double ge = gx * et.x + gy * et.y;
+  const double2 mi = mu[i];
+  lam[i] = make_double2(mi.x + ge * gx + r * (hxx * et.x + hxy * et.y),
+                        mi.y + ge * gy + r * (hxy * et.x + hyy * et.y));
+  scatter_taps(cbar + P.pix_off, P.height, P.width, cx, fx, cy, fy, ge, r * et.x, r * et.y);
+}
+
+// Per pair: the alpha partials of its node items summed in item order.
+__global__ void k_alpha_finish(const DevPair *__restrict__ pairs, int n_pairs,
+                               const double *__restrict__ alpha_part, double *__restrict__ g_alpha) {
+  const int lane = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < n_pairs; p += blockDim.x >> 6) {
+    const DevPair Q = pairs[p];
+    double s = 0.0;
+    for (int k = lane; k < Q.n_items; k += 64) s += alpha_part[Q.item_off + k];
+    s = wave_sum(s);
+    if (lane == 0) g_alpha[p] = s;
+  }
+}
+
+}  // namespace mr
+
+using namespace mr;
+
+static int bfail(int code, const std::string &msg) { return mr_set_error(code, msg); }
+
+#define HIP_OK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return bfail(MR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
+                     double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s) {
+  if (!u0 || !g_msd || n_iter < 0 || ckpt_every < 1 || ((uintptr_t)u0 & 15) ||
+      (g_u0 && ((uintptr_t)g_u0 & 15)))
+    return bfail(MR_EINVAL, "backward: need aligned u0, g_msd, n_iter >= 0, ckpt_every >= 1");
+  int rc = check_flags();
+  if (rc) return rc;
+  const int64_t N = n_nodes;
+  const int n_ck = n_iter / ckpt_every + 1;
+  const size_t nb = sizeof(double2) * (size_t)N;
+  if ((int64_t)d_ck.count < (int64_t)n_ck * N) HIP_OK(d_ck.alloc((size_t)n_ck * N));
+  if ((int64_t)d_seg.count < (int64_t)(ckpt_every + 1) * N) HIP_OK(d_seg.alloc((size_t)(ckpt_every + 1) * N));
+  if ((int64_t)d_lam.count < N) {
+    HIP_OK(d_lam.alloc(N));
+    HIP_OK(d_mu.alloc(N));
+    HIP_OK(d_eta.alloc(N));
+  }
+  if ((int64_t)d_cbar.count < n_pix) HIP_OK(d_cbar.alloc(n_pix));
+  if ((int)d_alpha_part.count < n_node_items) HIP_OK(d_alpha_part.alloc(n_node_items));
+  if (!d_kptr.ptr) {
+    rc = upload_adjoint_operators(s);
+    if (rc) return rc;
+  }
+  double2 *ck = d_ck.ptr, *seg = d_seg.ptr;
+  // forward with checkpoints
+  HIP_OK(hipMemcpyAsync(ck, u0, nb, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemcpyAsync(seg, u0, nb, hipMemcpyDeviceToDevice, s));
+  double *pending = nullptr;
+  for (int k = 0; k < n_iter; ++k) {
+    HIP_OK(iterate(seg, nullptr, &pending, s));
+    if ((k + 1) % ckpt_every == 0 && (k + 1) < n_iter)
+      HIP_OK(hipMemcpyAsync(ck + (size_t)((k + 1) / ckpt_every) * N, seg, nb,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  // warp adjoint at u^N (seg[0] holds it)
+  HIP_OK(hipMemsetAsync(d_lam.ptr, 0, nb, s));
+  HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
+  HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
+  timed_begin(MR_KF_WARP, s);
+  k_warp_adjoint<<<n_tiles, kTile * kTile, 0, s>>>(d_tiles.ptr, d_pairs.ptr, seg, d_xy.ptr,
+                                                   d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
+                                                   g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr);
+  HIP_OK(hipGetLastError());
+  timed_end(s);
+  if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));
+  // reverse sweep, one checkpoint segment at a time
+  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  for (int sg = n_seg - 1; sg >= 0; --sg) {
+    const int k0 = sg * ckpt_every, k1 = std::min(n_iter, k0 + ckpt_every);
+    HIP_OK(hipMemcpyAsync(seg, ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s));
+    for (int k = k0; k < k1; ++k) {
+      double2 *dst = seg + (size_t)(k - k0 + 1) * N;
+      HIP_OK(hipMemcpyAsync(dst, seg + (size_t)(k - k0) * N, nb, hipMemcpyDeviceToDevice, s));
+      HIP_OK(iterate(dst, nullptr, &pending, s));
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double2 *uk = seg + (size_t)(k - k0) * N, *uk1 = seg + (size_t)(k - k0 + 1) * N;
+      // mu = S^-1 lambda^{k+1}
+      HIP_OK(launch_to_solve_order((int)N, d_lam.ptr, d_iperm.ptr, d_x.ptr, s));
+      HIP_OK(solve(d_x.ptr, d_mu.ptr, s));
+      timed_begin(MR_KF_ASSEMBLE, s);
+      k_adjoint_alpha_eta<<<n_node_items, kNodeChunk, 0, s>>>(
+          d_node_items.ptr, d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, d_mu.ptr, uk1,
+          d_eta.ptr, d_alpha_part.ptr, params.tau, params.force_mode == MR_FORCE_NODAL ? 1 : 0);
+      HIP_OK(hipGetLastError());
+      timed_end(s);
+      timed_begin(MR_KF_SAMPLE, s);
+      k_node_adjoint<<<n_node_items, kNodeChunk, 0, s>>>(d_node_items.ptr, d_pairs.ptr, uk,
+                                                         d_xy.ptr, d_coef.ptr, d_rho.ptr,
+                                                         d_mu.ptr, d_eta.ptr, d_lam.ptr,
+                                                         d_cbar.ptr);
+      HIP_OK(hipGetLastError());
+      timed_end(s);
+    }
+  }
+  if (g_u0) HIP_OK(hipMemcpyAsync(g_u0, d_lam.ptr, nb, hipMemcpyDeviceToDevice, s));
+  if (g_alpha) {
+    k_alpha_finish<<<1, 256, 0, s>>>(d_pairs.ptr, n_pairs, d_alpha_part.ptr, g_alpha);
+    HIP_OK(hipGetLastError());
+  }
+  if (g_te)
+    for (int p = 0; p < n_pairs; ++p) {
+      rc = prefilter_pair_d(p, d_cbar.ptr + dpairs[p].pix_off, g_te + dpairs[p].pix_off, s);
+      if (rc) return rc;
+    }
+  post_flags(s);
+  return MR_OK;
+}
+
+// Stiffness rows (FP64) and the column-normalised mass M_ij / m_j on the
+// operator pattern, for the adjoint kernels.
+int mr_ctx::upload_adjoint_operators(hipStream_t s) {
+  std::vector<int32_t> kptr(n_nodes + 1, 0), kcol;
+  std::vector<double> kval, mwt_t;
+  for (int p = 0; p < n_pairs; ++p) {
+    const PairHost &h = host[p];
+    const int32_t no = dpairs[p].node_off;
+    for (int i = 0; i < h.n; ++i) {
+      for (int64_t q = h.tab.t3_ptr[i]; q < h.tab.t3_ptr[i + 1]; ++q) {
+        const int32_t jn = (int32_t)h.tab.t3_idx[q];
+        kcol.push_back(no + jn);
+        kval.push_back(h.kval[q]);
+        mwt_t.push_back((double)h.mval[q] / (4.0 * (double)h.tab.t5[jn]));
+      }
+      kptr[no + i + 1] = (int32_t)kcol.size();
+    }
+  }
+  auto put = [&](auto &dst, const auto &v) -> hipError_t {
+    hipError_t e = dst.alloc(v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(dst.ptr, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s);
+  };
+  HIP_OK(put(d_kptr, kptr));
+  HIP_OK(put(d_kcol, kcol));
+  HIP_OK(put(d_kval, kval));
+  HIP_OK(put(d_mwt_t, mwt_t));
+  HIP_OK(hipStreamSynchronize(s));
+  return MR_OK;
 }

@@ -20,10 +20,12 @@ using namespace mr;
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const std::string &msg) {
+int mr_set_error(int code, const std::string &msg) {
   g_last_error = msg;
   return code;
 }
+
+static int fail(int code, const std::string &msg) { return mr_set_error(code, msg); }
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -208,8 +210,10 @@ int mr_ctx::upload_all(hipStream_t s) {
     d.pad0 = 0;
     for (int y = 0; y < ty; ++y)
       for (int x = 0; x < d.tiles_x; ++x) tiles.push_back({p, y * kTile, x * kTile, 0});
+    d.item_off = (int32_t)items.size();
     for (int b = 0; b < h.n; b += kNodeChunk)
       items.push_back({p, d.node_off + b, d.node_off + std::min(h.n, b + kNodeChunk), 0});
+    d.n_items = (int32_t)items.size() - d.item_off;
     n_nodes += h.n;
     n_tris += h.nt;
     n_pix += (int64_t)h.height * h.width;
@@ -435,16 +439,25 @@ int64_t mr_ctx::device_bytes() const {
                    d_msd_tmp.bytes() + d_flags.bytes());
 }
 
-// B-spline coefficients of one pair's image (FP32 device input).
-int mr_ctx::prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s) {
-  const DevPair &d = dpairs[p];
+// B-spline coefficients (B^-1 along rows, then columns) of one pair's FP32 or
+// FP64 image; B is symmetric, so the same map is its own adjoint.
+static int prefilter_any(const DevPair &d, const float *img_f, const double *img_d,
+                         float *coef_out, hipStream_t s) {
   DevArray<double> tmp, cpw, cph;
   HIP_TRY(tmp.alloc((size_t)d.height * d.width));
   HIP_TRY(upload(cpw, thomas_cp(d.width), s));
   HIP_TRY(upload(cph, thomas_cp(d.height), s));
-  HIP_TRY(launch_prefilter(img, nullptr, tmp.ptr, coef_out, d.height, d.width, cpw.ptr, cph.ptr, s));
+  HIP_TRY(launch_prefilter(img_f, img_d, tmp.ptr, coef_out, d.height, d.width, cpw.ptr, cph.ptr, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MR_OK;
+}
+
+int mr_ctx::prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s) {
+  return prefilter_any(dpairs[p], img, nullptr, coef_out, s);
+}
+
+int mr_ctx::prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s) {
+  return prefilter_any(dpairs[p], nullptr, img, coef_out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -487,6 +500,7 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   c->host_only = host_only;
   c->host.resize(n_pairs);
   OrderOptions opt;
+  if (const char *env = std::getenv("MESHREG_APEX_MAX")) opt.apex_max = std::max(0, std::atoi(env));
   for (int p = 0; p < n_pairs; ++p) {
     const mr_pair &q = pairs[p];
     PairHost &h = c->host[p];

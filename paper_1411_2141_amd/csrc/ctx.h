@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "../../include/meshreg.h"
@@ -89,6 +90,11 @@ struct mr_ctx {
   mr::DevArray<unsigned> d_flags;
   unsigned *host_flags = nullptr;            // pinned copy of d_flags
 
+  // adjoint (allocated by the first backward call)
+  mr::DevArray<double2> d_ck, d_seg, d_lam, d_mu, d_eta;
+  mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
+  mr::DevArray<int32_t> d_kptr, d_kcol;
+
   bool timing = false;
   std::vector<mr::TimedLaunch> pending;
 
@@ -96,6 +102,8 @@ struct mr_ctx {
   int upload_all(hipStream_t s);
   int upload_factor(int pair, hipStream_t s);
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
+  int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
+  int upload_adjoint_operators(hipStream_t s);
   hipError_t sample(const double2 *u, double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
   hipError_t solve(double2 *x, double2 *out, hipStream_t s);
@@ -113,3 +121,6 @@ struct mr_ctx {
 namespace mr {
 using Ctx = ::mr_ctx;
 }
+
+// Records the thread-local last-error text; returns `code`.
+int mr_set_error(int code, const std::string &msg);

@@ -22,7 +22,9 @@ struct DevPair {
   int32_t node_off, n;    // nodes [node_off, node_off + n) of the packed node arrays
   int32_t tri_off, nt;
   int32_t tile_off, n_tiles;   // warp tiles [tile_off, tile_off + n_tiles)
-  int32_t tiles_x, pad0;
+  int32_t tiles_x;
+  int32_t item_off, n_items;   // node work items [item_off, item_off + n_items)
+  int32_t pad0;
 };
 
 struct DevBlock {

@@ -90,7 +90,7 @@ struct PairHost {
 struct OrderOptions {
   int32_t leaf_max = 32;                   // nested-dissection leaf size
   int32_t block_max = 96;                  // largest dense diagonal block
-  int32_t apex_max = 1536;                 // largest apex (0: none)
+  int32_t apex_max = 4000;                 // largest apex (0: none); its t/y vectors fit 64 KB of LDS
 };
 
 // Each returns an empty string on success, else the reason.

@@ -358,10 +358,16 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
     pl.n_fwd_levels = std::max(pl.n_fwd_levels, B.fwd_level + 1);
     pl.n_bwd_levels = std::max(pl.n_bwd_levels, B.bwd_level + 1);
   }
-  // dense storage
+  // blocks in forward-level order: dense inverses, panels and update entries
+  // of one level are stored contiguously
+  std::vector<int32_t> lorder(nb);
+  for (int32_t s = 0; s < nb; ++s) lorder[s] = s;
+  std::stable_sort(lorder.begin(), lorder.end(), [&](int32_t a, int32_t b) {
+    return pl.blocks[a].fwd_level < pl.blocks[b].fwd_level;
+  });
   pl.dense_off.assign(nb, 0);
   int64_t tot = 0;
-  for (int32_t s = 0; s < nb; ++s) {
+  for (int32_t s : lorder) {
     const int64_t b = pl.blocks[s].r1 - pl.blocks[s].r0;
     pl.dense_off[s] = tot;
     tot += b * (b + 1) / 2;
@@ -391,7 +397,7 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
   pl.max_below = 0;
   pl.panel_off.assign(nb, 0);
   int64_t ptot = 0;
-  for (int32_t s = 0; s < nb; ++s) {
+  for (int32_t s : lorder) {
     const int64_t m = pl.below_ptr[s + 1] - pl.below_ptr[s];
     pl.max_below = std::max<int32_t>(pl.max_below, (int32_t)m);
     pl.panel_off[s] = ptot;

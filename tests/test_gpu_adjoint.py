@@ -1,0 +1,180 @@
+"""GPU parity of the reverse mode (gradient of the final MSD with respect to
+u0, alpha and the template) against the FP64 oracle's adjoint, whose own
+correctness is pinned by central finite differences in the CPU tests.
+
+Tolerance: normwise relative 1e-4 (the forward trajectory the GPU
+differentiates is computed with FP32 samples; the adjoint itself is FP64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as oadj, registration as reg
+from synth import make_pair, uniform_mesh
+from tests._problems import small_pair
+
+pytestmark = pytest.mark.gpu
+
+G_TOL = 1e-4
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def pkg():
+    import paper_1411_2141_amd
+    return paper_1411_2141_amd
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def cases():
+    p = make_pair(1)
+    te, re_, V, T, _ = small_pair(seed=1, side=48, s_min=1, s_max=16)
+    Vu, Tu, _ = uniform_mesh(24, 40, 4)
+    te2, re2 = small_pair(seed=2, side=48)[:2]
+    return {
+        "c1_128": dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=0.1),
+        "adaptive_48": dict(te=te, re=re_, V=V, T=T, alpha=0.3),
+        "ragged_40x24": dict(te=te2[:24, :40].copy(), re=re2[:24, :40].copy(), V=Vu, T=Tu, alpha=0.2),
+    }
+
+
+@pytest.mark.parametrize("case,n_iter,ckpt,force_mode", [
+    ("c1_128", 6, 4, 0), ("adaptive_48", 5, 2, 0), ("ragged_40x24", 4, 1, 0), ("adaptive_48", 3, 3, 1),
+])
+def test_gradient_matches_oracle(case, n_iter, ckpt, force_mode):
+    say(f"adjoint parity {case} N={n_iter} ckpt={ckpt} mode={force_mode}")
+    d = cases()[case]
+    tau = 0.8
+    ctx = pkg().MeshReg([d], tau=tau, force_mode=force_mode)
+    u0 = np.random.default_rng(7).normal(scale=0.3, size=(d["V"].shape[0], 2))
+    msd, g_u0, g_alpha, g_te = ctx.backward(dev(u0), n_iter, ckpt)
+    torch.cuda.synchronize()
+    pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau, force_mode=force_mode)
+    L, gu, ga, gt = oadj.gradient(pb, u0, n_iter)
+    assert abs(msd.item() - L) <= 1e-5 * L
+    assert rel(g_u0.cpu().numpy(), gu) < G_TOL
+    assert abs(g_alpha.item() - ga) <= G_TOL * abs(ga) + 1e-14
+    H, W = d["te"].shape
+    assert rel(g_te.cpu().numpy().reshape(H, W), gt) < G_TOL
+    ctx.close()
+
+
+def test_batched_gradients_scale_with_upstream_weights():
+    say("adjoint batched: 2 pairs, weighted")
+    cs = cases()
+    ds = [cs["adaptive_48"], cs["ragged_40x24"]]
+    tau, N = 0.5, 4
+    ctx = pkg().MeshReg(ds, tau=tau)
+    u0 = np.random.default_rng(8).normal(scale=0.2, size=(ctx.total_nodes, 2))
+    w = np.array([0.7, -1.3])
+    msd, g_u0, g_alpha, g_te = ctx.backward(dev(u0), N, 3, g_msd=dev(w))
+    torch.cuda.synchronize()
+    gu_all = g_u0.cpu().numpy()
+    gt_all = g_te.cpu().numpy()
+    for k, d in enumerate(ds):
+        pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        L, gu, ga, gt = oadj.gradient(pb, u0[sl], N)
+        assert abs(msd[k].item() - L) <= 1e-5 * L
+        assert rel(gu_all[sl], w[k] * gu) < G_TOL
+        assert abs(g_alpha[k].item() - w[k] * ga) <= G_TOL * abs(ga) + 1e-14
+        px = slice(ctx.pixel_offsets[k], ctx.pixel_offsets[k + 1])
+        assert rel(gt_all[px].reshape(d["te"].shape), w[k] * gt) < G_TOL
+    ctx.close()
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    say("adjoint checkpoint independence")
+    d = cases()["c1_128"]
+    ctx = pkg().MeshReg([d], tau=0.5)
+    u0 = dev(np.zeros((d["V"].shape[0], 2)))
+    outs = [ctx.backward(u0, 7, k) for k in (1, 3, 7)]
+    torch.cuda.synchronize()
+    ref = outs[0]
+    for o in outs[1:]:
+        assert rel(o[1].cpu().numpy(), ref[1].cpu().numpy()) < 1e-10
+        assert abs(o[2].item() - ref[2].item()) <= 1e-10 * abs(ref[2].item())
+        assert rel(o[3].cpu().numpy(), ref[3].cpu().numpy()) < 1e-6
+    ctx.close()
+
+
+def test_gradient_against_gpu_finite_differences():
+    """Central differences of the GPU forward MSD (each node moved by up to
+    h = 1e-3 px along a random direction; alpha by 1e-3 relative) against the
+    GPU adjoint.  The forward samples in FP32, so the differences carry ~1e-3
+    relative noise; the oracle comparisons above are the tight check."""
+    say("adjoint vs GPU central differences (c1, N=10)")
+    d = cases()["c1_128"]
+    tau, N = 0.5, 10
+    ctx = pkg().MeshReg([d], tau=tau)
+    rng = np.random.default_rng(9)
+    u0 = rng.normal(scale=0.2, size=(d["V"].shape[0], 2))
+    _, g_u0, g_alpha, _ = ctx.backward(dev(u0), N, 5)
+    g = g_u0.cpu().numpy()
+
+    def loss(v):
+        u = dev(v)
+        ctx.step(u, N)
+        return ctx.warp_msd(u).item()
+
+    for _ in range(4):
+        dvec = rng.uniform(-1.0, 1.0, size=u0.shape)
+        h = 1e-3
+        fd = (loss(u0 + h * dvec) - loss(u0 - h * dvec)) / (2 * h)
+        an = float(np.sum(g * dvec))
+        assert abs(fd - an) <= 1e-2 * abs(an) + 1e-9, (fd, an)
+    a0 = d["alpha"]
+    ha = 1e-3 * a0
+    ctx.set_alpha(0, a0 + ha)
+    lp = loss(u0)
+    ctx.set_alpha(0, a0 - ha)
+    lm = loss(u0)
+    ctx.set_alpha(0, a0)
+    fda = (lp - lm) / (2 * ha)
+    assert abs(fda - g_alpha.item()) <= 1e-2 * abs(g_alpha.item()), (fda, g_alpha.item())
+    ctx.close()
+
+
+def test_autograd_function_matches_library_backward():
+    say("autograd.Function")
+    d = cases()["adaptive_48"]
+    ctx = pkg().MeshReg([d], tau=0.6)
+    u0 = torch.zeros((d["V"].shape[0], 2), dtype=torch.float64, device="cuda", requires_grad=True)
+    alpha = torch.tensor([d["alpha"]], dtype=torch.float64, requires_grad=True)
+    te = torch.as_tensor(d["te"], device="cuda").reshape(-1).clone().requires_grad_(True)
+    msd = pkg().unrolled_msd(ctx, u0, alpha, te, n_iter=4, ckpt_every=2)
+    (3.0 * msd.sum()).backward()
+    torch.cuda.synchronize()
+    pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], 0.6)
+    L, gu, ga, gt = oadj.gradient(pb, None, 4)
+    assert abs(msd.item() - L) <= 1e-5 * L
+    assert rel(u0.grad.cpu().numpy(), 3.0 * gu) < G_TOL
+    assert abs(alpha.grad.item() - 3.0 * ga) <= G_TOL * abs(3.0 * ga)
+    assert rel(te.grad.cpu().numpy().reshape(d["te"].shape), 3.0 * gt) < G_TOL
+    # a changed alpha re-factorises and changes the result consistently
+    alpha2 = torch.tensor([0.9], dtype=torch.float64)
+    m2 = pkg().unrolled_msd(ctx, u0.detach(), alpha2, None, n_iter=4)
+    pb2 = reg.setup(d["te"], d["re"], d["V"], d["T"], 0.9, 0.6)
+    assert abs(m2.item() - reg.msd(pb2, reg.run(pb2, None, 4)[0])) <= 1e-5 * m2.item()
+    ctx.close()
