@@ -1,15 +1,20 @@
 """Throughput of the registration hot path on one MI355X.
 
-One step = one iteration of the method on the 512x512 12-bit single-pair
-workload (quadtree mesh s=1..32, g=0.08; alpha=0.05, tau=0.5): template
-sampling at the displaced nodes, P1 force assembly, the two FP64 triangular
-solves of (I + tau alpha K), and the full-pixel warp + MSD (every iteration).
-The timed region runs exactly ``--steps`` iterations from u = 0 with every
-input already resident in device memory.
+Headline (``value``): one step = one iteration of the method on the 512x512
+12-bit single-pair workload (quadtree mesh s=1..32, g=0.08; alpha=0.05,
+tau=0.5): template sampling at the displaced nodes, P1 force assembly, the
+two FP64 triangular solves of (I + tau alpha K), and the full-pixel warp + MSD
+(every iteration).  The timed region runs exactly ``--steps`` iterations from
+u = 0 with every input already resident in device memory.
 
-Prints one JSON line: node-updates/s, plus the dominant kernel's roofline
-(algorithmic bytes / HIP-event kernel time) and the FP64 oracle timed on a
-bounded sample on the host cores.
+Extra legs in the same JSON line (same numerator, nodes x iterations):
+  fwd_bwd  -- the same pair, 100 iterations forward plus the checkpointed
+              reverse pass (gradients w.r.t. u0, alpha and the template);
+  batched  -- 256 ragged pairs (sides 128..1024, s=1..32, g=0.10), 100
+              iterations per call, all pairs in every launch, HIP-graph replay.
+Each leg reports its dominant kernel family's roofline (algorithmic bytes per
+launch over the HIP-event launch time).  The FP64 oracle is timed on a
+bounded sample on one host core (``cpu_baseline``).
 """
 from __future__ import annotations
 
@@ -33,27 +38,57 @@ METRIC = "node-updates/s per registration iteration, fwd+bwd vs plain; achieved 
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(ctx, pair, V, H, W) -> dict:
-    """Bytes each kernel family must move per launch (each datum once)."""
-    n = int(V.shape[0])
-    nt = ctx.info(0, "n_tris")
-    nnz_m = ctx.info(0, "mass_nnz")
-    off = ctx.info(0, "solve_offblock")
-    dense = ctx.info(0, "solve_dense")
-    # coefficients touched by the node samples at u = 0 (4x4 taps per node)
-    fx = V[:, 0] - 1
-    fy = V[:, 1] - 1
-    taps = set()
-    for dm in range(-1, 3):
-        for dn in range(-1, 3):
-            r = np.clip(fy + dm, 0, H - 1)
-            c = np.clip(fx + dn, 0, W - 1)
-            taps.update((r * W + c).tolist())
-    sample = 36 * n + 4 * len(taps)                    # u 16, xy 8, rho 4, h 8 + coefficients
-    assemble = 48 * n + 8 * nnz_m                       # ptr 4, u 16, iperm 4, h 8, b 16 + col/wt
-    solve_call = 2 * (32 * n + 12 * off + 8 * dense + 8 * n) + 4 * n + 16 * n
-    warp = 12 * H * W + 24 * n + 16 * nt                # t6, Re, coef per pixel; u, xy; triangles
-    return dict(sample=sample, assemble=assemble, solve_call=solve_call, warp=warp)
+def family_bytes(ctx, pairs) -> dict:
+    """Algorithmic bytes per launch of each kernel family (each datum once),
+    summed over the pairs of the context; the solve entry is per solve call."""
+    n = sum(p.n_nodes for p in pairs)
+    nt = sum(int(p.T.shape[0]) for p in pairs)
+    pix = sum(p.height * p.width for p in pairs)
+    nnz_m = sum(ctx.info(k, "mass_nnz") for k in range(len(pairs)))
+    panel = sum(ctx.info(k, "solve_offblock") for k in range(len(pairs)))
+    dense = sum(ctx.info(k, "solve_dense") for k in range(len(pairs)))
+    taps = 0
+    for p in pairs:                      # coefficients touched by node samples at u = 0
+        H, W = p.height, p.width
+        s = set()
+        for dm in range(-1, 3):
+            r = np.clip(p.V[:, 1] - 1 + dm, 0, H - 1)
+            for dn in range(-1, 3):
+                s.update((r * W + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)).tolist())
+        taps += len(s)
+    return {
+        "sample": 36 * n + 4 * taps,
+        "assemble": 48 * n + 8 * nnz_m,
+        "solve_call": 2 * (32 * n + 8 * panel + 8 * dense + 8 * n) + 20 * n,
+        "warp": 12 * pix + 24 * n + 16 * nt,
+    }
+
+
+def profile(ctx, run, steps, nbytes) -> tuple:
+    """Per-family HIP-event timing of one run; returns (kernels, roofline)."""
+    import torch
+    ctx.enable_timing(True)
+    run()
+    torch.cuda.synchronize()
+    times = ctx.kernel_times()
+    ctx.enable_timing(False)
+    solve_launches = max(1, times["solve"][1])
+    per_launch = {"sample": nbytes["sample"], "assemble": nbytes["assemble"], "warp": nbytes["warp"],
+                  "solve": nbytes["solve_call"] * (steps / solve_launches)}
+    total = sum(t[0] for t in times.values())
+    kernels = {}
+    for fam, (ms, cnt) in times.items():
+        if cnt:
+            avg = ms / cnt
+            kernels[fam] = {"avg_us": round(avg * 1e3, 3), "launches": cnt,
+                            "gbs": round(per_launch[fam] / (avg * 1e-3) / 1e9, 2),
+                            "share": round(ms / total, 4)}
+    dom = max(kernels, key=lambda f: kernels[f]["share"])
+    ach = kernels[dom]["gbs"]
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+            "bytes_per_launch": int(per_launch[dom]), "avg_launch_us": kernels[dom]["avg_us"]}
+    return kernels, roof
 
 
 def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
@@ -65,8 +100,8 @@ def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
         u = reg.step(pb, u)
         reg.msd(pb, u)
     dt = time.perf_counter() - t0
-    return {"value": pair.n_nodes * n_iter_sample / dt, "unit": "node-updates/s", "cores": 1,
-            "kind": "oracle",
+    return {"value": round(pair.n_nodes * n_iter_sample / dt, 1), "unit": "node-updates/s",
+            "cores": 1, "kind": "oracle",
             "sample": f"first {n_iter_sample} iterations (each with warp+MSD) of the same "
                       f"512x512 pair, FP64 NumPy/SciPy oracle with CG solves, 1 thread, "
                       f"{dt:.1f} s"}
@@ -80,26 +115,34 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--fwdbwd-iters", type=int, default=100, help="0 skips the fwd+bwd leg")
+    ap.add_argument("--batched-pairs", type=int, default=256, help="0 skips the batched leg")
+    ap.add_argument("--batched-iters", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
               f"sharding of this path is described in DESIGN.md and not built.", file=sys.stderr)
         return 2
 
+    from synth import make_pair, make_pairs
+    # inputs first, before anything touches the GPU
+    pair = make_pair(2)
+    cpus = len(os.sched_getaffinity(0))
+    batch = (make_pairs(4, args.batched_pairs, processes=min(16, cpus))
+             if args.batched_pairs else [])
+
     import torch
     import paper_1411_2141_amd as pkg
-    from synth import make_pair
+    B = pkg.binding
 
-    pair = make_pair(2)
     tau = 0.5
-    H, W = pair.height, pair.width
     n = pair.n_nodes
     ctx = pkg.MeshReg([pair], tau=tau)
     u = ctx.zeros_u()
     trace = torch.empty((max(args.steps, args.warmup), 1), dtype=torch.float64, device="cuda")
 
     def run(k):
-        pkg.binding.mesh_reg_step(ctx.ctx, u, k, trace, torch.cuda.current_stream().cuda_stream)
+        B.mesh_reg_step(ctx.ctx, u, k, trace, torch.cuda.current_stream().cuda_stream)
 
     run(args.warmup)
     torch.cuda.synchronize()
@@ -112,36 +155,63 @@ def main() -> int:
     final_msd = float(trace[args.steps - 1, 0].item())
     value = n * args.steps / dt
 
-    roof = None
-    kernels = {}
+    kernels, roof = {}, None
     if not args.no_profile:
         u.zero_()
-        ctx.enable_timing(True)
-        run(args.steps)
-        torch.cuda.synchronize()
-        times = ctx.kernel_times()
-        ctx.enable_timing(False)
-        nbytes = algorithmic_bytes(ctx, 0, pair.V, H, W)
-        per_launch = {
-            "sample": nbytes["sample"], "assemble": nbytes["assemble"], "warp": nbytes["warp"],
-            "solve": nbytes["solve_call"] / max(1, times["solve"][1] / max(1, args.steps)),
-        }
-        for fam, (ms, cnt) in times.items():
-            if cnt:
-                avg_ms = ms / cnt
-                kernels[fam] = {"avg_us": round(avg_ms * 1e3, 3), "launches": cnt,
-                                "gbs": round(per_launch[fam] / (avg_ms * 1e-3) / 1e9, 2),
-                                "share": round(ms / sum(t[0] for t in times.values()), 4)}
-        dom = max(times, key=lambda f: times[f][0])
-        ach = kernels[dom]["gbs"]
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
-                "bytes_per_launch": int(per_launch[dom]),
-                "avg_launch_us": kernels[dom]["avg_us"]}
+        kernels, roof = profile(ctx, lambda: run(args.steps), args.steps,
+                                family_bytes(ctx, [pair]))
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pair, tau, args.cpu_iters)
+    fwd_bwd = None
+    if args.fwdbwd_iters:
+        N = args.fwdbwd_iters
+        u0 = ctx.zeros_u()
+        ctx.backward(u0, N, 10)             # warm-up (allocates the adjoint buffers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uu = u0.clone()
+        ctx.step(uu, N)
+        ctx.warp_msd(uu)
+        msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        fwd_bwd = {"value": round(n * N / dtb, 1), "unit": "node-updates/s",
+                   "iterations": N, "ckpt_every": 10, "ms_per_iteration": round(dtb / N * 1e3, 4),
+                   "vs_plain": round(n * N / dtb / value, 4),
+                   "grad_evals_per_s": round(1.0 / dtb, 3),
+                   "note": "forward N iterations + warp/MSD, then the checkpointed reverse pass "
+                           "(recompute + adjoint), same 512x512 pair"}
+    ctx.close()
+
+    batched = None
+    if batch:
+        nb = sum(p.n_nodes for p in batch)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            bctx = pkg.MeshReg(batch, tau=tau, graph=True)
+            ub = bctx.zeros_u()
+            K = args.batched_iters
+            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)     # capture + warm-up
+            side.synchronize()
+            ub.zero_()
+            side.synchronize()
+            t0 = time.perf_counter()
+            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)
+            msd_b = bctx.warp_msd(ub)
+            side.synchronize()
+            dtc = time.perf_counter() - t0
+            bk, broof = {}, None
+            if not args.no_profile:
+                ub.zero_()
+                bk, broof = profile(bctx, lambda: bctx.step(ub, K), K, family_bytes(bctx, batch))
+        batched = {"value": round(nb * K / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
+                   "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),
+                   "iterations": K, "ms_per_iteration": round(dtc / K * 1e3, 4),
+                   "iterations_per_s": round(K / dtc, 2), "graph": True,
+                   "mean_final_msd": float(msd_b.mean().item()),
+                   "kernels": bk, "roofline": broof}
+        bctx.close()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "node-updates/s", "n_gpus": 1,
@@ -150,13 +220,13 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "single pair 512x512 12-bit blobs+disk, sine warp A=8, quadtree "
                                "s=1..32 g=0.08, alpha=0.05 tau=0.5, warp+MSD every iteration",
-                   "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": H * W,
+                   "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": pair.height * pair.width,
                    "iterations": args.steps, "parallelism": "single GPU",
                    "final_msd": final_msd},
         "kernels": kernels, "roofline": roof, "cpu_baseline": cpu,
+        "fwd_bwd": fwd_bwd, "batched": batched,
     }
     print(json.dumps(out))
-    ctx.close()
     return 0
 
 

@@ -73,7 +73,10 @@ enum {
 enum { MR_FORCE_P1 = 0, MR_FORCE_NODAL = 1 };
 
 enum {
-  MR_FLAG_HOST_ONLY = 1 /* build tables, operators and the factor only; no device work */
+  MR_FLAG_HOST_ONLY = 1, /* build tables, operators and the factor only; no device work */
+  MR_FLAG_GRAPH = 2      /* mesh_reg_step captures its launches in a HIP graph once per
+                            (u, n_iter, msd_trace, stream) and replays it on later calls
+                            with the same arguments (a NULL stream runs eagerly) */
 };
 
 /* One registration pair (Algorithm 1, "Inputs"; Section 2.1 for (V, T)). */
@@ -92,6 +95,9 @@ typedef struct {
   double tau;                  /* step size of eq. 5, > 0 */
   int32_t force_mode;          /* MR_FORCE_P1 (default) or MR_FORCE_NODAL (f = h, eq. 6 literally) */
   int32_t flags;               /* MR_FLAG_* */
+  int32_t apex_rows;           /* solve schedule: rows of the dense apex per pair; 0 = automatic
+                                  (4000 for one pair, shrinking with the batch), -1 = none */
+  int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic */
 } mr_params;
 
 /* Pre-computation (Algorithm 1): validates every mesh, builds tables T1-T6

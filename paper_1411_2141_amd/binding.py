@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmeshreg.
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_ENOTSPD, MR_ESTATE, MR_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MR_FORCE_P1, MR_FORCE_NODAL = 0, 1
 MR_FLAG_HOST_ONLY = 1
+MR_FLAG_GRAPH = 2
 TABLES = {"t1_ptr": 10, "t1_slot": 11, "t2_ptr": 20, "t2_idx": 21, "t3_ptr": 30, "t3_idx": 31,
           "t4": 40, "t5": 50, "t6": 60, "perm": 70}
 INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "bwd_levels": 6,
@@ -45,7 +46,8 @@ class MrPair(ctypes.Structure):
 
 class MrParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("force_mode", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("apex_rows", ctypes.c_int32),
+                ("bwd_split_rows", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,7 +99,7 @@ def _ptr(t) -> int | None:
 
 
 def mesh_reg_init(pairs: list, tau: float, force_mode: int = MR_FORCE_P1, flags: int = 0,
-                  stream: int | None = None):
+                  stream: int | None = None, apex_rows: int = 0, bwd_split_rows: int = 0):
     """``pairs``: sequence of dicts with ``V`` (int32 [n][2]), ``T`` (int32 [nT][3]),
     ``te``/``re`` (device FP32 [H][W] tensors, or None with the host-only flag),
     ``height``, ``width`` and ``alpha``.  Returns the opaque context handle."""
@@ -111,7 +113,7 @@ def mesh_reg_init(pairs: list, tau: float, force_mode: int = MR_FORCE_P1, flags:
         arr[k] = MrPair(int(p["height"]), int(p["width"]), V.shape[0], T.shape[0],
                         V.ctypes.data, T.ctypes.data, _ptr(p.get("te")), _ptr(p.get("re")),
                         float(p["alpha"]))
-    params = MrParams(float(tau), int(force_mode), int(flags))
+    params = MrParams(float(tau), int(force_mode), int(flags), int(apex_rows), int(bwd_split_rows))
     out = ctypes.c_void_p()
     _check(lib.mesh_reg_init(arr, len(pairs), ctypes.byref(params), stream, ctypes.byref(out)))
     return out

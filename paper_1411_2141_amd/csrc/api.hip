@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -179,6 +181,7 @@ void mr_ctx::post_flags(hipStream_t s) {
 }
 
 mr_ctx::~mr_ctx() {
+  if (graph_exec) hipGraphExecDestroy(graph_exec);
   for (auto &p : pending) {
     hipEventDestroy(p.start);
     hipEventDestroy(p.stop);
@@ -247,7 +250,6 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
   int32_t n_partials = 0, n_counters = 0;
-  if (const char *env = std::getenv("MESHREG_BWD_SPLIT_ROWS")) bwd_split_rows = std::max(8, std::atoi(env));
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
     const DevPair &d = dpairs[p];
@@ -474,6 +476,17 @@ static int check_ctx(mr_ctx *c, bool need_device) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Dense apex rows per pair when the caller leaves it to the library: a single
+// pair needs the apex to cut the narrow top levels of its block tree; a batch
+// already fills those levels across pairs, and the apex bytes grow with it.
+static int32_t auto_apex_rows(int32_t n_pairs) {
+  if (n_pairs <= 1) return 4000;
+  if (n_pairs <= 4) return 2048;
+  if (n_pairs <= 16) return 1024;
+  if (n_pairs <= 64) return 256;
+  return 0;
+}
+
 extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
                              void *stream, mr_ctx **out) {
   if (!out) return fail(MR_EINVAL, "out is null");
@@ -500,7 +513,10 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   c->host_only = host_only;
   c->host.resize(n_pairs);
   OrderOptions opt;
-  if (const char *env = std::getenv("MESHREG_APEX_MAX")) opt.apex_max = std::max(0, std::atoi(env));
+  opt.apex_max = params->apex_rows > 0 ? params->apex_rows
+                 : params->apex_rows < 0 ? 0
+                 : auto_apex_rows(n_pairs);
+  if (params->bwd_split_rows > 0) c->bwd_split_rows = std::max(8, params->bwd_split_rows);
   for (int p = 0; p < n_pairs; ++p) {
     const mr_pair &q = pairs[p];
     PairHost &h = c->host[p];
@@ -511,13 +527,30 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     h.alpha = q.alpha;
     h.xy.assign(q.node_xy, q.node_xy + 2 * (size_t)q.n_nodes);
     h.tri.assign(q.tris, q.tris + 3 * (size_t)q.n_tris);
-    bool not_spd = false;
-    std::string e = prepare_pair(h, params->tau, opt, &not_spd);
-    if (!e.empty()) {
-      delete c;
-      return fail(not_spd ? MR_ENOTSPD : MR_EINVAL, "pair " + std::to_string(p) + ": " + e);
-    }
   }
+  // pairs are prepared independently, on up to 32 host threads
+  std::vector<std::string> errs(n_pairs);
+  std::vector<char> not_spd(n_pairs, 0);
+  {
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      for (int p = next++; p < n_pairs; p = next++) {
+        bool ns = false;
+        errs[p] = prepare_pair(c->host[p], params->tau, opt, &ns);
+        not_spd[p] = ns;
+      }
+    };
+    const int nt = std::max(1, std::min<int>({n_pairs, 32, (int)std::thread::hardware_concurrency()}));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+  }
+  for (int p = 0; p < n_pairs; ++p)
+    if (!errs[p].empty()) {
+      delete c;
+      return fail(not_spd[p] ? MR_ENOTSPD : MR_EINVAL, "pair " + std::to_string(p) + ": " + errs[p]);
+    }
   if (host_only) {
     *out = c;
     return MR_OK;
@@ -558,6 +591,16 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   return MR_OK;
 }
 
+// The launches of n_iter iterations (no host synchronisation, no memsets, so
+// the sequence can be captured in a graph).
+int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
+  double *pending = nullptr;
+  for (int k = 0; k < n_iter; ++k)
+    HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, s));
+  if (pending) HIP_TRY(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, pending, s));
+  return MR_OK;
+}
+
 extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace,
                              void *stream) {
   int rc = check_ctx(c, true);
@@ -566,10 +609,36 @@ extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_t
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
   double2 *u2 = reinterpret_cast<double2 *>(u);
-  double *pending = nullptr;
-  for (int k = 0; k < n_iter; ++k)
-    HIP_TRY(c->iterate(u2, msd_trace ? msd_trace + (size_t)k * c->n_pairs : nullptr, &pending, s));
-  if (pending) HIP_TRY(launch_msd_finish(c->d_pairs.ptr, c->n_pairs, c->d_partials.ptr, pending, s));
+  // graphs cannot be captured on the legacy default stream
+  const bool use_graph = (c->params.flags & MR_FLAG_GRAPH) && !c->timing && n_iter > 0 && s;
+  if (!use_graph) {
+    if ((rc = c->step(u2, n_iter, msd_trace, s))) return rc;
+  } else {
+    if (!c->graph_exec || c->graph_u != u || c->graph_trace != msd_trace ||
+        c->graph_iters != n_iter || c->graph_stream != s) {
+      if (c->graph_exec) {
+        hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      rc = c->step(u2, n_iter, msd_trace, s);
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      HIP_TRY(e);
+      e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIP_TRY(e);
+      c->graph_u = u;
+      c->graph_trace = msd_trace;
+      c->graph_iters = n_iter;
+      c->graph_stream = s;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+  }
   c->post_flags(s);
   return MR_OK;
 }

@@ -80,7 +80,7 @@ struct mr_ctx {
   mr::DevArray<double> d_apex_inv_row, d_apex_inv_col;
   mr::DevArray<int2> d_apex_fitems, d_apex_bitems;
   mr::DevArray<double2> d_apex_t, d_apex_y;
-  int32_t bwd_split_rows = 1 << 30;          // panel rows per backward workgroup
+  int32_t bwd_split_rows = 128;              // panel rows per backward workgroup
   mr::DevArray<unsigned> d_blk_counters;
   mr::DevArray<int64_t> d_cptr;
   mr::DevArray<int32_t> d_cidx, d_below;
@@ -94,6 +94,12 @@ struct mr_ctx {
   mr::DevArray<double2> d_ck, d_seg, d_lam, d_mu, d_eta;
   mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
   mr::DevArray<int32_t> d_kptr, d_kcol;
+
+  // cached HIP graph of one mesh_reg_step call
+  hipGraphExec_t graph_exec = nullptr;
+  const void *graph_u = nullptr, *graph_trace = nullptr;
+  int32_t graph_iters = -1;
+  hipStream_t graph_stream = nullptr;
 
   bool timing = false;
   std::vector<mr::TimedLaunch> pending;
@@ -110,6 +116,7 @@ struct mr_ctx {
   hipError_t iterate(double2 *u, double *msd_out, double **pending, hipStream_t s);
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
+  int step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s);
   void post_flags(hipStream_t s);
   void timed_begin(int family, hipStream_t s);
   void timed_end(hipStream_t s);

@@ -99,10 +99,24 @@ def make_pair(config_id: int, pair_index: int = 0, side: int | None = None) -> P
                 params=params)
 
 
-def make_workload(config_id: int, n_pairs: int | None = None) -> Workload:
+def _make_pair_args(args):
+    return make_pair(*args)
+
+
+def make_pairs(config_id: int, n_pairs: int, processes: int = 1) -> list:
+    """Pairs ``0 .. n_pairs-1`` of a workload, optionally in a process pool
+    (``spawn`` start method, so no GPU state is inherited)."""
+    if processes <= 1 or n_pairs <= 1:
+        return [make_pair(config_id, p) for p in range(n_pairs)]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(processes) as pool:
+        return pool.map(_make_pair_args, [(config_id, p) for p in range(n_pairs)], chunksize=1)
+
+
+def make_workload(config_id: int, n_pairs: int | None = None, processes: int = 1) -> Workload:
     spec = SPECS[config_id]
     k = spec["n_pairs"] if n_pairs is None else n_pairs
-    pairs = [make_pair(config_id, p) for p in range(k)]
+    pairs = make_pairs(config_id, k, processes)
     return Workload(config_id=config_id, name=spec["name"], pairs=pairs, tau=spec["tau"],
                     n_iter=spec["n_iter"], msd_every_iter=spec.get("msd_every_iter", False),
                     ckpt_every=spec.get("ckpt_every", 0))
