@@ -74,6 +74,8 @@ enum { MR_FORCE_P1 = 0, MR_FORCE_NODAL = 1 };
 
 enum {
   MR_FLAG_HOST_ONLY = 1, /* build tables, operators and the factor only; no device work */
+  MR_FLAG_NO_TUNE = 4,   /* skip the solve-schedule autotuning at init (fixed 256-thread
+                            workgroups) */
   MR_FLAG_GRAPH = 2      /* mesh_reg_step captures its launches in a HIP graph once per
                             (u, n_iter, msd_trace, stream) and replays it on later calls
                             with the same arguments (a NULL stream runs eagerly) */
@@ -97,7 +99,8 @@ typedef struct {
   int32_t flags;               /* MR_FLAG_* */
   int32_t apex_rows;           /* solve schedule: rows of the dense apex per pair; 0 = automatic
                                   (4000 for one pair, shrinking with the batch), -1 = none */
-  int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic */
+  int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic
+                                  (128 for one pair, unsplit for a batch) */
 } mr_params;
 
 /* Pre-computation (Algorithm 1): validates every mesh, builds tables T1-T6
@@ -106,7 +109,9 @@ typedef struct {
  * ordering, the FP64 Cholesky factor of (I + tau alpha K) per pair and its block
  * solve schedule, then (unless MR_FLAG_HOST_ONLY) uploads everything, computes
  * the B-spline coefficients of te and re and the reference samples at the
- * undisplaced nodes on the device.  Synchronises `stream` before returning.
+ * undisplaced nodes on the device, and (unless MR_FLAG_NO_TUNE) times the
+ * admissible workgroup sizes of every solve level on this data and keeps the
+ * fastest.  Synchronises `stream` before returning.
  * Errors: MR_EINVAL (bad argument or mesh: index out of range, non-positive area,
  * unreferenced node, node outside the image, uncovered pixel, tau <= 0, alpha < 0,
  * NaN), MR_ENOTSPD, MR_ENOMEM, MR_EHIP. */

@@ -18,6 +18,7 @@ MR_OK, MR_EINVAL, MR_ENOMEM, MR_EHIP, MR_ENOTSPD, MR_ESTATE, MR_ENONFINITE = 0, 
 MR_FORCE_P1, MR_FORCE_NODAL = 0, 1
 MR_FLAG_HOST_ONLY = 1
 MR_FLAG_GRAPH = 2
+MR_FLAG_NO_TUNE = 4
 TABLES = {"t1_ptr": 10, "t1_slot": 11, "t2_ptr": 20, "t2_idx": 21, "t3_ptr": 30, "t3_idx": 31,
           "t4": 40, "t5": 50, "t6": 60, "perm": 70}
 INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "bwd_levels": 6,

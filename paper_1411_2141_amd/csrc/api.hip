@@ -75,14 +75,29 @@ void mr_ctx::timed_end(hipStream_t s) {
 
 // Launches the two triangular solves on x (solve order, in place).  When `out`
 // is given, the backward pass also scatters the result to natural order there.
+hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s) {
+  if (fwd) {
+    const int cnt = fwd_ptr[lev + 1] - fwd_ptr[lev];
+    if (!cnt) return hipSuccess;
+    const int nt = fwd_nt[lev];
+    return launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt,
+                                  fwd_lds[lev] + 16 * nt, nt, d_cptr.ptr, d_cidx.ptr, d_dcol.ptr,
+                                  d_prow.ptr, x, d_upd.ptr, s);
+  }
+  const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
+  if (!cnt) return hipSuccess;
+  const int nt = bwd_nt[lev];
+  return launch_solve_bwd_level(d_blocks.ptr, d_bwd_items.ptr + bwd_ptr[lev], cnt,
+                                bwd_lds[lev] + 16 * nt, nt, d_below.ptr, d_drow.ptr, d_prow.ptr,
+                                x, d_perm.ptr, out, d_partials2.ptr, d_blk_counters.ptr, s);
+}
+
 hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (int lev = 0; lev < (int)fwd_ptr.size() - 1; ++lev) {
-    const int cnt = fwd_ptr[lev + 1] - fwd_ptr[lev];
-    if (!cnt) continue;
+    if (fwd_ptr[lev + 1] == fwd_ptr[lev]) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt, fwd_lds[lev],
-                               d_cptr.ptr, d_cidx.ptr, d_dcol.ptr, d_prow.ptr, x, d_upd.ptr, s);
+    e = solve_level(true, lev, x, out, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
@@ -100,16 +115,61 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   for (int lev = 0; lev < (int)bwd_ptr.size() - 1; ++lev) {
-    const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
-    if (!cnt) continue;
+    if (bwd_ptr[lev + 1] == bwd_ptr[lev]) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = launch_solve_bwd_level(d_blocks.ptr, d_bwd_items.ptr + bwd_ptr[lev], cnt, bwd_lds[lev],
-                               d_below.ptr, d_drow.ptr, d_prow.ptr, x, d_perm.ptr, out,
-                               d_partials2.ptr, d_blk_counters.ptr, s);
+    e = solve_level(false, lev, x, out, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
   return e;
+}
+
+// Autotuner: for every solve level, times each admissible workgroup size
+// (64, 128, 256 threads; at least the level's largest block rounded up to a
+// power of two) on the context's own data and keeps the fastest.  The level
+// kernels only read and write the solve scratch vectors, so running them on
+// whatever those hold is harmless.
+int mr_ctx::tune(hipStream_t s) {
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int rc = MR_OK;
+  for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
+    const bool fwd = dir == 0;
+    std::vector<int32_t> &choice = fwd ? fwd_nt : bwd_nt;
+    const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
+    for (size_t lev = 0; lev < choice.size() && rc == MR_OK; ++lev) {
+      float best = 1e30f;
+      int best_nt = choice[lev];
+      for (int nt : {64, 128, 256}) {
+        if (nt < minnt[lev]) continue;
+        choice[lev] = nt;
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          hipError_t e = hipEventRecord(a, s);
+          if (e == hipSuccess) e = solve_level(fwd, (int)lev, d_x.ptr, nullptr, s);
+          if (e == hipSuccess) e = hipEventRecord(b, s);
+          if (e == hipSuccess) e = hipEventSynchronize(b);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+          if (e != hipSuccess) {
+            rc = fail(MR_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+          }
+          if (rep > 0) t_min = std::min(t_min, ms);
+        }
+        if (rc) break;
+        if (t_min < best) {
+          best = t_min;
+          best_nt = nt;
+        }
+      }
+      choice[lev] = best_nt;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return rc;
 }
 
 hipError_t mr_ctx::sample(const double2 *u, double *finish_msd, hipStream_t s) {
@@ -249,6 +309,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   int32_t apex_nmax = 0;
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
+  std::vector<int32_t> fwd_bp_v(max_fl, 64), bwd_bp_v(max_bl, 64);
   int32_t n_partials = 0, n_counters = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
@@ -305,9 +366,11 @@ int mr_ctx::upload_all(hipStream_t s) {
         n_partials += bs * b;
       }
       const int32_t kn = std::min(rs, m);
-      const int64_t lf = solve_fwd_lds_bytes(b, kn), lb = solve_bwd_lds_bytes(b, kn);
-      if (lf > kSolveLdsBudget || lb > kSolveLdsBudget)
+      const int64_t lf = solve_fwd_lds_bytes(b, kn, 0), lb = solve_bwd_lds_bytes(b, kn, 0);
+      if (lf + 16 * 256 > kSolveLdsBudget || lb + 16 * 256 > kSolveLdsBudget)
         return fail(MR_EINVAL, "solve block does not fit the LDS budget");
+      int32_t bp = 64;
+      while (bp < b) bp <<= 1;
       const int32_t id = boff + (int32_t)k;
       if (!pl.is_apex[k]) {
         const int32_t bl = pl.rel_bwd_level[k];
@@ -315,6 +378,8 @@ int mr_ctx::upload_all(hipStream_t s) {
         for (int32_t q = 0; q < bs; ++q) bwd_lv[bl].push_back(make_int2(id, q));
         fwd_lds_v[B.fwd_level] = std::max<int32_t>(fwd_lds_v[B.fwd_level], (int32_t)lf);
         bwd_lds_v[bl] = std::max<int32_t>(bwd_lds_v[bl], (int32_t)lb);
+        fwd_bp_v[B.fwd_level] = std::max(fwd_bp_v[B.fwd_level], bp);
+        bwd_bp_v[bl] = std::max(bwd_bp_v[bl], bp);
       }
       blocks.push_back(db);
     }
@@ -360,6 +425,10 @@ int mr_ctx::upload_all(hipStream_t s) {
   }
   fwd_lds = fwd_lds_v;
   bwd_lds = bwd_lds_v;
+  fwd_bp = fwd_bp_v;
+  bwd_bp = bwd_bp_v;
+  fwd_nt.assign(fwd_bp.size(), 256);
+  bwd_nt.assign(bwd_bp.size(), 256);
   if (below.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "solve update buffer too large");
   nnz_factor = (int64_t)prow.size() + (int64_t)dcol.size();
   HIP_TRY(upload(d_pairs, dpairs, s));
@@ -516,7 +585,10 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   opt.apex_max = params->apex_rows > 0 ? params->apex_rows
                  : params->apex_rows < 0 ? 0
                  : auto_apex_rows(n_pairs);
-  if (params->bwd_split_rows > 0) c->bwd_split_rows = std::max(8, params->bwd_split_rows);
+  // splitting a backward panel over workgroups costs a device-scope fence per
+  // workgroup; it only pays when a single pair leaves most of the GPU idle
+  c->bwd_split_rows = params->bwd_split_rows > 0 ? std::max(8, params->bwd_split_rows)
+                      : n_pairs == 1 ? 128 : (1 << 30);
   for (int p = 0; p < n_pairs; ++p) {
     const mr_pair &q = pairs[p];
     PairHost &h = c->host[p];
@@ -586,6 +658,10 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   if (e != hipSuccess) {
     delete c;
     return fail(MR_EHIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  if (!(params->flags & MR_FLAG_NO_TUNE) && (rc = c->tune(s)) != MR_OK) {
+    delete c;
+    return rc;
   }
   *out = c;
   return MR_OK;

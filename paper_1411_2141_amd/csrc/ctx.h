@@ -69,7 +69,10 @@ struct mr_ctx {
   mr::DevArray<mr::DevBlock> d_blocks;
   mr::DevArray<int2> d_fwd_items, d_bwd_items;   // (block, slice) per level
   std::vector<int32_t> fwd_ptr, bwd_ptr;     // level -> range of the item lists (host)
-  std::vector<int32_t> fwd_lds, bwd_lds;     // level -> dynamic LDS bytes
+  std::vector<int32_t> fwd_lds, bwd_lds;     // level -> dynamic LDS bytes without the
+                                             // per-thread part (16 B per thread added at launch)
+  std::vector<int32_t> fwd_nt, bwd_nt;       // level -> workgroup size (autotuned)
+  std::vector<int32_t> fwd_bp, bwd_bp;       // level -> smallest allowed workgroup size
   mr::DevArray<double2> d_partials2;         // backward slice partial sums
   // apex (dense top of every pair's block tree)
   int64_t n_apex_rows = 0;
@@ -116,6 +119,8 @@ struct mr_ctx {
   hipError_t iterate(double2 *u, double *msd_out, double **pending, hipStream_t s);
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
+  int tune(hipStream_t s);
+  hipError_t solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s);
   int step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s);
   void post_flags(hipStream_t s);
   void timed_begin(int family, hipStream_t s);

@@ -19,14 +19,14 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
                            const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
                            double tau, hipStream_t s);
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
-                                  int lds_bytes, const int64_t *cptr, const int32_t *cidx,
+                                  int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
                                   const double *dcol, const double *prow, double2 *x,
                                   double2 *upd, hipStream_t s);
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
-                                  int lds_bytes, const int32_t *below_idx, const double *drow,
-                                  const double *prow, double2 *x, const int32_t *perm,
-                                  double2 *out, double2 *partials, unsigned *counters,
-                                  hipStream_t s);
+                                  int lds_bytes, int nt, const int32_t *below_idx,
+                                  const double *drow, const double *prow, double2 *x,
+                                  const int32_t *perm, double2 *out, double2 *partials,
+                                  unsigned *counters, hipStream_t s);
 hipError_t launch_apex_fwd(int n_rows, const int32_t *rows, const int64_t *acptr,
                            const int32_t *acidx, const double2 *upd, const double2 *x,
                            double2 *tbuf, const int2 *items, int n_items, int lds_bytes,

@@ -175,19 +175,20 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
 
 // Copies n doubles from global memory to LDS with all of a thread's loads of
 // a batch in flight before the first LDS store (predicated, no serial tail).
+template <int NT>
 __device__ __forceinline__ void stage_to_lds(double *__restrict__ dst, const double *__restrict__ src,
                                              int n) {
   constexpr int U = 16;
-  for (int e0 = threadIdx.x; e0 < n; e0 += U * kSolveThreads) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kSolveThreads;
+      const int e = e0 + u * NT;
       v[u] = e < n ? src[e] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kSolveThreads;
+      const int e = e0 + u * NT;
       if (e < n) dst[e] = v[u];
     }
   }
@@ -219,7 +220,8 @@ __device__ __forceinline__ double2 combine_parts(const double2 *red, int o, int 
 //   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block)).
 // Slice 0 also writes y to x (in place).  Each phase spreads its sums over all
 // threads and combines the partial sums in a fixed order (deterministic).
-__global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
+template <int NT>
+__global__ __launch_bounds__(NT) void k_solve_fwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
     const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *upd) {
@@ -237,10 +239,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
   double2 *t = reinterpret_cast<double2 *>(smem + (nd + kn * b + 1) / 2 * 2);
   double2 *yv = t + b;
   double2 *red = yv + b;
-  stage_to_lds(D, dcol + B.doff, nd);
-  stage_to_lds(Ps, prow + B.poff + (int64_t)k0 * b, kn * b);
+  stage_to_lds<NT>(D, dcol + B.doff, nd);
+  stage_to_lds<NT>(Ps, prow + B.poff + (int64_t)k0 * b, kn * b);
   const int bp = pow2_at_least(b);
-  const int np = kSolveThreads / bp;          // threads per row
+  const int np = NT / bp;          // threads per row
   const int r = tid & (bp - 1), part = tid / bp;
   // phase 1: gathers of the contributions, all loads of a thread in flight
   {
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
   __syncthreads();
   // phase 3: the slice's update entries, 4 partial sums per panel row
   constexpr int kParts = 4;
-  constexpr int kRows = kSolveThreads / kParts;
+  constexpr int kRows = NT / kParts;
   for (int base = 0; base < kn; base += kRows) {
     const int kk = base + tid % kRows;
     const int pp = tid / kRows;
@@ -328,7 +330,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_fwd(
 // forms t = y_block - s and z = D^-T t (row-major packed inverse in LDS),
 // writes z in place and, when `out` is given, scatters it to natural order.
 // The finisher resets the counter.
-__global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
+template <int NT>
+__global__ __launch_bounds__(NT) void k_solve_bwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
     const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
     const double *__restrict__ prow, double2 *x, const int32_t *__restrict__ perm,
@@ -349,17 +352,17 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
   double *Ps = smem;
   double2 *zb = reinterpret_cast<double2 *>(smem + (cap * b + 1) / 2 * 2);
   double2 *red = zb + cap;
-  double2 *t = red + kSolveThreads;
+  double2 *t = red + NT;
   double *D = reinterpret_cast<double *>(t + b);
-  if (B.bslice == 1) stage_to_lds(D, drow + B.doff, nd);
+  if (B.bslice == 1) stage_to_lds<NT>(D, drow + B.doff, nd);
   const int bp = pow2_at_least(b);
-  const int np = kSolveThreads / bp;
+  const int np = NT / bp;
   const int j = tid & (bp - 1), g = tid / bp;
   double ax = 0.0, ay = 0.0;
   for (int c0 = kb; c0 < ke; c0 += cap) {
     const int kn = min(cap, ke - c0);
-    stage_to_lds(Ps, prow + B.poff + (int64_t)c0 * b, kn * b);
-    for (int k = tid; k < kn; k += kSolveThreads) zb[k] = x[below_idx[B.boff + c0 + k]];
+    stage_to_lds<NT>(Ps, prow + B.poff + (int64_t)c0 * b, kn * b);
+    for (int k = tid; k < kn; k += NT) zb[k] = x[below_idx[B.boff + c0 + k]];
     __syncthreads();
     if (j < b) {
 #pragma unroll 8
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_bwd(
     __syncthreads();
     if (!last) return;
     __threadfence();
-    stage_to_lds(D, drow + B.doff, nd);
+    stage_to_lds<NT>(D, drow + B.doff, nd);
     if (g == 0 && j < b) {
       double sx = 0.0, sy = 0.0;
       for (int q = 0; q < B.bslice; ++q) {
@@ -627,21 +630,40 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
 }
 
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
-                                  int lds_bytes, const int64_t *cptr, const int32_t *cidx,
+                                  int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
                                   const double *dcol, const double *prow, double2 *x,
                                   double2 *upd, hipStream_t s) {
-  k_solve_fwd<<<count, kSolveThreads, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x,
-                                                      upd);
+  switch (nt) {
+    case 64:
+      k_solve_fwd<64><<<count, 64, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
+      break;
+    case 128:
+      k_solve_fwd<128><<<count, 128, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
+      break;
+    default:
+      k_solve_fwd<256><<<count, 256, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
-                                  int lds_bytes, const int32_t *below_idx, const double *drow,
-                                  const double *prow, double2 *x, const int32_t *perm,
-                                  double2 *out, double2 *partials, unsigned *counters,
-                                  hipStream_t s) {
-  k_solve_bwd<<<count, kSolveThreads, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x,
-                                                      perm, out, partials, counters);
+                                  int lds_bytes, int nt, const int32_t *below_idx,
+                                  const double *drow, const double *prow, double2 *x,
+                                  const int32_t *perm, double2 *out, double2 *partials,
+                                  unsigned *counters, hipStream_t s) {
+  switch (nt) {
+    case 64:
+      k_solve_bwd<64><<<count, 64, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
+                                                   out, partials, counters);
+      break;
+    case 128:
+      k_solve_bwd<128><<<count, 128, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
+                                                     out, partials, counters);
+      break;
+    default:
+      k_solve_bwd<256><<<count, 256, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
+                                                     out, partials, counters);
+  }
   return hipGetLastError();
 }
 

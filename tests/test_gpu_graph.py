@@ -26,10 +26,12 @@ def test_graph_replays_match_eager():
     te, re_, V, T, _ = small_pair(seed=1, side=48, s_min=1, s_max=16)
     p = make_pair(1)
     pairs = [dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=0.1), dict(te=te, re=re_, V=V, T=T, alpha=0.3)]
-    eager = pkg.MeshReg(pairs, tau=0.5)
+    # fixed schedules: two tuned contexts may pick different workgroup sizes,
+    # which changes the rounding of the partial sums
+    eager = pkg.MeshReg(pairs, tau=0.5, tune=False)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        graphed = pkg.MeshReg(pairs, tau=0.5, graph=True)
+        graphed = pkg.MeshReg(pairs, tau=0.5, graph=True, tune=False)
         u = graphed.zeros_u()
         trace = torch.empty((6, 2), dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(0)
