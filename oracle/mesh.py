@@ -112,31 +112,42 @@ def table_t6(V: np.ndarray, T: np.ndarray, height: int, width: int) -> np.ndarra
     Exact integer test in doubled coordinates: the centre of pixel ``(i, j)`` is
     ``(2j+1, 2i+1) / 2`` and ``p`` lies in triangle ``(a, b, c)`` iff the three
     edge cross products ``(b-a) x (p-a)``, ``(c-b) x (p-b)``, ``(a-c) x (p-c)``
-    are all >= 0 (triangles have positive orientation).
+    are all >= 0 (triangles have positive orientation).  Triangles are tested
+    in groups of equal bounding-box size (all candidate pixels of a group at
+    once); each pixel keeps the minimum id that contains it.
     """
     V2 = 2 * np.asarray(V, dtype=np.int64)
     T = np.asarray(T, dtype=np.int64)
     big = np.iinfo(np.int64).max
-    t6 = np.full((height, width), big, dtype=np.int64)
+    t6 = np.full(height * width, big, dtype=np.int64)
     P = V2[T]                                   # [nT][3][2]
-    xlo = np.clip((P[:, :, 0].min(1) - 1) // 2, 0, width)     # first column with 2j+1 >= min
+    xlo = np.clip((P[:, :, 0].min(1) - 1) // 2, 0, width)
     xhi = np.clip((P[:, :, 0].max(1) - 1) // 2 + 1, 0, width)
     ylo = np.clip((P[:, :, 1].min(1) - 1) // 2, 0, height)
     yhi = np.clip((P[:, :, 1].max(1) - 1) // 2 + 1, 0, height)
-    for t in range(T.shape[0]):
-        if xlo[t] >= xhi[t] or ylo[t] >= yhi[t]:
+    bw, bh = xhi - xlo, yhi - ylo
+    keys = bw * (height + 1) + bh
+    for key in np.unique(keys):
+        ts = np.nonzero(keys == key)[0]
+        w, h = int(bw[ts[0]]), int(bh[ts[0]])
+        if w <= 0 or h <= 0:
             continue
-        jj, ii = np.meshgrid(np.arange(xlo[t], xhi[t]), np.arange(ylo[t], yhi[t]))
-        px, py = 2 * jj + 1, 2 * ii + 1
-        inside = np.ones(px.shape, dtype=bool)
-        for k in range(3):
-            a, b = P[t, k], P[t, (k + 1) % 3]
-            cr = (b[0] - a[0]) * (py - a[1]) - (b[1] - a[1]) * (px - a[0])
-            inside &= cr >= 0
-        sub = t6[ylo[t]:yhi[t], xlo[t]:xhi[t]]
-        sub[inside] = np.minimum(sub[inside], t)
+        for chunk in np.array_split(ts, max(1, ts.size * w * h // 4_000_000 + 1)):
+            jj = xlo[chunk, None, None] + np.arange(w)[None, None, :]
+            ii = ylo[chunk, None, None] + np.arange(h)[None, :, None]
+            px, py = 2 * jj + 1, 2 * ii + 1
+            inside = np.ones((chunk.size, h, w), dtype=bool)
+            for k in range(3):
+                a = P[chunk, k][:, :, None, None]
+                b = P[chunk, (k + 1) % 3][:, :, None, None]
+                cr = (b[:, 0] - a[:, 0]) * (py - a[:, 1]) - (b[:, 1] - a[:, 1]) * (px - a[:, 0])
+                inside &= cr >= 0
+            tid = np.broadcast_to(chunk[:, None, None], inside.shape)
+            flat = (ii * width + jj)
+            flat = np.broadcast_to(flat, inside.shape)
+            np.minimum.at(t6, flat[inside], tid[inside])
     t6[t6 == big] = -1
-    return t6.astype(np.int64)
+    return t6.reshape(height, width)
 
 
 def tables(V, T, height: int, width: int) -> dict:
