@@ -118,7 +118,18 @@ def main() -> int:
     ap.add_argument("--fwdbwd-iters", type=int, default=100, help="0 skips the fwd+bwd leg")
     ap.add_argument("--batched-pairs", type=int, default=256, help="0 skips the batched leg")
     ap.add_argument("--batched-iters", type=int, default=100)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel(), "copies": 5}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
               f"sharding of this path is described in DESIGN.md and not built.", file=sys.stderr)

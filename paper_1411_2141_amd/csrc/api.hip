@@ -103,14 +103,9 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
   }
   if (n_apex_rows) {
     timed_begin(MR_KF_SOLVE, s);
-    e = launch_apex_fwd((int)n_apex_rows, d_apex_rows.ptr, d_apex_cptr.ptr, d_apex_cidx.ptr,
-                        d_upd.ptr, x, d_apex_t.ptr, d_apex_fitems.ptr, (int)d_apex_fitems.count,
-                        apex_lds, d_apex.ptr, d_apex_inv_row.ptr, d_apex_y.ptr, s);
-    timed_end(s);
-    if (e != hipSuccess) return e;
-    timed_begin(MR_KF_SOLVE, s);
-    e = launch_apex_bwd(d_apex_bitems.ptr, (int)d_apex_bitems.count, apex_lds, d_apex.ptr,
-                        d_apex_inv_col.ptr, d_apex_rows.ptr, d_apex_y.ptr, x, d_perm.ptr, out, s);
+    e = launch_apex_solve((int)n_apex_rows, d_apex_rows.ptr, d_apex_cptr.ptr, d_apex_cidx.ptr,
+                          d_upd.ptr, x, d_apex_t.ptr, d_apex_items.ptr, (int)d_apex_items.count,
+                          apex_lds, d_apex.ptr, d_apex_gram.ptr, d_perm.ptr, out, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
@@ -303,9 +298,9 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> apex_rows_g;
   std::vector<int64_t> apex_cptr_g(1, 0);
   std::vector<int32_t> apex_cidx_g;
-  std::vector<double> apex_inv_row_g, apex_inv_col_g;
   std::vector<ApexDesc> apex_desc;
-  std::vector<int2> apex_fitems, apex_bitems;
+  std::vector<int2> apex_items;
+  int64_t gram_total = 0;
   int32_t apex_nmax = 0;
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
@@ -390,7 +385,8 @@ int mr_ctx::upload_all(hipStream_t s) {
     // apex of this pair
     {
       const int32_t na = (int32_t)pl.apex_rows.size();
-      ApexDesc ad{na, 0, (int64_t)apex_rows_g.size(), (int64_t)apex_inv_row_g.size()};
+      ApexDesc ad{na, 0, (int64_t)apex_rows_g.size(), gram_total};
+      gram_total += (int64_t)na * na;
       apex_desc.push_back(ad);
       apex_off.push_back(ad.inv_off);
       apex_nmax = std::max(apex_nmax, na);
@@ -400,12 +396,7 @@ int mr_ctx::upload_all(hipStream_t s) {
           apex_cidx_g.push_back((int32_t)(uoff + pl.apex_cidx[q]));
         apex_cptr_g.push_back((int64_t)apex_cidx_g.size());
       }
-      apex_inv_row_g.insert(apex_inv_row_g.end(), pl.apex_inv_row.begin(), pl.apex_inv_row.end());
-      apex_inv_col_g.insert(apex_inv_col_g.end(), pl.apex_inv_col.begin(), pl.apex_inv_col.end());
-      for (int32_t i = 0; i < na; i += kApexRowsPerGroup) {
-        apex_fitems.push_back(make_int2(p, i));
-        apex_bitems.push_back(make_int2(p, i));
-      }
+      for (int32_t i = 0; i < na; i += kApexRowsPerGroup) apex_items.push_back(make_int2(p, i));
     }
     const int64_t co = (int64_t)cidx.size();
     for (int r = 0; r < h.n; ++r) cptr[no + r + 1] = co + pl.cptr[r + 1];
@@ -450,12 +441,11 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_apex_rows, apex_rows_g, s));
   HIP_TRY(upload(d_apex_cptr, apex_cptr_g, s));
   HIP_TRY(upload(d_apex_cidx, apex_cidx_g, s));
-  HIP_TRY(upload(d_apex_inv_row, apex_inv_row_g, s));
-  HIP_TRY(upload(d_apex_inv_col, apex_inv_col_g, s));
-  HIP_TRY(upload(d_apex_fitems, apex_fitems, s));
-  HIP_TRY(upload(d_apex_bitems, apex_bitems, s));
+  HIP_TRY(upload(d_apex_items, apex_items, s));
   HIP_TRY(d_apex_t.alloc(std::max<int64_t>(n_apex_rows, 1)));
-  HIP_TRY(d_apex_y.alloc(std::max<int64_t>(n_apex_rows, 1)));
+  HIP_TRY(d_apex_gram.alloc(std::max<int64_t>(gram_total, 1)));
+  for (int p = 0; p < n_pairs; ++p)
+    if (int rc = upload_apex_gram(p, s)) return rc;
   HIP_TRY(upload(d_fwd_items, fwd_items, s));
   HIP_TRY(upload(d_bwd_items, bwd_items, s));
   HIP_TRY(d_partials2.alloc(std::max(n_partials, 1)));
@@ -490,8 +480,7 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
                      : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
   };
   HIP_TRY(put(d_prow.ptr + panel_off[p], pl.panel_row));
-  HIP_TRY(put(d_apex_inv_row.ptr + apex_off[p], pl.apex_inv_row));
-  HIP_TRY(put(d_apex_inv_col.ptr + apex_off[p], pl.apex_inv_col));
+  if (int rc = upload_apex_gram(p, s)) return rc;
   HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
   HIP_TRY(put(d_drow.ptr + dense_off[p], pl.dinv_row));
   HIP_TRY(hipStreamSynchronize(s));
@@ -506,8 +495,21 @@ int64_t mr_ctx::device_bytes() const {
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
                    d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
-                   d_apex_inv_row.bytes() + d_apex_inv_col.bytes() + d_apex_cidx.bytes() +
+                   d_apex_gram.bytes() + d_apex_cidx.bytes() +
                    d_msd_tmp.bytes() + d_flags.bytes());
+}
+
+// Dense symmetric apex operator G = X^T X, X = L(apex, apex)^-1, of one pair,
+// formed on the device from the host's packed inverse.
+int mr_ctx::upload_apex_gram(int p, hipStream_t s) {
+  const SolvePlan &pl = host[p].plan;
+  const int n = (int)pl.apex_rows.size();
+  if (n == 0) return MR_OK;
+  DevArray<double> xrow;
+  HIP_TRY(upload(xrow, pl.apex_inv_row, s));
+  HIP_TRY(launch_apex_gram(n, xrow.ptr, d_apex_gram.ptr + apex_off[p], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MR_OK;
 }
 
 // B-spline coefficients (B^-1 along rows, then columns) of one pair's FP32 or

@@ -80,9 +80,9 @@ struct mr_ctx {
   mr::DevArray<mr::ApexDesc> d_apex;
   mr::DevArray<int32_t> d_apex_rows, d_apex_cidx;
   mr::DevArray<int64_t> d_apex_cptr;
-  mr::DevArray<double> d_apex_inv_row, d_apex_inv_col;
-  mr::DevArray<int2> d_apex_fitems, d_apex_bitems;
-  mr::DevArray<double2> d_apex_t, d_apex_y;
+  mr::DevArray<double> d_apex_gram;            // dense symmetric apex operator per pair
+  mr::DevArray<int2> d_apex_items;
+  mr::DevArray<double2> d_apex_t;
   int32_t bwd_split_rows = 128;              // panel rows per backward workgroup
   mr::DevArray<unsigned> d_blk_counters;
   mr::DevArray<int64_t> d_cptr;
@@ -113,6 +113,7 @@ struct mr_ctx {
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
   int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
   int upload_adjoint_operators(hipStream_t s);
+  int upload_apex_gram(int p, hipStream_t s);
   hipError_t sample(const double2 *u, double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
   hipError_t solve(double2 *x, double2 *out, hipStream_t s);

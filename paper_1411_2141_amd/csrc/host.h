@@ -59,13 +59,14 @@ struct SolvePlan {
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
   int32_t max_below = 0;
   // Apex: the top of the block tree (blocks with fwd_level >= apex_level)
-  // solved as one dense unit: rows ascending, the packed lower triangle of
-  // L(apex, apex)^-1 row-major (forward) and column-major (backward), and per
-  // apex row the update-buffer positions written by non-apex blocks.
+  // solved as one dense unit: rows ascending, the packed row-major lower
+  // triangle of L(apex, apex)^-1 (the device forms the symmetric product of its
+  // transpose with itself), and per apex row the update-buffer positions
+  // written by non-apex blocks.
   int32_t apex_level = 0;                  // == n_fwd_levels when there is no apex
   std::vector<uint8_t> is_apex;            // per block
   std::vector<int32_t> apex_rows;
-  std::vector<double> apex_inv_row, apex_inv_col;
+  std::vector<double> apex_inv_row;
   std::vector<int64_t> apex_cptr;          // apex rows + 1
   std::vector<int32_t> apex_cidx;
   std::vector<int32_t> rel_bwd_level;      // backward level of non-apex blocks below the apex

@@ -479,7 +479,6 @@ void fill_apex_inverse(PairHost &p) {
   const Factor &L = p.L;
   const int64_t nt = (int64_t)pl.apex_rows.size();
   pl.apex_inv_row.assign(nt * (nt + 1) / 2, 0.0);
-  pl.apex_inv_col.assign(nt * (nt + 1) / 2, 0.0);
   if (nt == 0) return;
   // sparse L(apex, apex) by columns, in apex positions
   std::vector<int32_t> pos(L.n, -1);
@@ -503,11 +502,7 @@ void fill_apex_inverse(PairHost &p) {
       const double xj = x[j];
       for (auto &e : col[j]) x[e.first] -= e.second * xj;
     }
-    const int64_t oc = c * nt - c * (c - 1) / 2;
-    for (int64_t i = c; i < nt; ++i) {
-      pl.apex_inv_col[oc + (i - c)] = x[i];
-      pl.apex_inv_row[i * (i + 1) / 2 + c] = x[i];
-    }
+    for (int64_t i = c; i < nt; ++i) pl.apex_inv_row[i * (i + 1) / 2 + c] = x[i];
   }
 }
 

@@ -27,14 +27,12 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
                                   const double *drow, const double *prow, double2 *x,
                                   const int32_t *perm, double2 *out, double2 *partials,
                                   unsigned *counters, hipStream_t s);
-hipError_t launch_apex_fwd(int n_rows, const int32_t *rows, const int64_t *acptr,
-                           const int32_t *acidx, const double2 *upd, const double2 *x,
-                           double2 *tbuf, const int2 *items, int n_items, int lds_bytes,
-                           const ApexDesc *apex, const double *inv_row, double2 *ybuf,
-                           hipStream_t s);
-hipError_t launch_apex_bwd(const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
-                           const double *inv_col, const int32_t *rows, const double2 *ybuf,
-                           double2 *x, const int32_t *perm, double2 *out, hipStream_t s);
+hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,
+                             const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
+                             const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
+                             const double *gram, const int32_t *perm, double2 *out,
+                             hipStream_t s);
+hipError_t launch_apex_gram(int n, const double *xrow, double *g, hipStream_t s);
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
                                 int n_pairs, const double2 *u, const int2 *xy, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,

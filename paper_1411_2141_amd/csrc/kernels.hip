@@ -455,75 +455,76 @@ __global__ __launch_bounds__(256) void k_apex_rhs(int n_rows, const int32_t *__r
   tbuf[g] = make_double2(bb.x - ax, bb.y - ay);
 }
 
-// Apex of the forward solve, step 2: y = L(apex, apex)^-1 t, one wavefront per
-// row over the row-major packed inverse (t staged in LDS).  Work item =
-// (pair, first row).
-__global__ __launch_bounds__(256) void k_apex_fwd(const int2 *__restrict__ items,
-                                                  const ApexDesc *__restrict__ apex,
-                                                  const double *__restrict__ inv_row,
-                                                  const double2 *__restrict__ tbuf,
-                                                  double2 *__restrict__ ybuf) {
+// Apex, step 2: z = G t with G = L(apex,apex)^-T L(apex,apex)^-1 (dense,
+// symmetric, row-major), i.e. both triangular solves of the apex at once; one
+// wavefront per row (t staged in LDS); z goes to x and, when `out` is given,
+// to natural node order.  Work item = (pair, first row).
+__global__ __launch_bounds__(256) void k_apex_solve(const int2 *__restrict__ items,
+                                                    const ApexDesc *__restrict__ apex,
+                                                    const double *__restrict__ gram,
+                                                    const int32_t *__restrict__ rows,
+                                                    const double2 *__restrict__ tbuf, double2 *x,
+                                                    const int32_t *__restrict__ perm,
+                                                    double2 *__restrict__ out) {
   extern __shared__ double smem[];
   double2 *tl = reinterpret_cast<double2 *>(smem);
   const int2 it = items[blockIdx.x];
   const ApexDesc A = apex[it.x];
-  const int last = min(A.n - 1, it.y + kApexRowsPerGroup - 1);
-  for (int j = threadIdx.x; j <= last; j += blockDim.x) tl[j] = tbuf[A.rows_off + j];
+  for (int j = threadIdx.x; j < A.n; j += blockDim.x) tl[j] = tbuf[A.rows_off + j];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int i = it.y + (threadIdx.x >> 6);
-  if (i > last) return;
-  const double *row = inv_row + A.inv_off + (int64_t)i * (i + 1) / 2;
+  if (i >= A.n) return;
+  const double *row = gram + A.inv_off + (int64_t)i * A.n;
   double ax = 0.0, ay = 0.0;
-#pragma unroll 8
-  for (int j = lane; j <= i; j += 64) {
-    const double v = row[j];
-    ax += v * tl[j].x;
-    ay += v * tl[j].y;
+  constexpr int U = 8;
+  for (int j0 = lane; j0 < A.n; j0 += 64 * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + 64 * u;
+      v[u] = j < A.n ? row[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + 64 * u;
+      if (j < A.n) {
+        ax += v[u] * tl[j].x;
+        ay += v[u] * tl[j].y;
+      }
+    }
   }
   ax = wave_sum(ax);
   ay = wave_sum(ay);
-  if (lane == 0) ybuf[A.rows_off + i] = make_double2(ax, ay);
+  if (lane == 0) {
+    const double2 z = make_double2(ax, ay);
+    const int r = rows[A.rows_off + i];
+    x[r] = z;
+    if (out) out[perm[r]] = z;
+  }
 }
 
-// Apex of the backward solve: z = L(apex, apex)^-T y, one wavefront per
-// column over the column-major packed inverse (y staged in LDS); z goes to x
-// and, when `out` is given, to natural node order.  Work item = (pair, first
-// column).
-__global__ __launch_bounds__(256) void k_apex_bwd(const int2 *__restrict__ items,
-                                                  const ApexDesc *__restrict__ apex,
-                                                  const double *__restrict__ inv_col,
-                                                  const int32_t *__restrict__ rows,
-                                                  const double2 *__restrict__ ybuf, double2 *x,
-                                                  const int32_t *__restrict__ perm,
-                                                  double2 *__restrict__ out) {
-  extern __shared__ double smem[];
-  double2 *yl = reinterpret_cast<double2 *>(smem);
-  const int2 it = items[blockIdx.x];
-  const ApexDesc A = apex[it.x];
-  const int first = it.y;
-  for (int i = first + (int)threadIdx.x; i < A.n; i += blockDim.x) yl[i - first] = ybuf[A.rows_off + i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int j = first + (threadIdx.x >> 6);
-  if (j >= A.n) return;
-  const int64_t n = A.n;
-  const double *col = inv_col + A.inv_off + (int64_t)j * n - (int64_t)j * (j - 1) / 2 - j;
-  double zx = 0.0, zy = 0.0;
-#pragma unroll 8
-  for (int i = j + lane; i < A.n; i += 64) {
-    const double v = col[i];
-    zx += v * yl[i - first].x;
-    zy += v * yl[i - first].y;
+// G = X^T X for the lower-triangular X = L(apex,apex)^-1 given as a packed
+// row-major triangle (init / re-factorisation only): 16x16 output tiles,
+// k-tiles staged in LDS.
+__global__ __launch_bounds__(256) void k_apex_gram(int n, const double *__restrict__ xrow,
+                                                   double *__restrict__ g) {
+  __shared__ double Xi[16][17], Xj[16][17];
+  const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
+  const int r = threadIdx.x / 16, c = threadIdx.x % 16;
+  double acc = 0.0;
+  for (int k0 = max(ti, tj); k0 < n; k0 += 16) {
+    const int k = k0 + r;
+    // X[k][col] for col = ti + c and tj + c (zero above the diagonal)
+    const int ci = ti + c, cj = tj + c;
+    Xi[r][c] = (k < n && ci <= k) ? xrow[(int64_t)k * (k + 1) / 2 + ci] : 0.0;
+    Xj[r][c] = (k < n && cj <= k) ? xrow[(int64_t)k * (k + 1) / 2 + cj] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += Xi[q][r] * Xj[q][c];
+    __syncthreads();
   }
-  zx = wave_sum(zx);
-  zy = wave_sum(zy);
-  if (lane == 0) {
-    const double2 z = make_double2(zx, zy);
-    const int row = rows[A.rows_off + j];
-    x[row] = z;
-    if (out) out[perm[row]] = z;
-  }
+  if (ti + r < n && tj + c < n) g[(int64_t)(ti + r) * n + (tj + c)] = acc;
 }
 
 // Warp + MSD over kTile x kTile pixel tiles.  Each workgroup writes its FP64
@@ -667,23 +668,22 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   return hipGetLastError();
 }
 
-hipError_t launch_apex_fwd(int n_rows, const int32_t *rows, const int64_t *acptr,
-                           const int32_t *acidx, const double2 *upd, const double2 *x,
-                           double2 *tbuf, const int2 *items, int n_items, int lds_bytes,
-                           const ApexDesc *apex, const double *inv_row, double2 *ybuf,
-                           hipStream_t s) {
+hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,
+                             const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
+                             const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
+                             const double *gram, const int32_t *perm, double2 *out,
+                             hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   k_apex_rhs<<<(n_rows + 255) / 256, 256, 0, s>>>(n_rows, rows, acptr, acidx, upd, x, tbuf);
-  k_apex_fwd<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, inv_row, tbuf, ybuf);
+  k_apex_solve<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, gram, rows, tbuf, x,
+                                                                  perm, out);
   return hipGetLastError();
 }
 
-hipError_t launch_apex_bwd(const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
-                           const double *inv_col, const int32_t *rows, const double2 *ybuf,
-                           double2 *x, const int32_t *perm, double2 *out, hipStream_t s) {
-  if (n_items == 0) return hipSuccess;
-  k_apex_bwd<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, inv_col, rows, ybuf,
-                                                                x, perm, out);
+hipError_t launch_apex_gram(int n, const double *xrow, double *g, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int t = (n + 15) / 16;
+  k_apex_gram<<<dim3(t, t), 256, 0, s>>>(n, xrow, g);
   return hipGetLastError();
 }
 
