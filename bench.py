@@ -38,15 +38,15 @@ METRIC = "node-updates/s per registration iteration, fwd+bwd vs plain; achieved 
 HBM_PEAK_GBS = 8000.0
 
 
-def family_bytes(ctx, pairs) -> dict:
-    """Algorithmic bytes per launch of each kernel family (each datum once),
-    summed over the pairs of the context; the solve entry is per solve call."""
+def unit_bytes(ctx, pairs) -> dict:
+    """Algorithmic bytes of one pass of each stage over all pairs of the
+    context (each datum counted once)."""
     n = sum(p.n_nodes for p in pairs)
     nt = sum(int(p.T.shape[0]) for p in pairs)
     pix = sum(p.height * p.width for p in pairs)
+    tiles = sum(-(-p.height // 16) * -(-p.width // 16) for p in pairs)
     nnz_m = sum(ctx.info(k, "mass_nnz") for k in range(len(pairs)))
-    panel = sum(ctx.info(k, "solve_offblock") for k in range(len(pairs)))
-    dense = sum(ctx.info(k, "solve_dense") for k in range(len(pairs)))
+    solve = sum(ctx.info(k, "solve_bytes") for k in range(len(pairs)))
     taps = 0
     for p in pairs:                      # coefficients touched by node samples at u = 0
         H, W = p.height, p.width
@@ -59,35 +59,49 @@ def family_bytes(ctx, pairs) -> dict:
     return {
         "sample": 36 * n + 4 * taps,
         "assemble": 48 * n + 8 * nnz_m,
-        "solve_call": 2 * (32 * n + 8 * panel + 8 * dense + 8 * n) + 20 * n,
-        "warp": 12 * pix + 24 * n + 16 * nt,
+        "solve": solve,
+        "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
+        "finish": 8 * tiles + 8 * len(pairs),
     }
 
 
-def profile(ctx, run, steps, nbytes) -> tuple:
-    """Per-family HIP-event timing of one run; returns (kernels, roofline)."""
+def run_bytes(ub: dict, iters: int, trace: bool) -> dict:
+    """Algorithmic bytes per kernel family of one ``step`` of ``iters``
+    iterations.  The force assembly runs inside the first forward solve
+    launch (solve family).  With an MSD trace the warp of iterate k's result
+    shares the sample launch of iterate k+1 and its final sum the first solve
+    launch; the last result is warped by one warp + finish pair."""
+    w = max(iters - 1, 0) if trace else 0
+    return {"sample": iters * ub["sample"] + w * ub["warp"],
+            "assemble": 0,
+            "solve": iters * (ub["solve"] + ub["assemble"]) + w * ub["finish"],
+            "warp": (ub["warp"] + ub["finish"]) if (trace and iters) else 0}
+
+
+def profile(ctx, run, total_bytes: dict) -> tuple:
+    """Per-family timing of one run from events attached to each kernel
+    dispatch; returns (kernels, roofline of the family with the largest
+    share of GPU time)."""
     import torch
     ctx.enable_timing(True)
     run()
     torch.cuda.synchronize()
     times = ctx.kernel_times()
     ctx.enable_timing(False)
-    solve_launches = max(1, times["solve"][1])
-    per_launch = {"sample": nbytes["sample"], "assemble": nbytes["assemble"], "warp": nbytes["warp"],
-                  "solve": nbytes["solve_call"] * (steps / solve_launches)}
     total = sum(t[0] for t in times.values())
     kernels = {}
     for fam, (ms, cnt) in times.items():
         if cnt:
-            avg = ms / cnt
-            kernels[fam] = {"avg_us": round(avg * 1e3, 3), "launches": cnt,
-                            "gbs": round(per_launch[fam] / (avg * 1e-3) / 1e9, 2),
+            kernels[fam] = {"avg_us": round(ms / cnt * 1e3, 3), "launches": cnt,
+                            "total_ms": round(ms, 4),
+                            "gbs": round(total_bytes[fam] / (ms * 1e-3) / 1e9, 2),
                             "share": round(ms / total, 4)}
     dom = max(kernels, key=lambda f: kernels[f]["share"])
     ach = kernels[dom]["gbs"]
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
-            "bytes_per_launch": int(per_launch[dom]), "avg_launch_us": kernels[dom]["avg_us"]}
+            "bytes_per_launch": int(total_bytes[dom] / kernels[dom]["launches"]),
+            "avg_launch_us": kernels[dom]["avg_us"]}
     return kernels, roof
 
 
@@ -148,43 +162,63 @@ def main() -> int:
 
     tau = 0.5
     n = pair.n_nodes
-    ctx = pkg.MeshReg([pair], tau=tau)
-    u = ctx.zeros_u()
-    trace = torch.empty((max(args.steps, args.warmup), 1), dtype=torch.float64, device="cuda")
+    K = args.steps
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx = pkg.MeshReg([pair], tau=tau, graph=True)
+        u = ctx.zeros_u()
+        trace = torch.empty((K, 1), dtype=torch.float64, device="cuda")
 
-    def run(k):
-        B.mesh_reg_step(ctx.ctx, u, k, trace, torch.cuda.current_stream().cuda_stream)
+        def run(k):
+            B.mesh_reg_step(ctx.ctx, u, k, trace, side.cuda_stream)
 
-    run(args.warmup)
-    torch.cuda.synchronize()
-    u.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    final_msd = float(trace[args.steps - 1, 0].item())
-    value = n * args.steps / dt
-
-    kernels, roof = {}, None
-    if not args.no_profile:
+        # warm-up: W eager iterations, then the K-iteration graph is captured
+        # and replayed once
+        ctx.set_graph(False)
+        run(args.warmup)
+        side.synchronize()
+        ctx.set_graph(True)
         u.zero_()
-        kernels, roof = profile(ctx, lambda: run(args.steps), args.steps,
-                                family_bytes(ctx, [pair]))
+        run(K)
+        side.synchronize()
+        u.zero_()
+        side.synchronize()
+        t0 = time.perf_counter()
+        run(K)                                  # graph replay: K iterations, MSD every iteration
+        side.synchronize()
+        dt = time.perf_counter() - t0
+        final_msd = float(trace[K - 1, 0].item())
+        value = n * K / dt
+
+        # the same K iterations launched eagerly (no graph), for comparison
+        ctx.set_graph(False)
+        u.zero_()
+        side.synchronize()
+        t0 = time.perf_counter()
+        run(K)
+        side.synchronize()
+        dt_eager = time.perf_counter() - t0
+
+        kernels, roof = {}, None
+        if not args.no_profile:
+            u.zero_()
+            kernels, roof = profile(ctx, lambda: run(K),
+                                    run_bytes(unit_bytes(ctx, [pair]), K, True))
 
     fwd_bwd = None
     if args.fwdbwd_iters:
         N = args.fwdbwd_iters
-        u0 = ctx.zeros_u()
-        ctx.backward(u0, N, 10)             # warm-up (allocates the adjoint buffers)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        uu = u0.clone()
-        ctx.step(uu, N)
-        ctx.warp_msd(uu)
-        msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
-        torch.cuda.synchronize()
-        dtb = time.perf_counter() - t0
+        with torch.cuda.stream(side):
+            u0 = ctx.zeros_u()
+            ctx.backward(u0, N, 10)             # warm-up (allocates the adjoint buffers)
+            side.synchronize()
+            t0 = time.perf_counter()
+            uu = u0.clone()
+            B.mesh_reg_step(ctx.ctx, uu, N, None, side.cuda_stream)     # eager (graph off)
+            ctx.warp_msd(uu)
+            msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
+            side.synchronize()
+            dtb = time.perf_counter() - t0
         fwd_bwd = {"value": round(n * N / dtb, 1), "unit": "node-updates/s",
                    "iterations": N, "ckpt_every": 10, "ms_per_iteration": round(dtb / N * 1e3, 4),
                    "vs_plain": round(n * N / dtb / value, 4),
@@ -196,28 +230,29 @@ def main() -> int:
     batched = None
     if batch:
         nb = sum(p.n_nodes for p in batch)
-        side = torch.cuda.Stream()
         with torch.cuda.stream(side):
             bctx = pkg.MeshReg(batch, tau=tau, graph=True)
             ub = bctx.zeros_u()
-            K = args.batched_iters
-            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)     # capture + warm-up
+            KB = args.batched_iters
+            B.mesh_reg_step(bctx.ctx, ub, KB, None, side.cuda_stream)     # capture + warm-up
             side.synchronize()
             ub.zero_()
             side.synchronize()
             t0 = time.perf_counter()
-            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)
+            B.mesh_reg_step(bctx.ctx, ub, KB, None, side.cuda_stream)
             msd_b = bctx.warp_msd(ub)
             side.synchronize()
             dtc = time.perf_counter() - t0
             bk, broof = {}, None
             if not args.no_profile:
                 ub.zero_()
-                bk, broof = profile(bctx, lambda: bctx.step(ub, K), K, family_bytes(bctx, batch))
-        batched = {"value": round(nb * K / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
+                bk, broof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, KB, None,
+                                                                  side.cuda_stream),
+                                    run_bytes(unit_bytes(bctx, batch), KB, False))
+        batched = {"value": round(nb * KB / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
                    "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),
-                   "iterations": K, "ms_per_iteration": round(dtc / K * 1e3, 4),
-                   "iterations_per_s": round(K / dtc, 2), "graph": True,
+                   "iterations": KB, "ms_per_iteration": round(dtc / KB * 1e3, 4),
+                   "iterations_per_s": round(KB / dtc, 2), "graph": True,
                    "mean_final_msd": float(msd_b.mean().item()),
                    "kernels": bk, "roofline": broof}
         bctx.close()
@@ -226,14 +261,14 @@ def main() -> int:
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "node-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(dt / K * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "single pair 512x512 12-bit blobs+disk, sine warp A=8, quadtree "
                                "s=1..32 g=0.08, alpha=0.05 tau=0.5, warp+MSD every iteration",
                    "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": pair.height * pair.width,
-                   "iterations": args.steps, "parallelism": "single GPU",
-                   "final_msd": final_msd},
+                   "iterations": K, "parallelism": "single GPU", "graph": True,
+                   "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
         "kernels": kernels, "roofline": roof, "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd, "batched": batched,
     }

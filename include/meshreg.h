@@ -97,8 +97,10 @@ typedef struct {
   double tau;                  /* step size of eq. 5, > 0 */
   int32_t force_mode;          /* MR_FORCE_P1 (default) or MR_FORCE_NODAL (f = h, eq. 6 literally) */
   int32_t flags;               /* MR_FLAG_* */
-  int32_t apex_rows;           /* solve schedule: rows of the dense apex per pair; 0 = automatic
-                                  (4000 for one pair, shrinking with the batch), -1 = none */
+  int32_t apex_rows;           /* solve schedule: most rows per pair in the apex (the top levels
+                                  of the block tree, solved with the explicit inverse of their
+                                  factor block); 0 = automatic (a level joins while the inverse
+                                  entries it adds stay within 2^21 / n_pairs), -1 = none */
   int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic
                                   (128 for one pair, unsplit for a batch) */
 } mr_params;
@@ -179,17 +181,25 @@ enum {
   MR_INFO_PIXEL_OFFSET = 8, MR_INFO_N_PAIRS = 9, MR_INFO_DEVICE_BYTES = 10,
   MR_INFO_SOLVE_OFFBLOCK = 11,  /* off-block factor entries per direction */
   MR_INFO_SOLVE_DENSE = 12,     /* packed dense-inverse entries per direction */
-  MR_INFO_MASS_NNZ = 13         /* entries of the force operator rows */
+  MR_INFO_MASS_NNZ = 13,        /* entries of the force operator rows */
+  MR_INFO_APEX_ROWS = 14,       /* rows of the apex of the solve (0: none) */
+  MR_INFO_SOLVE_BYTES = 15      /* algorithmic bytes of one solve call (both triangular passes) */
 };
 int mesh_reg_get_info(mr_ctx *ctx, int32_t pair, int32_t key, int64_t *value);
 
-/* Per-kernel timing: when enabled, HIP events are recorded around every launch
- * of each kernel family on the launch stream; mesh_reg_kernel_times returns,
+/* Per-kernel timing: when enabled, every kernel launch carries a start/stop
+ * event pair attached to its dispatch (hipExtLaunchKernel), so host gaps are
+ * not counted; mesh_reg_kernel_times returns,
  * per family (MR_KF_*), the summed milliseconds and the launch count, and resets
  * them.  Synchronises the stream of the last launch. */
 enum { MR_KF_SAMPLE = 0, MR_KF_ASSEMBLE = 1, MR_KF_SOLVE = 2, MR_KF_WARP = 3, MR_KF_COUNT = 4 };
 int mesh_reg_enable_timing(mr_ctx *ctx, int32_t enable);
 int mesh_reg_kernel_times(mr_ctx *ctx, double *ms, int64_t *launches);
+
+/* Switches the graph replay of mesh_reg_step (MR_FLAG_GRAPH) on or off for
+ * later calls; switching it off drops the cached graph.  While timing is
+ * enabled mesh_reg_step always runs eagerly. */
+int mesh_reg_set_graph(mr_ctx *ctx, int32_t enable);
 
 void mesh_reg_destroy(mr_ctx *ctx);
 

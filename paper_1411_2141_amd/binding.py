@@ -23,13 +23,15 @@ TABLES = {"t1_ptr": 10, "t1_slot": 11, "t2_ptr": 20, "t2_idx": 21, "t3_ptr": 30,
           "t4": 40, "t5": 50, "t6": 60, "perm": 70}
 INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "bwd_levels": 6,
         "node_offset": 7, "pixel_offset": 8, "n_pairs": 9, "device_bytes": 10,
-        "solve_offblock": 11, "solve_dense": 12, "mass_nnz": 13}
+        "solve_offblock": 11, "solve_dense": 12, "mass_nnz": 13, "apex_rows": 14,
+        "solve_bytes": 15}
 KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
 EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_warp_msd", "mesh_reg_force",
             "mesh_reg_solve", "mesh_reg_backward", "mesh_reg_set_alpha", "mesh_reg_set_template",
             "mesh_reg_get_tables", "mesh_reg_get_info", "mesh_reg_enable_timing",
-            "mesh_reg_kernel_times", "mesh_reg_destroy", "mesh_reg_last_error")
+            "mesh_reg_kernel_times", "mesh_reg_set_graph", "mesh_reg_destroy",
+            "mesh_reg_last_error")
 
 
 class MeshRegError(RuntimeError):
@@ -77,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mesh_reg_get_info": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(i64)]),
         "mesh_reg_enable_timing": (ctypes.c_int, [vp, i32]),
         "mesh_reg_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "mesh_reg_set_graph": (ctypes.c_int, [vp, i32]),
         "mesh_reg_destroy": (None, [vp]),
         "mesh_reg_last_error": (ctypes.c_char_p, []),
     }
@@ -169,6 +172,10 @@ def mesh_reg_get_info(ctx, pair: int, key: str) -> int:
 
 def mesh_reg_enable_timing(ctx, enable: bool) -> None:
     _check(load_library().mesh_reg_enable_timing(ctx, 1 if enable else 0))
+
+
+def mesh_reg_set_graph(ctx, enable: bool) -> None:
+    _check(load_library().mesh_reg_set_graph(ctx, 1 if enable else 0))
 
 
 def mesh_reg_kernel_times(ctx) -> dict:

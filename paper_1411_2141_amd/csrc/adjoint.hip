@@ -26,6 +26,7 @@
 #include "../../include/meshreg.h"
 #include "ctx.h"
 #include "kernels.h"
+#include "launch.h"
 #include "spline.h"
 
 namespace mr {
@@ -286,10 +287,9 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
   HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
   timed_begin(MR_KF_WARP, s);
-  k_warp_adjoint<<<n_tiles, kTile * kTile, 0, s>>>(d_tiles.ptr, d_pairs.ptr, seg, d_xy.ptr,
-                                                   d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
-                                                   g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr);
-  HIP_OK(hipGetLastError());
+  HIP_OK(launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr, d_pairs.ptr,
+                (const double2 *)seg, d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, g_msd,
+                d_lam.ptr, d_cbar.ptr, d_partials.ptr));
   timed_end(s);
   if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));
   // reverse sweep, one checkpoint segment at a time
@@ -306,26 +306,23 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
       const double2 *uk = seg + (size_t)(k - k0) * N, *uk1 = seg + (size_t)(k - k0 + 1) * N;
       // mu = S^-1 lambda^{k+1}
       HIP_OK(launch_to_solve_order((int)N, d_lam.ptr, d_iperm.ptr, d_x.ptr, s));
-      HIP_OK(solve(d_x.ptr, d_mu.ptr, s));
+      HIP_OK(solve(d_x.ptr, d_mu.ptr, s, nullptr));
       timed_begin(MR_KF_ASSEMBLE, s);
-      k_adjoint_alpha_eta<<<n_node_items, kNodeChunk, 0, s>>>(
-          d_node_items.ptr, d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, d_mu.ptr, uk1,
-          d_eta.ptr, d_alpha_part.ptr, params.tau, params.force_mode == MR_FORCE_NODAL ? 1 : 0);
-      HIP_OK(hipGetLastError());
+      HIP_OK(launch(k_adjoint_alpha_eta, n_node_items, kNodeChunk, 0, s, d_node_items.ptr,
+                    d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, d_mu.ptr, uk1, d_eta.ptr,
+                    d_alpha_part.ptr, params.tau, params.force_mode == MR_FORCE_NODAL ? 1 : 0));
       timed_end(s);
       timed_begin(MR_KF_SAMPLE, s);
-      k_node_adjoint<<<n_node_items, kNodeChunk, 0, s>>>(d_node_items.ptr, d_pairs.ptr, uk,
-                                                         d_xy.ptr, d_coef.ptr, d_rho.ptr,
-                                                         d_mu.ptr, d_eta.ptr, d_lam.ptr,
-                                                         d_cbar.ptr);
-      HIP_OK(hipGetLastError());
+      HIP_OK(launch(k_node_adjoint, n_node_items, kNodeChunk, 0, s, d_node_items.ptr, d_pairs.ptr,
+                    uk, d_xy.ptr, d_coef.ptr, d_rho.ptr, d_mu.ptr, d_eta.ptr, d_lam.ptr,
+                    d_cbar.ptr));
       timed_end(s);
     }
   }
   if (g_u0) HIP_OK(hipMemcpyAsync(g_u0, d_lam.ptr, nb, hipMemcpyDeviceToDevice, s));
   if (g_alpha) {
-    k_alpha_finish<<<1, 256, 0, s>>>(d_pairs.ptr, n_pairs, d_alpha_part.ptr, g_alpha);
-    HIP_OK(hipGetLastError());
+    HIP_OK(launch(k_alpha_finish, 1, 256, 0, s, d_pairs.ptr, n_pairs, d_alpha_part.ptr,
+                  g_alpha));
   }
   if (g_te)
     for (int p = 0; p < n_pairs; ++p) {

@@ -59,30 +59,28 @@ static std::vector<double> thomas_cp(int N) {
 
 }  // namespace mr
 
-void mr_ctx::timed_begin(int fam, hipStream_t s) {
+// Per-launch timing: between timed_begin and timed_end every launch of the
+// calling thread records dispatch-attached events under `fam`.
+void mr_ctx::timed_begin(int fam, hipStream_t) {
   if (!timing) return;
-  hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  hipEventRecord(a, s);
-  pending.push_back({fam, a, b});
+  timer.family = fam;
+  timer.out = &pending;
+  mr::tl_launch_timer = &timer;
 }
 
-void mr_ctx::timed_end(hipStream_t s) {
-  if (!timing || pending.empty()) return;
-  hipEventRecord(pending.back().stop, s);
-}
+void mr_ctx::timed_end(hipStream_t) { mr::tl_launch_timer = nullptr; }
 
 // Launches the two triangular solves on x (solve order, in place).  When `out`
 // is given, the backward pass also scatters the result to natural order there.
-hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s) {
+hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s,
+                               const AssembleArgs *fuse) {
   if (fwd) {
     const int cnt = fwd_ptr[lev + 1] - fwd_ptr[lev];
-    if (!cnt) return hipSuccess;
+    if (!cnt && !fuse) return hipSuccess;
     const int nt = fwd_nt[lev];
     return launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt,
                                   fwd_lds[lev] + 16 * nt, nt, d_cptr.ptr, d_cidx.ptr, d_dcol.ptr,
-                                  d_prow.ptr, x, d_upd.ptr, s);
+                                  d_prow.ptr, x, d_upd.ptr, fuse, s);
   }
   const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
   if (!cnt) return hipSuccess;
@@ -92,27 +90,34 @@ hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipS
                                 x, d_perm.ptr, out, d_partials2.ptr, d_blk_counters.ptr, s);
 }
 
-hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s) {
+// With `fuse`, the right-hand side is assembled by the first forward level's
+// launch (AssembleArgs) instead of being read from x.
+hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const AssembleArgs *fuse) {
   hipError_t e = hipSuccess;
-  for (int lev = 0; lev < (int)fwd_ptr.size() - 1; ++lev) {
-    if (fwd_ptr[lev + 1] == fwd_ptr[lev]) continue;
+  const int n_fl = (int)fwd_ptr.size() - 1;
+  for (int lev = 0; lev < std::max(n_fl, fuse ? 1 : 0); ++lev) {
+    const AssembleArgs *f = lev == 0 ? fuse : nullptr;
+    if (!f && fwd_ptr[lev + 1] == fwd_ptr[lev]) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = solve_level(true, lev, x, out, s);
+    e = solve_level(true, lev, x, out, s, f);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
   if (n_apex_rows) {
     timed_begin(MR_KF_SOLVE, s);
     e = launch_apex_solve((int)n_apex_rows, d_apex_rows.ptr, d_apex_cptr.ptr, d_apex_cidx.ptr,
-                          d_upd.ptr, x, d_apex_t.ptr, d_apex_items.ptr, (int)d_apex_items.count,
-                          apex_lds, d_apex.ptr, d_apex_gram.ptr, d_perm.ptr, out, s);
+                          d_upd.ptr, x, d_apex_t.ptr, d_apex_fitems.ptr,
+                          (int)d_apex_fitems.count, d_apex_xf.ptr, d_apex_part.ptr,
+                          d_apex_arow.ptr, d_apex_y.ptr, d_apex_bitems.ptr,
+                          (int)d_apex_bitems.count, d_apex_rng.ptr, apex_bwd_lds, d_apex_xb.ptr,
+                          d_perm.ptr, out, s);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
   for (int lev = 0; lev < (int)bwd_ptr.size() - 1; ++lev) {
     if (bwd_ptr[lev + 1] == bwd_ptr[lev]) continue;
     timed_begin(MR_KF_SOLVE, s);
-    e = solve_level(false, lev, x, out, s);
+    e = solve_level(false, lev, x, out, s, nullptr);
     timed_end(s);
     if (e != hipSuccess) return e;
   }
@@ -142,7 +147,7 @@ int mr_ctx::tune(hipStream_t s) {
         float t_min = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
           hipError_t e = hipEventRecord(a, s);
-          if (e == hipSuccess) e = solve_level(fwd, (int)lev, d_x.ptr, nullptr, s);
+          if (e == hipSuccess) e = solve_level(fwd, (int)lev, d_x.ptr, nullptr, s, nullptr);
           if (e == hipSuccess) e = hipEventRecord(b, s);
           if (e == hipSuccess) e = hipEventSynchronize(b);
           float ms = 0.0f;
@@ -167,51 +172,59 @@ int mr_ctx::tune(hipStream_t s) {
   return rc;
 }
 
-hipError_t mr_ctx::sample(const double2 *u, double *finish_msd, hipStream_t s) {
+// Sample launch at u; with `with_warp` it also writes the warp partials of u.
+hipError_t mr_ctx::sample(const double2 *u, bool with_warp, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
-  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u, d_xy.ptr,
-                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, d_partials.ptr,
-                               finish_msd, s);
+  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr,
+                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
+                               with_warp ? n_tiles : 0, d_tri.ptr, d_t6.ptr, d_re.ptr,
+                               d_partials.ptr, s);
+  timed_end(s);
+  return e;
+}
+
+hipError_t mr_ctx::assemble(const double2 *u, double *finish_msd, hipStream_t s) {
+  timed_begin(MR_KF_ASSEMBLE, s);
+  hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u,
+                                 d_iperm.ptr, d_x.ptr, params.tau, d_pairs.ptr, n_pairs,
+                                 d_partials.ptr, finish_msd, s);
   timed_end(s);
   return e;
 }
 
 hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
-  hipError_t e = sample(u, nullptr, s);
+  hipError_t e = sample(u, false, s);
   if (e != hipSuccess) return e;
-  timed_begin(MR_KF_ASSEMBLE, s);
-  e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u, d_iperm.ptr,
-                      d_x.ptr, params.tau, s);
-  timed_end(s);
+  return assemble(u, nullptr, s);
+}
+
+// One iteration u <- S^-1 (u - tau f(u)).  `*pending`, when set, is the MSD
+// output for the current u: its warp shares the sample launch and its final
+// sum the assemble launch.  On return `*pending` is `msd_out` (the MSD of the
+// new u, to be produced by the next iteration or by finish_pending).
+hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, hipStream_t s) {
+  double *msd_now = *pending;
+  *pending = nullptr;
+  hipError_t e = sample(u, msd_now != nullptr, s);
+  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr,    d_mwt.ptr,  d_h.ptr,
+                          u,          d_perm.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count,
+                          n_pairs,    params.tau,    d_pairs.ptr, d_partials.ptr,
+                          msd_now};
+  if (e == hipSuccess) e = solve(d_x.ptr, u, s, &fuse);
+  if (e == hipSuccess) *pending = msd_out;
   return e;
 }
 
-// One iteration: sample, force assembly (right-hand side in solve order), the
-// forward and backward solves (the latter writing u), and (if msd_out) the
-// warp partials, whose final sum is left pending for the next sample launch
-// or a finish launch.
-hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, hipStream_t s) {
-  hipError_t e = sample(u, *pending, s);
+hipError_t mr_ctx::finish_pending(const double2 *u, double **pending, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (*pending) e = warp(u, *pending, nullptr, s);
   *pending = nullptr;
-  if (e != hipSuccess) return e;
-  timed_begin(MR_KF_ASSEMBLE, s);
-  e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u, d_iperm.ptr,
-                      d_x.ptr, params.tau, s);
-  timed_end(s);
-  if (e != hipSuccess) return e;
-  e = solve(d_x.ptr, u, s);
-  if (e != hipSuccess || !msd_out) return e;
-  timed_begin(MR_KF_WARP, s);
-  e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr, d_tri.ptr,
-                           d_t6.ptr, d_coef.ptr, d_re.ptr, nullptr, d_partials.ptr, d_flags.ptr, s);
-  timed_end(s);
-  *pending = msd_out;
   return e;
 }
 
 hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_t s) {
   timed_begin(MR_KF_WARP, s);
-  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, n_pairs, u, d_xy.ptr,
+  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, u, d_xy.ptr,
                                       d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
                                       d_partials.ptr, d_flags.ptr, s);
   if (e == hipSuccess) e = launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s);
@@ -298,10 +311,15 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> apex_rows_g;
   std::vector<int64_t> apex_cptr_g(1, 0);
   std::vector<int32_t> apex_cidx_g;
-  std::vector<ApexDesc> apex_desc;
-  std::vector<int2> apex_items;
-  int64_t gram_total = 0;
-  int32_t apex_nmax = 0;
+  std::vector<ApexFwdItem> apex_fitems;
+  std::vector<ApexBwdItem> apex_bitems;
+  std::vector<int2> apex_rng;
+  std::vector<ApexRow> apex_arow;
+  int64_t apex_xf_total = 0, apex_xb_total = 0, apex_part_total = 0;
+  int32_t apex_path_max = 0;
+  std::vector<int32_t> upper_rows;              // solve rows outside the first forward level
+  apex_xf_base.assign(n_pairs, 0);
+  apex_xb_base.assign(n_pairs, 0);
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
   std::vector<int32_t> fwd_bp_v(max_fl, 64), bwd_bp_v(max_bl, 64);
@@ -367,6 +385,8 @@ int mr_ctx::upload_all(hipStream_t s) {
       int32_t bp = 64;
       while (bp < b) bp <<= 1;
       const int32_t id = boff + (int32_t)k;
+      if (pl.is_apex[k] || B.fwd_level != 0)
+        for (int32_t r = B.r0; r < B.r1; ++r) upper_rows.push_back(no + r);
       if (!pl.is_apex[k]) {
         const int32_t bl = pl.rel_bwd_level[k];
         for (int32_t q = 0; q < ns; ++q) fwd_lv[B.fwd_level].push_back(make_int2(id, q));
@@ -382,21 +402,58 @@ int mr_ctx::upload_all(hipStream_t s) {
     drow.insert(drow.end(), pl.dinv_row.begin(), pl.dinv_row.end());
     prow.insert(prow.end(), pl.panel_row.begin(), pl.panel_row.end());
     for (int32_t r : pl.below_idx) below.push_back(no + r);
-    // apex of this pair
+    // apex of this pair, in the shared numbering of apex positions
     {
+      const int32_t A0 = (int32_t)apex_rows_g.size();
       const int32_t na = (int32_t)pl.apex_rows.size();
-      ApexDesc ad{na, 0, (int64_t)apex_rows_g.size(), gram_total};
-      gram_total += (int64_t)na * na;
-      apex_desc.push_back(ad);
-      apex_off.push_back(ad.inv_off);
-      apex_nmax = std::max(apex_nmax, na);
+      apex_xf_base[p] = apex_xf_total;
+      apex_xb_base[p] = apex_xb_total;
       for (int32_t i = 0; i < na; ++i) {
         apex_rows_g.push_back(no + pl.apex_rows[i]);
         for (int64_t q = pl.apex_cptr[i]; q < pl.apex_cptr[i + 1]; ++q)
           apex_cidx_g.push_back((int32_t)(uoff + pl.apex_cidx[q]));
         apex_cptr_g.push_back((int64_t)apex_cidx_g.size());
       }
-      for (int32_t i = 0; i < na; i += kApexRowsPerGroup) apex_items.push_back(make_int2(p, i));
+      apex_xf_total += na ? pl.apex_xf_off[na] : 0;
+      apex_xb_total += na ? pl.apex_xb_off[na] : 0;
+      for (const ApexBlock &A : pl.apex_blocks) {
+        const int32_t nr = A.a1 - A.a0;
+        const int32_t nseg = (A.a1 - A.c0 + kApexSeg - 1) / kApexSeg;
+        if (apex_part_total + (int64_t)nr * nseg >= INT32_MAX) return fail(MR_EINVAL, "apex too large");
+        const int32_t pbase = (int32_t)apex_part_total;
+        apex_part_total += (int64_t)nr * nseg;
+        for (int32_t i = A.a0; i < A.a1; ++i)
+          apex_arow.push_back({pbase + (i - A.a0), nr, (i - A.c0) / kApexSeg + 1,
+                               no + pl.apex_rows[i]});
+        for (int32_t q = 0; q < nseg; ++q) {
+          const int32_t k0 = A.c0 + q * kApexSeg, k1 = std::min(A.a1, k0 + kApexSeg);
+          for (int32_t g = A.a0; g < A.a1; g += kApexRowsPerItem) {
+            const int32_t g1 = std::min(A.a1, g + kApexRowsPerItem);
+            if (g1 - 1 < k0) continue;          // no row of the group reaches the segment
+            apex_fitems.push_back({A0 + g, A0 + g1, A0 + k0, A0 + k1, A0 + A.c0,
+                                   pbase + q * nr + (g - A.a0),
+                                   apex_xf_base[p] + pl.apex_xf_off[g]});
+          }
+        }
+        // ancestor ranges, adjacent ones merged
+        const int32_t roff = (int32_t)apex_rng.size();
+        for (int32_t k = A.anc_off; k < A.anc_off + A.n_anc; ++k) {
+          const ApexBlock &G = pl.apex_blocks[pl.apex_anc[k]];
+          if ((int32_t)apex_rng.size() > roff && apex_rng.back().y == A0 + G.a0)
+            apex_rng.back().y = A0 + G.a1;
+          else
+            apex_rng.push_back(make_int2(A0 + G.a0, A0 + G.a1));
+        }
+        const int32_t nrng = (int32_t)apex_rng.size() - roff;
+        for (int32_t g = A.a0; g < A.a1; g += kApexRowsPerItem) {
+          const int32_t g1 = std::min(A.a1, g + kApexRowsPerItem);
+          const int32_t len = (A.a1 - g) + A.anc_rows;
+          if (len > kApexPath) return fail(MR_EINVAL, "apex path longer than the LDS limit");
+          apex_path_max = std::max(apex_path_max, len);
+          apex_bitems.push_back({A0 + g, A0 + g1, A0 + A.a1, roff, nrng, len,
+                                 apex_xb_base[p] + pl.apex_xb_off[g]});
+        }
+      }
     }
     const int64_t co = (int64_t)cidx.size();
     for (int r = 0; r < h.n; ++r) cptr[no + r + 1] = co + pl.cptr[r + 1];
@@ -435,17 +492,29 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_mwt, mwt, s));
   HIP_TRY(upload(d_blocks, blocks, s));
   n_apex_rows = (int64_t)apex_rows_g.size();
-  apex_lds = 16 * std::max(apex_nmax, 1);
-  if (apex_lds > 64 * 1024) return fail(MR_EINVAL, "apex larger than the LDS limit");
-  HIP_TRY(upload(d_apex, apex_desc, s));
+  HIP_TRY(upload(d_upper_rows, upper_rows, s));
   HIP_TRY(upload(d_apex_rows, apex_rows_g, s));
   HIP_TRY(upload(d_apex_cptr, apex_cptr_g, s));
   HIP_TRY(upload(d_apex_cidx, apex_cidx_g, s));
-  HIP_TRY(upload(d_apex_items, apex_items, s));
+  HIP_TRY(upload(d_apex_fitems, apex_fitems, s));
+  HIP_TRY(upload(d_apex_bitems, apex_bitems, s));
+  HIP_TRY(upload(d_apex_rng, apex_rng, s));
+  HIP_TRY(upload(d_apex_arow, apex_arow, s));
+  HIP_TRY(d_apex_y.alloc(std::max<int64_t>(n_apex_rows, 1)));
+  apex_bwd_lds = 16 * std::max(apex_path_max, 1);
+  HIP_TRY(d_apex_xf.alloc(std::max<int64_t>(apex_xf_total, 1)));
+  HIP_TRY(d_apex_xb.alloc(std::max<int64_t>(apex_xb_total, 1)));
+  HIP_TRY(d_apex_part.alloc(std::max<int64_t>(apex_part_total, 1)));
   HIP_TRY(d_apex_t.alloc(std::max<int64_t>(n_apex_rows, 1)));
-  HIP_TRY(d_apex_gram.alloc(std::max<int64_t>(gram_total, 1)));
-  for (int p = 0; p < n_pairs; ++p)
-    if (int rc = upload_apex_gram(p, s)) return rc;
+  for (int p = 0; p < n_pairs; ++p) {
+    const SolvePlan &pl = host[p].plan;
+    if (!pl.apex_xf.empty())
+      HIP_TRY(hipMemcpyAsync(d_apex_xf.ptr + apex_xf_base[p], pl.apex_xf.data(),
+                             pl.apex_xf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (!pl.apex_xb.empty())
+      HIP_TRY(hipMemcpyAsync(d_apex_xb.ptr + apex_xb_base[p], pl.apex_xb.data(),
+                             pl.apex_xb.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(upload(d_fwd_items, fwd_items, s));
   HIP_TRY(upload(d_bwd_items, bwd_items, s));
   HIP_TRY(d_partials2.alloc(std::max(n_partials, 1)));
@@ -480,7 +549,8 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
                      : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
   };
   HIP_TRY(put(d_prow.ptr + panel_off[p], pl.panel_row));
-  if (int rc = upload_apex_gram(p, s)) return rc;
+  HIP_TRY(put(d_apex_xf.ptr + apex_xf_base[p], pl.apex_xf));
+  HIP_TRY(put(d_apex_xb.ptr + apex_xb_base[p], pl.apex_xb));
   HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
   HIP_TRY(put(d_drow.ptr + dense_off[p], pl.dinv_row));
   HIP_TRY(hipStreamSynchronize(s));
@@ -495,21 +565,10 @@ int64_t mr_ctx::device_bytes() const {
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
                    d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
-                   d_apex_gram.bytes() + d_apex_cidx.bytes() +
+                   d_apex_xf.bytes() + d_apex_xb.bytes() + d_apex_part.bytes() +
+                   d_apex_cidx.bytes() + d_apex_arow.bytes() + d_apex_fitems.bytes() +
+                   d_apex_bitems.bytes() +
                    d_msd_tmp.bytes() + d_flags.bytes());
-}
-
-// Dense symmetric apex operator G = X^T X, X = L(apex, apex)^-1, of one pair,
-// formed on the device from the host's packed inverse.
-int mr_ctx::upload_apex_gram(int p, hipStream_t s) {
-  const SolvePlan &pl = host[p].plan;
-  const int n = (int)pl.apex_rows.size();
-  if (n == 0) return MR_OK;
-  DevArray<double> xrow;
-  HIP_TRY(upload(xrow, pl.apex_inv_row, s));
-  HIP_TRY(launch_apex_gram(n, xrow.ptr, d_apex_gram.ptr + apex_off[p], s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return MR_OK;
 }
 
 // B-spline coefficients (B^-1 along rows, then columns) of one pair's FP32 or
@@ -547,15 +606,12 @@ static int check_ctx(mr_ctx *c, bool need_device) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Dense apex rows per pair when the caller leaves it to the library: a single
-// pair needs the apex to cut the narrow top levels of its block tree; a batch
-// already fills those levels across pairs, and the apex bytes grow with it.
-static int32_t auto_apex_rows(int32_t n_pairs) {
-  if (n_pairs <= 1) return 4000;
-  if (n_pairs <= 4) return 2048;
-  if (n_pairs <= 16) return 1024;
-  if (n_pairs <= 64) return 256;
-  return 0;
+// Entries of X one level may add to the apex, per pair: moving a level into
+// the apex saves two launches of the whole batch (a fixed latency) and costs
+// streaming its entries of X for every pair, so the budget shrinks with the
+// number of pairs.
+static int64_t apex_level_budget(int32_t n_pairs) {
+  return std::max<int64_t>(4096, (int64_t(1) << 21) / std::max(1, n_pairs));
 }
 
 extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
@@ -584,9 +640,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   c->host_only = host_only;
   c->host.resize(n_pairs);
   OrderOptions opt;
-  opt.apex_max = params->apex_rows > 0 ? params->apex_rows
-                 : params->apex_rows < 0 ? 0
-                 : auto_apex_rows(n_pairs);
+  opt.apex_max = params->apex_rows > 0 ? params->apex_rows : params->apex_rows < 0 ? 0 : 1 << 30;
+  opt.apex_level_entries = params->apex_rows > 0 ? (int64_t(1) << 40) : apex_level_budget(n_pairs);
   // splitting a backward panel over workgroups costs a device-scope fence per
   // workgroup; it only pays when a single pair leaves most of the GPU idle
   c->bwd_split_rows = params->bwd_split_rows > 0 ? std::max(8, params->bwd_split_rows)
@@ -675,7 +730,7 @@ int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
   double *pending = nullptr;
   for (int k = 0; k < n_iter; ++k)
     HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, s));
-  if (pending) HIP_TRY(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, pending, s));
+  HIP_TRY(finish_pending(u, &pending, s));
   return MR_OK;
 }
 
@@ -755,7 +810,7 @@ extern "C" int mesh_reg_solve(mr_ctx *c, const double *b, double *x, void *strea
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_to_solve_order((int)c->n_nodes, reinterpret_cast<const double2 *>(b),
                                 c->d_iperm.ptr, c->d_x.ptr, s));
-  HIP_TRY(c->solve(c->d_x.ptr, reinterpret_cast<double2 *>(x), s));
+  HIP_TRY(c->solve(c->d_x.ptr, reinterpret_cast<double2 *>(x), s, nullptr));
   return MR_OK;
 }
 
@@ -777,7 +832,8 @@ extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *s
   }
   fill_dense_inverses(h);
   fill_panels(h);
-  fill_apex_inverse(h);
+  e = fill_apex_inverse(h);
+  if (!e.empty()) return fail(MR_EINVAL, e);
   if (c->host_only) return MR_OK;
   hipStream_t s = (hipStream_t)stream;
   return c->upload_factor(pair, s);
@@ -822,6 +878,29 @@ extern "C" int mesh_reg_get_tables(mr_ctx *c, int32_t pair, int32_t table_id, vo
   return MR_OK;
 }
 
+// Algorithmic bytes of one solve call of a pair, each datum counted once per
+// pass that needs it: the dense inverses (forward and backward copies) and
+// panels (read by both passes) of the blocks below the apex, the apex's X by
+// rows and by columns, the update buffer (written and read) with its index
+// lists, the right-hand side, the intermediate and final vectors, and the
+// result scattered to natural order.
+static int64_t solve_bytes(const PairHost &h) {
+  const SolvePlan &pl = h.plan;
+  int64_t b = 0;
+  for (size_t s = 0; s < pl.blocks.size(); ++s) {
+    if (pl.is_apex[s]) continue;
+    const int64_t r = pl.blocks[s].r1 - pl.blocks[s].r0;
+    const int64_t m = pl.below_ptr[s + 1] - pl.below_ptr[s];
+    b += 2 * 8 * (r * (r + 1) / 2) + 2 * 8 * (m * r);   // dense inverses, panel twice
+    b += 16 * m + 16 * m + 4 * m;                        // updates written and read, below index
+  }
+  b += 4 * (int64_t)pl.cidx.size();                      // contribution lists
+  const int64_t na = (int64_t)pl.apex_rows.size();
+  if (na) b += 8 * (pl.apex_xf_off[na] + pl.apex_xb_off[na]) + 16 * na;   // X twice, t
+  b += (int64_t)h.n * (16 + 16 + 16 + 16 + 16 + 4);     // b in, y out, y in, z out, out, perm
+  return b;
+}
+
 extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
@@ -846,6 +925,8 @@ extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *
     case MR_INFO_MASS_NNZ:
       *value = c->params.force_mode == MR_FORCE_NODAL ? h.n : (int64_t)h.tab.t3_idx.size();
       break;
+    case MR_INFO_APEX_ROWS: *value = (int64_t)h.plan.apex_rows.size(); break;
+    case MR_INFO_SOLVE_BYTES: *value = solve_bytes(h); break;
     case MR_INFO_FWD_LEVELS: *value = h.plan.n_fwd_levels; break;
     case MR_INFO_BWD_LEVELS: *value = h.plan.n_bwd_levels; break;
     case MR_INFO_NODE_OFFSET: {
@@ -869,6 +950,21 @@ extern "C" int mesh_reg_enable_timing(mr_ctx *c, int32_t enable) {
   int rc = check_ctx(c, true);
   if (rc) return rc;
   c->timing = enable != 0;
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_set_graph(mr_ctx *c, int32_t enable) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (enable) {
+    c->params.flags |= MR_FLAG_GRAPH;
+  } else {
+    c->params.flags &= ~MR_FLAG_GRAPH;
+    if (c->graph_exec) {
+      HIP_TRY(hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+    }
+  }
   return MR_OK;
 }
 

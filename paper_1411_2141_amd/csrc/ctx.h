@@ -11,6 +11,7 @@
 #include "../../include/meshreg.h"
 #include "device.h"
 #include "host.h"
+#include "launch.h"
 
 namespace mr {
 
@@ -36,11 +37,6 @@ struct DevArray {
   size_t bytes() const { return count * sizeof(T); }
 };
 
-struct TimedLaunch {
-  int family;
-  hipEvent_t start, stop;
-};
-
 }  // namespace mr
 
 struct mr_ctx {
@@ -53,7 +49,7 @@ struct mr_ctx {
   int64_t n_nodes = 0, n_tris = 0, n_pix = 0, nnz_factor = 0;
   int n_node_items = 0, n_tiles = 0;
   // per pair offsets into the packed factor arrays (for re-factorisation)
-  std::vector<int64_t> dense_off, panel_off, apex_off;
+  std::vector<int64_t> dense_off, panel_off;
 
   mr::DevArray<mr::DevPair> d_pairs;
   mr::DevArray<mr::NodeItem> d_node_items;
@@ -74,14 +70,19 @@ struct mr_ctx {
   std::vector<int32_t> fwd_nt, bwd_nt;       // level -> workgroup size (autotuned)
   std::vector<int32_t> fwd_bp, bwd_bp;       // level -> smallest allowed workgroup size
   mr::DevArray<double2> d_partials2;         // backward slice partial sums
-  // apex (dense top of every pair's block tree)
+  // apex (top of every pair's block tree, explicit inverse by subtree structure)
+  mr::DevArray<int32_t> d_upper_rows;           // solve rows outside the first forward level
   int64_t n_apex_rows = 0;
-  int32_t apex_lds = 0;
-  mr::DevArray<mr::ApexDesc> d_apex;
+  int32_t apex_bwd_lds = 16;                    // dynamic LDS of the apex backward launch
   mr::DevArray<int32_t> d_apex_rows, d_apex_cidx;
   mr::DevArray<int64_t> d_apex_cptr;
-  mr::DevArray<double> d_apex_gram;            // dense symmetric apex operator per pair
-  mr::DevArray<int2> d_apex_items;
+  mr::DevArray<mr::ApexFwdItem> d_apex_fitems;
+  mr::DevArray<mr::ApexBwdItem> d_apex_bitems;
+  mr::DevArray<int2> d_apex_rng;
+  mr::DevArray<mr::ApexRow> d_apex_arow;
+  mr::DevArray<double> d_apex_xf, d_apex_xb;
+  mr::DevArray<double2> d_apex_part, d_apex_y;
+  std::vector<int64_t> apex_xf_base, apex_xb_base;   // per pair offsets into d_apex_xf / d_apex_xb
   mr::DevArray<double2> d_apex_t;
   int32_t bwd_split_rows = 128;              // panel rows per backward workgroup
   mr::DevArray<unsigned> d_blk_counters;
@@ -106,6 +107,7 @@ struct mr_ctx {
 
   bool timing = false;
   std::vector<mr::TimedLaunch> pending;
+  mr::LaunchTimer timer;
 
   ~mr_ctx();
   int upload_all(hipStream_t s);
@@ -113,15 +115,17 @@ struct mr_ctx {
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
   int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
   int upload_adjoint_operators(hipStream_t s);
-  int upload_apex_gram(int p, hipStream_t s);
-  hipError_t sample(const double2 *u, double *finish_msd, hipStream_t s);
+  hipError_t sample(const double2 *u, bool with_warp, hipStream_t s);
+  hipError_t assemble(const double2 *u, double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
-  hipError_t solve(double2 *x, double2 *out, hipStream_t s);
+  hipError_t solve(double2 *x, double2 *out, hipStream_t s, const mr::AssembleArgs *fuse);
   hipError_t iterate(double2 *u, double *msd_out, double **pending, hipStream_t s);
+  hipError_t finish_pending(const double2 *u, double **pending, hipStream_t s);
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
   int tune(hipStream_t s);
-  hipError_t solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s);
+  hipError_t solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s,
+                         const mr::AssembleArgs *fuse);
   int step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s);
   void post_flags(hipStream_t s);
   void timed_begin(int family, hipStream_t s);

@@ -53,15 +53,51 @@ inline int64_t solve_bwd_lds_bytes(int b, int rs, int nt) {
   return 8 * (((int64_t)rs * b + 1) / 2 * 2) + 16 * ((int64_t)rs + nt + b) + 8 * nd;
 }
 
-// Apex (dense top of the block tree) of one pair.
-struct ApexDesc {
-  int32_t n;              // apex rows
-  int32_t pad;
-  int64_t rows_off;       // offset into the apex row list, contribution CSR and t/y buffers
-  int64_t inv_off;        // offset of the packed inverse triangles
+// Apex of the block tree (all pairs share one numbering of apex positions).
+// Forward work item: rows [a0, a1) of one apex block (consecutive, so their
+// rows of X follow each other from xoff0 on, row r holding columns c0 .. r)
+// against the columns [k0, k1) of one segment of the block's column range;
+// the partial sums of row r go to slot part + (r - a0).
+struct ApexFwdItem {
+  int32_t a0, a1, k0, k1, c0, part;
+  int64_t xoff0;
+};
+// Backward work item: rows [a0, a1) of one apex block ending at e; the path
+// list is rows [a0, e) followed by the ancestor ranges rng[rng_off ..
+// rng_off + n_rng), len entries in all; row r's column of X covers list
+// positions r - a0 .. len - 1 and the columns follow each other from xoff0 on.
+struct ApexBwdItem {
+  int32_t a0, a1, e, rng_off, n_rng, len;
+  int64_t xoff0;
+};
+// Per apex position: its forward partial slots part + q * stride, q < nseg.
+struct ApexRow {
+  int32_t part, stride, nseg, row;
 };
 
-constexpr int kApexRowsPerGroup = 4;   // one wavefront per apex row / column
+constexpr int kApexSeg = 1024;        // columns per forward segment (16 KB of LDS)
+constexpr int kApexPath = 2048;       // longest backward path (32 KB of LDS)
+constexpr int kApexRowsPerItem = 8;   // rows per apex work item (two per wavefront)
+
+// Right-hand side assembly folded into the first forward level: b for the
+// rows of the level's (leaf) blocks is formed by their own workgroups, the
+// workgroups after the block items form b for the other solve rows (`rows`,
+// NT per workgroup), and, when finish_msd is set, the workgroups after those
+// finish the MSD of `partials`.
+struct AssembleArgs {
+  const int32_t *mptr, *mcol;
+  const float *mwt;
+  const float2 *h;
+  const double2 *u;
+  const int32_t *perm;          // solve row -> node
+  const int32_t *rows;          // solve rows outside the first level
+  int32_t n_rows;
+  int32_t n_pairs;
+  double tau;
+  const DevPair *pairs;
+  const double *partials;
+  double *finish_msd;
+};
 
 // Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`.
 struct NodeItem {

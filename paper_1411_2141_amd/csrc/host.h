@@ -40,6 +40,13 @@ struct SolveBlock {
   int32_t fwd_group;                       // lanes per row for the forward gathers
 };
 
+// One block of the apex in apex positions: rows [a0, a1); c0 = first apex
+// position of its subtree; anc_off / n_anc index SolvePlan::apex_anc;
+// anc_rows = rows of all its ancestors.
+struct ApexBlock {
+  int32_t a0, a1, c0, anc_off, n_anc, anc_rows;
+};
+
 struct SolvePlan {
   std::vector<SolveBlock> blocks;
   // dense inverses of the diagonal blocks, packed lower triangles:
@@ -58,17 +65,27 @@ struct SolvePlan {
   std::vector<int32_t> cidx;
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
   int32_t max_below = 0;
-  // Apex: the top of the block tree (blocks with fwd_level >= apex_level)
-  // solved as one dense unit: rows ascending, the packed row-major lower
-  // triangle of L(apex, apex)^-1 (the device forms the symmetric product of its
-  // transpose with itself), and per apex row the update-buffer positions
-  // written by non-apex blocks.
+  // Apex: the top of the block tree (blocks with fwd_level >= apex_level),
+  // solved with X = L(apex, apex)^-1 held explicitly.  X(i, j) can be nonzero
+  // only when j's block lies in the subtree of i's block (the inverse of a
+  // triangular factor keeps the elimination-tree ancestry), and in nested-
+  // dissection order the apex rows of a subtree are one contiguous run of
+  // apex positions.  So row i of X is kept from column apex_c0[i] to the
+  // diagonal (forward), and column j of X over the rows of j's block from j on
+  // followed by the rows of that block's ancestors (backward).
   int32_t apex_level = 0;                  // == n_fwd_levels when there is no apex
   std::vector<uint8_t> is_apex;            // per block
-  std::vector<int32_t> apex_rows;
-  std::vector<double> apex_inv_row;
+  std::vector<int32_t> apex_rows;          // solve rows of the apex, ascending
+  std::vector<ApexBlock> apex_blocks;      // ascending apex position
+  std::vector<int32_t> apex_anc;           // per apex block: its ancestors (apex block ids), parent first
+  std::vector<int32_t> apex_c0;            // per apex row
+  std::vector<int32_t> apex_blk;           // per apex row: its apex block
+  std::vector<int64_t> apex_xf_off;        // apex rows + 1: X(i, apex_c0[i] .. i) at apex_xf_off[i]
+  std::vector<double> apex_xf;
+  std::vector<int64_t> apex_xb_off;        // apex rows + 1: X(path(j), j) at apex_xb_off[j]
+  std::vector<double> apex_xb;
   std::vector<int64_t> apex_cptr;          // apex rows + 1
-  std::vector<int32_t> apex_cidx;
+  std::vector<int32_t> apex_cidx;          // update-buffer positions written by non-apex blocks
   std::vector<int32_t> rel_bwd_level;      // backward level of non-apex blocks below the apex
   int32_t n_rel_bwd_levels = 0;
 };
@@ -88,10 +105,15 @@ struct PairHost {
   SolvePlan plan;
 };
 
+// Longest backward path (rows of a block plus rows of its ancestors) an apex
+// may have; the device stages one path in 32 KB of LDS.
+constexpr int32_t kApexPathMax = 2048;
+
 struct OrderOptions {
   int32_t leaf_max = 32;                   // nested-dissection leaf size
   int32_t block_max = 96;                  // largest dense diagonal block
-  int32_t apex_max = 4000;                 // largest apex (0: none); its t/y vectors fit 64 KB of LDS
+  int32_t apex_max = 1 << 30;              // most apex rows (0: no apex)
+  int64_t apex_level_entries = 1 << 21;    // most entries of X one level may add (per direction)
 };
 
 // Each returns an empty string on success, else the reason.
@@ -111,10 +133,12 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
 // Numeric parts of the plan (after a refactor with unchanged structure).
 void fill_dense_inverses(PairHost &p);
 void fill_panels(PairHost &p);
-// Chooses the apex (largest top set of levels within opt.apex_max rows) and
-// builds its structure; fill_apex_inverse computes the dense inverse.
-void build_apex(PairHost &p, const OrderOptions &opt);
-void fill_apex_inverse(PairHost &p);
+// Chooses the apex (the longest top run of levels within opt.apex_max rows,
+// whose backward paths fit kApexPathMax and each of whose levels adds at most
+// opt.apex_level_entries entries to X) and builds its structure;
+// fill_apex_inverse computes the entries of X.  Both return "" or a reason.
+std::string build_apex(PairHost &p, const OrderOptions &opt);
+std::string fill_apex_inverse(PairHost &p);
 
 // Everything above in order.
 std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd);

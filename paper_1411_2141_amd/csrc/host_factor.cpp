@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <functional>
+#include <thread>
 
 #include "host.h"
 
@@ -427,16 +428,40 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
   return "";
 }
 
-void build_apex(PairHost &p, const OrderOptions &opt) {
+std::string build_apex(PairHost &p, const OrderOptions &opt) {
   SolvePlan &pl = p.plan;
   const int32_t nb = (int32_t)pl.blocks.size();
-  // rows per forward level; the apex is the highest run of levels that fits
+  // rows per forward level, and per block the rows of all its ancestors
   std::vector<int64_t> rows_at(pl.n_fwd_levels, 0);
   for (auto &B : pl.blocks) rows_at[B.fwd_level] += B.r1 - B.r0;
+  std::vector<int64_t> anc_rows(nb, 0);
+  std::vector<int32_t> by_level(nb);
+  for (int32_t s = 0; s < nb; ++s) by_level[s] = s;
+  std::stable_sort(by_level.begin(), by_level.end(), [&](int32_t x, int32_t y) {
+    return pl.blocks[x].fwd_level > pl.blocks[y].fwd_level;
+  });
+  for (int32_t s : by_level) {
+    const int32_t q = pl.blocks[s].parent;
+    if (q >= 0) anc_rows[s] = anc_rows[q] + (pl.blocks[q].r1 - pl.blocks[q].r0);
+  }
+  std::vector<int64_t> path_at(pl.n_fwd_levels, 0);     // longest path of a block at a level
+  for (int32_t s = 0; s < nb; ++s)
+    path_at[pl.blocks[s].fwd_level] = std::max<int64_t>(
+        path_at[pl.blocks[s].fwd_level], anc_rows[s] + pl.blocks[s].r1 - pl.blocks[s].r0);
+  // entries a level adds to X: each block's own triangle and its rows
+  // against every ancestor block's rows
+  std::vector<int64_t> ent_at(pl.n_fwd_levels, 0);
+  for (int32_t s = 0; s < nb; ++s) {
+    const int64_t b = pl.blocks[s].r1 - pl.blocks[s].r0;
+    ent_at[pl.blocks[s].fwd_level] += b * (b + 1) / 2 + b * anc_rows[s];
+  }
+  // the apex is the highest run of levels within the limits
   int32_t cut = pl.n_fwd_levels;
   int64_t acc = 0;
   for (int32_t l = pl.n_fwd_levels - 1; l >= 1 && opt.apex_max > 0; --l) {
-    if (acc + rows_at[l] > opt.apex_max) break;
+    if (acc + rows_at[l] > opt.apex_max || path_at[l] > kApexPathMax ||
+        ent_at[l] > opt.apex_level_entries)
+      break;
     acc += rows_at[l];
     cut = l;
   }
@@ -444,12 +469,60 @@ void build_apex(PairHost &p, const OrderOptions &opt) {
   pl.apex_level = cut;
   pl.is_apex.assign(nb, 0);
   pl.apex_rows.clear();
+  pl.apex_blocks.clear();
+  pl.apex_anc.clear();
+  pl.apex_c0.clear();
+  pl.apex_blk.clear();
+  std::vector<int32_t> ablocks;                // apex block -> block id, ascending rows
   for (int32_t s = 0; s < nb; ++s)
     if (pl.blocks[s].fwd_level >= cut) {
       pl.is_apex[s] = 1;
-      for (int32_t r = pl.blocks[s].r0; r < pl.blocks[s].r1; ++r) pl.apex_rows.push_back(r);
+      ablocks.push_back(s);
     }
-  std::sort(pl.apex_rows.begin(), pl.apex_rows.end());
+  std::sort(ablocks.begin(), ablocks.end(),
+            [&](int32_t x, int32_t y) { return pl.blocks[x].r0 < pl.blocks[y].r0; });
+  std::vector<int32_t> apex_id(nb, -1);
+  for (size_t k = 0; k < ablocks.size(); ++k) {
+    const SolveBlock &B = pl.blocks[ablocks[k]];
+    apex_id[ablocks[k]] = (int32_t)k;
+    ApexBlock A{(int32_t)pl.apex_rows.size(), 0, 0, 0, 0, 0};
+    for (int32_t r = B.r0; r < B.r1; ++r) pl.apex_rows.push_back(r);
+    A.a1 = (int32_t)pl.apex_rows.size();
+    A.c0 = A.a0;
+    pl.apex_blocks.push_back(A);
+  }
+  // subtree start: children come before their parent in row order
+  for (size_t k = 0; k < ablocks.size(); ++k) {
+    const int32_t q = pl.blocks[ablocks[k]].parent;
+    if (q >= 0 && apex_id[q] >= 0) {
+      ApexBlock &P = pl.apex_blocks[apex_id[q]];
+      P.c0 = std::min(P.c0, pl.apex_blocks[k].c0);
+    }
+  }
+  for (size_t k = 0; k < ablocks.size(); ++k) {
+    ApexBlock &A = pl.apex_blocks[k];
+    A.anc_off = (int32_t)pl.apex_anc.size();
+    for (int32_t q = pl.blocks[ablocks[k]].parent; q >= 0; q = pl.blocks[q].parent) {
+      if (apex_id[q] < 0) return "apex block with a non-apex ancestor";
+      pl.apex_anc.push_back(apex_id[q]);
+      A.anc_rows += pl.apex_blocks[apex_id[q]].a1 - pl.apex_blocks[apex_id[q]].a0;
+    }
+    A.n_anc = (int32_t)pl.apex_anc.size() - A.anc_off;
+    if (A.a1 - A.a0 + A.anc_rows > kApexPathMax) return "apex path longer than the limit";
+    for (int32_t i = A.a0; i < A.a1; ++i) {
+      pl.apex_c0.push_back(A.c0);
+      pl.apex_blk.push_back((int32_t)k);
+    }
+  }
+  // storage offsets of X by rows (forward) and by columns (backward)
+  const int32_t na = (int32_t)pl.apex_rows.size();
+  pl.apex_xf_off.assign(na + 1, 0);
+  pl.apex_xb_off.assign(na + 1, 0);
+  for (int32_t i = 0; i < na; ++i) {
+    const ApexBlock &A = pl.apex_blocks[pl.apex_blk[i]];
+    pl.apex_xf_off[i + 1] = pl.apex_xf_off[i] + (i - pl.apex_c0[i] + 1);
+    pl.apex_xb_off[i + 1] = pl.apex_xb_off[i] + (A.a1 - i) + A.anc_rows;
+  }
   // contributions to apex rows from non-apex blocks only
   std::vector<int32_t> blk_of_upd(pl.below_idx.size());
   for (int32_t s = 0; s < nb; ++s)
@@ -471,39 +544,78 @@ void build_apex(PairHost &p, const OrderOptions &opt) {
     pl.rel_bwd_level[s] = (par < 0 || pl.is_apex[par]) ? 0 : pl.rel_bwd_level[par] + 1;
     pl.n_rel_bwd_levels = std::max(pl.n_rel_bwd_levels, pl.rel_bwd_level[s] + 1);
   }
-  fill_apex_inverse(p);
+  return fill_apex_inverse(p);
 }
 
-void fill_apex_inverse(PairHost &p) {
+std::string fill_apex_inverse(PairHost &p) {
   SolvePlan &pl = p.plan;
   const Factor &L = p.L;
-  const int64_t nt = (int64_t)pl.apex_rows.size();
-  pl.apex_inv_row.assign(nt * (nt + 1) / 2, 0.0);
-  if (nt == 0) return;
+  const int32_t na = (int32_t)pl.apex_rows.size();
+  pl.apex_xf.assign(pl.apex_xf_off[na], 0.0);
+  pl.apex_xb.assign(pl.apex_xb_off[na], 0.0);
+  if (na == 0) return "";
   // sparse L(apex, apex) by columns, in apex positions
   std::vector<int32_t> pos(L.n, -1);
-  for (int64_t i = 0; i < nt; ++i) pos[pl.apex_rows[i]] = (int32_t)i;
-  std::vector<std::vector<std::pair<int32_t, double>>> col(nt);
-  std::vector<double> diag(nt);
-  for (int64_t j = 0; j < nt; ++j) {
+  for (int32_t i = 0; i < na; ++i) pos[pl.apex_rows[i]] = i;
+  std::vector<std::vector<std::pair<int32_t, double>>> col(na);
+  std::vector<double> diag(na);
+  for (int32_t j = 0; j < na; ++j) {
     const int32_t c = pl.apex_rows[j];
     diag[j] = L.val[L.colptr[c]];
     for (int64_t q = L.colptr[c] + 1; q < L.colptr[c + 1]; ++q)
       if (pos[L.rowidx[q]] >= 0) col[j].emplace_back(pos[L.rowidx[q]], L.val[q]);
   }
-  // column c of the inverse: forward substitution of e_c (column-oriented)
-  std::vector<double> x(nt);
-  for (int64_t c = 0; c < nt; ++c) {
-    std::fill(x.begin() + c, x.end(), 0.0);
-    x[c] = 1.0;
-    for (int64_t j = c; j < nt; ++j) {
-      if (x[j] == 0.0) continue;
-      x[j] /= diag[j];
-      const double xj = x[j];
-      for (auto &e : col[j]) x[e.first] -= e.second * xj;
+  // column c of X: forward substitution of e_c (column-oriented, skipping
+  // zeros); its entries are then read along c's path (c's block from c on,
+  // then the ancestor blocks), and every entry off that path must be zero.
+  // Columns are independent: large apexes split them over threads.
+  auto columns = [&](int32_t c_begin, int32_t c_step, bool *bad) {
+    std::vector<double> x(na, 0.0);
+    for (int32_t c = c_begin; c < na; c += c_step) {
+      x[c] = 1.0;
+      for (int32_t j = c; j < na; ++j) {
+        if (x[j] == 0.0) continue;
+        x[j] /= diag[j];
+        const double xj = x[j];
+        for (auto &e : col[j]) x[e.first] -= e.second * xj;
+      }
+      const ApexBlock &A = pl.apex_blocks[pl.apex_blk[c]];
+      int64_t kb = pl.apex_xb_off[c];
+      auto take = [&](int32_t i) {
+        pl.apex_xf[pl.apex_xf_off[i] + (c - pl.apex_c0[i])] = x[i];
+        pl.apex_xb[kb++] = x[i];
+        x[i] = 0.0;
+      };
+      for (int32_t i = c; i < A.a1; ++i) take(i);
+      for (int32_t k = A.anc_off; k < A.anc_off + A.n_anc; ++k) {
+        const ApexBlock &G = pl.apex_blocks[pl.apex_anc[k]];
+        for (int32_t i = G.a0; i < G.a1; ++i) take(i);
+      }
+      for (int32_t i = c; i < na; ++i)
+        if (x[i] != 0.0) {
+          *bad = true;
+          x[i] = 0.0;
+        }
     }
-    for (int64_t i = c; i < nt; ++i) pl.apex_inv_row[i * (i + 1) / 2 + c] = x[i];
+  };
+  const int32_t nthr =
+      na >= 2048 ? (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+  std::vector<uint8_t> bad(nthr, 0);
+  auto run = [&](int32_t t) {
+    bool b = false;
+    columns(t, nthr, &b);
+    bad[t] = b;
+  };
+  if (nthr == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int32_t t = 0; t < nthr; ++t) th.emplace_back(run, t);
+    for (auto &t : th) t.join();
   }
+  for (uint8_t b : bad)
+    if (b) return "apex inverse has an entry outside the subtree structure";
+  return "";
 }
 
 std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool *not_spd) {
@@ -521,8 +633,7 @@ std::string prepare_pair(PairHost &p, double tau, const OrderOptions &opt, bool 
   if (!e.empty()) return e;
   e = build_solve_plan(p, ranges, rparent, opt);
   if (!e.empty()) return e;
-  build_apex(p, opt);
-  return "";
+  return build_apex(p, opt);
 }
 
 }  // namespace mr

@@ -11,30 +11,37 @@ hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp
                             int H, int W, const double *cp_w, const double *cp_h, hipStream_t s);
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
-hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs, int n_pairs,
+// Sample launch; with n_tiles > 0 it also writes the warp/MSD partials of u.
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
-                         float2 *h, unsigned *flags, const double *partials, double *finish_msd,
+                         float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
+                         const int4 *tri, const int32_t *t6, const float *re, double *partials,
                          hipStream_t s);
+// Assemble launch; with finish_msd it also finishes the MSD of `partials`.
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
-                           double tau, hipStream_t s);
+                           double tau, const DevPair *pairs, int n_pairs, const double *partials,
+                           double *finish_msd, hipStream_t s);
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
                                   const double *dcol, const double *prow, double2 *x,
-                                  double2 *upd, hipStream_t s);
+                                  double2 *upd, const AssembleArgs *fuse, hipStream_t s);
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int32_t *below_idx,
                                   const double *drow, const double *prow, double2 *x,
                                   const int32_t *perm, double2 *out, double2 *partials,
                                   unsigned *counters, hipStream_t s);
+// The apex of the solve: t = b - (non-apex updates), segment partials of
+// y = X t, y, then z = X^T y written to x (and out[perm] when out is given).
 hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,
                              const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
-                             const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
-                             const double *gram, const int32_t *perm, double2 *out,
+                             const ApexFwdItem *fitems, int n_fitems, const double *xf,
+                             double2 *part, const ApexRow *arow, double2 *ybuf,
+                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng,
+                             int bwd_lds, const double *xb, const int32_t *perm, double2 *out,
                              hipStream_t s);
-hipError_t launch_apex_gram(int n, const double *xrow, double *g, hipStream_t s);
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                int n_pairs, const double2 *u, const int2 *xy, const int4 *tri,
+                                const double2 *u, const int2 *xy, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,
                                 float *warped, double *partials, unsigned *flags, hipStream_t s);
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,

@@ -10,9 +10,11 @@
 //   k_solve_fwd / k_solve_bwd
 //               block-level-scheduled FP64 triangular solves with the Cholesky
 //               factor of I + tau alpha K (eq. 7-8 made implicit, solved directly)
-//   k_warp_msd  pixel-tile-parallel: piecewise-linear displacement of each
+//   warp tiles  pixel-tile-parallel: piecewise-linear displacement of each
 //               pixel's triangle, template sample at the displaced pixel centre,
-//               squared error, deterministic FP64 reduction to the MSD
+//               squared error, deterministic FP64 reduction to the MSD; run in
+//               the next iteration's sample launch (both read the same u), the
+//               final sum in its assemble launch
 // All node-, tile- and block-parallel launches cover every pair of a batch
 // through work lists, so one launch per kernel family advances all pairs.
 #include <hip/hip_runtime.h>
@@ -23,6 +25,7 @@
 
 #include "device.h"
 #include "kernels.h"
+#include "launch.h"
 #include "spline.h"
 
 namespace mr {
@@ -104,35 +107,92 @@ __global__ __launch_bounds__(256) void k_sample_rho(const NodeItem *__restrict__
 // Hot path
 // ---------------------------------------------------------------------------
 
-// Second pass of the MSD, run by one workgroup: per pair, the tile partials
-// summed in tile order by one wavefront (deterministic) over the pixel count.
-__device__ __forceinline__ void msd_finish_block(const DevPair *__restrict__ pairs, int n_pairs,
+// Second pass of the MSD: workgroup `group` finishes pairs 4 group .. 4 group + 3,
+// one wavefront per pair summing that pair's tile partials in a fixed order
+// (deterministic) and dividing by its pixel count.
+__device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pairs, int n_pairs,
                                                  const double *__restrict__ partials,
-                                                 double *__restrict__ msd) {
+                                                 double *__restrict__ msd, int group) {
   const int lane = threadIdx.x & 63;
-  for (int p = threadIdx.x >> 6; p < n_pairs; p += blockDim.x >> 6) {
-    const DevPair Q = pairs[p];
-    double s = 0.0;
-    for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
-    s = wave_sum(s);
-    if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
-  }
+  const int p = group * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+  if (p >= n_pairs) return;
+  const DevPair Q = pairs[p];
+  double s = 0.0;
+  for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
+  s = wave_sum(s);
+  if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
 }
 
+// Warp + MSD of one kTile x kTile pixel tile: each pixel takes the
+// piecewise-linear displacement of its triangle (barycentric weights from exact
+// cross products in doubled integer coordinates), the template spline is
+// sampled at the displaced pixel centre (FP64 weights and sums), and the
+// tile's FP64 sum of squared differences goes to partials[tile].
+__device__ __forceinline__ void warp_tile(int tile, const TileItem *__restrict__ tiles,
+                                          const DevPair *__restrict__ pairs,
+                                          const double2 *__restrict__ u,
+                                          const int2 *__restrict__ xy,
+                                          const int4 *__restrict__ tri,
+                                          const int32_t *__restrict__ t6,
+                                          const float *__restrict__ coef,
+                                          const float *__restrict__ re,
+                                          float *__restrict__ warped,
+                                          double *__restrict__ partials, unsigned *flags) {
+  const TileItem it = tiles[tile];
+  const DevPair P = pairs[it.pair];
+  const int i = it.y0 + (int)(threadIdx.x / kTile);
+  const int j = it.x0 + (int)(threadIdx.x % kTile);
+  double acc = 0.0;
+  if (i < P.height && j < P.width) {
+    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
+    const int4 nd = tri[P.tri_off + t6[pix]];
+    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
+    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
+    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+    const double inv = 1.0 / (ca + cb + cc);
+    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
+    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
+    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
+    int qx, qy;
+    double fx, fy;
+    const bool okx = split_coord_d(j, dx, qx, fx);
+    const bool ok = split_coord_d(i, dy, qy, fy) && okx;
+    if (!ok) atomicOr(flags, kFlagNonFinitePixel);
+    const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
+    if (warped) warped[pix] = (float)w;
+    const double e = w - (double)re[pix];
+    acc = e * e;
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[tile] = (red[0] + red[1]) + (red[2] + red[3]);
+}
 
-// Node sampling.  When `finish_msd` is set, one extra workgroup (the last)
-// completes the MSD of the previous warp instead (saves a launch per iteration).
+// Node sampling of u (one workgroup per node item).  When `n_tiles` > 0 the
+// workgroups after the node items warp the same u into the MSD partials, so
+// the MSD of the previous iteration's result shares this launch.
 __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items, int n_items,
-                                                const DevPair *__restrict__ pairs, int n_pairs,
+                                                const DevPair *__restrict__ pairs,
                                                 const double2 *__restrict__ u,
                                                 const int2 *__restrict__ xy,
                                                 const float *__restrict__ coef,
                                                 const float *__restrict__ rho,
                                                 float2 *__restrict__ h, unsigned *flags,
-                                                const double *__restrict__ partials,
-                                                double *__restrict__ finish_msd) {
-  if ((int)blockIdx.x == n_items) {
-    msd_finish_block(pairs, n_pairs, partials, finish_msd);
+                                                const TileItem *__restrict__ tiles,
+                                                const int4 *__restrict__ tri,
+                                                const int32_t *__restrict__ t6,
+                                                const float *__restrict__ re,
+                                                double *__restrict__ partials) {
+  if ((int)blockIdx.x >= n_items) {
+    warp_tile((int)blockIdx.x - n_items, tiles, pairs, u, xy, tri, t6, coef, re, nullptr,
+              partials, flags);
     return;
   }
   const NodeItem it = items[blockIdx.x];
@@ -152,25 +212,59 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
   h[i] = make_float2(r * gx, r * gy);
 }
 
+// b_i = u_i - tau f_i, f_i = sum_q w_q h(col_q) over node i's force operator
+// row (FP32 sum in row order), loads issued in batches of U.
+__device__ __forceinline__ double2 assemble_b(int i, const int32_t *__restrict__ mptr,
+                                              const int32_t *__restrict__ mcol,
+                                              const float *__restrict__ mwt,
+                                              const float2 *__restrict__ h,
+                                              const double2 *__restrict__ u, double tau) {
+  const int q0 = mptr[i], q1 = mptr[i + 1];
+  float fx = 0.0f, fy = 0.0f;
+  constexpr int U = 8;
+  for (int q = q0; q < q1; q += U) {
+    int c[U];
+    float w[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      c[k] = q + k < q1 ? mcol[q + k] : -1;
+      w[k] = q + k < q1 ? mwt[q + k] : 0.0f;
+    }
+    float2 hv[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) hv[k] = c[k] >= 0 ? h[c[k]] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (q + k < q1) {
+        fx += w[k] * hv[k].x;
+        fy += w[k] * hv[k].y;
+      }
+  }
+  const double2 ui = u[i];
+  return make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
+}
+
+// Force assembly (thread per node), b written in solve order.  When
+// `finish_msd` is given, the workgroups after the node range finish the MSD of
+// the partials written by the preceding sample launch.
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
                                                   const int32_t *__restrict__ mcol,
                                                   const float *__restrict__ mwt,
                                                   const float2 *__restrict__ h,
                                                   const double2 *__restrict__ u,
                                                   const int32_t *__restrict__ iperm,
-                                                  double2 *__restrict__ x, double tau) {
+                                                  double2 *__restrict__ x, double tau,
+                                                  const DevPair *__restrict__ pairs, int n_pairs,
+                                                  const double *__restrict__ partials,
+                                                  double *__restrict__ finish_msd) {
+  const int node_groups = (n + 255) / 256;
+  if ((int)blockIdx.x >= node_groups) {
+    msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - node_groups);
+    return;
+  }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float fx = 0.0f, fy = 0.0f;
-  const int q1 = mptr[i + 1];
-  for (int q = mptr[i]; q < q1; ++q) {
-    const float w = mwt[q];
-    const float2 hj = h[mcol[q]];
-    fx += w * hj.x;
-    fy += w * hj.y;
-  }
-  const double2 ui = u[i];
-  x[iperm[i]] = make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
+  x[iperm[i]] = assemble_b(i, mptr, mcol, mwt, h, u, tau);
 }
 
 // Copies n doubles from global memory to LDS with all of a thread's loads of
@@ -220,12 +314,30 @@ __device__ __forceinline__ double2 combine_parts(const double2 *red, int o, int 
 //   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block)).
 // Slice 0 also writes y to x (in place).  Each phase spreads its sums over all
 // threads and combines the partial sums in a fixed order (deterministic).
-template <int NT>
+// With FUSED (first level only, no contributions) the workgroup forms b of
+// its rows itself, and the workgroups after the `count` block items assemble
+// the other rows and finish the MSD (AssembleArgs).
+template <int NT, bool FUSED>
 __global__ __launch_bounds__(NT) void k_solve_fwd(
-    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
-    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *upd) {
+    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *upd,
+    AssembleArgs A) {
   extern __shared__ double smem[];
+  if (FUSED && (int)blockIdx.x >= count) {
+    const int g = (int)blockIdx.x - count;
+    const int row_groups = (A.n_rows + NT - 1) / NT;
+    if (g < row_groups) {
+      const int k = g * NT + (int)threadIdx.x;
+      if (k < A.n_rows) {
+        const int row = A.rows[k];
+        x[row] = assemble_b(A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      }
+    } else {
+      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
+    }
+    return;
+  }
   const int2 it = items[blockIdx.x];
   const DevBlock B = blocks[it.x];
   const int b = B.r1 - B.r0;
@@ -245,7 +357,12 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   const int np = NT / bp;          // threads per row
   const int r = tid & (bp - 1), part = tid / bp;
   // phase 1: gathers of the contributions, all loads of a thread in flight
-  {
+  if (FUSED) {
+    if (part == 0 && r < b) {
+      const int row = B.r0 + r;
+      t[r] = assemble_b(A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+    }
+  } else {
     double ax = 0.0, ay = 0.0;
     if (r < b) {
       const int row = B.r0 + r;
@@ -269,12 +386,12 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
       }
     }
     red[tid] = make_double2(ax, ay);
-  }
-  __syncthreads();
-  if (part == 0 && r < b) {
-    const double2 c = combine_parts(red, r, bp, np);
-    const double2 bb = x[B.r0 + r];
-    t[r] = make_double2(bb.x - c.x, bb.y - c.y);
+    __syncthreads();
+    if (part == 0 && r < b) {
+      const double2 c = combine_parts(red, r, bp, np);
+      const double2 bb = x[B.r0 + r];
+      t[r] = make_double2(bb.x - c.x, bb.y - c.y);
+    }
   }
   __syncthreads();
   // phase 2: y_i = sum_{j <= i} D(i, j) t_j, j split over the row's threads
@@ -455,128 +572,188 @@ __global__ __launch_bounds__(256) void k_apex_rhs(int n_rows, const int32_t *__r
   tbuf[g] = make_double2(bb.x - ax, bb.y - ay);
 }
 
-// Apex, step 2: z = G t with G = L(apex,apex)^-T L(apex,apex)^-1 (dense,
-// symmetric, row-major), i.e. both triangular solves of the apex at once; one
-// wavefront per row (t staged in LDS); z goes to x and, when `out` is given,
-// to natural node order.  Work item = (pair, first row).
-__global__ __launch_bounds__(256) void k_apex_solve(const int2 *__restrict__ items,
-                                                    const ApexDesc *__restrict__ apex,
-                                                    const double *__restrict__ gram,
-                                                    const int32_t *__restrict__ rows,
-                                                    const double2 *__restrict__ tbuf, double2 *x,
-                                                    const int32_t *__restrict__ perm,
-                                                    double2 *__restrict__ out) {
-  extern __shared__ double smem[];
-  double2 *tl = reinterpret_cast<double2 *>(smem);
-  const int2 it = items[blockIdx.x];
-  const ApexDesc A = apex[it.x];
-  for (int j = threadIdx.x; j < A.n; j += blockDim.x) tl[j] = tbuf[A.rows_off + j];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int i = it.y + (threadIdx.x >> 6);
-  if (i >= A.n) return;
-  const double *row = gram + A.inv_off + (int64_t)i * A.n;
-  double ax = 0.0, ay = 0.0;
-  constexpr int U = 8;
-  for (int j0 = lane; j0 < A.n; j0 += 64 * U) {
-    double v[U];
+// Dot products of one wavefront's two rows against an LDS vector: row A has
+// entries q in [qa, la), row B in [qb, lb), each at base[q] of its own pointer
+// (position q of the LDS vector).  The first batch of loads is issued by the
+// caller (before its LDS staging); U loads per lane per row and batch.
+template <int U>
+struct RowPair {
+  double va[U], vb[U];
+  __device__ __forceinline__ void load(const double *pa, int qa, int la, const double *pb, int qb,
+                                       int lb, int lane) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = j0 + 64 * u;
-      v[u] = j < A.n ? row[j] : 0.0;
+      const int q0 = qa + lane + 64 * u, q1 = qb + lane + 64 * u;
+      va[u] = q0 < la ? pa[q0] : 0.0;
+      vb[u] = q1 < lb ? pb[q1] : 0.0;
     }
+  }
+  __device__ __forceinline__ void fma(const double2 *v, int qa, int la, int qb, int lb, int lane,
+                                      double2 &sa, double2 &sb) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = j0 + 64 * u;
-      if (j < A.n) {
-        ax += v[u] * tl[j].x;
-        ay += v[u] * tl[j].y;
+      const int q0 = qa + lane + 64 * u, q1 = qb + lane + 64 * u;
+      if (q0 < la) {
+        const double2 t = v[q0];
+        sa.x += va[u] * t.x;
+        sa.y += va[u] * t.y;
+      }
+      if (q1 < lb) {
+        const double2 t = v[q1];
+        sb.x += vb[u] * t.x;
+        sb.y += vb[u] * t.y;
       }
     }
   }
-  ax = wave_sum(ax);
-  ay = wave_sum(ay);
-  if (lane == 0) {
-    const double2 z = make_double2(ax, ay);
-    const int r = rows[A.rows_off + i];
-    x[r] = z;
-    if (out) out[perm[r]] = z;
-  }
-}
+};
 
-// G = X^T X for the lower-triangular X = L(apex,apex)^-1 given as a packed
-// row-major triangle (init / re-factorisation only): 16x16 output tiles,
-// k-tiles staged in LDS.
-__global__ __launch_bounds__(256) void k_apex_gram(int n, const double *__restrict__ xrow,
-                                                   double *__restrict__ g) {
-  __shared__ double Xi[16][17], Xj[16][17];
-  const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
-  const int r = threadIdx.x / 16, c = threadIdx.x % 16;
-  double acc = 0.0;
-  for (int k0 = max(ti, tj); k0 < n; k0 += 16) {
-    const int k = k0 + r;
-    // X[k][col] for col = ti + c and tj + c (zero above the diagonal)
-    const int ci = ti + c, cj = tj + c;
-    Xi[r][c] = (k < n && ci <= k) ? xrow[(int64_t)k * (k + 1) / 2 + ci] : 0.0;
-    Xj[r][c] = (k < n && cj <= k) ? xrow[(int64_t)k * (k + 1) / 2 + cj] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc += Xi[q][r] * Xj[q][c];
-    __syncthreads();
-  }
-  if (ti + r < n && tj + c < n) g[(int64_t)(ti + r) * n + (tj + c)] = acc;
-}
-
-// Warp + MSD over kTile x kTile pixel tiles.  Each workgroup writes its FP64
-// partial sum; the last workgroup to finish sums every pair's partials in a
-// fixed order (deterministic) and resets the counter for the next launch.
-__global__ __launch_bounds__(256) void k_warp_msd(
-    const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, int n_pairs,
-    const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
-    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
-    float *__restrict__ warped, double *__restrict__ partials, unsigned *flags) {
-  const TileItem it = tiles[blockIdx.x];
-  const DevPair P = pairs[it.pair];
-  const int i = it.y0 + (int)(threadIdx.x / kTile);
-  const int j = it.x0 + (int)(threadIdx.x % kTile);
-  double acc = 0.0;
-  if (i < P.height && j < P.width) {
-    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
-    const int4 nd = tri[P.tri_off + t6[pix]];
-    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
-    // barycentric weights in doubled coordinates (exact integer cross products)
-    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
-    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
-    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
-    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
-    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-    const double inv = 1.0 / (ca + cb + cc);
-    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
-    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
-    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
-    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
-    int qx, qy;
-    double fx, fy;
-    const bool okx = split_coord_d(j, dx, qx, fx);
-    const bool ok = split_coord_d(i, dy, qy, fy) && okx;
-    if (!ok) atomicOr(flags, kFlagNonFinitePixel);
-    const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
-    if (warped) warped[pix] = (float)w;
-    const double e = w - (double)re[pix];
-    acc = e * e;
-  }
-  __shared__ double red[4];
-  acc = wave_sum(acc);
+// Apex forward, y = X t with X = L(apex, apex)^-1: row r of X is nonzero
+// only on columns [c0, r] (its block's subtree).  A work item takes up to 8
+// rows of one block against one segment of at most kApexSeg columns: each
+// wavefront loads its two rows' entries of the segment, the segment of t is
+// staged in LDS meanwhile, and the dot products (fixed-order reduction) go to
+// the item's partial slots.
+__global__ __launch_bounds__(256) void k_apex_fwd(const ApexFwdItem *__restrict__ items,
+                                                  const double *__restrict__ xf,
+                                                  const double2 *__restrict__ tbuf,
+                                                  double2 *__restrict__ part) {
+  __shared__ double2 tl[kApexSeg];
+  const ApexFwdItem it = items[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = acc;
+  // rows ra, rb; entries of row r in the segment: columns k0 .. min(k1, r+1)-1,
+  // stored from xoff0 + sum_{a0 <= s < r} (s - c0 + 1) + (k0 - c0) on
+  const int ra = it.a0 + wave, rb = ra + 4;
+  const int la = ra < it.a1 ? max(0, min(it.k1, ra + 1) - it.k0) : 0;
+  const int lb = rb < it.a1 ? max(0, min(it.k1, rb + 1) - it.k0) : 0;
+  const int64_t w0 = it.a0 - it.c0 + 1;                 // length of row a0
+  const int64_t da = ra - it.a0, db = rb - it.a0;
+  const double *pa = xf + it.xoff0 + da * w0 + da * (da - 1) / 2 + (it.k0 - it.c0);
+  const double *pb = xf + it.xoff0 + db * w0 + db * (db - 1) / 2 + (it.k0 - it.c0);
+  constexpr int U = 8;
+  RowPair<U> rp;
+  rp.load(pa, 0, la, pb, 0, lb, lane);
+  const int kn = it.k1 - it.k0;
+  for (int j = threadIdx.x; j < kn; j += blockDim.x) tl[j] = tbuf[it.k0 + j];
   __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  rp.fma(tl, 0, la, 0, lb, lane, sa, sb);
+  for (int o = 64 * U; o < la || o < lb; o += 64 * U) {
+    rp.load(pa, o, la, pb, o, lb, lane);
+    rp.fma(tl, o, la, o, lb, lane, sa, sb);
+  }
+  sa.x = wave_sum(sa.x);
+  sa.y = wave_sum(sa.y);
+  sb.x = wave_sum(sb.x);
+  sb.y = wave_sum(sb.y);
+  if (lane == 0) {
+    if (la > 0) part[it.part + (ra - it.a0)] = sa;
+    if (lb > 0) part[it.part + (rb - it.a0)] = sb;
+  }
+}
+
+// y_a = sum of row a's forward segment partials, in segment order (thread per
+// apex position).
+__global__ __launch_bounds__(256) void k_apex_combine(int n, const ApexRow *__restrict__ arow,
+                                                      const double2 *__restrict__ part,
+                                                      double2 *__restrict__ y) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const ApexRow R = arow[a];
+  double2 s = make_double2(0.0, 0.0);
+  constexpr int U = 4;
+  for (int g0 = 0; g0 < R.nseg; g0 += U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = g0 + u < R.nseg ? part[R.part + (int64_t)(g0 + u) * R.stride] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s.x += v[u].x;
+      s.y += v[u].y;
+    }
+  }
+  y[a] = s;
+}
+
+// Apex backward, z = X^T y: z_r is the dot product of column r of X over r's
+// path (its block's rows from r on, then the ancestor blocks' rows) with y on
+// the same rows.  A work item takes up to 8 rows of one block: each
+// wavefront loads its two columns' first entries while the path list of the
+// first row is staged in LDS from y; row r uses the list from position r - a0
+// on.  z goes to x and, when `out` is given, to natural node order.
+__global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict__ items,
+                                                  const int2 *__restrict__ rng,
+                                                  const int32_t *__restrict__ rows,
+                                                  const double2 *__restrict__ y,
+                                                  const double *__restrict__ xb, double2 *x,
+                                                  const int32_t *__restrict__ perm,
+                                                  double2 *__restrict__ out) {
+  extern __shared__ double2 yl[];              // the longest path of the launch
+  const ApexBwdItem it = items[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ra = it.a0 + wave, rb = ra + 4;
+  const int qa = ra - it.a0, qb = rb - it.a0;
+  const int la = ra < it.a1 ? it.len : 0, lb = rb < it.a1 ? it.len : 0;
+  // column r stores list positions r - a0 .. len - 1, columns back to back
+  const int64_t da = qa, db = qb;
+  const double *pa = xb + (it.xoff0 + da * it.len - da * (da - 1) / 2 - qa);
+  const double *pb = xb + (it.xoff0 + db * it.len - db * (db - 1) / 2 - qb);
+  constexpr int U = 8;
+  RowPair<U> rp;
+  rp.load(pa, qa, la, pb, qb, lb, lane);
+  const int own = it.e - it.a0;
+  for (int q = threadIdx.x; q < it.len; q += blockDim.x) {
+    int a;
+    if (q < own) {
+      a = it.a0 + q;
+    } else {
+      int r = q - own, k = it.rng_off;
+      const int kend = it.rng_off + it.n_rng;
+      while (k + 1 < kend && r >= rng[k].y - rng[k].x) {
+        r -= rng[k].y - rng[k].x;
+        ++k;
+      }
+      a = rng[k].x + r;
+    }
+    yl[q] = y[a];
+  }
+  __syncthreads();
+  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  rp.fma(yl, qa, la, qb, lb, lane, sa, sb);
+  for (int o = 64 * U; qa + o < la || qb + o < lb; o += 64 * U) {
+    rp.load(pa, qa + o, la, pb, qb + o, lb, lane);
+    rp.fma(yl, qa + o, la, qb + o, lb, lane, sa, sb);
+  }
+  sa.x = wave_sum(sa.x);
+  sa.y = wave_sum(sa.y);
+  sb.x = wave_sum(sb.x);
+  sb.y = wave_sum(sb.y);
+  if (lane == 0) {
+    if (la > 0) {
+      const int row = rows[ra];
+      x[row] = sa;
+      if (out) out[perm[row]] = sa;
+    }
+    if (lb > 0) {
+      const int row = rows[rb];
+      x[row] = sb;
+      if (out) out[perm[row]] = sb;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_warp_msd(
+    const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, const double2 *__restrict__ u,
+    const int2 *__restrict__ xy, const int4 *__restrict__ tri, const int32_t *__restrict__ t6,
+    const float *__restrict__ coef, const float *__restrict__ re, float *__restrict__ warped,
+    double *__restrict__ partials, unsigned *flags) {
+  warp_tile(blockIdx.x, tiles, pairs, u, xy, tri, t6, coef, re, warped, partials, flags);
 }
 
 __global__ __launch_bounds__(256) void k_msd_finish(const DevPair *__restrict__ pairs, int n_pairs,
                                                     const double *__restrict__ partials,
                                                     double *__restrict__ msd) {
-  msd_finish_block(pairs, n_pairs, partials, msd);
+  msd_finish_group(pairs, n_pairs, partials, msd, blockIdx.x);
 }
 
 // Gather / scatter between the natural node order and the solve order.
@@ -596,55 +773,62 @@ __global__ void k_from_solve_order(int n, const double2 *__restrict__ x,
 // Launch wrappers
 // ---------------------------------------------------------------------------
 
+thread_local LaunchTimer *tl_launch_timer = nullptr;
+
 hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp, float *out,
                             int H, int W, const double *cp_w, const double *cp_h,
                             hipStream_t s) {
   const int tb = 64;
-  if (src_f)
-    k_prefilter_rows<float><<<(H + tb - 1) / tb, tb, 0, s>>>(src_f, tmp, H, W, cp_w);
-  else
-    k_prefilter_rows<double><<<(H + tb - 1) / tb, tb, 0, s>>>(src_d, tmp, H, W, cp_w);
-  k_prefilter_cols<<<(W + tb - 1) / tb, tb, 0, s>>>(tmp, out, H, W, cp_h);
-  return hipGetLastError();
+  hipError_t e = src_f ? launch(k_prefilter_rows<float>, (H + tb - 1) / tb, tb, 0, s, src_f, tmp,
+                                H, W, cp_w)
+                       : launch(k_prefilter_rows<double>, (H + tb - 1) / tb, tb, 0, s, src_d, tmp,
+                                H, W, cp_w);
+  if (e != hipSuccess) return e;
+  return launch(k_prefilter_cols, (W + tb - 1) / tb, tb, 0, s, tmp, out, H, W, cp_h);
 }
 
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s) {
-  k_sample_rho<<<n_items, kNodeChunk, 0, s>>>(items, pairs, xy, coef_re, rho);
-  return hipGetLastError();
+  return launch(k_sample_rho, n_items, kNodeChunk, 0, s, items, pairs, xy, coef_re, rho);
 }
 
-hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs, int n_pairs,
+hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
-                         float2 *h, unsigned *flags, const double *partials, double *finish_msd,
+                         float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
+                         const int4 *tri, const int32_t *t6, const float *re, double *partials,
                          hipStream_t s) {
-  k_sample<<<n_items + (finish_msd ? 1 : 0), kNodeChunk, 0, s>>>(
-      items, n_items, pairs, n_pairs, u, xy, coef, rho, h, flags, partials, finish_msd);
-  return hipGetLastError();
+  return launch(k_sample, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u, xy, coef,
+                rho, h, flags, tiles, tri, t6, re, partials);
 }
 
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
-                           double tau, hipStream_t s) {
-  k_assemble<<<(n + 255) / 256, 256, 0, s>>>(n, mptr, mcol, mwt, h, u, iperm, x, tau);
-  return hipGetLastError();
+                           double tau, const DevPair *pairs, int n_pairs, const double *partials,
+                           double *finish_msd, hipStream_t s) {
+  const int groups = (n + 255) / 256 + (finish_msd ? (n_pairs + 3) / 4 : 0);
+  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, iperm, x, tau, pairs,
+                n_pairs, partials, finish_msd);
 }
 
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
                                   const double *dcol, const double *prow, double2 *x,
-                                  double2 *upd, hipStream_t s) {
-  switch (nt) {
-    case 64:
-      k_solve_fwd<64><<<count, 64, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
-      break;
-    case 128:
-      k_solve_fwd<128><<<count, 128, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
-      break;
-    default:
-      k_solve_fwd<256><<<count, 256, lds_bytes, s>>>(blocks, items, cptr, cidx, dcol, prow, x, upd);
+                                  double2 *upd, const AssembleArgs *fuse, hipStream_t s) {
+  nt = nt == 64 || nt == 128 ? nt : 256;
+  if (!fuse) {
+    auto k = nt == 64 ? k_solve_fwd<64, false> : nt == 128 ? k_solve_fwd<128, false>
+                                                           : k_solve_fwd<256, false>;
+    if (count == 0) return hipSuccess;
+    return launch(k, count, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x,
+                  upd, AssembleArgs{});
   }
-  return hipGetLastError();
+  auto k = nt == 64 ? k_solve_fwd<64, true> : nt == 128 ? k_solve_fwd<128, true>
+                                                        : k_solve_fwd<256, true>;
+  const int groups = count + (fuse->n_rows + nt - 1) / nt +
+                     (fuse->finish_msd ? (fuse->n_pairs + nt / 64 - 1) / (nt / 64) : 0);
+  if (groups == 0) return hipSuccess;
+  return launch(k, groups, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x, upd,
+                *fuse);
 }
 
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
@@ -652,66 +836,50 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
                                   const double *drow, const double *prow, double2 *x,
                                   const int32_t *perm, double2 *out, double2 *partials,
                                   unsigned *counters, hipStream_t s) {
-  switch (nt) {
-    case 64:
-      k_solve_bwd<64><<<count, 64, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
-                                                   out, partials, counters);
-      break;
-    case 128:
-      k_solve_bwd<128><<<count, 128, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
-                                                     out, partials, counters);
-      break;
-    default:
-      k_solve_bwd<256><<<count, 256, lds_bytes, s>>>(blocks, items, below_idx, drow, prow, x, perm,
-                                                     out, partials, counters);
-  }
-  return hipGetLastError();
+  auto k = nt == 64 ? k_solve_bwd<64> : nt == 128 ? k_solve_bwd<128> : k_solve_bwd<256>;
+  return launch(k, count, nt == 64 || nt == 128 ? nt : 256, lds_bytes, s, blocks, items,
+                below_idx, drow, prow, x, perm, out, partials, counters);
 }
 
 hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,
                              const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
-                             const int2 *items, int n_items, int lds_bytes, const ApexDesc *apex,
-                             const double *gram, const int32_t *perm, double2 *out,
+                             const ApexFwdItem *fitems, int n_fitems, const double *xf,
+                             double2 *part, const ApexRow *arow, double2 *ybuf,
+                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng,
+                             int bwd_lds, const double *xb, const int32_t *perm, double2 *out,
                              hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  k_apex_rhs<<<(n_rows + 255) / 256, 256, 0, s>>>(n_rows, rows, acptr, acidx, upd, x, tbuf);
-  k_apex_solve<<<n_items, 64 * kApexRowsPerGroup, lds_bytes, s>>>(items, apex, gram, rows, tbuf, x,
-                                                                  perm, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_apex_gram(int n, const double *xrow, double *g, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const int t = (n + 15) / 16;
-  k_apex_gram<<<dim3(t, t), 256, 0, s>>>(n, xrow, g);
-  return hipGetLastError();
+  hipError_t e = launch(k_apex_rhs, (n_rows + 255) / 256, 256, 0, s, n_rows, rows, acptr, acidx,
+                        upd, x, tbuf);
+  if (e == hipSuccess) e = launch(k_apex_fwd, n_fitems, 256, 0, s, fitems, xf, tbuf, part);
+  if (e == hipSuccess)
+    e = launch(k_apex_combine, (n_rows + 255) / 256, 256, 0, s, n_rows, arow, part, ybuf);
+  if (e == hipSuccess)
+    e = launch(k_apex_bwd, n_bitems, 256, bwd_lds, s, bitems, rng, rows, ybuf, xb, x, perm, out);
+  return e;
 }
 
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                int n_pairs, const double2 *u, const int2 *xy, const int4 *tri,
+                                const double2 *u, const int2 *xy, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,
                                 float *warped, double *partials, unsigned *flags, hipStream_t s) {
-  k_warp_msd<<<n_tiles, kTile * kTile, 0, s>>>(tiles, pairs, n_pairs, u, xy, tri, t6, coef, re,
-                                               warped, partials, flags);
-  return hipGetLastError();
+  return launch(k_warp_msd, n_tiles, kTile * kTile, 0, s, tiles, pairs, u, xy, tri, t6, coef, re,
+                warped, partials, flags);
 }
 
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
                              double *msd, hipStream_t s) {
-  k_msd_finish<<<1, 256, 0, s>>>(pairs, n_pairs, partials, msd);
-  return hipGetLastError();
+  return launch(k_msd_finish, (n_pairs + 3) / 4, 256, 0, s, pairs, n_pairs, partials, msd);
 }
 
 hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
                                  hipStream_t s) {
-  k_to_solve_order<<<(n + 255) / 256, 256, 0, s>>>(n, src, iperm, x);
-  return hipGetLastError();
+  return launch(k_to_solve_order, (n + 255) / 256, 256, 0, s, n, src, iperm, x);
 }
 
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,
                                    hipStream_t s) {
-  k_from_solve_order<<<(n + 255) / 256, 256, 0, s>>>(n, x, iperm, dst);
-  return hipGetLastError();
+  return launch(k_from_solve_order, (n + 255) / 256, 256, 0, s, n, x, iperm, dst);
 }
 
 }  // namespace mr

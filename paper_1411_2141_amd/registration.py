@@ -134,6 +134,10 @@ class MeshReg:
     def enable_timing(self, on: bool = True) -> None:
         B.mesh_reg_enable_timing(self.ctx, on)
 
+    def set_graph(self, on: bool) -> None:
+        """Graph replay of ``step`` on or off (off drops the cached graph)."""
+        B.mesh_reg_set_graph(self.ctx, on)
+
     def kernel_times(self) -> dict:
         return B.mesh_reg_kernel_times(self.ctx)
 
