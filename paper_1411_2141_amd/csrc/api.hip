@@ -186,7 +186,7 @@ hipError_t mr_ctx::sample(const double2 *u, bool with_warp, hipStream_t s) {
 hipError_t mr_ctx::assemble(const double2 *u, double *finish_msd, hipStream_t s) {
   timed_begin(MR_KF_ASSEMBLE, s);
   hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u,
-                                 d_iperm.ptr, d_x.ptr, params.tau, d_pairs.ptr, n_pairs,
+                                 d_perm.ptr, d_x.ptr, params.tau, d_pairs.ptr, n_pairs,
                                  d_partials.ptr, finish_msd, s);
   timed_end(s);
   return e;
@@ -336,9 +336,11 @@ int mr_ctx::upload_all(hipStream_t s) {
       iperm[no + i] = no + h.iperm[i];
       perm[no + i] = no + h.perm[i];
     }
-    // force operator rows: f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j, i.e. the
-    // mass row divided by the lumped mass, with 6 m_i = t5_i
-    for (int i = 0; i < h.n; ++i) {
+    // force operator rows, in solve order (row k is node perm[k]):
+    // f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j, i.e. the mass row divided by
+    // the lumped mass, with 6 m_i = t5_i
+    for (int k = 0; k < h.n; ++k) {
+      const int i = h.perm[k];
       if (params.force_mode == MR_FORCE_NODAL) {
         mcol.push_back(no + i);
         mwt.push_back(1.0f);
@@ -349,7 +351,7 @@ int mr_ctx::upload_all(hipStream_t s) {
           mwt.push_back((float)((double)h.mval[q] / den));
         }
       }
-      mptr[no + i + 1] = (int32_t)mcol.size();
+      mptr[no + k + 1] = (int32_t)mcol.size();
     }
     // solve plan, shifted to global rows
     const SolvePlan &pl = h.plan;

@@ -19,7 +19,7 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
                          hipStream_t s);
 // Assemble launch; with finish_msd it also finishes the MSD of `partials`.
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
-                           const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
+                           const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
                            double tau, const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s);
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,

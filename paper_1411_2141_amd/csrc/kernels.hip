@@ -212,14 +212,15 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
   h[i] = make_float2(r * gx, r * gy);
 }
 
-// b_i = u_i - tau f_i, f_i = sum_q w_q h(col_q) over node i's force operator
-// row (FP32 sum in row order), loads issued in batches of U.
-__device__ __forceinline__ double2 assemble_b(int i, const int32_t *__restrict__ mptr,
+// b for solve row k (node i): u_i - tau f_i, f_i = sum_q w_q h(col_q) over
+// the force operator row k (FP32 sum in row order), loads issued in batches
+// of U.  Operator rows are stored in solve order.
+__device__ __forceinline__ double2 assemble_b(int k, int i, const int32_t *__restrict__ mptr,
                                               const int32_t *__restrict__ mcol,
                                               const float *__restrict__ mwt,
                                               const float2 *__restrict__ h,
                                               const double2 *__restrict__ u, double tau) {
-  const int q0 = mptr[i], q1 = mptr[i + 1];
+  const int q0 = mptr[k], q1 = mptr[k + 1];
   float fx = 0.0f, fy = 0.0f;
   constexpr int U = 8;
   for (int q = q0; q < q1; q += U) {
@@ -244,7 +245,7 @@ __device__ __forceinline__ double2 assemble_b(int i, const int32_t *__restrict__
   return make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
 }
 
-// Force assembly (thread per node), b written in solve order.  When
+// Force assembly (thread per solve row), b written in solve order.  When
 // `finish_msd` is given, the workgroups after the node range finish the MSD of
 // the partials written by the preceding sample launch.
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
                                                   const float *__restrict__ mwt,
                                                   const float2 *__restrict__ h,
                                                   const double2 *__restrict__ u,
-                                                  const int32_t *__restrict__ iperm,
+                                                  const int32_t *__restrict__ perm,
                                                   double2 *__restrict__ x, double tau,
                                                   const DevPair *__restrict__ pairs, int n_pairs,
                                                   const double *__restrict__ partials,
@@ -262,9 +263,9 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - node_groups);
     return;
   }
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  x[iperm[i]] = assemble_b(i, mptr, mcol, mwt, h, u, tau);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  x[k] = assemble_b(k, perm[k], mptr, mcol, mwt, h, u, tau);
 }
 
 // Copies n doubles from global memory to LDS with all of a thread's loads of
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
       const int k = g * NT + (int)threadIdx.x;
       if (k < A.n_rows) {
         const int row = A.rows[k];
-        x[row] = assemble_b(A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
       }
     } else {
       msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   if (FUSED) {
     if (part == 0 && r < b) {
       const int row = B.r0 + r;
-      t[r] = assemble_b(A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t[r] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
     }
   } else {
     double ax = 0.0, ay = 0.0;
@@ -802,11 +803,11 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
 }
 
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
-                           const float2 *h, const double2 *u, const int32_t *iperm, double2 *x,
+                           const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
                            double tau, const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s) {
   const int groups = (n + 255) / 256 + (finish_msd ? (n_pairs + 3) / 4 : 0);
-  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, iperm, x, tau, pairs,
+  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, perm, x, tau, pairs,
                 n_pairs, partials, finish_msd);
 }
 
