@@ -36,6 +36,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node-updates/s per registration iteration, fwd+bwd vs plain; achieved HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_digest() -> str:
+    """sha256 over the library's device and host sources (sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1411_2141_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(leg: str, family: str):
+    """HBM bytes per launch of a kernel family from the committed counter
+    measurement (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None
+    when there is none for this leg or the sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_digest():
+        return None
+    v = t.get("legs", {}).get(leg, {}).get("bytes_per_launch", {}).get(family)
+    return int(v) if v is not None else None
 
 
 def unit_bytes(ctx, pairs) -> dict:
@@ -78,7 +107,7 @@ def run_bytes(ub: dict, iters: int, trace: bool) -> dict:
             "warp": (ub["warp"] + ub["finish"]) if (trace and iters) else 0}
 
 
-def profile(ctx, run, total_bytes: dict) -> tuple:
+def profile(ctx, run, total_bytes: dict, leg: str) -> tuple:
     """Per-family timing of one run from events attached to each kernel
     dispatch; returns (kernels, roofline of the family with the largest
     share of GPU time)."""
@@ -99,7 +128,8 @@ def profile(ctx, run, total_bytes: dict) -> tuple:
     dom = max(kernels, key=lambda f: kernels[f]["share"])
     ach = kernels[dom]["gbs"]
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(leg, dom),
+            "kernel": dom,
             "bytes_per_launch": int(total_bytes[dom] / kernels[dom]["launches"]),
             "avg_launch_us": kernels[dom]["avg_us"]}
     return kernels, roof
@@ -203,7 +233,7 @@ def main() -> int:
         if not args.no_profile:
             u.zero_()
             kernels, roof = profile(ctx, lambda: run(K),
-                                    run_bytes(unit_bytes(ctx, [pair]), K, True))
+                                    run_bytes(unit_bytes(ctx, [pair]), K, True), "single_pair")
 
     fwd_bwd = None
     if args.fwdbwd_iters:
@@ -248,7 +278,7 @@ def main() -> int:
                 ub.zero_()
                 bk, broof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, KB, None,
                                                                   side.cuda_stream),
-                                    run_bytes(unit_bytes(bctx, batch), KB, False))
+                                    run_bytes(unit_bytes(bctx, batch), KB, False), "batched")
         batched = {"value": round(nb * KB / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
                    "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),
                    "iterations": KB, "ms_per_iteration": round(dtc / KB * 1e3, 4),

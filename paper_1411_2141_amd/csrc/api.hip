@@ -80,14 +80,15 @@ hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipS
     const int nt = fwd_nt[lev];
     return launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt,
                                   fwd_lds[lev] + 16 * nt, nt, d_cptr.ptr, d_cidx.ptr, d_dcol.ptr,
-                                  d_prow.ptr, x, d_upd.ptr, fuse, s);
+                                  d_prow.ptr, d_pcol.ptr, x, d_ybuf.ptr, d_upd.ptr, fuse, s);
   }
   const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
   if (!cnt) return hipSuccess;
   const int nt = bwd_nt[lev];
   return launch_solve_bwd_level(d_blocks.ptr, d_bwd_items.ptr + bwd_ptr[lev], cnt,
                                 bwd_lds[lev] + 16 * nt, nt, d_below.ptr, d_drow.ptr, d_prow.ptr,
-                                x, d_perm.ptr, out, d_partials2.ptr, d_blk_counters.ptr, s);
+                                x, d_ybuf.ptr, d_perm.ptr, out, d_partials2.ptr,
+                                d_blk_counters.ptr, s);
 }
 
 // With `fuse`, the right-hand side is assembled by the first forward level's
@@ -124,43 +125,89 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
   return e;
 }
 
-// Autotuner: for every solve level, times each admissible workgroup size
-// (64, 128, 256 threads; at least the level's largest block rounded up to a
-// power of two) on the context's own data and keeps the fastest.  The level
-// kernels only read and write the solve scratch vectors, so running them on
-// whatever those hold is harmless.
+// Autotuner: for every solve level, times each admissible kernel on the
+// context's own data (first each level alone, then each level inside the
+// whole solve) and keeps the fastest: the wavefront-per-block kernels
+// (blocks of at most 64 rows; backward: no split blocks) and the workgroup-per-block
+// kernels with 64, 128, 256 threads (at least the level's largest block
+// rounded up to a power of two).  The level kernels only read and write the
+// solve scratch vectors, so running them on whatever those hold is harmless.
 int mr_ctx::tune(hipStream_t s) {
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
   int rc = MR_OK;
+  // the first forward level runs fused with the force assembly in the
+  // iteration, so it is timed that way (on scratch data: u = x)
+  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr, d_perm.ptr,
+                          d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs, params.tau,
+                          d_pairs.ptr, d_partials.ptr, nullptr};
+  // best of the second and third of three runs, in ms (negative on error)
+  auto time_it = [&](auto &&run) -> float {
+    float t_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipError_t e = hipEventRecord(a, s);
+      if (e == hipSuccess) e = run();
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) {
+        rc = fail(MR_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        return -1.0f;
+      }
+      if (rep > 0) t_min = std::min(t_min, ms);
+    }
+    return t_min;
+  };
+  auto admissible = [&](bool fwd, size_t lev, int nt) {
+    const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
+    if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
+    return nt >= minnt[lev];
+  };
+  static const int kCandidates[] = {8, 16, 64, 128, 256};
+  // pass 1: every level on its own
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
     std::vector<int32_t> &choice = fwd ? fwd_nt : bwd_nt;
-    const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
     for (size_t lev = 0; lev < choice.size() && rc == MR_OK; ++lev) {
       float best = 1e30f;
       int best_nt = choice[lev];
-      for (int nt : {64, 128, 256}) {
-        if (nt < minnt[lev]) continue;
+      for (int nt : kCandidates) {
+        if (!admissible(fwd, lev, nt)) continue;
         choice[lev] = nt;
-        float t_min = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-          hipError_t e = hipEventRecord(a, s);
-          if (e == hipSuccess) e = solve_level(fwd, (int)lev, d_x.ptr, nullptr, s, nullptr);
-          if (e == hipSuccess) e = hipEventRecord(b, s);
-          if (e == hipSuccess) e = hipEventSynchronize(b);
-          float ms = 0.0f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-          if (e != hipSuccess) {
-            rc = fail(MR_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-            break;
-          }
-          if (rep > 0) t_min = std::min(t_min, ms);
+        const float t = time_it([&] {
+          return solve_level(fwd, (int)lev, d_x.ptr, nullptr, s, fwd && lev == 0 ? &fuse : nullptr);
+        });
+        if (t < 0.0f) break;
+        if (t < best) {
+          best = t;
+          best_nt = nt;
         }
-        if (rc) break;
-        if (t_min < best) {
-          best = t_min;
+      }
+      choice[lev] = best_nt;
+    }
+  }
+  // pass 2: one level at a time inside the whole solve (the other levels and
+  // the apex evict the caches as in an iteration), keeping a change only when
+  // the whole solve gets faster
+  auto whole = [&] { return solve(d_x.ptr, nullptr, s, &fuse); };
+  float cur = rc == MR_OK ? time_it(whole) : -1.0f;
+  for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
+    const bool fwd = dir == 0;
+    std::vector<int32_t> &choice = fwd ? fwd_nt : bwd_nt;
+    const std::vector<int32_t> &ptr = fwd ? fwd_ptr : bwd_ptr;
+    for (size_t lev = 0; lev < choice.size() && rc == MR_OK; ++lev) {
+      if (ptr[lev + 1] == ptr[lev] && !(fwd && lev == 0)) continue;
+      const int kept = choice[lev];
+      int best_nt = kept;
+      for (int nt : kCandidates) {
+        if (nt == kept || !admissible(fwd, lev, nt)) continue;
+        choice[lev] = nt;
+        const float t = time_it(whole);
+        if (t < 0.0f) break;
+        if (t < cur) {
+          cur = t;
           best_nt = nt;
         }
       }
@@ -257,6 +304,17 @@ mr_ctx::~mr_ctx() {
   if (host_flags) hipHostFree(host_flags);
 }
 
+// Column-major copies of the row-major block panels (same offsets): entry
+// (k, j) of block B's m x b panel moves from poff + k b + j to poff + j m + k.
+static void transpose_panels(const std::vector<DevBlock> &blocks, const std::vector<double> &prow,
+                             std::vector<double> &pcol) {
+  for (const DevBlock &B : blocks) {
+    const int64_t b = B.r1 - B.r0, m = B.m;
+    for (int64_t k = 0; k < m; ++k)
+      for (int64_t j = 0; j < b; ++j) pcol[B.poff + j * m + k] = prow[B.poff + k * b + j];
+  }
+}
+
 // Uploads tables, operators and the factor of every pair into packed device
 // arrays, and builds the work lists.
 int mr_ctx::upload_all(hipStream_t s) {
@@ -306,7 +364,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   int max_fl = 0, max_bl = 0;
   for (int p = 0; p < n_pairs; ++p) {
     max_fl = std::max(max_fl, host[p].plan.apex_level);
-    max_bl = std::max(max_bl, host[p].plan.n_rel_bwd_levels);
+    max_bl = std::max(max_bl, host[p].plan.apex_level);
   }
   std::vector<int32_t> apex_rows_g;
   std::vector<int64_t> apex_cptr_g(1, 0);
@@ -323,6 +381,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<std::vector<int2>> fwd_lv(max_fl), bwd_lv(max_bl);
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
   std::vector<int32_t> fwd_bp_v(max_fl, 64), bwd_bp_v(max_bl, 64);
+  std::vector<uint8_t> bwd_split_v(max_bl, 0);
   int32_t n_partials = 0, n_counters = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
@@ -390,13 +449,16 @@ int mr_ctx::upload_all(hipStream_t s) {
       if (pl.is_apex[k] || B.fwd_level != 0)
         for (int32_t r = B.r0; r < B.r1; ++r) upper_rows.push_back(no + r);
       if (!pl.is_apex[k]) {
-        const int32_t bl = pl.rel_bwd_level[k];
+        // backward levels: the forward levels below the apex, top first
+        // (a parent's forward level is higher than its children's)
+        const int32_t bl = max_fl - 1 - B.fwd_level;
         for (int32_t q = 0; q < ns; ++q) fwd_lv[B.fwd_level].push_back(make_int2(id, q));
         for (int32_t q = 0; q < bs; ++q) bwd_lv[bl].push_back(make_int2(id, q));
         fwd_lds_v[B.fwd_level] = std::max<int32_t>(fwd_lds_v[B.fwd_level], (int32_t)lf);
         bwd_lds_v[bl] = std::max<int32_t>(bwd_lds_v[bl], (int32_t)lb);
         fwd_bp_v[B.fwd_level] = std::max(fwd_bp_v[B.fwd_level], bp);
         bwd_bp_v[bl] = std::max(bwd_bp_v[bl], bp);
+        if (bs > 1) bwd_split_v[bl] = 1;
       }
       blocks.push_back(db);
     }
@@ -477,6 +539,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   bwd_lds = bwd_lds_v;
   fwd_bp = fwd_bp_v;
   bwd_bp = bwd_bp_v;
+  bwd_split = bwd_split_v;
   fwd_nt.assign(fwd_bp.size(), 256);
   bwd_nt.assign(bwd_bp.size(), 256);
   if (below.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "solve update buffer too large");
@@ -526,6 +589,12 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_cidx, cidx, s));
   HIP_TRY(upload(d_below, below, s));
   HIP_TRY(upload(d_prow, prow, s));
+  {
+    std::vector<double> pcol(prow.size());
+    transpose_panels(blocks, prow, pcol);
+    HIP_TRY(upload(d_pcol, pcol, s));
+  }
+  HIP_TRY(d_ybuf.alloc(n_nodes));
   HIP_TRY(d_upd.alloc(std::max<size_t>(below.size(), 1)));
   HIP_TRY(upload(d_dcol, dcol, s));
   HIP_TRY(upload(d_drow, drow, s));
@@ -551,6 +620,19 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
                      : hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s);
   };
   HIP_TRY(put(d_prow.ptr + panel_off[p], pl.panel_row));
+  {
+    // column-major copy of this pair's panels (blocks are stored per pair in order)
+    std::vector<double> pcol(pl.panel_row.size());
+    std::vector<DevBlock> bl(pl.blocks.size());
+    for (size_t k = 0; k < pl.blocks.size(); ++k) {
+      bl[k].r0 = pl.blocks[k].r0;
+      bl[k].r1 = pl.blocks[k].r1;
+      bl[k].m = (int32_t)(pl.below_ptr[k + 1] - pl.below_ptr[k]);
+      bl[k].poff = pl.panel_off[k];
+    }
+    transpose_panels(bl, pl.panel_row, pcol);
+    HIP_TRY(put(d_pcol.ptr + panel_off[p], pcol));
+  }
   HIP_TRY(put(d_apex_xf.ptr + apex_xf_base[p], pl.apex_xf));
   HIP_TRY(put(d_apex_xb.ptr + apex_xb_base[p], pl.apex_xb));
   HIP_TRY(put(d_dcol.ptr + dense_off[p], pl.dinv_col));
@@ -567,6 +649,7 @@ int64_t mr_ctx::device_bytes() const {
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
                    d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +
+                   d_pcol.bytes() + d_ybuf.bytes() +
                    d_apex_xf.bytes() + d_apex_xb.bytes() + d_apex_part.bytes() +
                    d_apex_cidx.bytes() + d_apex_arow.bytes() + d_apex_fitems.bytes() +
                    d_apex_bitems.bytes() +

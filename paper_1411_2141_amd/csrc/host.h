@@ -86,8 +86,6 @@ struct SolvePlan {
   std::vector<double> apex_xb;
   std::vector<int64_t> apex_cptr;          // apex rows + 1
   std::vector<int32_t> apex_cidx;          // update-buffer positions written by non-apex blocks
-  std::vector<int32_t> rel_bwd_level;      // backward level of non-apex blocks below the apex
-  int32_t n_rel_bwd_levels = 0;
 };
 
 struct PairHost {

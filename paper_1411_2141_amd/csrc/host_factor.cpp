@@ -535,15 +535,6 @@ std::string build_apex(PairHost &p, const OrderOptions &opt) {
       if (!pl.is_apex[blk_of_upd[pl.cidx[q]]]) pl.apex_cidx.push_back(pl.cidx[q]);
     pl.apex_cptr[i + 1] = (int64_t)pl.apex_cidx.size();
   }
-  // backward levels of the non-apex blocks, counted from the apex down
-  pl.rel_bwd_level.assign(nb, -1);
-  pl.n_rel_bwd_levels = 0;
-  for (int32_t s = nb - 1; s >= 0; --s) {
-    if (pl.is_apex[s]) continue;
-    const int32_t par = pl.blocks[s].parent;
-    pl.rel_bwd_level[s] = (par < 0 || pl.is_apex[par]) ? 0 : pl.rel_bwd_level[par] + 1;
-    pl.n_rel_bwd_levels = std::max(pl.n_rel_bwd_levels, pl.rel_bwd_level[s] + 1);
-  }
   return fill_apex_inverse(p);
 }
 

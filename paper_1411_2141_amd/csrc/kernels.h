@@ -22,15 +22,20 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
                            const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
                            double tau, const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s);
+// One level of the forward / backward block solve; nt = 8 or 16 selects the
+// wavefront-per-block kernels (blocks of at most 64 rows) issuing nt loads per
+// lane at a time, 64 / 128 / 256 the workgroup-per-block ones with that many
+// threads (LDS staged).
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
-                                  const double *dcol, const double *prow, double2 *x,
-                                  double2 *upd, const AssembleArgs *fuse, hipStream_t s);
+                                  const double *dcol, const double *prow, const double *pcol,
+                                  double2 *x, double2 *ybuf, double2 *upd,
+                                  const AssembleArgs *fuse, hipStream_t s);
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int32_t *below_idx,
                                   const double *drow, const double *prow, double2 *x,
-                                  const int32_t *perm, double2 *out, double2 *partials,
-                                  unsigned *counters, hipStream_t s);
+                                  const double2 *ybuf, const int32_t *perm, double2 *out,
+                                  double2 *partials, unsigned *counters, hipStream_t s);
 // The apex of the solve: t = b - (non-apex updates), segment partials of
 // y = X t, y, then z = X^T y written to x (and out[perm] when out is given).
 hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,

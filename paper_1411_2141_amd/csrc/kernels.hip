@@ -313,7 +313,8 @@ __device__ __forceinline__ double2 combine_parts(const double2 *red, int o, int 
 //   y = D^-1 t              (dense inverse, column-major packed, staged in LDS)
 // and then its slice of the block's own update entries
 //   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block)).
-// Slice 0 also writes y to x (in place).  Each phase spreads its sums over all
+// Slice 0 also writes y to ybuf (b stays in x for the other slices).  Each
+// phase spreads its sums over all
 // threads and combines the partial sums in a fixed order (deterministic).
 // With FUSED (first level only, no contributions) the workgroup forms b of
 // its rows itself, and the workgroups after the `count` block items assemble
@@ -322,8 +323,8 @@ template <int NT, bool FUSED>
 __global__ __launch_bounds__(NT) void k_solve_fwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
-    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *upd,
-    AssembleArgs A) {
+    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *ybuf,
+    double2 *upd, AssembleArgs A) {
   extern __shared__ double smem[];
   if (FUSED && (int)blockIdx.x >= count) {
     const int g = (int)blockIdx.x - count;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   if (part == 0 && r < b) {
     const double2 y = combine_parts(red, r, bp, np);
     yv[r] = y;
-    if (it.y == 0) x[B.r0 + r] = y;
+    if (it.y == 0) ybuf[B.r0 + r] = y;
   }
   __syncthreads();
   // phase 3: the slice's update entries, 4 partial sums per panel row
@@ -445,14 +446,15 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
 // sums s_j = sum_k P[k][j] z(below_k).  A block with one workgroup finishes at
 // once; otherwise each workgroup writes its partials, and the last to arrive
 // (device-scope counter) adds them in slice order.  The finishing workgroup
-// forms t = y_block - s and z = D^-T t (row-major packed inverse in LDS),
+// forms t = y_block - s (y from ybuf) and z = D^-T t (row-major packed inverse in LDS),
 // writes z in place and, when `out` is given, scatters it to natural order.
 // The finisher resets the counter.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_solve_bwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
     const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
-    const double *__restrict__ prow, double2 *x, const int32_t *__restrict__ perm,
+    const double *__restrict__ prow, double2 *x, const double2 *__restrict__ ybuf,
+    const int32_t *__restrict__ perm,
     double2 *__restrict__ out, double2 *partials, unsigned *counters) {
   extern __shared__ double smem[];
   __shared__ int last;
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
     if (tid == 0) atomicExch(&counters[B.cnt_idx], 0u);
   }
   if (g == 0 && j < b) {
-    const double2 yy = x[B.r0 + j];
+    const double2 yy = ybuf[B.r0 + j];
     t[j] = make_double2(yy.x - sum.x, yy.y - sum.y);
   }
   __syncthreads();
@@ -540,6 +542,210 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
     const double2 z = combine_parts(red, j, bp, np);
     x[B.r0 + j] = z;
     if (out) out[perm[B.r0 + j]] = z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-per-block level kernels: one wavefront solves one block (lane r
+// holds rows r and r + 64), reading the dense inverse and the panel straight
+// from global memory in coalesced order (each entry is used once, so nothing
+// is staged in LDS) and broadcasting the vector entries across lanes.  Four
+// independent wavefronts per workgroup, no barriers.
+// ---------------------------------------------------------------------------
+
+// v of lane `src` (uniform) in every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double2 lane_bcast2(double2 v, int src) {
+  return make_double2(lane_bcast(v.x, src), lane_bcast(v.y, src));
+}
+
+// Sum of the update entries upd[cidx[q]], q in [q0, q1), loads in batches.
+__device__ __forceinline__ double2 gather_updates(int64_t q0, int64_t q1,
+                                                  const int32_t *__restrict__ cidx,
+                                                  const double2 *__restrict__ upd) {
+  double ax = 0.0, ay = 0.0;
+  constexpr int U = 8;
+  for (int64_t q = q0; q < q1; q += U) {
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) idx[u] = q + u < q1 ? cidx[q + u] : -1;
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = idx[u] >= 0 ? upd[idx[u]] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ax += v[u].x;
+      ay += v[u].y;
+    }
+  }
+  return make_double2(ax, ay);
+}
+
+// Forward, one level (blocks of at most 64 rows): per item (block, slice)
+//   t = b_rows - contributions,  y = D t (D packed column-major),
+//   upd[k] = sum_j P(k, j) y_j for the slice's panel rows (P column-major),
+// slice 0 writes y to ybuf.  Lane r holds row r for the first two steps and
+// panel row k0 + kc + r for the third.  Loads are issued C per lane at a
+// time (all independent); D's first C columns before the right-hand side is
+// formed.  With FUSED (first level) b is assembled here and the workgroups
+// after the items assemble the other rows and finish the MSD.
+template <bool FUSED, int C>
+__global__ __launch_bounds__(256) void k_wave_fwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
+    const double *__restrict__ dcol, const double *__restrict__ pcol, double2 *x,
+    double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
+  const int item_groups = (count + 3) / 4;
+  if (FUSED && (int)blockIdx.x >= item_groups) {
+    const int g = (int)blockIdx.x - item_groups;
+    const int row_groups = (A.n_rows + 255) / 256;
+    if (g < row_groups) {
+      const int k = g * 256 + (int)threadIdx.x;
+      if (k < A.n_rows) {
+        const int row = A.rows[k];
+        // rows outside the first level keep b in x (read by later levels)
+        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      }
+    } else {
+      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
+    }
+    return;
+  }
+  const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (w >= count) return;
+  const int lane = threadIdx.x & 63;
+  const int2 it = items[w];
+  const DevBlock B = blocks[it.x];
+  const int b = B.r1 - B.r0, m = B.m;
+  const int k0 = it.y * B.rslice;
+  const int kn = max(0, min(B.rslice, m - k0));
+  // D(r, j), r >= j, at doff + j b - j (j - 1) / 2 + (r - j)
+  auto dload = [&](int j) {
+    return (j < b && j <= lane && lane < b)
+               ? dcol[B.doff + (int64_t)j * b - (int64_t)j * (j - 1) / 2 + (lane - j)]
+               : 0.0;
+  };
+  double v[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) v[u] = dload(u);
+  double2 t = make_double2(0.0, 0.0);
+  if (lane < b) {
+    const int row = B.r0 + lane;
+    if (FUSED) {
+      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+    } else {
+      const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
+      const double2 bb = x[row];
+      t = make_double2(bb.x - c.x, bb.y - c.y);
+    }
+  }
+  // y_r = sum_{j <= r} D(r, j) t_j
+  double2 y = make_double2(0.0, 0.0);
+  for (int j0 = 0; j0 < b; j0 += C) {
+    if (j0 > 0) {
+#pragma unroll
+      for (int u = 0; u < C; ++u) v[u] = dload(j0 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+      if (j0 + u < b) {
+        const double2 tj = lane_bcast2(t, j0 + u);
+        y.x += v[u] * tj.x;
+        y.y += v[u] * tj.y;
+      }
+  }
+  // upd[k] = sum_j P(k, j) y_j, panel entry (k, j) at poff + j m + k
+  for (int kc = 0; kc < kn; kc += 64) {
+    const int kk = k0 + kc + lane;
+    const bool on = kc + lane < kn;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j0 = 0; j0 < b; j0 += C) {
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        v[u] = (j0 + u < b && on) ? pcol[B.poff + (int64_t)(j0 + u) * m + kk] : 0.0;
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        if (j0 + u < b) {
+          const double2 yj = lane_bcast2(y, j0 + u);
+          acc.x += v[u] * yj.x;
+          acc.y += v[u] * yj.y;
+        }
+    }
+    if (on) upd[B.boff + kk] = acc;
+  }
+  if (it.y == 0 && lane < b) ybuf[B.r0 + lane] = y;
+}
+
+// Backward, one level (blocks of at most 64 rows, not split): per block
+//   s_j = sum_k P(k, j) z(below_k)   (P row-major; z gathered 64 rows at a time),
+//   t = y - s,  z_j = sum_{i >= j} D(i, j) t_i   (D packed row-major),
+// z written to x and, when `out` is given, to natural node order.  Lane j holds
+// column j.  Loads are issued C per lane at a time; the first panel chunk's
+// with the z gather.
+template <int C>
+__global__ __launch_bounds__(256) void k_wave_bwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
+    const double *__restrict__ prow, double2 *x, const double2 *__restrict__ ybuf,
+    const int32_t *__restrict__ perm, double2 *__restrict__ out) {
+  const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (w >= count) return;
+  const int lane = threadIdx.x & 63;
+  const int2 it = items[w];
+  const DevBlock B = blocks[it.x];
+  const int b = B.r1 - B.r0, m = B.m;
+  const bool col = lane < b;
+  auto pload = [&](int k) { return (k < m && col) ? prow[B.poff + (int64_t)k * b + lane] : 0.0; };
+  double v[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) v[u] = pload(u);
+  double2 s = make_double2(0.0, 0.0);
+  for (int kc = 0; kc < m; kc += 64) {
+    const double2 zl = kc + lane < m ? x[below_idx[B.boff + kc + lane]] : make_double2(0.0, 0.0);
+    const int kend = min(64, m - kc);
+    for (int k0 = 0; k0 < kend; k0 += C) {
+      if (kc > 0 || k0 > 0) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) v[u] = pload(kc + k0 + u);
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        if (k0 + u < kend) {
+          const double2 zk = lane_bcast2(zl, k0 + u);
+          s.x += v[u] * zk.x;
+          s.y += v[u] * zk.y;
+        }
+    }
+  }
+  double2 t = make_double2(0.0, 0.0);
+  if (col) {
+    const double2 y = ybuf[B.r0 + lane];
+    t = make_double2(y.x - s.x, y.y - s.y);
+  }
+  // z_j = sum_{i >= j} D(i, j) t_i, D(i, j) at doff + i (i + 1) / 2 + j
+  double2 z = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < b; i0 += C) {
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int i = i0 + u;
+      v[u] = (i < b && lane <= i && col) ? drow[B.doff + (int64_t)i * (i + 1) / 2 + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+      if (i0 + u < b) {
+        const double2 ti = lane_bcast2(t, i0 + u);
+        z.x += v[u] * ti.x;
+        z.y += v[u] * ti.y;
+      }
+  }
+  if (col) {
+    x[B.r0 + lane] = z;
+    if (out) out[perm[B.r0 + lane]] = z;
   }
 }
 
@@ -813,33 +1019,54 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
 
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
-                                  const double *dcol, const double *prow, double2 *x,
-                                  double2 *upd, const AssembleArgs *fuse, hipStream_t s) {
+                                  const double *dcol, const double *prow, const double *pcol,
+                                  double2 *x, double2 *ybuf, double2 *upd,
+                                  const AssembleArgs *fuse, hipStream_t s) {
+  if (nt == 8 || nt == 16) {                  // wavefront per block, nt loads per batch
+    int groups = (count + 3) / 4;
+    if (fuse)
+      groups += (fuse->n_rows + 255) / 256 + (fuse->finish_msd ? (fuse->n_pairs + 3) / 4 : 0);
+    if (groups == 0) return hipSuccess;
+    const AssembleArgs none{};
+    if (nt == 8)
+      return fuse ? launch(k_wave_fwd<true, 8>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, *fuse)
+                  : launch(k_wave_fwd<false, 8>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, none);
+    return fuse ? launch(k_wave_fwd<true, 16>, groups, 256, 0, s, blocks, items, count, cptr, cidx,
+                         dcol, pcol, x, ybuf, upd, *fuse)
+                : launch(k_wave_fwd<false, 16>, groups, 256, 0, s, blocks, items, count, cptr,
+                         cidx, dcol, pcol, x, ybuf, upd, none);
+  }
   nt = nt == 64 || nt == 128 ? nt : 256;
   if (!fuse) {
     auto k = nt == 64 ? k_solve_fwd<64, false> : nt == 128 ? k_solve_fwd<128, false>
                                                            : k_solve_fwd<256, false>;
     if (count == 0) return hipSuccess;
     return launch(k, count, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x,
-                  upd, AssembleArgs{});
+                  ybuf, upd, AssembleArgs{});
   }
   auto k = nt == 64 ? k_solve_fwd<64, true> : nt == 128 ? k_solve_fwd<128, true>
                                                         : k_solve_fwd<256, true>;
   const int groups = count + (fuse->n_rows + nt - 1) / nt +
                      (fuse->finish_msd ? (fuse->n_pairs + nt / 64 - 1) / (nt / 64) : 0);
   if (groups == 0) return hipSuccess;
-  return launch(k, groups, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x, upd,
-                *fuse);
+  return launch(k, groups, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x,
+                ybuf, upd, *fuse);
 }
 
 hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int32_t *below_idx,
                                   const double *drow, const double *prow, double2 *x,
-                                  const int32_t *perm, double2 *out, double2 *partials,
-                                  unsigned *counters, hipStream_t s) {
+                                  const double2 *ybuf, const int32_t *perm, double2 *out,
+                                  double2 *partials, unsigned *counters, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (nt == 8 || nt == 16)
+    return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
+                  items, count, below_idx, drow, prow, x, ybuf, perm, out);
   auto k = nt == 64 ? k_solve_bwd<64> : nt == 128 ? k_solve_bwd<128> : k_solve_bwd<256>;
   return launch(k, count, nt == 64 || nt == 128 ? nt : 256, lds_bytes, s, blocks, items,
-                below_idx, drow, prow, x, perm, out, partials, counters);
+                below_idx, drow, prow, x, ybuf, perm, out, partials, counters);
 }
 
 hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,
