@@ -79,12 +79,10 @@ def unit_bytes(ctx, pairs) -> dict:
     taps = 0
     for p in pairs:                      # coefficients touched by node samples at u = 0
         H, W = p.height, p.width
-        s = set()
-        for dm in range(-1, 3):
-            r = np.clip(p.V[:, 1] - 1 + dm, 0, H - 1)
-            for dn in range(-1, 3):
-                s.update((r * W + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)).tolist())
-        taps += len(s)
+        idx = [np.clip(p.V[:, 1] - 1 + dm, 0, H - 1).astype(np.int64) * W
+               + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)
+               for dm in range(-1, 3) for dn in range(-1, 3)]
+        taps += int(np.unique(np.concatenate(idx)).size)
     return {
         "sample": 36 * n + 4 * taps,
         "assemble": 48 * n + 8 * nnz_m,
@@ -133,6 +131,31 @@ def profile(ctx, run, total_bytes: dict, leg: str) -> tuple:
             "bytes_per_launch": int(total_bytes[dom] / kernels[dom]["launches"]),
             "avg_launch_us": kernels[dom]["avg_us"]}
     return kernels, roof
+
+
+def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
+    """Sample, assemble and warp each timed on their own (the library's force
+    and warp entry points, which launch them unfused), with dispatch-attached
+    events: achieved GB/s on algorithmic bytes against the HBM peak."""
+    import torch
+    ub = unit_bytes(ctx, pairs)
+    ctx.enable_timing(True)
+    for _ in range(reps):
+        ctx.force(u)
+    for _ in range(reps):
+        ctx.warp_msd(u)
+    torch.cuda.synchronize()
+    times = ctx.kernel_times()
+    ctx.enable_timing(False)
+    out = {}
+    for fam, nbytes in (("sample", ub["sample"]), ("assemble", ub["assemble"]),
+                        ("warp", ub["warp"] + ub["finish"])):
+        ms, cnt = times[fam]
+        if cnt:
+            gbs = reps * nbytes / (ms * 1e-3) / 1e9
+            out[fam] = {"us_per_call": round(ms / reps * 1e3, 3), "bytes_per_call": int(nbytes),
+                        "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
@@ -229,11 +252,12 @@ def main() -> int:
         side.synchronize()
         dt_eager = time.perf_counter() - t0
 
-        kernels, roof = {}, None
+        kernels, roof, stages = {}, None, None
         if not args.no_profile:
             u.zero_()
             kernels, roof = profile(ctx, lambda: run(K),
                                     run_bytes(unit_bytes(ctx, [pair]), K, True), "single_pair")
+            stages = stage_rooflines(ctx, [pair], u)
 
     fwd_bwd = None
     if args.fwdbwd_iters:
@@ -273,18 +297,19 @@ def main() -> int:
             msd_b = bctx.warp_msd(ub)
             side.synchronize()
             dtc = time.perf_counter() - t0
-            bk, broof = {}, None
+            bk, broof, bstages = {}, None, None
             if not args.no_profile:
                 ub.zero_()
                 bk, broof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, KB, None,
                                                                   side.cuda_stream),
                                     run_bytes(unit_bytes(bctx, batch), KB, False), "batched")
+                bstages = stage_rooflines(bctx, batch, ub)
         batched = {"value": round(nb * KB / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
                    "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),
                    "iterations": KB, "ms_per_iteration": round(dtc / KB * 1e3, 4),
                    "iterations_per_s": round(KB / dtc, 2), "graph": True,
                    "mean_final_msd": float(msd_b.mean().item()),
-                   "kernels": bk, "roofline": broof}
+                   "kernels": bk, "roofline": broof, "stage_rooflines": bstages}
         bctx.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
@@ -299,7 +324,7 @@ def main() -> int:
                    "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": pair.height * pair.width,
                    "iterations": K, "parallelism": "single GPU", "graph": True,
                    "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
-        "kernels": kernels, "roofline": roof, "cpu_baseline": cpu,
+        "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd, "batched": batched,
     }
     print(json.dumps(out))

@@ -83,7 +83,7 @@ enum {
 
 /* One registration pair (Algorithm 1, "Inputs"; Section 2.1 for (V, T)). */
 typedef struct {
-  int32_t height, width;       /* image rows, columns (>= 1) */
+  int32_t height, width;       /* image rows, columns (1 .. 65535) */
   int32_t n_nodes, n_tris;     /* >= 3 and >= 1 */
   const int32_t *node_xy;      /* HOST [n_nodes][2] integer corners (x, y) in [0,W]x[0,H]; copied */
   const int32_t *tris;         /* HOST [n_tris][3] node indices, positive signed area
@@ -103,6 +103,13 @@ typedef struct {
                                   entries it adds stay within 2^21 / n_pairs), -1 = none */
   int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic
                                   (128 for one pair, unsplit for a batch) */
+  int32_t solve_kernel;        /* solve schedule: 0 = autotuned per level; 8 or 16 = the
+                                  wavefront-per-block kernels (8 or 16 loads per lane in flight)
+                                  wherever admissible (blocks <= 64 rows, no split backward
+                                  blocks); 64, 128 or 256 = workgroup-per-block kernels of that
+                                  size; levels where the choice is not admissible take the
+                                  smallest admissible workgroup size.  MR_FLAG_NO_TUNE with 0
+                                  means 256 everywhere. */
 } mr_params;
 
 /* Pre-computation (Algorithm 1): validates every mesh, builds tables T1-T6

@@ -50,7 +50,7 @@ class MrPair(ctypes.Structure):
 class MrParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("force_mode", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("apex_rows", ctypes.c_int32),
-                ("bwd_split_rows", ctypes.c_int32)]
+                ("bwd_split_rows", ctypes.c_int32), ("solve_kernel", ctypes.c_int32)]
 
 
 _lib = None
@@ -103,7 +103,8 @@ def _ptr(t) -> int | None:
 
 
 def mesh_reg_init(pairs: list, tau: float, force_mode: int = MR_FORCE_P1, flags: int = 0,
-                  stream: int | None = None, apex_rows: int = 0, bwd_split_rows: int = 0):
+                  stream: int | None = None, apex_rows: int = 0, bwd_split_rows: int = 0,
+                  solve_kernel: int = 0):
     """``pairs``: sequence of dicts with ``V`` (int32 [n][2]), ``T`` (int32 [nT][3]),
     ``te``/``re`` (device FP32 [H][W] tensors, or None with the host-only flag),
     ``height``, ``width`` and ``alpha``.  Returns the opaque context handle."""
@@ -117,7 +118,8 @@ def mesh_reg_init(pairs: list, tau: float, force_mode: int = MR_FORCE_P1, flags:
         arr[k] = MrPair(int(p["height"]), int(p["width"]), V.shape[0], T.shape[0],
                         V.ctypes.data, T.ctypes.data, _ptr(p.get("te")), _ptr(p.get("re")),
                         float(p["alpha"]))
-    params = MrParams(float(tau), int(force_mode), int(flags), int(apex_rows), int(bwd_split_rows))
+    params = MrParams(float(tau), int(force_mode), int(flags), int(apex_rows), int(bwd_split_rows),
+                      int(solve_kernel))
     out = ctypes.c_void_p()
     _check(lib.mesh_reg_init(arr, len(pairs), ctypes.byref(params), stream, ctypes.byref(out)))
     return out

@@ -132,6 +132,34 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
 // kernels with 64, 128, 256 threads (at least the level's largest block
 // rounded up to a power of two).  The level kernels only read and write the
 // solve scratch vectors, so running them on whatever those hold is harmless.
+bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
+  const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
+  if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
+  return nt >= minnt[lev];
+}
+
+// Every level takes `nt` where admissible, else the smallest admissible
+// workgroup size.
+void mr_ctx::force_solve_kernel(int nt) {
+  for (int dir = 0; dir < 2; ++dir) {
+    const bool fwd = dir == 0;
+    std::vector<int32_t> &choice = fwd ? fwd_nt : bwd_nt;
+    for (size_t lev = 0; lev < choice.size(); ++lev) {
+      int pick = 256;
+      if (admissible(fwd, lev, nt)) {
+        pick = nt;
+      } else {
+        for (int w : {64, 128, 256})
+          if (admissible(fwd, lev, w)) {
+            pick = w;
+            break;
+          }
+      }
+      choice[lev] = pick;
+    }
+  }
+}
+
 int mr_ctx::tune(hipStream_t s) {
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
@@ -159,11 +187,6 @@ int mr_ctx::tune(hipStream_t s) {
       if (rep > 0) t_min = std::min(t_min, ms);
     }
     return t_min;
-  };
-  auto admissible = [&](bool fwd, size_t lev, int nt) {
-    const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
-    if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
-    return nt >= minnt[lev];
   };
   static const int kCandidates[] = {8, 16, 64, 128, 256};
   // pass 1: every level on its own
@@ -224,7 +247,7 @@ hipError_t mr_ctx::sample(const double2 *u, bool with_warp, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
   hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr,
                                d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
-                               with_warp ? n_tiles : 0, d_tri.ptr, d_t6.ptr, d_re.ptr,
+                               with_warp ? n_tiles : 0, d_tri.ptr, d_tpos.ptr, d_t6.ptr, d_re.ptr,
                                d_partials.ptr, s);
   timed_end(s);
   return e;
@@ -271,7 +294,7 @@ hipError_t mr_ctx::finish_pending(const double2 *u, double **pending, hipStream_
 
 hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_t s) {
   timed_begin(MR_KF_WARP, s);
-  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, u, d_xy.ptr,
+  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, u, d_tpos.ptr,
                                       d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
                                       d_partials.ptr, d_flags.ptr, s);
   if (e == hipSuccess) e = launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s);
@@ -549,6 +572,15 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_tiles, tiles, s));
   HIP_TRY(upload(d_xy, xy, s));
   HIP_TRY(upload(d_tri, tri, s));
+  {
+    // triangle corners packed as x | y << 16 (image sides below 65536)
+    std::vector<int4> tpos(tri.size());
+    for (size_t t = 0; t < tri.size(); ++t) {
+      auto pk = [&](int node) { return (int)((uint32_t)xy[node].x | ((uint32_t)xy[node].y << 16)); };
+      tpos[t] = make_int4(pk(tri[t].x), pk(tri[t].y), pk(tri[t].z), 0);
+    }
+    HIP_TRY(upload(d_tpos, tpos, s));
+  }
   HIP_TRY(upload(d_t6, t6, s));
   HIP_TRY(upload(d_iperm, iperm, s));
   HIP_TRY(upload(d_perm, perm, s));
@@ -643,7 +675,7 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
 
 int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
-                   d_tri.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
+                   d_tri.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
@@ -707,6 +739,11 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   if (!(params->tau > 0.0) || !std::isfinite(params->tau)) return fail(MR_EINVAL, "tau must be finite and > 0");
   if (params->force_mode != MR_FORCE_P1 && params->force_mode != MR_FORCE_NODAL)
     return fail(MR_EINVAL, "unknown force_mode");
+  {
+    const int32_t k = params->solve_kernel;
+    if (k != 0 && k != 8 && k != 16 && k != 64 && k != 128 && k != 256)
+      return fail(MR_EINVAL, "solve_kernel must be 0, 8, 16, 64, 128 or 256");
+  }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {
     const mr_pair &q = pairs[p];
@@ -715,6 +752,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     if (!q.node_xy || !q.tris) return fail(MR_EINVAL, "pair " + std::to_string(p) + ": null mesh");
     if (q.n_nodes < 3 || q.n_tris < 1 || q.height < 1 || q.width < 1)
       return fail(MR_EINVAL, "pair " + std::to_string(p) + ": empty mesh or image");
+    if (q.height > 65535 || q.width > 65535)
+      return fail(MR_EINVAL, "pair " + std::to_string(p) + ": image sides must be below 65536");
     if (!host_only && (!q.te || !q.re))
       return fail(MR_EINVAL, "pair " + std::to_string(p) + ": null te/re");
   }
@@ -801,7 +840,9 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     delete c;
     return fail(MR_EHIP, std::string("init: ") + hipGetErrorString(e));
   }
-  if (!(params->flags & MR_FLAG_NO_TUNE) && (rc = c->tune(s)) != MR_OK) {
+  if (params->solve_kernel != 0) {
+    c->force_solve_kernel(params->solve_kernel);
+  } else if (!(params->flags & MR_FLAG_NO_TUNE) && (rc = c->tune(s)) != MR_OK) {
     delete c;
     return rc;
   }

@@ -56,6 +56,7 @@ struct mr_ctx {
   mr::DevArray<mr::TileItem> d_tiles;
   mr::DevArray<int2> d_xy;
   mr::DevArray<int4> d_tri;
+  mr::DevArray<int4> d_tpos;                    // triangle corners, x | y << 16
   mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
   mr::DevArray<float> d_coef, d_re, d_rho;
   mr::DevArray<int32_t> d_mptr, d_mcol;
@@ -127,6 +128,8 @@ struct mr_ctx {
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
   int tune(hipStream_t s);
+  bool admissible(bool fwd, size_t lev, int nt) const;
+  void force_solve_kernel(int nt);
   hipError_t solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s,
                          const mr::AssembleArgs *fuse);
   int step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s);

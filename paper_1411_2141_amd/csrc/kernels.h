@@ -15,8 +15,8 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const int4 *tri, const int32_t *t6, const float *re, double *partials,
-                         hipStream_t s);
+                         const int4 *tri, const int4 *tpos, const int32_t *t6, const float *re,
+                         double *partials, hipStream_t s);
 // Assemble launch; with finish_msd it also finishes the MSD of `partials`.
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
@@ -42,11 +42,11 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
                              const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
                              const ApexFwdItem *fitems, int n_fitems, const double *xf,
                              double2 *part, const ApexRow *arow, double2 *ybuf,
-                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng,
-                             int bwd_lds, const double *xb, const int32_t *perm, double2 *out,
-                             hipStream_t s);
+                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng, int bwd_lds,
+                             const double *xb, const int32_t *perm, double2 *out, hipStream_t s);
+// Warp partials of u; tpos holds each triangle's corners packed as x | y << 16.
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                const double2 *u, const int2 *xy, const int4 *tri,
+                                const double2 *u, const int4 *tpos, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,
                                 float *warped, double *partials, unsigned *flags, hipStream_t s);
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,

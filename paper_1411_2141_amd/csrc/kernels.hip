@@ -123,61 +123,97 @@ __device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pai
   if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
 }
 
-// Warp + MSD of one kTile x kTile pixel tile: each pixel takes the
-// piecewise-linear displacement of its triangle (barycentric weights from exact
-// cross products in doubled integer coordinates), the template spline is
-// sampled at the displaced pixel centre (FP64 weights and sums), and the
-// tile's FP64 sum of squared differences goes to partials[tile].
-__device__ __forceinline__ void warp_tile(int tile, const TileItem *__restrict__ tiles,
-                                          const DevPair *__restrict__ pairs,
-                                          const double2 *__restrict__ u,
-                                          const int2 *__restrict__ xy,
-                                          const int4 *__restrict__ tri,
-                                          const int32_t *__restrict__ t6,
-                                          const float *__restrict__ coef,
-                                          const float *__restrict__ re,
-                                          float *__restrict__ warped,
-                                          double *__restrict__ partials, unsigned *flags) {
-  const TileItem it = tiles[tile];
-  const DevPair P = pairs[it.pair];
+// Squared difference of one pixel of a tile (0 outside the image): the pixel
+// takes the piecewise-linear displacement of its triangle (barycentric
+// weights from exact cross products in doubled integer coordinates) and the
+// template spline is sampled at the displaced pixel centre (FP64 weights and
+// sums).
+__device__ __forceinline__ double warp_pixel(const TileItem &it, const DevPair &P,
+                                             const double2 *__restrict__ u,
+                                             const int4 *__restrict__ tpos,
+                                             const int4 *__restrict__ tri,
+                                             const int32_t *__restrict__ t6,
+                                             const float *__restrict__ coef,
+                                             const float *__restrict__ re,
+                                             float *__restrict__ warped, unsigned *flags) {
   const int i = it.y0 + (int)(threadIdx.x / kTile);
   const int j = it.x0 + (int)(threadIdx.x % kTile);
-  double acc = 0.0;
-  if (i < P.height && j < P.width) {
-    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
-    const int4 nd = tri[P.tri_off + t6[pix]];
-    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
-    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
-    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
-    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
-    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
-    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-    const double inv = 1.0 / (ca + cb + cc);
-    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
-    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
-    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
-    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
-    int qx, qy;
-    double fx, fy;
-    const bool okx = split_coord_d(j, dx, qx, fx);
-    const bool ok = split_coord_d(i, dy, qy, fy) && okx;
-    if (!ok) atomicOr(flags, kFlagNonFinitePixel);
-    const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
-    if (warped) warped[pix] = (float)w;
-    const double e = w - (double)re[pix];
-    acc = e * e;
+  if (i >= P.height || j >= P.width) return 0.0;
+  const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
+  const int tt = P.tri_off + t6[pix];
+  const int4 nd = tri[tt];
+  const int4 ps = tpos[tt];                   // corners as x | y << 16
+  const int2 a = make_int2(ps.x & 0xffff, (int)((unsigned)ps.x >> 16));
+  const int2 b = make_int2(ps.y & 0xffff, (int)((unsigned)ps.y >> 16));
+  const int2 c = make_int2(ps.z & 0xffff, (int)((unsigned)ps.z >> 16));
+  const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
+  const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+  const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+  const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+  const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+  const double inv = 1.0 / (ca + cb + cc);
+  const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+  const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
+  const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
+  const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
+  int qx, qy;
+  double fx, fy;
+  const bool okx = split_coord_d(j, dx, qx, fx);
+  const bool ok = split_coord_d(i, dy, qy, fy) && okx;
+  if (!ok) atomicOr(flags, kFlagNonFinitePixel);
+  const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
+  if (warped) warped[pix] = (float)w;
+  const double e = w - (double)re[pix];
+  return e * e;
+}
+
+// Warp + MSD of NT (1 or 2) kTile x kTile pixel tiles, tile0 and tile1
+// (tile1 < 0: none): with two, every thread takes the same pixel position in
+// both, so the two dependent gather chains overlap.  Each tile's FP64 sum of squared
+// differences (wavefront sums, then the four wavefronts in order) goes to
+// partials[tile].
+template <int NT>
+__device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem *__restrict__ tiles,
+                                           const DevPair *__restrict__ pairs,
+                                           const double2 *__restrict__ u,
+                                           const int4 *__restrict__ tpos,
+                                           const int4 *__restrict__ tri,
+                                           const int32_t *__restrict__ t6,
+                                           const float *__restrict__ coef,
+                                           const float *__restrict__ re,
+                                           float *__restrict__ warped,
+                                           double *__restrict__ partials, unsigned *flags) {
+  // NT == 1: tile0 only.  NT == 2 without a second tile: the first is
+  // evaluated twice (same values, same writes) and only its sum is kept.
+  const TileItem it0 = tiles[tile0];
+  const DevPair P0 = pairs[it0.pair];
+  double a0 = warp_pixel(it0, P0, u, tpos, tri, t6, coef, re, warped, flags);
+  double a1 = 0.0;
+  if (NT == 2) {
+    const int t1 = tile1 >= 0 ? tile1 : tile0;
+    const TileItem it1 = tiles[t1];
+    const DevPair P1 = pairs[it1.pair];
+    a1 = warp_pixel(it1, P1, u, tpos, tri, t6, coef, re, warped, flags);
   }
-  __shared__ double red[4];
-  acc = wave_sum(acc);
+  __shared__ double red[8];
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = acc;
+  if (lane == 0) {
+    red[wave] = a0;
+    red[4 + wave] = a1;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) partials[tile] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    partials[tile0] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (NT == 2 && tile1 >= 0) partials[tile1] = (red[4] + red[5]) + (red[6] + red[7]);
+  }
 }
 
 // Node sampling of u (one workgroup per node item).  When `n_tiles` > 0 the
-// workgroups after the node items warp the same u into the MSD partials, so
-// the MSD of the previous iteration's result shares this launch.
+// workgroups after the node items warp the same u into the MSD partials (one
+// tile each: this launch is short, and a workgroup's latency matters more
+// than overlap), so the MSD of the previous iteration's result shares it.
 __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items, int n_items,
                                                 const DevPair *__restrict__ pairs,
                                                 const double2 *__restrict__ u,
@@ -187,12 +223,13 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
                                                 float2 *__restrict__ h, unsigned *flags,
                                                 const TileItem *__restrict__ tiles,
                                                 const int4 *__restrict__ tri,
+                                                const int4 *__restrict__ tpos,
                                                 const int32_t *__restrict__ t6,
                                                 const float *__restrict__ re,
-                                                double *__restrict__ partials) {
+                                                double *__restrict__ partials, int n_tiles) {
   if ((int)blockIdx.x >= n_items) {
-    warp_tile((int)blockIdx.x - n_items, tiles, pairs, u, xy, tri, t6, coef, re, nullptr,
-              partials, flags);
+    warp_tiles<1>((int)blockIdx.x - n_items, -1, tiles, pairs, u, tpos, tri, t6, coef, re,
+                  nullptr, partials, flags);
     return;
   }
   const NodeItem it = items[blockIdx.x];
@@ -886,8 +923,8 @@ __global__ __launch_bounds__(256) void k_apex_combine(int n, const ApexRow *__re
 // path (its block's rows from r on, then the ancestor blocks' rows) with y on
 // the same rows.  A work item takes up to 8 rows of one block: each
 // wavefront loads its two columns' first entries while the path list of the
-// first row is staged in LDS from y; row r uses the list from position r - a0
-// on.  z goes to x and, when `out` is given, to natural node order.
+// first row is staged in LDS from y; row r uses the list from position
+// r - a0 on.  z goes to x and, when `out` is given, to natural node order.
 __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict__ items,
                                                   const int2 *__restrict__ rng,
                                                   const int32_t *__restrict__ rows,
@@ -951,10 +988,12 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
 
 __global__ __launch_bounds__(256) void k_warp_msd(
     const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, const double2 *__restrict__ u,
-    const int2 *__restrict__ xy, const int4 *__restrict__ tri, const int32_t *__restrict__ t6,
+    const int4 *__restrict__ tpos, const int4 *__restrict__ tri, const int32_t *__restrict__ t6,
     const float *__restrict__ coef, const float *__restrict__ re, float *__restrict__ warped,
-    double *__restrict__ partials, unsigned *flags) {
-  warp_tile(blockIdx.x, tiles, pairs, u, xy, tri, t6, coef, re, warped, partials, flags);
+    double *__restrict__ partials, unsigned *flags, int n_tiles) {
+  const int t0 = 2 * (int)blockIdx.x;
+  warp_tiles<2>(t0, t0 + 1 < n_tiles ? t0 + 1 : -1, tiles, pairs, u, tpos, tri, t6, coef, re,
+                warped, partials, flags);
 }
 
 __global__ __launch_bounds__(256) void k_msd_finish(const DevPair *__restrict__ pairs, int n_pairs,
@@ -1002,10 +1041,10 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *u, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const int4 *tri, const int32_t *t6, const float *re, double *partials,
-                         hipStream_t s) {
+                         const int4 *tri, const int4 *tpos, const int32_t *t6, const float *re,
+                         double *partials, hipStream_t s) {
   return launch(k_sample, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u, xy, coef,
-                rho, h, flags, tiles, tri, t6, re, partials);
+                rho, h, flags, tiles, tri, tpos, t6, re, partials, n_tiles);
 }
 
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
@@ -1073,9 +1112,8 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
                              const int32_t *acidx, const double2 *upd, double2 *x, double2 *tbuf,
                              const ApexFwdItem *fitems, int n_fitems, const double *xf,
                              double2 *part, const ApexRow *arow, double2 *ybuf,
-                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng,
-                             int bwd_lds, const double *xb, const int32_t *perm, double2 *out,
-                             hipStream_t s) {
+                             const ApexBwdItem *bitems, int n_bitems, const int2 *rng, int bwd_lds,
+                             const double *xb, const int32_t *perm, double2 *out, hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   hipError_t e = launch(k_apex_rhs, (n_rows + 255) / 256, 256, 0, s, n_rows, rows, acptr, acidx,
                         upd, x, tbuf);
@@ -1083,16 +1121,18 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
   if (e == hipSuccess)
     e = launch(k_apex_combine, (n_rows + 255) / 256, 256, 0, s, n_rows, arow, part, ybuf);
   if (e == hipSuccess)
-    e = launch(k_apex_bwd, n_bitems, 256, bwd_lds, s, bitems, rng, rows, ybuf, xb, x, perm, out);
+    e = launch(k_apex_bwd, n_bitems, 256, bwd_lds, s, bitems, rng, rows, (const double2 *)ybuf, xb,
+               x, perm, out);
   return e;
 }
 
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                const double2 *u, const int2 *xy, const int4 *tri,
+                                const double2 *u, const int4 *tpos, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,
                                 float *warped, double *partials, unsigned *flags, hipStream_t s) {
-  return launch(k_warp_msd, n_tiles, kTile * kTile, 0, s, tiles, pairs, u, xy, tri, t6, coef, re,
-                warped, partials, flags);
+  if (n_tiles == 0) return hipSuccess;
+  return launch(k_warp_msd, (n_tiles + 1) / 2, kTile * kTile, 0, s, tiles, pairs, u, tpos, tri, t6,
+                coef, re, warped, partials, flags, n_tiles);
 }
 
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,

@@ -84,6 +84,25 @@ struct Taps {
   const float *row[4];
 };
 
+// The four taps of one coefficient row around cell cx: one 16-byte load when
+// all four lie inside the row (the common case), else the folded taps one by
+// one.
+struct __attribute__((aligned(4))) Row4 {
+  float v[4];
+};
+__device__ __forceinline__ void row_taps(const float *__restrict__ r, const Taps &tp, int cx, int W,
+                                         float t[4]) {
+  if (cx >= 1 && cx + 2 < W) {
+    Row4 q;
+    __builtin_memcpy(&q, r + (cx - 1), sizeof(Row4));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = q.v[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = r[tp.col[k]];
+  }
+}
+
 __device__ __forceinline__ void make_taps(const float *__restrict__ c, int H, int W, int cx,
                                           int cy, Taps &tp) {
 #pragma unroll
@@ -103,9 +122,9 @@ __device__ __forceinline__ float spline_value(const float *__restrict__ c, int H
   float v = 0.0f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const float *r = tp.row[m];
-    const float rv = r[tp.col[0]] * wx[0] + r[tp.col[1]] * wx[1] + r[tp.col[2]] * wx[2] +
-                     r[tp.col[3]] * wx[3];
+    float c[4];
+    row_taps(tp.row[m], tp, cx, W, c);
+    const float rv = c[0] * wx[0] + c[1] * wx[1] + c[2] * wx[2] + c[3] * wx[3];
     v += wy[m] * rv;
   }
   return v;
@@ -122,9 +141,10 @@ __device__ __forceinline__ double spline_value_d(const float *__restrict__ c, in
   double v = 0.0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const float *r = tp.row[m];
-    const double rv = (double)r[tp.col[0]] * wx[0] + (double)r[tp.col[1]] * wx[1] +
-                      (double)r[tp.col[2]] * wx[2] + (double)r[tp.col[3]] * wx[3];
+    float c[4];
+    row_taps(tp.row[m], tp, cx, W, c);
+    const double rv = (double)c[0] * wx[0] + (double)c[1] * wx[1] + (double)c[2] * wx[2] +
+                      (double)c[3] * wx[3];
     v += wy[m] * rv;
   }
   return v;
@@ -143,8 +163,9 @@ __device__ __forceinline__ void spline_value_grad(const float *__restrict__ c, i
   val = gx = gy = 0.0f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const float *r = tp.row[m];
-    const float c0 = r[tp.col[0]], c1 = r[tp.col[1]], c2 = r[tp.col[2]], c3 = r[tp.col[3]];
+    float c[4];
+    row_taps(tp.row[m], tp, cx, W, c);
+    const float c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
     const float rv = c0 * wx[0] + c1 * wx[1] + c2 * wx[2] + c3 * wx[3];
     const float rd = c0 * dx[0] + c1 * dx[1] + c2 * dx[2] + c3 * dx[3];
     val += wy[m] * rv;

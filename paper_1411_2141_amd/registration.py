@@ -27,7 +27,7 @@ class MeshReg:
     def __init__(self, pairs, tau: float, force_mode: int = B.MR_FORCE_P1,
                  host_only: bool = False, device: str | torch.device = "cuda",
                  apex_rows: int = 0, bwd_split_rows: int = 0, graph: bool = False,
-                 tune: bool = True):
+                 tune: bool = True, solve_kernel: int = 0):
         self.host_only = host_only
         self.device = torch.device(device) if not host_only else torch.device("cpu")
         get = (lambda p, k: p[k]) if isinstance(pairs[0], dict) else (lambda p, k: getattr(p, k))
@@ -49,7 +49,8 @@ class MeshReg:
         if not tune:
             flags |= B.MR_FLAG_NO_TUNE
         stream = None if host_only else _stream()
-        self.ctx = B.mesh_reg_init(specs, tau, force_mode, flags, stream, apex_rows, bwd_split_rows)
+        self.ctx = B.mesh_reg_init(specs, tau, force_mode, flags, stream, apex_rows, bwd_split_rows,
+                                   solve_kernel)
         self._images = []          # the library keeps its own copies
         self.tau = float(tau)
         self.n_pairs = len(pairs)

@@ -114,6 +114,11 @@ def test_invalid_inputs_are_rejected():
     _expect(B.MR_EINVAL, tau=float("nan"))
     _expect(B.MR_EINVAL, dict(p, alpha=-1.0))
     _expect(B.MR_EINVAL, dict(p, alpha=float("inf")))
+    # image sides up to 65535 (triangle corners are packed as 16-bit pairs)
+    wide = np.zeros((1, 65536), np.float32)
+    Vw = np.array([[0, 0], [65536, 0], [0, 1], [65536, 1]], np.int32)
+    Tw = np.array([[0, 1, 3], [0, 3, 2]], np.int32)
+    assert "65536" in _expect(B.MR_EINVAL, dict(te=wide, re=wide, V=Vw, T=Tw, alpha=0.1))
 
 
 def test_uncovered_pixel_is_rejected():
