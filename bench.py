@@ -8,10 +8,14 @@ two FP64 triangular solves of (I + tau alpha K), and the full-pixel warp + MSD
 u = 0 with every input already resident in device memory.
 
 Extra legs in the same JSON line (same numerator, nodes x iterations):
-  fwd_bwd  -- the same pair, 100 iterations forward plus the checkpointed
-              reverse pass (gradients w.r.t. u0, alpha and the template);
-  batched  -- 256 ragged pairs (sides 128..1024, s=1..32, g=0.10), 100
-              iterations per call, all pairs in every launch, HIP-graph replay.
+  fwd_bwd    -- the same pair, 100 iterations forward plus the checkpointed
+                reverse pass (gradients w.r.t. u0, alpha and the template);
+  batched    -- 256 ragged pairs (sides 128..1024, s=1..32, g=0.10), 100
+                iterations per call, all pairs in every launch, HIP-graph replay;
+  large_pair -- one 2048x2048 pair (559k nodes), 50 iterations: plain against
+                forward + reverse pass (checkpoint 10);
+  diff_batch -- 64 pairs of 512x512 with per-pair alpha, 100 iterations: plain
+                against forward + reverse pass (checkpoint 10).
 Each leg reports its dominant kernel family's roofline (algorithmic bytes per
 launch over the HIP-event launch time).  The FP64 oracle is timed on a
 bounded sample on one host core (``cpu_baseline``).
@@ -158,6 +162,57 @@ def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
     return out
 
 
+def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload) -> dict:
+    """Plain iterations against forward + checkpointed reverse pass on the same
+    pairs: N iterations from u = 0 (graph replay), then the gradient of the
+    summed final MSDs w.r.t. u0, every alpha and every template (checkpoint
+    every 10 iterations)."""
+    import torch
+    nb = sum(p.n_nodes for p in pairs)
+    with torch.cuda.stream(stream):
+        ctx = pkg.MeshReg(pairs, tau=tau, graph=True)
+        u = ctx.zeros_u()
+        B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream)      # capture + warm-up
+        ctx.backward(ctx.zeros_u(), N, 10)                             # adjoint buffers
+        stream.synchronize()
+        u.zero_()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream)
+        msd = ctx.warp_msd(u)
+        stream.synchronize()
+        dt_plain = time.perf_counter() - t0
+        u0 = ctx.zeros_u()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
+        stream.synchronize()
+        dt_bwd = time.perf_counter() - t0
+        roof = None
+        if not no_profile:
+            u.zero_()
+            _, roof = profile(ctx, lambda: B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream),
+                              run_bytes(unit_bytes(ctx, pairs), N, False), "diff")
+        ctx.close()
+    # the reverse pass recomputes the forward from checkpoints, so one gradient
+    # evaluation costs (forward) + (reverse pass)
+    grad_eval = dt_plain + dt_bwd
+    return {"workload": workload, "pairs": len(pairs), "nodes": nb,
+            "pixels": int(sum(p.height * p.width for p in pairs)), "iterations": N,
+            "ckpt_every": 10,
+            "plain": {"ms_per_iteration": round(dt_plain / N * 1e3, 4),
+                      "iterations_per_s": round(N / dt_plain, 2),
+                      "node_updates_per_s": round(nb * N / dt_plain, 1),
+                      "mean_final_msd": float(msd.mean().item())},
+            "fwd_bwd": {"ms_per_iteration": round(grad_eval / N * 1e3, 4),
+                        "grad_evals_per_s": round(1.0 / grad_eval, 3),
+                        "node_updates_per_s": round(nb * N / grad_eval, 1),
+                        "vs_plain": round(dt_plain / grad_eval, 4),
+                        "mean_final_msd": float(msd_b.mean().item()),
+                        "g_alpha_norm": float(torch.linalg.vector_norm(g_alpha).item())},
+            "roofline": roof}
+
+
 def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
     from oracle import registration as reg
     pb = reg.setup(pair.te, pair.re, pair.V, pair.T, pair.alpha, tau)
@@ -185,6 +240,11 @@ def main() -> int:
     ap.add_argument("--fwdbwd-iters", type=int, default=100, help="0 skips the fwd+bwd leg")
     ap.add_argument("--batched-pairs", type=int, default=256, help="0 skips the batched leg")
     ap.add_argument("--batched-iters", type=int, default=100)
+    ap.add_argument("--large-iters", type=int, default=50,
+                    help="iterations of the 2048x2048 differentiable leg (0 skips it)")
+    ap.add_argument("--diff-batch-pairs", type=int, default=64,
+                    help="pairs of the differentiable 512x512 batch leg (0 skips it)")
+    ap.add_argument("--diff-batch-iters", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +268,9 @@ def main() -> int:
     cpus = len(os.sched_getaffinity(0))
     batch = (make_pairs(4, args.batched_pairs, processes=min(16, cpus))
              if args.batched_pairs else [])
+    large = make_pair(3) if args.large_iters else None
+    dbatch = (make_pairs(5, args.diff_batch_pairs, processes=min(16, cpus))
+              if args.diff_batch_pairs else [])
 
     import torch
     import paper_1411_2141_amd as pkg
@@ -312,6 +375,16 @@ def main() -> int:
                    "kernels": bk, "roofline": broof, "stage_rooflines": bstages}
         bctx.close()
 
+    large_leg = None
+    if large is not None:
+        large_leg = diff_leg(pkg, B, [large], tau, args.large_iters, side, args.no_profile,
+                             "single pair 2048x2048 FP32, quadtree s=1..32 g=0.08, alpha=0.05")
+    dbatch_leg = None
+    if dbatch:
+        dbatch_leg = diff_leg(pkg, B, dbatch, tau, args.diff_batch_iters, side, args.no_profile,
+                              f"{len(dbatch)} pairs 512x512 12-bit, per-pair alpha log-uniform "
+                              f"in [0.02, 0.2]")
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
 
     out = {
@@ -325,7 +398,8 @@ def main() -> int:
                    "iterations": K, "parallelism": "single GPU", "graph": True,
                    "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
         "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
-        "fwd_bwd": fwd_bwd, "batched": batched,
+        "fwd_bwd": fwd_bwd, "batched": batched, "large_pair": large_leg,
+        "diff_batch": dbatch_leg,
     }
     print(json.dumps(out))
     return 0

@@ -103,13 +103,14 @@ typedef struct {
                                   entries it adds stay within 2^21 / n_pairs), -1 = none */
   int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic
                                   (128 for one pair, unsplit for a batch) */
-  int32_t solve_kernel;        /* solve schedule: 0 = autotuned per level; 8 or 16 = the
-                                  wavefront-per-block kernels (8 or 16 loads per lane in flight)
-                                  wherever admissible (blocks <= 64 rows, no split backward
-                                  blocks); 64, 128 or 256 = workgroup-per-block kernels of that
-                                  size; levels where the choice is not admissible take the
-                                  smallest admissible workgroup size.  MR_FLAG_NO_TUNE with 0
-                                  means 256 everywhere. */
+  int32_t solve_kernel;        /* solve schedule: 0 = autotuned per level; 1 = wavefront per
+                                  block with the block's factor data copied straight into LDS
+                                  (blocks <= 64 rows, <= 64 KB); 8 or 16 = wavefront per block
+                                  with 8 or 16 loads per lane in flight (blocks <= 64 rows); both
+                                  need unsplit backward blocks; 64, 128 or 256 = workgroup per
+                                  block of that size; levels where the choice is not admissible
+                                  take the smallest admissible workgroup size.  MR_FLAG_NO_TUNE
+                                  with 0 means 256 everywhere. */
 } mr_params;
 
 /* Pre-computation (Algorithm 1): validates every mesh, builds tables T1-T6

@@ -79,14 +79,16 @@ hipError_t mr_ctx::solve_level(bool fwd, int lev, double2 *x, double2 *out, hipS
     if (!cnt && !fuse) return hipSuccess;
     const int nt = fwd_nt[lev];
     return launch_solve_fwd_level(d_blocks.ptr, d_fwd_items.ptr + fwd_ptr[lev], cnt,
-                                  fwd_lds[lev] + 16 * nt, nt, d_cptr.ptr, d_cidx.ptr, d_dcol.ptr,
+                                  nt == 1 ? fwd_direct[lev] : fwd_lds[lev] + 16 * nt, nt,
+                                  d_cptr.ptr, d_cidx.ptr, d_dcol.ptr,
                                   d_prow.ptr, d_pcol.ptr, x, d_ybuf.ptr, d_upd.ptr, fuse, s);
   }
   const int cnt = bwd_ptr[lev + 1] - bwd_ptr[lev];
   if (!cnt) return hipSuccess;
   const int nt = bwd_nt[lev];
   return launch_solve_bwd_level(d_blocks.ptr, d_bwd_items.ptr + bwd_ptr[lev], cnt,
-                                bwd_lds[lev] + 16 * nt, nt, d_below.ptr, d_drow.ptr, d_prow.ptr,
+                                nt == 1 ? bwd_direct[lev] : bwd_lds[lev] + 16 * nt, nt,
+                                d_below.ptr, d_drow.ptr, d_prow.ptr,
                                 x, d_ybuf.ptr, d_perm.ptr, out, d_partials2.ptr,
                                 d_blk_counters.ptr, s);
 }
@@ -127,13 +129,18 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
 
 // Autotuner: for every solve level, times each admissible kernel on the
 // context's own data (first each level alone, then each level inside the
-// whole solve) and keeps the fastest: the wavefront-per-block kernels
-// (blocks of at most 64 rows; backward: no split blocks) and the workgroup-per-block
+// whole solve) and keeps the fastest: the wavefront-per-block kernels with
+// direct LDS staging (blocks of at most 64 rows whose factor data fits 64 KB)
+// or with register batches (blocks of at most 64 rows) (backward: no split
+// blocks), and the workgroup-per-block
 // kernels with 64, 128, 256 threads (at least the level's largest block
 // rounded up to a power of two).  The level kernels only read and write the
 // solve scratch vectors, so running them on whatever those hold is harmless.
 bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
   const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
+  if (nt == 1)
+    return minnt[lev] <= 64 && (fwd ? fwd_direct[lev] : bwd_direct[lev]) <= 64 * 1024 &&
+           (fwd || !bwd_split[lev]);
   if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
   return nt >= minnt[lev];
 }
@@ -188,7 +195,7 @@ int mr_ctx::tune(hipStream_t s) {
     }
     return t_min;
   };
-  static const int kCandidates[] = {8, 16, 64, 128, 256};
+  static const int kCandidates[] = {1, 8, 16, 64, 128, 256};
   // pass 1: every level on its own
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
@@ -405,6 +412,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> fwd_lds_v(max_fl, 0), bwd_lds_v(max_bl, 0);
   std::vector<int32_t> fwd_bp_v(max_fl, 64), bwd_bp_v(max_bl, 64);
   std::vector<uint8_t> bwd_split_v(max_bl, 0);
+  std::vector<int32_t> fwd_direct_v(max_fl, 0), bwd_direct_v(max_bl, 0);
   int32_t n_partials = 0, n_counters = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
@@ -482,6 +490,12 @@ int mr_ctx::upload_all(hipStream_t s) {
         fwd_bp_v[B.fwd_level] = std::max(fwd_bp_v[B.fwd_level], bp);
         bwd_bp_v[bl] = std::max(bwd_bp_v[bl], bp);
         if (bs > 1) bwd_split_v[bl] = 1;
+        // LDS of the direct-staged kernels: the whole dense inverse and panel,
+        // each rounded up to 16 bytes (the copies move whole 16-byte chunks)
+        const int32_t direct = (int32_t)std::min<int64_t>(
+            INT32_MAX, 8 * ((nd + 1) / 2 * 2 + ((int64_t)m * b + 1) / 2 * 2));
+        fwd_direct_v[B.fwd_level] = std::max(fwd_direct_v[B.fwd_level], direct);
+        bwd_direct_v[bl] = std::max(bwd_direct_v[bl], direct);
       }
       blocks.push_back(db);
     }
@@ -563,6 +577,8 @@ int mr_ctx::upload_all(hipStream_t s) {
   fwd_bp = fwd_bp_v;
   bwd_bp = bwd_bp_v;
   bwd_split = bwd_split_v;
+  fwd_direct = fwd_direct_v;
+  bwd_direct = bwd_direct_v;
   fwd_nt.assign(fwd_bp.size(), 256);
   bwd_nt.assign(bwd_bp.size(), 256);
   if (below.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "solve update buffer too large");
@@ -741,8 +757,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     return fail(MR_EINVAL, "unknown force_mode");
   {
     const int32_t k = params->solve_kernel;
-    if (k != 0 && k != 8 && k != 16 && k != 64 && k != 128 && k != 256)
-      return fail(MR_EINVAL, "solve_kernel must be 0, 8, 16, 64, 128 or 256");
+    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 64 && k != 128 && k != 256)
+      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 64, 128 or 256");
   }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {

@@ -75,6 +75,7 @@ struct mr_ctx {
   mr::DevArray<double> d_pcol;                  // panels, column-major copy (forward wave kernel)
   mr::DevArray<double2> d_ybuf;                 // forward solve result y (solve order)
   std::vector<uint8_t> bwd_split;               // per backward level: has split blocks
+  std::vector<int32_t> fwd_direct, bwd_direct;  // per level: LDS of the direct-staged kernels
   mr::DevArray<int32_t> d_upper_rows;           // solve rows outside the first forward level
   int64_t n_apex_rows = 0;
   int32_t apex_bwd_lds = 16;                    // dynamic LDS of the apex backward launch

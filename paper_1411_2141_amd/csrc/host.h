@@ -51,6 +51,7 @@ struct SolvePlan {
   std::vector<SolveBlock> blocks;
   // dense inverses of the diagonal blocks, packed lower triangles:
   // column-major (forward) and row-major (backward), both b(b+1)/2 per block
+  // (each block's entries start at an even offset, as do the panels')
   std::vector<int64_t> dense_off;          // per block, same offset in both arrays
   std::vector<double> dinv_col, dinv_row;
   // rows below each block touched by its columns, ascending; the positions

@@ -366,12 +366,14 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
   std::stable_sort(lorder.begin(), lorder.end(), [&](int32_t a, int32_t b) {
     return pl.blocks[a].fwd_level < pl.blocks[b].fwd_level;
   });
+  // every block's entries start on a 16-byte boundary (sizes rounded up to an
+  // even number of doubles) so the device can stage them with 16-byte loads
   pl.dense_off.assign(nb, 0);
   int64_t tot = 0;
   for (int32_t s : lorder) {
     const int64_t b = pl.blocks[s].r1 - pl.blocks[s].r0;
     pl.dense_off[s] = tot;
-    tot += b * (b + 1) / 2;
+    tot += (b * (b + 1) / 2 + 1) / 2 * 2;
   }
   pl.dinv_col.assign(tot, 0.0);
   pl.dinv_row.assign(tot, 0.0);
@@ -402,7 +404,7 @@ std::string build_solve_plan(PairHost &p, const std::vector<std::pair<int32_t, i
     const int64_t m = pl.below_ptr[s + 1] - pl.below_ptr[s];
     pl.max_below = std::max<int32_t>(pl.max_below, (int32_t)m);
     pl.panel_off[s] = ptot;
-    ptot += m * (pl.blocks[s].r1 - pl.blocks[s].r0);
+    ptot += (m * (pl.blocks[s].r1 - pl.blocks[s].r0) + 1) / 2 * 2;
   }
   pl.panel_row.assign(ptot, 0.0);
   // contributors of each row, in increasing block order

@@ -22,10 +22,12 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
                            const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
                            double tau, const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s);
-// One level of the forward / backward block solve; nt = 8 or 16 selects the
-// wavefront-per-block kernels (blocks of at most 64 rows) issuing nt loads per
-// lane at a time, 64 / 128 / 256 the workgroup-per-block ones with that many
-// threads (LDS staged).
+// One level of the forward / backward block solve; nt = 1 selects the
+// wavefront-per-block kernels with direct global-to-LDS staging (blocks of at
+// most 64 rows, panels not split), nt = 8 or 16 the wavefront-per-block
+// kernels issuing nt loads per lane at a time (blocks of at most 64 rows),
+// 64 / 128 / 256 the workgroup-per-block ones with that many threads (LDS
+// staged); lds_bytes is the launch's dynamic LDS.
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
                                   int lds_bytes, int nt, const int64_t *cptr, const int32_t *cidx,
                                   const double *dcol, const double *prow, const double *pcol,

@@ -786,6 +786,161 @@ __global__ __launch_bounds__(256) void k_wave_bwd(
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged wavefront-per-block level kernels: one wavefront (the whole
+// workgroup) per block of at most 64 rows whose panel is not split; the
+// block's dense inverse and panel are copied straight from global memory into
+// LDS with 16-byte direct loads (all in flight at once, no registers held)
+// while the right-hand side is gathered, then read back in conflict-free
+// order (consecutive lanes, consecutive doubles).
+// ---------------------------------------------------------------------------
+
+// Copies `bytes` from 16-byte aligned global memory into this wavefront's LDS
+// (16-byte aligned), 16 bytes per lane and instruction; completion is waited
+// for by the caller.
+__device__ __forceinline__ void stage_direct(const void *src, void *lds, int bytes, int lane) {
+  const int nch = (bytes + 15) >> 4;
+  for (int c0 = 0; c0 < nch; c0 += 64)
+    if (c0 + lane < nch)
+      __builtin_amdgcn_global_load_lds(
+          static_cast<const char *>(src) + (size_t)(c0 + lane) * 16,
+          (__attribute__((address_space(3))) void *)(static_cast<char *>(lds) + (size_t)c0 * 16),
+          16, 0, 0);
+}
+
+// Waits for every outstanding load (direct LDS copies included) of the wavefront.
+__device__ __forceinline__ void wait_all_loads() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Forward, one level: per block, t = b_rows - contributions (or the assembled
+// b with FUSED), y = D t, upd = P y (D packed column-major, P column-major,
+// both staged in LDS), y to ybuf.  The item of slice 0 takes the whole panel
+// (the other slices' items return at once).  With FUSED the workgroups after the blocks
+// assemble the other rows (64 per workgroup) and finish the MSD.
+template <bool FUSED>
+__global__ __launch_bounds__(64) void k_lds_fwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
+    const double *__restrict__ dcol, const double *__restrict__ pcol, double2 *x,
+    double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
+  extern __shared__ double smem[];
+  if (FUSED && (int)blockIdx.x >= count) {
+    const int g = (int)blockIdx.x - count;
+    const int row_groups = (A.n_rows + 63) / 64;
+    if (g < row_groups) {
+      const int k = g * 64 + (int)threadIdx.x;
+      if (k < A.n_rows) {
+        const int row = A.rows[k];
+        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      }
+    } else {
+      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
+    }
+    return;
+  }
+  const int lane = threadIdx.x;
+  const int2 it = items[blockIdx.x];
+  if (it.y != 0) return;                      // slice 0 takes the whole panel
+  const DevBlock B = blocks[it.x];
+  const int b = B.r1 - B.r0, m = B.m;
+  const int nd = b * (b + 1) / 2;
+  double *D = smem;
+  double *P = smem + (nd + 1) / 2 * 2;
+  stage_direct(dcol + B.doff, D, 8 * nd, lane);
+  stage_direct(pcol + B.poff, P, 8 * m * b, lane);
+  double2 t = make_double2(0.0, 0.0);
+  if (lane < b) {
+    const int row = B.r0 + lane;
+    if (FUSED) {
+      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+    } else {
+      const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
+      const double2 bb = x[row];
+      t = make_double2(bb.x - c.x, bb.y - c.y);
+    }
+  }
+  wait_all_loads();
+  // y_r = sum_{j <= r} D(r, j) t_j, D(r, j) at j b - j (j - 1) / 2 + (r - j)
+  double2 y = make_double2(0.0, 0.0);
+  for (int j = 0; j < b; ++j) {
+    const double2 tj = lane_bcast2(t, j);
+    if (lane >= j && lane < b) {
+      const double d = D[j * b - j * (j - 1) / 2 + (lane - j)];
+      y.x += d * tj.x;
+      y.y += d * tj.y;
+    }
+  }
+  // upd[k] = sum_j P(k, j) y_j, P(k, j) at j m + k
+  for (int kc = 0; kc < m; kc += 64) {
+    const int kk = kc + lane;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < b; ++j) {
+      const double2 yj = lane_bcast2(y, j);
+      if (kk < m) {
+        const double v = P[j * m + kk];
+        acc.x += v * yj.x;
+        acc.y += v * yj.y;
+      }
+    }
+    if (kk < m) upd[B.boff + kk] = acc;
+  }
+  if (lane < b) ybuf[B.r0 + lane] = y;
+}
+
+// Backward, one level: per block, s = P^T z(below) (P row-major in LDS, z
+// gathered 64 rows at a time), t = y - s, z = D^-T t (D packed row-major in
+// LDS); z to x and, when `out` is given, to natural node order.
+__global__ __launch_bounds__(64) void k_lds_bwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
+    const double *__restrict__ prow, double2 *x, const double2 *__restrict__ ybuf,
+    const int32_t *__restrict__ perm, double2 *__restrict__ out) {
+  extern __shared__ double smem[];
+  const int lane = threadIdx.x;
+  const int2 it = items[blockIdx.x];
+  const DevBlock B = blocks[it.x];
+  const int b = B.r1 - B.r0, m = B.m;
+  const int nd = b * (b + 1) / 2;
+  double *D = smem;
+  double *P = smem + (nd + 1) / 2 * 2;
+  stage_direct(drow + B.doff, D, 8 * nd, lane);
+  stage_direct(prow + B.poff, P, 8 * m * b, lane);
+  const double2 y = lane < b ? ybuf[B.r0 + lane] : make_double2(0.0, 0.0);
+  double2 zl = lane < m ? x[below_idx[B.boff + lane]] : make_double2(0.0, 0.0);
+  wait_all_loads();
+  // s_j = sum_k P(k, j) z_k, P(k, j) at k b + j
+  double2 s = make_double2(0.0, 0.0);
+  for (int kc = 0; kc < m; kc += 64) {
+    if (kc > 0) zl = kc + lane < m ? x[below_idx[B.boff + kc + lane]] : make_double2(0.0, 0.0);
+    const int kend = min(64, m - kc);
+    for (int k = 0; k < kend; ++k) {
+      const double2 zk = lane_bcast2(zl, k);
+      if (lane < b) {
+        const double v = P[(kc + k) * b + lane];
+        s.x += v * zk.x;
+        s.y += v * zk.y;
+      }
+    }
+  }
+  const double2 t = make_double2(y.x - s.x, y.y - s.y);
+  // z_j = sum_{i >= j} D(i, j) t_i, D(i, j) at i (i + 1) / 2 + j
+  double2 z = make_double2(0.0, 0.0);
+  for (int i = 0; i < b; ++i) {
+    const double2 ti = lane_bcast2(t, i);
+    if (lane <= i && lane < b) {
+      const double d = D[i * (i + 1) / 2 + lane];
+      z.x += d * ti.x;
+      z.y += d * ti.y;
+    }
+  }
+  if (lane < b) {
+    x[B.r0 + lane] = z;
+    if (out) out[perm[B.r0 + lane]] = z;
+  }
+}
+
 // Apex of the forward solve, step 1: t = b - (update entries of the non-apex
 // blocks) for every apex row of every pair (thread per row, global list).
 __global__ __launch_bounds__(256) void k_apex_rhs(int n_rows, const int32_t *__restrict__ rows,
@@ -1061,6 +1216,15 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
                                   const double *dcol, const double *prow, const double *pcol,
                                   double2 *x, double2 *ybuf, double2 *upd,
                                   const AssembleArgs *fuse, hipStream_t s) {
+  if (nt == 1) {                              // wavefront per block, LDS staged
+    int groups = count;
+    if (fuse) groups += (fuse->n_rows + 63) / 64 + (fuse->finish_msd ? fuse->n_pairs : 0);
+    if (groups == 0) return hipSuccess;
+    return fuse ? launch(k_lds_fwd<true>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
+                         cidx, dcol, pcol, x, ybuf, upd, *fuse)
+                : launch(k_lds_fwd<false>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
+                         cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
+  }
   if (nt == 8 || nt == 16) {                  // wavefront per block, nt loads per batch
     int groups = (count + 3) / 4;
     if (fuse)
@@ -1100,6 +1264,9 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
                                   const double2 *ybuf, const int32_t *perm, double2 *out,
                                   double2 *partials, unsigned *counters, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (nt == 1)
+    return launch(k_lds_bwd, count, 64, lds_bytes, s, blocks, items, count, below_idx, drow, prow,
+                  x, ybuf, perm, out);
   if (nt == 8 || nt == 16)
     return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
                   items, count, below_idx, drow, prow, x, ybuf, perm, out);

@@ -1,8 +1,9 @@
 """GPU parity of every solve schedule the library can run.
 
-The autotuner picks, per level, one of five level kernels (wavefront per block
-with 8 or 16 loads in flight per lane, or a workgroup of 64 / 128 / 256
-threads per block); ``solve_kernel`` forces one of them wherever admissible.
+The autotuner picks, per level, one of six level kernels (wavefront per block
+with its factor data copied straight into LDS, or with 8 or 16 loads in
+flight per lane, or a workgroup of 64 / 128 / 256 threads per block);
+``solve_kernel`` forces one of them wherever admissible.
 Each schedule is checked against the FP64 oracle with and without the apex
 (the explicit inverse of the top levels), with split backward panels, on a
 single 512x512 pair and on a batch of ragged pairs: the solve alone (relative
@@ -22,7 +23,7 @@ from tests._problems import small_pair
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = (8, 16, 64, 128, 256)
+KERNELS = (1, 8, 16, 64, 128, 256)
 SOLVE_TOL = 1e-12
 U_TOL = 1e-5
 
