@@ -14,6 +14,7 @@
 //   end:    gbar_Te = B^-1 cbar                           (the prefilter is symmetric)
 //
 // The iterates are recomputed from checkpoints every `ckpt_every` iterations
+// (each segment's last iterate is the next checkpoint and is not recomputed)
 // with the forward kernels, so they equal the forward pass bit for bit.  The
 // adjoint arithmetic is FP64; the scatters into lambda^N and cbar use FP64
 // atomic adds (their summation order is not fixed).
@@ -133,18 +134,25 @@ __global__ __launch_bounds__(256) void k_warp_adjoint(
   if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Per node: (K u^{k+1})_i . mu_i accumulated into the node item's alpha partial
-// (fixed order), and eta_i = -tau (M (mu / m))_i.
-__global__ __launch_bounds__(256) void k_adjoint_alpha_eta(
-    const NodeItem *__restrict__ items, const int32_t *__restrict__ kptr,
-    const int32_t *__restrict__ kcol, const double *__restrict__ kval,
-    const double *__restrict__ mwt_t, const double2 *__restrict__ mu,
-    const double2 *__restrict__ u1, double2 *__restrict__ eta, double *__restrict__ alpha_part,
-    double tau, int nodal) {
+// One reverse step per node i, given mu = S^-1 lambda^{k+1}:
+//   the alpha partial (K u^{k+1})_i . mu_i (summed per node item in a fixed order),
+//   eta_i = -tau (M (mu / m))_i (-tau mu_i in the nodal mode),
+//   lambda^k_i = mu_i + (g_i . eta_i) g_i + r_i H_i eta_i at u^k, written in natural
+//   and in solve order (the right-hand side of the next step's solve),
+//   and the coefficient adjoint of the force density scattered into cbar.
+__global__ __launch_bounds__(256) void k_adjoint_step(
+    const NodeItem *__restrict__ items, const DevPair *__restrict__ pairs,
+    const int32_t *__restrict__ kptr, const int32_t *__restrict__ kcol,
+    const double *__restrict__ kval, const double *__restrict__ mwt_t,
+    const double2 *__restrict__ mu, const double2 *__restrict__ u1, const double2 *__restrict__ u,
+    const int2 *__restrict__ xy, const float *__restrict__ coef, const float *__restrict__ rho,
+    const int32_t *__restrict__ iperm, double2 *__restrict__ lam, double2 *__restrict__ lam_solve,
+    double *cbar, double *__restrict__ alpha_part, double tau, int nodal) {
   const NodeItem it = items[blockIdx.x];
   const int i = it.begin + threadIdx.x;
   double da = 0.0;
   if (i < it.end) {
+    const DevPair P = pairs[it.pair];
     double kx = 0.0, ky = 0.0, ex = 0.0, ey = 0.0;
     for (int q = kptr[i]; q < kptr[i + 1]; ++q) {
       const int jn = kcol[q];
@@ -159,68 +167,58 @@ __global__ __launch_bounds__(256) void k_adjoint_alpha_eta(
     }
     const double2 mi = mu[i];
     da = mi.x * kx + mi.y * ky;
-    eta[i] = nodal ? make_double2(-tau * mi.x, -tau * mi.y) : make_double2(-tau * ex, -tau * ey);
+    const double2 et = nodal ? make_double2(-tau * mi.x, -tau * mi.y)
+                             : make_double2(-tau * ex, -tau * ey);
+    // spline value, gradient and Hessian of the template at u^k
+    const double2 ui = u[i];
+    const int2 v = xy[i];
+    int cx, cy;
+    double fx, fy;
+    split_coord_d(v.x, ui.x - 0.5, cx, fx);
+    split_coord_d(v.y, ui.y - 0.5, cy, fy);
+    double wx[4], dx[4], exw[4], wy[4], dy[4], eyw[4];
+    bs_weights_d(fx, wx);
+    bs_deriv_d(fx, dx);
+    bs_deriv2_d(fx, exw);
+    bs_weights_d(fy, wy);
+    bs_deriv_d(fy, dy);
+    bs_deriv2_d(fy, eyw);
+    const float *c = coef + P.pix_off;
+    Taps tp;
+    make_taps(c, P.height, P.width, cx, cy, tp);
+    double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float cr[4];
+      row_taps(tp.row[m], tp, cx, P.width, cr);
+      double rv = 0.0, rd = 0.0, re2 = 0.0;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const double cv = (double)cr[n];
+        rv += cv * wx[n];
+        rd += cv * dx[n];
+        re2 += cv * exw[n];
+      }
+      val += wy[m] * rv;
+      gx += wy[m] * rd;
+      gy += dy[m] * rv;
+      hxx += wy[m] * re2;
+      hxy += dy[m] * rd;
+      hyy += eyw[m] * rv;
+    }
+    const double r = val - (double)rho[i];
+    const double ge = gx * et.x + gy * et.y;
+    const double2 l = make_double2(mi.x + ge * gx + r * (hxx * et.x + hxy * et.y),
+                                   mi.y + ge * gy + r * (hxy * et.x + hyy * et.y));
+    lam[i] = l;
+    lam_solve[iperm[i]] = l;
+    scatter_taps(cbar + P.pix_off, P.height, P.width, cx, fx, cy, fy, ge, r * et.x, r * et.y);
   }
   __shared__ double red[4];
   da = wave_sum(da);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = da;
   __syncthreads();
   if (threadIdx.x == 0) alpha_part[blockIdx.x] += -tau * ((red[0] + red[1]) + (red[2] + red[3]));
-}
-
-// Per node at u^k: lambda^k = mu + (g . eta) g + r H eta, and the coefficient
-// adjoint of the force density scattered into cbar.
-__global__ __launch_bounds__(256) void k_node_adjoint(
-    const NodeItem *__restrict__ items, const DevPair *__restrict__ pairs,
-    const double2 *__restrict__ u, const int2 *__restrict__ xy, const float *__restrict__ coef,
-    const float *__restrict__ rho, const double2 *__restrict__ mu,
-    const double2 *__restrict__ eta, double2 *__restrict__ lam, double *cbar) {
-  const NodeItem it = items[blockIdx.x];
-  const int i = it.begin + threadIdx.x;
-  if (i >= it.end) return;
-  const DevPair P = pairs[it.pair];
-  const double2 ui = u[i];
-  const int2 v = xy[i];
-  int cx, cy;
-  double fx, fy;
-  split_coord_d(v.x, ui.x - 0.5, cx, fx);
-  split_coord_d(v.y, ui.y - 0.5, cy, fy);
-  double wx[4], dx[4], ex[4], wy[4], dy[4], ey[4];
-  bs_weights_d(fx, wx);
-  bs_deriv_d(fx, dx);
-  bs_deriv2_d(fx, ex);
-  bs_weights_d(fy, wy);
-  bs_deriv_d(fy, dy);
-  bs_deriv2_d(fy, ey);
-  const float *c = coef + P.pix_off;
-  Taps tp;
-  make_taps(c, P.height, P.width, cx, cy, tp);
-  double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const float *r = tp.row[m];
-    double rv = 0.0, rd = 0.0, re2 = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const double cv = (double)r[tp.col[n]];
-      rv += cv * wx[n];
-      rd += cv * dx[n];
-      re2 += cv * ex[n];
-    }
-    val += wy[m] * rv;
-    gx += wy[m] * rd;
-    gy += dy[m] * rv;
-    hxx += wy[m] * re2;
-    hxy += dy[m] * rd;
-    hyy += ey[m] * rv;
-  }
-  const double r = val - (double)rho[i];
-  const double2 et = eta[i];
-  const double ge = gx * et.x + gy * et.y;
-  const double2 mi = mu[i];
-  lam[i] = make_double2(mi.x + ge * gx + r * (hxx * et.x + hxy * et.y),
-                        mi.y + ge * gy + r * (hxy * et.x + hyy * et.y));
-  scatter_taps(cbar + P.pix_off, P.height, P.width, cx, fx, cy, fy, ge, r * et.x, r * et.y);
 }
 
 // Per pair: the alpha partials of its node items summed in item order.
@@ -256,14 +254,17 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   int rc = check_flags();
   if (rc) return rc;
   const int64_t N = n_nodes;
-  const int n_ck = n_iter / ckpt_every + 1;
+  // checkpoints at every segment boundary: ck[q] = u^{q ckpt_every} for
+  // q < n_seg, ck[n_seg] = u^N
+  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  const int n_ck = n_seg + 1;
   const size_t nb = sizeof(double2) * (size_t)N;
   if ((int64_t)d_ck.count < (int64_t)n_ck * N) HIP_OK(d_ck.alloc((size_t)n_ck * N));
-  if ((int64_t)d_seg.count < (int64_t)(ckpt_every + 1) * N) HIP_OK(d_seg.alloc((size_t)(ckpt_every + 1) * N));
+  if ((int64_t)d_seg.count < (int64_t)ckpt_every * N) HIP_OK(d_seg.alloc((size_t)ckpt_every * N));
   if ((int64_t)d_lam.count < N) {
     HIP_OK(d_lam.alloc(N));
+    HIP_OK(d_lam_s.alloc(N));
     HIP_OK(d_mu.alloc(N));
-    HIP_OK(d_eta.alloc(N));
   }
   if ((int64_t)d_cbar.count < n_pix) HIP_OK(d_cbar.alloc(n_pix));
   if ((int)d_alpha_part.count < n_node_items) HIP_OK(d_alpha_part.alloc(n_node_items));
@@ -272,50 +273,51 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
     if (rc) return rc;
   }
   double2 *ck = d_ck.ptr, *seg = d_seg.ptr;
-  // forward with checkpoints
-  HIP_OK(hipMemcpyAsync(ck, u0, nb, hipMemcpyDeviceToDevice, s));
-  HIP_OK(hipMemcpyAsync(seg, u0, nb, hipMemcpyDeviceToDevice, s));
+  auto ckpt = [&](int q) { return ck + (size_t)q * N; };
+  // forward, iterating in the last checkpoint slot and copying at boundaries
+  double2 *w = ckpt(n_seg);
+  HIP_OK(hipMemcpyAsync(ckpt(0), u0, nb, hipMemcpyDeviceToDevice, s));
+  if (n_seg > 0) HIP_OK(hipMemcpyAsync(w, u0, nb, hipMemcpyDeviceToDevice, s));
   double *pending = nullptr;
   for (int k = 0; k < n_iter; ++k) {
-    HIP_OK(iterate(seg, nullptr, &pending, s));
+    HIP_OK(iterate(w, nullptr, &pending, s));
     if ((k + 1) % ckpt_every == 0 && (k + 1) < n_iter)
-      HIP_OK(hipMemcpyAsync(ck + (size_t)((k + 1) / ckpt_every) * N, seg, nb,
-                            hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(ckpt((k + 1) / ckpt_every), w, nb, hipMemcpyDeviceToDevice, s));
   }
-  // warp adjoint at u^N (seg[0] holds it)
+  // warp adjoint at u^N
   HIP_OK(hipMemsetAsync(d_lam.ptr, 0, nb, s));
   HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
   HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
   timed_begin(MR_KF_WARP, s);
   HIP_OK(launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr, d_pairs.ptr,
-                (const double2 *)seg, d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, g_msd,
-                d_lam.ptr, d_cbar.ptr, d_partials.ptr));
+                (const double2 *)ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
+                g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr));
   timed_end(s);
   if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));
-  // reverse sweep, one checkpoint segment at a time
-  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  // lambda^N in solve order (its own buffer: the recomputed iterations use x)
+  // for the first reverse solve; every reverse step writes the next one there
+  if (n_iter > 0) HIP_OK(launch_to_solve_order((int)N, d_lam.ptr, d_iperm.ptr, d_lam_s.ptr, s));
+  // reverse sweep, one checkpoint segment at a time: u^{k0} and u^{k1} are
+  // checkpoints, the iterates between are recomputed into seg[1 ..]
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int k0 = sg * ckpt_every, k1 = std::min(n_iter, k0 + ckpt_every);
-    HIP_OK(hipMemcpyAsync(seg, ck + (size_t)sg * N, nb, hipMemcpyDeviceToDevice, s));
-    for (int k = k0; k < k1; ++k) {
+    auto iterate_at = [&](int k) -> const double2 * {
+      return k == k0 ? ckpt(sg) : k == k1 ? ckpt(sg + 1) : seg + (size_t)(k - k0) * N;
+    };
+    for (int k = k0; k + 1 < k1; ++k) {
       double2 *dst = seg + (size_t)(k - k0 + 1) * N;
-      HIP_OK(hipMemcpyAsync(dst, seg + (size_t)(k - k0) * N, nb, hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(dst, iterate_at(k), nb, hipMemcpyDeviceToDevice, s));
       HIP_OK(iterate(dst, nullptr, &pending, s));
     }
     for (int k = k1 - 1; k >= k0; --k) {
-      const double2 *uk = seg + (size_t)(k - k0) * N, *uk1 = seg + (size_t)(k - k0 + 1) * N;
-      // mu = S^-1 lambda^{k+1}
-      HIP_OK(launch_to_solve_order((int)N, d_lam.ptr, d_iperm.ptr, d_x.ptr, s));
-      HIP_OK(solve(d_x.ptr, d_mu.ptr, s, nullptr));
+      // mu = S^-1 lambda^{k+1} (right-hand side in solve order, consumed in place)
+      HIP_OK(solve(d_lam_s.ptr, d_mu.ptr, s, nullptr));
       timed_begin(MR_KF_ASSEMBLE, s);
-      HIP_OK(launch(k_adjoint_alpha_eta, n_node_items, kNodeChunk, 0, s, d_node_items.ptr,
-                    d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, d_mu.ptr, uk1, d_eta.ptr,
-                    d_alpha_part.ptr, params.tau, params.force_mode == MR_FORCE_NODAL ? 1 : 0));
-      timed_end(s);
-      timed_begin(MR_KF_SAMPLE, s);
-      HIP_OK(launch(k_node_adjoint, n_node_items, kNodeChunk, 0, s, d_node_items.ptr, d_pairs.ptr,
-                    uk, d_xy.ptr, d_coef.ptr, d_rho.ptr, d_mu.ptr, d_eta.ptr, d_lam.ptr,
-                    d_cbar.ptr));
+      HIP_OK(launch(k_adjoint_step, n_node_items, kNodeChunk, 0, s, d_node_items.ptr, d_pairs.ptr,
+                    d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, (const double2 *)d_mu.ptr,
+                    iterate_at(k + 1), iterate_at(k), d_xy.ptr, d_coef.ptr, d_rho.ptr,
+                    d_iperm.ptr, d_lam.ptr, d_lam_s.ptr, d_cbar.ptr, d_alpha_part.ptr, params.tau,
+                    params.force_mode == MR_FORCE_NODAL ? 1 : 0));
       timed_end(s);
     }
   }

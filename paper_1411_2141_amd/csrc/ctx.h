@@ -100,7 +100,7 @@ struct mr_ctx {
   unsigned *host_flags = nullptr;            // pinned copy of d_flags
 
   // adjoint (allocated by the first backward call)
-  mr::DevArray<double2> d_ck, d_seg, d_lam, d_mu, d_eta;
+  mr::DevArray<double2> d_ck, d_seg, d_lam, d_lam_s, d_mu;  // d_lam_s: lambda in solve order
   mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
   mr::DevArray<int32_t> d_kptr, d_kcol;
 

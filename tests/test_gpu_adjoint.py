@@ -61,6 +61,7 @@ def cases():
 
 @pytest.mark.parametrize("case,n_iter,ckpt,force_mode", [
     ("c1_128", 6, 4, 0), ("adaptive_48", 5, 2, 0), ("ragged_40x24", 4, 1, 0), ("adaptive_48", 3, 3, 1),
+    ("c1_128", 3, 10, 0), ("adaptive_48", 0, 10, 0),
 ])
 def test_gradient_matches_oracle(case, n_iter, ckpt, force_mode):
     say(f"adjoint parity {case} N={n_iter} ckpt={ckpt} mode={force_mode}")
