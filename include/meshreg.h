@@ -38,7 +38,8 @@
  *   - mesh_reg_init copies the mesh and builds its own coefficient images, so te/re
  *     may be released after init returns (init synchronises its stream).
  *   - The context owns its tables, factor, schedules and scratch; mesh_reg_destroy
- *     frees them.  A context must not be used from two threads at once.
+ *     frees them.  A context must not be used from two threads at once, and its
+ *     calls must not overlap on different streams (they share its scratch).
  *
  * Errors
  *   - Every call returns an MR_* status; nothing is thrown across the ABI.

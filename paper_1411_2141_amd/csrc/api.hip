@@ -45,16 +45,23 @@ static hipError_t upload(DevArray<T> &dst, const std::vector<T> &src, hipStream_
   return hipMemcpyAsync(dst.ptr, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-static std::vector<double> thomas_cp(int N) {
-  std::vector<double> cp(std::max(N, 1), 0.0);
-  if (N <= 1) return cp;
+// Thomas elimination of the B-spline interpolation system of length N
+// (diagonal 4/6, 5/6 at both ends for the half-sample-symmetric boundary,
+// off-diagonal 1/6): per k, (cp_k, 1 / pivot_k) with pivot_0 = 5/6,
+// pivot_k = diag_k - cp_{k-1} / 6 and cp_k = (1/6) / pivot_k.
+static std::vector<double2> thomas_table(int N) {
+  std::vector<double2> t(std::max(N, 1), make_double2(0.0, 0.0));
+  if (N <= 1) return t;
   const double off = 1.0 / 6.0;
-  cp[0] = off / (5.0 / 6.0);
-  for (int k = 1; k < N; ++k) {
-    const double diag = (k == N - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
-    cp[k] = off / (diag - off * cp[k - 1]);
+  double cp_prev = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double diag = (k == 0 || k == N - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
+    const double piv = k == 0 ? diag : diag - off * cp_prev;
+    const double cp = off / piv;
+    t[k] = make_double2(cp, 1.0 / piv);
+    cp_prev = cp;
   }
-  return cp;
+  return t;
 }
 
 }  // namespace mr
@@ -706,23 +713,41 @@ int64_t mr_ctx::device_bytes() const {
 
 // B-spline coefficients (B^-1 along rows, then columns) of one pair's FP32 or
 // FP64 image; B is symmetric, so the same map is its own adjoint.
-static int prefilter_any(const DevPair &d, const float *img_f, const double *img_d,
-                         float *coef_out, hipStream_t s) {
-  DevArray<double> tmp, cpw, cph;
-  HIP_TRY(tmp.alloc((size_t)d.height * d.width));
-  HIP_TRY(upload(cpw, thomas_cp(d.width), s));
-  HIP_TRY(upload(cph, thomas_cp(d.height), s));
-  HIP_TRY(launch_prefilter(img_f, img_d, tmp.ptr, coef_out, d.height, d.width, cpw.ptr, cph.ptr, s));
-  HIP_TRY(hipStreamSynchronize(s));
+// Thomas tables of every image side of the context, back to back, and a
+// scratch image of the largest pair (built once; the prefilter launches of
+// all pairs share them in stream order).
+int mr_ctx::upload_prefilter_tables(hipStream_t s) {
+  std::vector<double2> all;
+  int64_t max_pix = 1;
+  for (const DevPair &d : dpairs) {
+    for (int N : {d.height, d.width})
+      if (!thomas_off.count(N)) {
+        thomas_off[N] = (int64_t)all.size();
+        const std::vector<double2> t = thomas_table(N);
+        all.insert(all.end(), t.begin(), t.end());
+      }
+    max_pix = std::max<int64_t>(max_pix, (int64_t)d.height * d.width);
+  }
+  HIP_TRY(upload(d_thomas, all, s));
+  HIP_TRY(d_prefilter_tmp.alloc(max_pix));
+  return MR_OK;
+}
+
+int mr_ctx::prefilter_any(int p, const float *img_f, const double *img_d, float *coef_out,
+                          hipStream_t s) {
+  const DevPair &d = dpairs[p];
+  HIP_TRY(launch_prefilter(img_f, img_d, d_prefilter_tmp.ptr, coef_out, d.height, d.width,
+                           d_thomas.ptr + thomas_off.at(d.width),
+                           d_thomas.ptr + thomas_off.at(d.height), s));
   return MR_OK;
 }
 
 int mr_ctx::prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s) {
-  return prefilter_any(dpairs[p], img, nullptr, coef_out, s);
+  return prefilter_any(p, img, nullptr, coef_out, s);
 }
 
 int mr_ctx::prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s) {
-  return prefilter_any(dpairs[p], nullptr, img, coef_out, s);
+  return prefilter_any(p, nullptr, img, coef_out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -830,7 +855,7 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     delete c;
     return fail(MR_EHIP, "no HIP device available");
   }
-  if ((rc = c->upload_all(s)) != MR_OK) {
+  if ((rc = c->upload_all(s)) != MR_OK || (rc = c->upload_prefilter_tables(s)) != MR_OK) {
     delete c;
     return rc;
   }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -76,6 +77,9 @@ struct mr_ctx {
   mr::DevArray<double2> d_ybuf;                 // forward solve result y (solve order)
   std::vector<uint8_t> bwd_split;               // per backward level: has split blocks
   std::vector<int32_t> fwd_direct, bwd_direct;  // per level: LDS of the direct-staged kernels
+  mr::DevArray<double2> d_thomas;                // prefilter tables of every image side
+  std::map<int32_t, int64_t> thomas_off;         // side -> offset into d_thomas
+  mr::DevArray<double> d_prefilter_tmp;          // prefilter scratch (largest pair)
   mr::DevArray<int32_t> d_upper_rows;           // solve rows outside the first forward level
   int64_t n_apex_rows = 0;
   int32_t apex_bwd_lds = 16;                    // dynamic LDS of the apex backward launch
@@ -117,6 +121,9 @@ struct mr_ctx {
   ~mr_ctx();
   int upload_all(hipStream_t s);
   int upload_factor(int pair, hipStream_t s);
+  int upload_prefilter_tables(hipStream_t s);
+  int prefilter_any(int p, const float *img_f, const double *img_d, float *coef_out,
+                    hipStream_t s);
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
   int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
   int upload_adjoint_operators(hipStream_t s);

@@ -7,8 +7,11 @@
 
 namespace mr {
 
+// B-spline prefilter (B^-1 along rows, then columns) of an FP32 or FP64 image;
+// tab_w / tab_h: Thomas tables (cp_k, 1 / pivot_k) of the row / column length.
 hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp, float *out,
-                            int H, int W, const double *cp_w, const double *cp_h, hipStream_t s);
+                            int H, int W, const double2 *tab_w, const double2 *tab_h,
+                            hipStream_t s);
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
 // Sample launch; with n_tiles > 0 it also writes the warp/MSD partials of u.

@@ -35,10 +35,11 @@ namespace mr {
 // ---------------------------------------------------------------------------
 
 // Solve B c = s along each row (thread per row) with the Thomas algorithm;
-// `cp` holds the eliminated super-diagonal, which depends only on the length.
+// tab[k] = (cp_k, 1 / pivot_k) depends only on the row length.  Loads are
+// issued U steps ahead of the recurrence.
 template <typename Tin>
 __global__ void k_prefilter_rows(const Tin *__restrict__ src, double *__restrict__ dst, int H,
-                                 int W, const double *__restrict__ cp) {
+                                 int W, const double2 *__restrict__ tab) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= H) return;
   const Tin *s = src + (size_t)r * W;
@@ -48,24 +49,44 @@ __global__ void k_prefilter_rows(const Tin *__restrict__ src, double *__restrict
     return;
   }
   const double off = 1.0 / 6.0;
-  double prev = (double)s[0] / (5.0 / 6.0);
-  d[0] = prev;
-  for (int k = 1; k < W; ++k) {
-    const double diag = (k == W - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
-    const double den = diag - off * cp[k - 1];
-    prev = ((double)s[k] - off * prev) / den;
-    d[k] = prev;
+  constexpr int U = 8;
+  double prev = 0.0;
+  for (int k0 = 0; k0 < W; k0 += U) {
+    double sv[U], mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      sv[u] = k < W ? (double)s[k] : 0.0;
+      mv[u] = k < W ? tab[k].y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < W) {
+        prev = (sv[u] - off * prev) * mv[u];
+        d[k0 + u] = prev;
+      }
   }
-  for (int k = W - 2; k >= 0; --k) {
-    prev = d[k] - cp[k] * prev;
-    d[k] = prev;
+  for (int k1 = W - 2; k1 >= 0; k1 -= U) {
+    double yv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k1 - u;
+      yv[u] = k >= 0 ? d[k] : 0.0;
+      cv[u] = k >= 0 ? tab[k].x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k1 - u >= 0) {
+        prev = yv[u] - cv[u] * prev;
+        d[k1 - u] = prev;
+      }
   }
 }
 
 // Column pass (thread per column, coalesced across threads), in place on
 // `tmp`, writing the FP32 coefficients.
 __global__ void k_prefilter_cols(double *__restrict__ tmp, float *__restrict__ out, int H, int W,
-                                 const double *__restrict__ cp) {
+                                 const double2 *__restrict__ tab) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= W) return;
   double *d = tmp + col;
@@ -74,18 +95,38 @@ __global__ void k_prefilter_cols(double *__restrict__ tmp, float *__restrict__ o
     return;
   }
   const double off = 1.0 / 6.0;
-  double prev = d[0] / (5.0 / 6.0);
-  d[0] = prev;
-  for (int k = 1; k < H; ++k) {
-    const double diag = (k == H - 1) ? 5.0 / 6.0 : 4.0 / 6.0;
-    const double den = diag - off * cp[k - 1];
-    prev = (d[(size_t)k * W] - off * prev) / den;
-    d[(size_t)k * W] = prev;
+  constexpr int U = 8;
+  double prev = 0.0;
+  for (int k0 = 0; k0 < H; k0 += U) {
+    double sv[U], mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      sv[u] = k < H ? d[(size_t)k * W] : 0.0;
+      mv[u] = k < H ? tab[k].y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < H) {
+        prev = (sv[u] - off * prev) * mv[u];
+        d[(size_t)(k0 + u) * W] = prev;
+      }
   }
   out[(size_t)(H - 1) * W + col] = (float)prev;
-  for (int k = H - 2; k >= 0; --k) {
-    prev = d[(size_t)k * W] - cp[k] * prev;
-    out[(size_t)k * W + col] = (float)prev;
+  for (int k1 = H - 2; k1 >= 0; k1 -= U) {
+    double yv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k1 - u;
+      yv[u] = k >= 0 ? d[(size_t)k * W] : 0.0;
+      cv[u] = k >= 0 ? tab[k].x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k1 - u >= 0) {
+        prev = yv[u] - cv[u] * prev;
+        out[(size_t)(k1 - u) * W + col] = (float)prev;
+      }
   }
 }
 
@@ -1177,15 +1218,15 @@ __global__ void k_from_solve_order(int n, const double2 *__restrict__ x,
 thread_local LaunchTimer *tl_launch_timer = nullptr;
 
 hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp, float *out,
-                            int H, int W, const double *cp_w, const double *cp_h,
+                            int H, int W, const double2 *tab_w, const double2 *tab_h,
                             hipStream_t s) {
   const int tb = 64;
   hipError_t e = src_f ? launch(k_prefilter_rows<float>, (H + tb - 1) / tb, tb, 0, s, src_f, tmp,
-                                H, W, cp_w)
+                                H, W, tab_w)
                        : launch(k_prefilter_rows<double>, (H + tb - 1) / tb, tb, 0, s, src_d, tmp,
-                                H, W, cp_w);
+                                H, W, tab_w);
   if (e != hipSuccess) return e;
-  return launch(k_prefilter_cols, (W + tb - 1) / tb, tb, 0, s, tmp, out, H, W, cp_h);
+  return launch(k_prefilter_cols, (W + tb - 1) / tb, tb, 0, s, tmp, out, H, W, tab_h);
 }
 
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
