@@ -245,6 +245,8 @@ def main() -> int:
     ap.add_argument("--diff-batch-pairs", type=int, default=64,
                     help="pairs of the differentiable 512x512 batch leg (0 skips it)")
     ap.add_argument("--diff-batch-iters", type=int, default=100)
+    ap.add_argument("--gen-procs", type=int, default=0,
+                    help="processes generating the batched inputs (0: up to 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -265,12 +267,10 @@ def main() -> int:
     from synth import make_pair, make_pairs
     # inputs first, before anything touches the GPU
     pair = make_pair(2)
-    cpus = len(os.sched_getaffinity(0))
-    batch = (make_pairs(4, args.batched_pairs, processes=min(16, cpus))
-             if args.batched_pairs else [])
+    procs = args.gen_procs or min(16, len(os.sched_getaffinity(0)))
+    batch = make_pairs(4, args.batched_pairs, processes=procs) if args.batched_pairs else []
     large = make_pair(3) if args.large_iters else None
-    dbatch = (make_pairs(5, args.diff_batch_pairs, processes=min(16, cpus))
-              if args.diff_batch_pairs else [])
+    dbatch = make_pairs(5, args.diff_batch_pairs, processes=procs) if args.diff_batch_pairs else []
 
     import torch
     import paper_1411_2141_amd as pkg

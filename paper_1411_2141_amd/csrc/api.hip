@@ -553,6 +553,7 @@ int mr_ctx::upload_all(hipStream_t s) {
             apex_rng.push_back(make_int2(A0 + G.a0, A0 + G.a1));
         }
         const int32_t nrng = (int32_t)apex_rng.size() - roff;
+        if (nrng > kApexMaxRanges) return fail(MR_EINVAL, "apex block with too many ancestor ranges");
         for (int32_t g = A.a0; g < A.a1; g += kApexRowsPerItem) {
           const int32_t g1 = std::min(A.a1, g + kApexRowsPerItem);
           const int32_t len = (A.a1 - g) + A.anc_rows;

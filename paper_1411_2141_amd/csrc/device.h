@@ -78,6 +78,7 @@ struct ApexRow {
 constexpr int kApexSeg = 1024;        // columns per forward segment (16 KB of LDS)
 constexpr int kApexPath = 2048;       // longest backward path (32 KB of LDS)
 constexpr int kApexRowsPerItem = 8;   // rows per apex work item (two per wavefront)
+constexpr int kApexMaxRanges = 256;   // ancestor ranges of one apex block (at most one per level)
 
 // Right-hand side assembly folded into the first forward level: b for the
 // rows of the level's (leaf) blocks is formed by their own workgroups, the

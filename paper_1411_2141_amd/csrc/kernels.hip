@@ -1129,6 +1129,7 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
                                                   const int32_t *__restrict__ perm,
                                                   double2 *__restrict__ out) {
   extern __shared__ double2 yl[];              // the longest path of the launch
+  __shared__ int2 rl[kApexMaxRanges];          // the item's ancestor ranges
   const ApexBwdItem it = items[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ra = it.a0 + wave, rb = ra + 4;
@@ -1142,18 +1143,19 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
   RowPair<U> rp;
   rp.load(pa, qa, la, pb, qb, lb, lane);
   const int own = it.e - it.a0;
+  if ((int)threadIdx.x < it.n_rng) rl[threadIdx.x] = rng[it.rng_off + threadIdx.x];
+  __syncthreads();
   for (int q = threadIdx.x; q < it.len; q += blockDim.x) {
     int a;
     if (q < own) {
       a = it.a0 + q;
     } else {
-      int r = q - own, k = it.rng_off;
-      const int kend = it.rng_off + it.n_rng;
-      while (k + 1 < kend && r >= rng[k].y - rng[k].x) {
-        r -= rng[k].y - rng[k].x;
+      int r = q - own, k = 0;
+      while (k + 1 < it.n_rng && r >= rl[k].y - rl[k].x) {
+        r -= rl[k].y - rl[k].x;
         ++k;
       }
-      a = rng[k].x + r;
+      a = rl[k].x + r;
     }
     yl[q] = y[a];
   }
