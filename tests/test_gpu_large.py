@@ -8,6 +8,10 @@ finite differences of the GPU forward on 64 seeded node directions at N=50
 
 64-pair differentiable batch (512x512, per-pair alpha): gradients of 4 pairs
 against the oracle and the alpha gradient against GPU finite differences.
+
+256-pair ragged batch in the launch configuration the benchmark times (graph
+replay on a side stream, autotuned schedule, automatic apex): 5 iterations,
+displacements of four sampled pairs of different sizes against the oracle.
 """
 import sys
 
@@ -17,7 +21,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import adjoint as oadj, bspline, mesh as omesh, registration as reg
-from synth import make_pair
+from synth import make_pair, make_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -175,4 +179,28 @@ def test_c5_batched_gradients_on_four_pairs():
         ctx.set_alpha(k, q.alpha)
         fd = (vals[0] - vals[1]) / (2 * ha)
         assert abs(fd - g_alpha[k].item()) <= 2e-2 * abs(g_alpha[k].item()), (k, fd, g_alpha[k].item())
+    ctx.close()
+
+
+def test_c4_full_batch_sampled_pairs():
+    say("c4: 256 ragged pairs, graph replay, 5 iterations, 4 sampled pairs vs oracle")
+    pairs = make_pairs(4, 256, processes=8)
+    sides = np.array([p.height for p in pairs])
+    picks = [int(np.argmin(sides)), int(np.argmax(sides)),
+             int(np.flatnonzero(sides == 384)[0]) if (sides == 384).any() else 1, 137]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx = pkg().MeshReg(pairs, tau=0.5, graph=True)
+        u = ctx.zeros_u()
+        pkg().binding.mesh_reg_step(ctx.ctx, u, 5, None, side.cuda_stream)   # capture + replay
+        u.zero_()
+        pkg().binding.mesh_reg_step(ctx.ctx, u, 5, None, side.cuda_stream)   # replay
+        side.synchronize()
+        ug = u.cpu().numpy()
+    for k in picks:
+        q = pairs[k]
+        pb = reg.setup(q.te, q.re, q.V, q.T, q.alpha, 0.5)
+        u_or, _, _ = reg.run(pb, None, 5)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or) < 1e-5, (k, q.height, rel(ug[sl], u_or))
     ctx.close()
