@@ -84,7 +84,7 @@ enum {
 
 /* One registration pair (Algorithm 1, "Inputs"; Section 2.1 for (V, T)). */
 typedef struct {
-  int32_t height, width;       /* image rows, columns (1 .. 65535) */
+  int32_t height, width;       /* image rows, columns (1 .. 65535; at most 2^31 - 1 pixels) */
   int32_t n_nodes, n_tris;     /* >= 3 and >= 1 */
   const int32_t *node_xy;      /* HOST [n_nodes][2] integer corners (x, y) in [0,W]x[0,H]; copied */
   const int32_t *tris;         /* HOST [n_tris][3] node indices, positive signed area
@@ -107,7 +107,8 @@ typedef struct {
   int32_t solve_kernel;        /* solve schedule: 0 = autotuned per level; 1 = wavefront per
                                   block with the block's factor data copied straight into LDS
                                   (blocks <= 64 rows, <= 64 KB); 8 or 16 = wavefront per block
-                                  with 8 or 16 loads per lane in flight (blocks <= 64 rows); both
+                                  with 8 or 16 loads per lane in flight (blocks <= 64 rows);
+                                  32 = half wavefront per block (blocks <= 32 rows); these three
                                   need unsplit backward blocks; 64, 128 or 256 = workgroup per
                                   block of that size; levels where the choice is not admissible
                                   take the smallest admissible workgroup size.  MR_FLAG_NO_TUNE

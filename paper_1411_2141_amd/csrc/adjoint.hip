@@ -41,16 +41,15 @@ __device__ __forceinline__ void spline_vg_d(const float *__restrict__ c, int H, 
   bs_deriv_d(fx, dx);
   bs_weights_d(fy, wy);
   bs_deriv_d(fy, dy);
-  Taps tp;
-  make_taps(c, H, W, cx, cy, tp);
+  float t[4][4];
+  load_taps(c, H, W, cx, cy, t);
   val = gx = gy = 0.0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const float *r = tp.row[m];
     double rv = 0.0, rd = 0.0;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-      const double cv = (double)r[tp.col[n]];
+      const double cv = (double)t[m][n];
       rv += cv * wx[n];
       rd += cv * dx[n];
     }
@@ -70,18 +69,27 @@ __device__ __forceinline__ void scatter_taps(double *__restrict__ cbar, int H, i
   bs_deriv_d(fx, dx);
   bs_weights_d(fy, wy);
   bs_deriv_d(fy, dy);
-  int col[4];
+  unsigned col[4], row[4];
+  if (cx >= 1 && cx + 2 < W && cy >= 1 && cy + 2 < H) {
 #pragma unroll
-  for (int n = 0; n < 4; ++n) col[n] = fold_index(cx - 1 + n, W);
+    for (int k = 0; k < 4; ++k) {
+      col[k] = (unsigned)(cx - 1 + k);
+      row[k] = (unsigned)(cy - 1 + k) * (unsigned)W;
+    }
+  } else {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    double *row = cbar + (size_t)fold_index(cy - 1 + m, H) * W;
+    for (int k = 0; k < 4; ++k) {
+      col[k] = (unsigned)fold_index(cx - 1 + k, W);
+      row[k] = (unsigned)fold_index(cy - 1 + k, H) * (unsigned)W;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const double v = cv * wy[m] * wx[n] + cgx * wy[m] * dx[n] + cgy * dy[m] * wx[n];
-      unsafeAtomicAdd(row + col[n], v);
+      unsafeAtomicAdd(cbar + (row[m] + col[n]), v);
     }
-  }
 }
 
 // Warp adjoint (and the forward MSD partials of the same pixels).
@@ -184,17 +192,15 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
     bs_deriv_d(fy, dy);
     bs_deriv2_d(fy, eyw);
     const float *c = coef + P.pix_off;
-    Taps tp;
-    make_taps(c, P.height, P.width, cx, cy, tp);
+    float t[4][4];
+    load_taps(c, P.height, P.width, cx, cy, t);
     double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      float cr[4];
-      row_taps(tp.row[m], tp, cx, P.width, cr);
       double rv = 0.0, rd = 0.0, re2 = 0.0;
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        const double cv = (double)cr[n];
+        const double cv = (double)t[m][n];
         rv += cv * wx[n];
         rd += cv * dx[n];
         re2 += cv * exw[n];

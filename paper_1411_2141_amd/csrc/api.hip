@@ -136,7 +136,8 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
 
 // Autotuner: for every solve level, times each admissible kernel on the
 // context's own data (first each level alone, then each level inside the
-// whole solve) and keeps the fastest: the wavefront-per-block kernels with
+// whole solve) and keeps the fastest: the half-wavefront-per-block kernels
+// (blocks of at most 32 rows), the wavefront-per-block kernels with
 // direct LDS staging (blocks of at most 64 rows whose factor data fits 64 KB)
 // or with register batches (blocks of at most 64 rows) (backward: no split
 // blocks), and the workgroup-per-block
@@ -148,6 +149,7 @@ bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
   if (nt == 1)
     return minnt[lev] <= 64 && (fwd ? fwd_direct[lev] : bwd_direct[lev]) <= 64 * 1024 &&
            (fwd || !bwd_split[lev]);
+  if (nt == 32) return (fwd ? fwd_maxb[lev] : bwd_maxb[lev]) <= 32 && (fwd || !bwd_split[lev]);
   if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
   return nt >= minnt[lev];
 }
@@ -202,7 +204,7 @@ int mr_ctx::tune(hipStream_t s) {
     }
     return t_min;
   };
-  static const int kCandidates[] = {1, 8, 16, 64, 128, 256};
+  static const int kCandidates[] = {1, 8, 16, 32, 64, 128, 256};
   // pass 1: every level on its own
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
@@ -420,6 +422,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> fwd_bp_v(max_fl, 64), bwd_bp_v(max_bl, 64);
   std::vector<uint8_t> bwd_split_v(max_bl, 0);
   std::vector<int32_t> fwd_direct_v(max_fl, 0), bwd_direct_v(max_bl, 0);
+  std::vector<int32_t> fwd_maxb_v(max_fl, 0), bwd_maxb_v(max_bl, 0);
   int32_t n_partials = 0, n_counters = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
@@ -497,6 +500,8 @@ int mr_ctx::upload_all(hipStream_t s) {
         fwd_bp_v[B.fwd_level] = std::max(fwd_bp_v[B.fwd_level], bp);
         bwd_bp_v[bl] = std::max(bwd_bp_v[bl], bp);
         if (bs > 1) bwd_split_v[bl] = 1;
+        fwd_maxb_v[B.fwd_level] = std::max(fwd_maxb_v[B.fwd_level], b);
+        bwd_maxb_v[bl] = std::max(bwd_maxb_v[bl], b);
         // LDS of the direct-staged kernels: the whole dense inverse and panel,
         // each rounded up to 16 bytes (the copies move whole 16-byte chunks)
         const int32_t direct = (int32_t)std::min<int64_t>(
@@ -587,6 +592,8 @@ int mr_ctx::upload_all(hipStream_t s) {
   bwd_split = bwd_split_v;
   fwd_direct = fwd_direct_v;
   bwd_direct = bwd_direct_v;
+  fwd_maxb = fwd_maxb_v;
+  bwd_maxb = bwd_maxb_v;
   fwd_nt.assign(fwd_bp.size(), 256);
   bwd_nt.assign(bwd_bp.size(), 256);
   if (below.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "solve update buffer too large");
@@ -783,8 +790,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     return fail(MR_EINVAL, "unknown force_mode");
   {
     const int32_t k = params->solve_kernel;
-    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 64 && k != 128 && k != 256)
-      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 64, 128 or 256");
+    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 64 && k != 128 && k != 256)
+      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 64, 128 or 256");
   }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {
@@ -796,6 +803,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
       return fail(MR_EINVAL, "pair " + std::to_string(p) + ": empty mesh or image");
     if (q.height > 65535 || q.width > 65535)
       return fail(MR_EINVAL, "pair " + std::to_string(p) + ": image sides must be below 65536");
+    if ((int64_t)q.height * q.width > INT32_MAX)
+      return fail(MR_EINVAL, "pair " + std::to_string(p) + ": more than 2^31 - 1 pixels");
     if (!host_only && (!q.te || !q.re))
       return fail(MR_EINVAL, "pair " + std::to_string(p) + ": null te/re");
   }

@@ -77,6 +77,7 @@ struct mr_ctx {
   mr::DevArray<double2> d_ybuf;                 // forward solve result y (solve order)
   std::vector<uint8_t> bwd_split;               // per backward level: has split blocks
   std::vector<int32_t> fwd_direct, bwd_direct;  // per level: LDS of the direct-staged kernels
+  std::vector<int32_t> fwd_maxb, bwd_maxb;      // per level: rows of its largest block
   mr::DevArray<double2> d_thomas;                // prefilter tables of every image side
   std::map<int32_t, int64_t> thomas_off;         // side -> offset into d_thomas
   mr::DevArray<double> d_prefilter_tmp;          // prefilter scratch (largest pair)

@@ -164,55 +164,112 @@ __device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pai
   if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
 }
 
-// Squared difference of one pixel of a tile (0 outside the image): the pixel
-// takes the piecewise-linear displacement of its triangle (barycentric
-// weights from exact cross products in doubled integer coordinates) and the
-// template spline is sampled at the displaced pixel centre (FP64 weights and
-// sums).
-__device__ __forceinline__ double warp_pixel(const TileItem &it, const DevPair &P,
-                                             const double2 *__restrict__ u,
-                                             const int4 *__restrict__ tpos,
-                                             const int4 *__restrict__ tri,
-                                             const int32_t *__restrict__ t6,
-                                             const float *__restrict__ coef,
-                                             const float *__restrict__ re,
-                                             float *__restrict__ warped, unsigned *flags) {
-  const int i = it.y0 + (int)(threadIdx.x / kTile);
-  const int j = it.x0 + (int)(threadIdx.x % kTile);
-  if (i >= P.height || j >= P.width) return 0.0;
-  const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
-  const int tt = P.tri_off + t6[pix];
-  const int4 nd = tri[tt];
-  const int4 ps = tpos[tt];                   // corners as x | y << 16
-  const int2 a = make_int2(ps.x & 0xffff, (int)((unsigned)ps.x >> 16));
-  const int2 b = make_int2(ps.y & 0xffff, (int)((unsigned)ps.y >> 16));
-  const int2 c = make_int2(ps.z & 0xffff, (int)((unsigned)ps.z >> 16));
-  const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
-  const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
-  const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
-  const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
-  const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-  const double inv = 1.0 / (ca + cb + cc);
-  const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
-  const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
-  const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
-  const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
-  int qx, qy;
-  double fx, fy;
-  const bool okx = split_coord_d(j, dx, qx, fx);
-  const bool ok = split_coord_d(i, dy, qy, fy) && okx;
-  if (!ok) atomicOr(flags, kFlagNonFinitePixel);
-  const double w = spline_value_d(coef + P.pix_off, P.height, P.width, qx, fx, qy, fy);
-  if (warped) warped[pix] = (float)w;
-  const double e = w - (double)re[pix];
-  return e * e;
+// Squared differences of NT pixels, the thread's position in each of NT
+// tiles (0 for positions outside the image): each pixel takes the
+// piecewise-linear displacement of its triangle (barycentric weights from
+// exact cross products in doubled integer coordinates) and the template
+// spline is sampled at the displaced pixel centre (FP64 weights and sums).
+// The NT pixels go through each step together so their dependent load chains
+// overlap; positions outside the image are clamped to its last row / column
+// for the loads and count 0.  Offsets within a pair's image are 32-bit (fewer
+// than 2^31 pixels).
+template <int NT>
+__device__ __forceinline__ void warp_pixels(const TileItem (&it)[NT], const DevPair (&P)[NT],
+                                            const double2 *__restrict__ u,
+                                            const int4 *__restrict__ tpos,
+                                            const int4 *__restrict__ tri,
+                                            const int32_t *__restrict__ t6,
+                                            const float *__restrict__ coef,
+                                            const float *__restrict__ re,
+                                            float *__restrict__ warped, unsigned *flags,
+                                            double (&sq)[NT]) {
+  int I[NT], J[NT], tt[NT];
+  unsigned po[NT];
+  bool in[NT];
+  float rv[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int i = it[q].y0 + (int)(threadIdx.x / kTile);
+    const int j = it[q].x0 + (int)(threadIdx.x % kTile);
+    in[q] = i < P[q].height && j < P[q].width;
+    I[q] = min(i, P[q].height - 1);
+    J[q] = min(j, P[q].width - 1);
+    po[q] = (unsigned)I[q] * (unsigned)P[q].width + (unsigned)J[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    tt[q] = P[q].tri_off + (t6 + P[q].pix_off)[po[q]];
+    rv[q] = (re + P[q].pix_off)[po[q]];
+  }
+  int4 nd[NT], ps[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    nd[q] = tri[tt[q]];
+    ps[q] = tpos[tt[q]];                        // corners as x | y << 16
+  }
+  double2 ua[NT], ub[NT], uc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    ua[q] = u[nd[q].x];
+    ub[q] = u[nd[q].y];
+    uc[q] = u[nd[q].z];
+  }
+  int qx[NT], qy[NT];
+  double fx[NT], fy[NT];
+  bool inside = true;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int2 a = make_int2(ps[q].x & 0xffff, (int)((unsigned)ps[q].x >> 16));
+    const int2 b = make_int2(ps[q].y & 0xffff, (int)((unsigned)ps[q].y >> 16));
+    const int2 c = make_int2(ps[q].z & 0xffff, (int)((unsigned)ps[q].z >> 16));
+    const double px = 2.0 * J[q] + 1.0, py = 2.0 * I[q] + 1.0;
+    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+    const double inv = 1.0 / (ca + cb + cc);
+    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+    const double dx = wa * ua[q].x + wb * ub[q].x + wc * uc[q].x;
+    const double dy = wa * ua[q].y + wb * ub[q].y + wc * uc[q].y;
+    const bool okx = split_coord_d(J[q], dx, qx[q], fx[q]);
+    const bool ok = split_coord_d(I[q], dy, qy[q], fy[q]) && okx;
+    if (in[q] && !ok) atomicOr(flags, kFlagNonFinitePixel);
+    inside = inside && taps_inside(P[q].height, P[q].width, qx[q], qy[q]);
+  }
+  float tap[NT][4][4];
+  if (inside) {
+    // every window inside its image: four 16-byte row loads per pixel
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps_inside(coef + P[q].pix_off, P[q].width, qx[q], qy[q], tap[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps(coef + P[q].pix_off, P[q].height, P[q].width, qx[q], qy[q], tap[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    double wx[4], wy[4];
+    bs_weights6_d(fx[q], wx);
+    bs_weights6_d(fy[q], wy);
+    double w = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double rs = (double)tap[q][m][0] * wx[0] + (double)tap[q][m][1] * wx[1] +
+                        (double)tap[q][m][2] * wx[2] + (double)tap[q][m][3] * wx[3];
+      w += wy[m] * rs;
+    }
+    w *= 1.0 / 36.0;
+    if (warped && in[q]) (warped + P[q].pix_off)[po[q]] = (float)w;
+    const double e = w - (double)rv[q];
+    sq[q] = in[q] ? e * e : 0.0;
+  }
 }
 
 // Warp + MSD of NT (1 or 2) kTile x kTile pixel tiles, tile0 and tile1
-// (tile1 < 0: none): with two, every thread takes the same pixel position in
-// both, so the two dependent gather chains overlap.  Each tile's FP64 sum of squared
-// differences (wavefront sums, then the four wavefronts in order) goes to
-// partials[tile].
+// (tile1 < 0: none), one after the other: every thread takes the same pixel
+// position in both.  Each tile's FP64 sum of squared differences (wavefront
+// sums, then the four wavefronts in order) goes to partials[tile].
 template <int NT>
 __device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem *__restrict__ tiles,
                                            const DevPair *__restrict__ pairs,
@@ -224,30 +281,85 @@ __device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem 
                                            const float *__restrict__ re,
                                            float *__restrict__ warped,
                                            double *__restrict__ partials, unsigned *flags) {
-  // NT == 1: tile0 only.  NT == 2 without a second tile: the first is
-  // evaluated twice (same values, same writes) and only its sum is kept.
-  const TileItem it0 = tiles[tile0];
-  const DevPair P0 = pairs[it0.pair];
-  double a0 = warp_pixel(it0, P0, u, tpos, tri, t6, coef, re, warped, flags);
-  double a1 = 0.0;
-  if (NT == 2) {
-    const int t1 = tile1 >= 0 ? tile1 : tile0;
-    const TileItem it1 = tiles[t1];
-    const DevPair P1 = pairs[it1.pair];
-    a1 = warp_pixel(it1, P1, u, tpos, tri, t6, coef, re, warped, flags);
+  // NT == 2 without a second tile: the first is evaluated twice (same values,
+  // same writes) and only its sum is kept.
+  double a[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const TileItem it[1] = {tiles[q == 0 || tile1 < 0 ? tile0 : tile1]};
+    const DevPair P[1] = {pairs[it[0].pair]};
+    double sq[1];
+    warp_pixels<1>(it, P, u, tpos, tri, t6, coef, re, warped, flags, sq);
+    a[q] = sq[0];
   }
-  __shared__ double red[8];
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
+  __shared__ double red[2 * 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[wave] = a0;
-    red[4 + wave] = a1;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    a[q] = wave_sum(a[q]);
+    if (lane == 0) red[4 * q + wave] = a[q];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     partials[tile0] = (red[0] + red[1]) + (red[2] + red[3]);
     if (NT == 2 && tile1 >= 0) partials[tile1] = (red[4] + red[5]) + (red[6] + red[7]);
+  }
+}
+
+// Node sampling of NT node items at once (the thread's node in each; a
+// thread past an item's end re-reads its first node and writes nothing):
+// r_i = s(V_i - 1/2 + u_i) - rho_i and h_i = r_i grad s, in FP32.  The NT
+// nodes go through each step together so their dependent loads overlap.
+template <int NT>
+__device__ __forceinline__ void sample_nodes(const NodeItem (&it)[NT], const DevPair (&P)[NT],
+                                             const double2 *__restrict__ u,
+                                             const int2 *__restrict__ xy,
+                                             const float *__restrict__ coef,
+                                             const float *__restrict__ rho,
+                                             float2 *__restrict__ h, unsigned *flags) {
+  int i[NT];
+  bool on[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    i[q] = it[q].begin + (int)threadIdx.x;
+    on[q] = i[q] < it[q].end;
+    if (!on[q]) i[q] = it[q].begin;
+  }
+  double2 ui[NT];
+  int2 v[NT];
+  float rh[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    ui[q] = u[i[q]];
+    v[q] = xy[i[q]];
+    rh[q] = rho[i[q]];
+  }
+  int cx[NT], cy[NT];
+  float fx[NT], fy[NT];
+  bool inside = true;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const bool okx = split_coord(v[q].x, ui[q].x - 0.5, cx[q], fx[q]);
+    const bool ok = split_coord(v[q].y, ui[q].y - 0.5, cy[q], fy[q]) && okx;
+    if (on[q] && !ok) atomicOr(flags, kFlagNonFiniteNode);
+    inside = inside && taps_inside(P[q].height, P[q].width, cx[q], cy[q]);
+  }
+  float tap[NT][4][4];
+  if (inside) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps_inside(coef + P[q].pix_off, P[q].width, cx[q], cy[q], tap[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps(coef + P[q].pix_off, P[q].height, P[q].width, cx[q], cy[q], tap[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    float val, gx, gy;
+    spline_value_grad_taps(tap[q], fx[q], fy[q], val, gx, gy);
+    const float r = val - rh[q];
+    if (on[q]) h[i[q]] = make_float2(r * gx, r * gy);
   }
 }
 
@@ -273,21 +385,10 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
                   nullptr, partials, flags);
     return;
   }
-  const NodeItem it = items[blockIdx.x];
-  const int i = it.begin + threadIdx.x;
-  if (i >= it.end) return;
-  const DevPair P = pairs[it.pair];
-  const double2 ui = u[i];
-  const int2 v = xy[i];
-  int cx, cy;
-  float fx, fy;
-  const bool okx = split_coord(v.x, ui.x - 0.5, cx, fx);
-  const bool ok = split_coord(v.y, ui.y - 0.5, cy, fy) && okx;
-  if (!ok) atomicOr(flags, kFlagNonFiniteNode);
-  float val, gx, gy;
-  spline_value_grad(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy, val, gx, gy);
-  const float r = val - rho[i];
-  h[i] = make_float2(r * gx, r * gy);
+  const NodeItem it[1] = {items[blockIdx.x]};
+  if (it[0].begin + (int)threadIdx.x >= it[0].end) return;
+  const DevPair P[1] = {pairs[it[0].pair]};
+  sample_nodes<1>(it, P, u, xy, coef, rho, h, flags);
 }
 
 // b for solve row k (node i): u_i - tau f_i, f_i = sum_q w_q h(col_q) over
@@ -298,6 +399,7 @@ __device__ __forceinline__ double2 assemble_b(int k, int i, const int32_t *__res
                                               const float *__restrict__ mwt,
                                               const float2 *__restrict__ h,
                                               const double2 *__restrict__ u, double tau) {
+  const double2 ui = u[i];
   const int q0 = mptr[k], q1 = mptr[k + 1];
   float fx = 0.0f, fy = 0.0f;
   constexpr int U = 8;
@@ -319,8 +421,61 @@ __device__ __forceinline__ double2 assemble_b(int k, int i, const int32_t *__res
         fy += w[k] * hv[k].y;
       }
   }
-  const double2 ui = u[i];
   return make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
+}
+
+// assemble_b for two rows at once (rows with on[r] false are skipped): both
+// rows' loads are issued together, so their gather chains overlap.  Same
+// arithmetic, in the same order, as assemble_b.
+__device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
+                                            const int32_t *__restrict__ mptr,
+                                            const int32_t *__restrict__ mcol,
+                                            const float *__restrict__ mwt,
+                                            const float2 *__restrict__ h,
+                                            const double2 *__restrict__ u,
+                                            const int32_t *__restrict__ perm, double tau,
+                                            double2 out[2]) {
+  int q0[2], q1[2], node[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    q0[r] = on[r] ? mptr[k[r]] : 0;
+    q1[r] = on[r] ? mptr[k[r] + 1] : 0;
+    node[r] = on[r] ? perm[k[r]] : 0;
+  }
+  double2 ui[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) ui[r] = on[r] ? u[node[r]] : make_double2(0.0, 0.0);
+  float fx[2] = {0.0f, 0.0f}, fy[2] = {0.0f, 0.0f};
+  constexpr int U = 8;
+  const int len = max(q1[0] - q0[0], q1[1] - q0[1]);
+  for (int d = 0; d < len; d += U) {
+    int c[2][U];
+    float w[2][U];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int q = q0[r] + d + k;
+        c[r][k] = q < q1[r] ? mcol[q] : -1;
+        w[r][k] = q < q1[r] ? mwt[q] : 0.0f;
+      }
+    float2 hv[2][U];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < U; ++k) hv[r][k] = c[r][k] >= 0 ? h[c[r][k]] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (q0[r] + d + k < q1[r]) {
+          fx[r] += w[r][k] * hv[r][k].x;
+          fy[r] += w[r][k] * hv[r][k].y;
+        }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    out[r] = make_double2(ui[r].x - tau * (double)fx[r], ui[r].y - tau * (double)fy[r]);
 }
 
 // Force assembly (thread per solve row), b written in solve order.  When
@@ -336,14 +491,20 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
                                                   const DevPair *__restrict__ pairs, int n_pairs,
                                                   const double *__restrict__ partials,
                                                   double *__restrict__ finish_msd) {
-  const int node_groups = (n + 255) / 256;
+  const int node_groups = (n + 511) / 512;
   if ((int)blockIdx.x >= node_groups) {
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - node_groups);
     return;
   }
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  x[k] = assemble_b(k, perm[k], mptr, mcol, mwt, h, u, tau);
+  // rows k and k + 256 of the workgroup's 512
+  const int k0 = (int)blockIdx.x * 512 + (int)threadIdx.x;
+  if (k0 >= n) return;
+  const int k[2] = {k0, k0 + 256};
+  const bool on[2] = {true, k0 + 256 < n};
+  double2 b[2];
+  assemble_b2(k, on, mptr, mcol, mwt, h, u, perm, tau, b);
+  x[k0] = b[0];
+  if (on[1]) x[k0 + 256] = b[1];
 }
 
 // Copies n doubles from global memory to LDS with all of a thread's loads of
@@ -828,6 +989,198 @@ __global__ __launch_bounds__(256) void k_wave_bwd(
 }
 
 // ---------------------------------------------------------------------------
+// Half-wavefront-per-block level kernels for levels whose blocks have at most
+// 32 rows (the leaves of the dissection): each wavefront solves two blocks,
+// one per 32-lane half, so a load instruction moves twice the data of the
+// wavefront-per-block form.  The vector entries a half broadcasts go through
+// its own 32-entry LDS slot (one read per entry, same address for the whole
+// half); within a wavefront LDS operations complete in issue order, so a slot
+// is rewritten only after the reads issued before it.
+// ---------------------------------------------------------------------------
+
+// Forward, one level: per item (block, slice) t = b_rows - contributions (or
+// the assembled b with FUSED), y = D t, upd = P y for the slice's panel rows
+// (D packed column-major, P column-major), y to ybuf by slice 0.  Lane r of a
+// half holds row r, then panel rows k0 + kc + r.
+template <bool FUSED, int C>
+__global__ __launch_bounds__(256) void k_half_fwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
+    const double *__restrict__ dcol, const double *__restrict__ pcol, double2 *x,
+    double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
+  const int item_groups = (count + 7) / 8;
+  if (FUSED && (int)blockIdx.x >= item_groups) {
+    const int g = (int)blockIdx.x - item_groups;
+    const int row_groups = (A.n_rows + 255) / 256;
+    if (g < row_groups) {
+      const int k = g * 256 + (int)threadIdx.x;
+      if (k < A.n_rows) {
+        const int row = A.rows[k];
+        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      }
+    } else {
+      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
+    }
+    return;
+  }
+  __shared__ double2 vec[8][32];
+  const int hw = (int)threadIdx.x >> 5, r = (int)threadIdx.x & 31;
+  const int w = (int)blockIdx.x * 8 + hw;
+  if ((int)blockIdx.x * 8 + (hw & ~1) >= count) return;    // both halves idle
+  DevBlock B{};
+  int b = 0, m = 1, k0 = 0, kn = 0, slice = 1;
+  if (w < count) {
+    const int2 it = items[w];
+    B = blocks[it.x];
+    b = B.r1 - B.r0;
+    m = B.m;
+    slice = it.y;
+    k0 = it.y * B.rslice;
+    kn = max(0, min(B.rslice, m - k0));
+  }
+  double2 *v2 = vec[hw];
+  // D(r, j), r >= j, at doff + j b - j (j - 1) / 2 + (r - j)
+  auto dload = [&](int j) {
+    return (j < b && j <= r && r < b)
+               ? dcol[B.doff + (int64_t)j * b - (int64_t)j * (j - 1) / 2 + (r - j)]
+               : 0.0;
+  };
+  double v[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) v[u] = dload(u);
+  double2 t = make_double2(0.0, 0.0);
+  if (r < b) {
+    const int row = B.r0 + r;
+    if (FUSED) {
+      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+    } else {
+      const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
+      const double2 bb = x[row];
+      t = make_double2(bb.x - c.x, bb.y - c.y);
+    }
+  }
+  v2[r] = t;
+  __builtin_amdgcn_wave_barrier();
+  // y_r = sum_{j <= r} D(r, j) t_j
+  double2 y = make_double2(0.0, 0.0);
+  for (int j0 = 0; j0 < b; j0 += C) {
+    if (j0 > 0) {
+#pragma unroll
+      for (int u = 0; u < C; ++u) v[u] = dload(j0 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+      if (j0 + u < b) {
+        const double2 tj = v2[j0 + u];
+        y.x += v[u] * tj.x;
+        y.y += v[u] * tj.y;
+      }
+  }
+  __builtin_amdgcn_wave_barrier();
+  v2[r] = y;
+  __builtin_amdgcn_wave_barrier();
+  // upd[k] = sum_j P(k, j) y_j, panel entry (k, j) at poff + j m + k
+  for (int kc = 0; kc < kn; kc += 32) {
+    const int kk = k0 + kc + r;
+    const bool on = kc + r < kn;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j0 = 0; j0 < b; j0 += C) {
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        v[u] = (j0 + u < b && on) ? pcol[B.poff + (int64_t)(j0 + u) * m + kk] : 0.0;
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        if (j0 + u < b) {
+          const double2 yj = v2[j0 + u];
+          acc.x += v[u] * yj.x;
+          acc.y += v[u] * yj.y;
+        }
+    }
+    if (on) upd[B.boff + kk] = acc;
+  }
+  if (slice == 0 && r < b) ybuf[B.r0 + r] = y;
+}
+
+// Backward, one level (blocks of at most 32 rows, not split): per block
+//   s_j = sum_k P(k, j) z(below_k)   (P row-major; z gathered 32 rows at a time),
+//   t = y - s,  z_j = sum_{i >= j} D(i, j) t_i   (D packed row-major),
+// z written to x and, when `out` is given, to natural node order.  Lane r of a
+// half holds column r.
+template <int C>
+__global__ __launch_bounds__(256) void k_half_bwd(
+    const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
+    const int32_t *__restrict__ below_idx, const double *__restrict__ drow,
+    const double *__restrict__ prow, double2 *x, const double2 *__restrict__ ybuf,
+    const int32_t *__restrict__ perm, double2 *__restrict__ out) {
+  __shared__ double2 vec[8][32];
+  const int hw = (int)threadIdx.x >> 5, r = (int)threadIdx.x & 31;
+  const int w = (int)blockIdx.x * 8 + hw;
+  if ((int)blockIdx.x * 8 + (hw & ~1) >= count) return;    // both halves idle
+  DevBlock B{};
+  int b = 0, m = 0;
+  if (w < count) {
+    B = blocks[items[w].x];
+    b = B.r1 - B.r0;
+    m = B.m;
+  }
+  double2 *v2 = vec[hw];
+  const bool col = r < b;
+  auto pload = [&](int k) { return (k < m && col) ? prow[B.poff + (int64_t)k * b + r] : 0.0; };
+  double v[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) v[u] = pload(u);
+  double2 s = make_double2(0.0, 0.0);
+  for (int kc = 0; kc < m; kc += 32) {
+    const double2 zl = kc + r < m ? x[below_idx[B.boff + kc + r]] : make_double2(0.0, 0.0);
+    __builtin_amdgcn_wave_barrier();
+    v2[r] = zl;
+    __builtin_amdgcn_wave_barrier();
+    const int kend = min(32, m - kc);
+    for (int k0 = 0; k0 < kend; k0 += C) {
+      if (kc > 0 || k0 > 0) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) v[u] = pload(kc + k0 + u);
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        if (k0 + u < kend) {
+          const double2 zk = v2[k0 + u];
+          s.x += v[u] * zk.x;
+          s.y += v[u] * zk.y;
+        }
+    }
+  }
+  double2 t = make_double2(0.0, 0.0);
+  if (col) {
+    const double2 yv = ybuf[B.r0 + r];
+    t = make_double2(yv.x - s.x, yv.y - s.y);
+  }
+  __builtin_amdgcn_wave_barrier();
+  v2[r] = t;
+  __builtin_amdgcn_wave_barrier();
+  // z_j = sum_{i >= j} D(i, j) t_i, D(i, j) at doff + i (i + 1) / 2 + j
+  double2 z = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < b; i0 += C) {
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int i = i0 + u;
+      v[u] = (i < b && r <= i && col) ? drow[B.doff + (int64_t)i * (i + 1) / 2 + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+      if (i0 + u < b) {
+        const double2 ti = v2[i0 + u];
+        z.x += v[u] * ti.x;
+        z.y += v[u] * ti.y;
+      }
+  }
+  if (col) {
+    x[B.r0 + r] = z;
+    if (out) out[perm[B.r0 + r]] = z;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // LDS-staged wavefront-per-block level kernels: one wavefront (the whole
 // workgroup) per block of at most 64 rows whose panel is not split; the
 // block's dense inverse and panel are copied straight from global memory into
@@ -1249,7 +1602,7 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, cons
                            const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
                            double tau, const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s) {
-  const int groups = (n + 255) / 256 + (finish_msd ? (n_pairs + 3) / 4 : 0);
+  const int groups = (n + 511) / 512 + (finish_msd ? (n_pairs + 3) / 4 : 0);
   return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, perm, x, tau, pairs,
                 n_pairs, partials, finish_msd);
 }
@@ -1266,6 +1619,16 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
     return fuse ? launch(k_lds_fwd<true>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
                          cidx, dcol, pcol, x, ybuf, upd, *fuse)
                 : launch(k_lds_fwd<false>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
+                         cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
+  }
+  if (nt == 32) {                             // half-wavefront per block (at most 32 rows)
+    int groups = (count + 7) / 8;
+    if (fuse)
+      groups += (fuse->n_rows + 255) / 256 + (fuse->finish_msd ? (fuse->n_pairs + 3) / 4 : 0);
+    if (groups == 0) return hipSuccess;
+    return fuse ? launch(k_half_fwd<true, 8>, groups, 256, 0, s, blocks, items, count, cptr, cidx,
+                         dcol, pcol, x, ybuf, upd, *fuse)
+                : launch(k_half_fwd<false, 8>, groups, 256, 0, s, blocks, items, count, cptr,
                          cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
   }
   if (nt == 8 || nt == 16) {                  // wavefront per block, nt loads per batch
@@ -1310,6 +1673,9 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   if (nt == 1)
     return launch(k_lds_bwd, count, 64, lds_bytes, s, blocks, items, count, below_idx, drow, prow,
                   x, ybuf, perm, out);
+  if (nt == 32)
+    return launch(k_half_bwd<8>, (count + 7) / 8, 256, 0, s, blocks, items, count, below_idx,
+                  drow, prow, x, ybuf, perm, out);
   if (nt == 8 || nt == 16)
     return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
                   items, count, below_idx, drow, prow, x, ybuf, perm, out);

@@ -43,6 +43,16 @@ __device__ __forceinline__ void bs_weights_d(double t, double w[4]) {
   w[3] = t3 * (1.0 / 6.0);
 }
 
+// Six times the FP64 weights (the caller divides by 6 per axis, or by 36
+// once for a 2-D sample): no scaling per weight.
+__device__ __forceinline__ void bs_weights6_d(double t, double w[4]) {
+  const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
+  w[0] = s * s * s;
+  w[1] = 3.0 * t3 - 6.0 * t2 + 4.0;
+  w[2] = -3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0;
+  w[3] = t3;
+}
+
 __device__ __forceinline__ void bs_deriv(float t, float d[4]) {
   const float s = 1.0f - t, t2 = t * t;
   d[0] = -0.5f * s * s;
@@ -79,36 +89,50 @@ __device__ __forceinline__ bool split_coord_d(int base, double off, int &cell, d
   return ok;
 }
 
-struct Taps {
-  int col[4];
-  const float *row[4];
-};
-
-// The four taps of one coefficient row around cell cx: one 16-byte load when
-// all four lie inside the row (the common case), else the folded taps one by
-// one.
-struct __attribute__((aligned(4))) Row4 {
-  float v[4];
-};
-__device__ __forceinline__ void row_taps(const float *__restrict__ r, const Taps &tp, int cx, int W,
-                                         float t[4]) {
-  if (cx >= 1 && cx + 2 < W) {
-    Row4 q;
-    __builtin_memcpy(&q, r + (cx - 1), sizeof(Row4));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) t[k] = q.v[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) t[k] = r[tp.col[k]];
-  }
+// Four consecutive floats from a 4-byte aligned address as one 16-byte load
+// (a vector type, so the load is neither split nor merged with the scalar
+// loads of the folded path).
+typedef float float4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ void load_row4(const float *__restrict__ p, float (&t)[4]) {
+  const float4_a4 q = *reinterpret_cast<const float4_a4 *>(p);
+  t[0] = q.x;
+  t[1] = q.y;
+  t[2] = q.z;
+  t[3] = q.w;
 }
 
-__device__ __forceinline__ void make_taps(const float *__restrict__ c, int H, int W, int cx,
-                                          int cy, Taps &tp) {
+// The 4x4 taps of cell (cx, cy) when the whole window lies inside the image
+// (1 <= cx, cx + 2 < W, likewise y): four row loads at one 32-bit offset from
+// c, one pair's coefficient image (fewer than 2^31 pixels).
+__device__ __forceinline__ bool taps_inside(int H, int W, int cx, int cy) {
+  return cx >= 1 && cx + 2 < W && cy >= 1 && cy + 2 < H;
+}
+__device__ __forceinline__ void load_taps_inside(const float *__restrict__ c, int W, int cx, int cy,
+                                                 float (&t)[4][4]) {
+  const unsigned o = (unsigned)(cy - 1) * (unsigned)W + (unsigned)(cx - 1);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    tp.col[k] = fold_index(cx - 1 + k, W);
-    tp.row[k] = c + (size_t)fold_index(cy - 1 + k, H) * W;
+  for (int m = 0; m < 4; ++m) load_row4(c + (o + (unsigned)m * (unsigned)W), t[m]);
+}
+
+// The 4x4 coefficient taps around cell (cx, cy), t[m][n] = c(cy - 1 + m,
+// cx - 1 + n) with folded indices: the row loads above when the window lies
+// inside the image (the common case), else each tap folded and loaded on its
+// own.
+__device__ __forceinline__ void load_taps(const float *__restrict__ c, int H, int W, int cx, int cy,
+                                          float (&t)[4][4]) {
+  if (taps_inside(H, W, cx, cy)) {
+    load_taps_inside(c, W, cx, cy, t);
+  } else {
+    unsigned col[4], row[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      col[k] = (unsigned)fold_index(cx - 1 + k, W);
+      row[k] = (unsigned)fold_index(cy - 1 + k, H) * (unsigned)W;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) t[m][n] = c[row[m] + col[n]];
   }
 }
 
@@ -117,14 +141,12 @@ __device__ __forceinline__ float spline_value(const float *__restrict__ c, int H
   float wx[4], wy[4];
   bs_weights(fx, wx);
   bs_weights(fy, wy);
-  Taps tp;
-  make_taps(c, H, W, cx, cy, tp);
+  float t[4][4];
+  load_taps(c, H, W, cx, cy, t);
   float v = 0.0f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    float c[4];
-    row_taps(tp.row[m], tp, cx, W, c);
-    const float rv = c[0] * wx[0] + c[1] * wx[1] + c[2] * wx[2] + c[3] * wx[3];
+    const float rv = t[m][0] * wx[0] + t[m][1] * wx[1] + t[m][2] * wx[2] + t[m][3] * wx[3];
     v += wy[m] * rv;
   }
   return v;
@@ -136,42 +158,44 @@ __device__ __forceinline__ double spline_value_d(const float *__restrict__ c, in
   double wx[4], wy[4];
   bs_weights_d(fx, wx);
   bs_weights_d(fy, wy);
-  Taps tp;
-  make_taps(c, H, W, cx, cy, tp);
+  float t[4][4];
+  load_taps(c, H, W, cx, cy, t);
   double v = 0.0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    float c[4];
-    row_taps(tp.row[m], tp, cx, W, c);
-    const double rv = (double)c[0] * wx[0] + (double)c[1] * wx[1] + (double)c[2] * wx[2] +
-                      (double)c[3] * wx[3];
+    const double rv = (double)t[m][0] * wx[0] + (double)t[m][1] * wx[1] +
+                      (double)t[m][2] * wx[2] + (double)t[m][3] * wx[3];
     v += wy[m] * rv;
   }
   return v;
 }
 
-__device__ __forceinline__ void spline_value_grad(const float *__restrict__ c, int H, int W,
-                                                  int cx, float fx, int cy, float fy, float &val,
-                                                  float &gx, float &gy) {
+// Value and gradient from the 16 taps t (as load_taps gives them).
+__device__ __forceinline__ void spline_value_grad_taps(const float (&t)[4][4], float fx, float fy,
+                                                       float &val, float &gx, float &gy) {
   float wx[4], dx[4], wy[4], dy[4];
   bs_weights(fx, wx);
   bs_deriv(fx, dx);
   bs_weights(fy, wy);
   bs_deriv(fy, dy);
-  Taps tp;
-  make_taps(c, H, W, cx, cy, tp);
   val = gx = gy = 0.0f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    float c[4];
-    row_taps(tp.row[m], tp, cx, W, c);
-    const float c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+    const float c0 = t[m][0], c1 = t[m][1], c2 = t[m][2], c3 = t[m][3];
     const float rv = c0 * wx[0] + c1 * wx[1] + c2 * wx[2] + c3 * wx[3];
     const float rd = c0 * dx[0] + c1 * dx[1] + c2 * dx[2] + c3 * dx[3];
     val += wy[m] * rv;
     gx += wy[m] * rd;
     gy += dy[m] * rv;
   }
+}
+
+__device__ __forceinline__ void spline_value_grad(const float *__restrict__ c, int H, int W,
+                                                  int cx, float fx, int cy, float fy, float &val,
+                                                  float &gx, float &gy) {
+  float t[4][4];
+  load_taps(c, H, W, cx, cy, t);
+  spline_value_grad_taps(t, fx, fy, val, gx, gy);
 }
 
 // ---------------------------------------------------------------------------

@@ -119,6 +119,11 @@ def test_invalid_inputs_are_rejected():
     Vw = np.array([[0, 0], [65536, 0], [0, 1], [65536, 1]], np.int32)
     Tw = np.array([[0, 1, 3], [0, 3, 2]], np.int32)
     assert "65536" in _expect(B.MR_EINVAL, dict(te=wide, re=wide, V=Vw, T=Tw, alpha=0.1))
+    # at most 2^31 - 1 pixels per image (32-bit offsets within a pair's image);
+    # a zero-stride view stands in for the image, whose pixels are never read
+    big = np.broadcast_to(np.float32(0.0), (65535, 32769))
+    Vb = np.array([[0, 0], [32769, 0], [0, 65535], [32769, 65535]], np.int32)
+    assert "2^31" in _expect(B.MR_EINVAL, dict(te=big, re=big, V=Vb, T=Tw, alpha=0.1))
 
 
 def test_uncovered_pixel_is_rejected():
