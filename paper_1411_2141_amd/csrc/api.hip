@@ -466,11 +466,9 @@ int mr_ctx::upload_all(hipStream_t s) {
       const int32_t m = (int32_t)(pl.below_ptr[k + 1] - pl.below_ptr[k]);
       const int32_t b = B.r1 - B.r0;
       if (b > kBlockMax) return fail(MR_EINVAL, "solve block larger than the kernel limit");
-      // panel rows per slice / chunk so that one work item fits the LDS budget
+      // panel rows per forward slice / backward chunk
       const int64_t nd = (int64_t)b * (b + 1) / 2;
-      const int64_t fixed = 8 * nd + 16 * (2 * (int64_t)b + 256) + 16;
-      int32_t rs = b ? (int32_t)((kSolveLdsBudget - fixed) / (8 * (int64_t)b + 16)) : 64;
-      rs = std::max(8, std::min(64, rs));
+      const int32_t rs = 64;
       const int32_t ns = std::max<int32_t>(1, (m + rs - 1) / rs);
       const int32_t bs = std::max<int32_t>(1, (m + bwd_split_rows - 1) / bwd_split_rows);
       DevBlock db{no + B.r0, no + B.r1, m, B.fwd_group, doff + pl.dense_off[k],

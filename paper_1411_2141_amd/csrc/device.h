@@ -42,15 +42,16 @@ struct DevBlock {
 };
 
 // LDS bytes a forward work item of block size b with kn panel rows needs,
-// and a backward work item with panel chunks of rs rows, for workgroups of
-// nt threads; the launch of a level uses the maximum over its items.
+// and a backward work item with chunks of rs panel rows, for workgroups of nt
+// threads (the factor entries are read from global memory, only vectors and
+// partial sums are held); the launch of a level uses the maximum over its
+// items.
 inline int64_t solve_fwd_lds_bytes(int b, int kn, int nt) {
-  const int64_t nd = (int64_t)b * (b + 1) / 2;
-  return 8 * ((nd + (int64_t)kn * b + 1) / 2 * 2) + 16 * (2 * (int64_t)b + nt);
+  (void)kn;
+  return 16 * (2 * (int64_t)b + nt);
 }
 inline int64_t solve_bwd_lds_bytes(int b, int rs, int nt) {
-  const int64_t nd = (int64_t)b * (b + 1) / 2;
-  return 8 * (((int64_t)rs * b + 1) / 2 * 2) + 16 * ((int64_t)rs + nt + b) + 8 * nd;
+  return 16 * ((int64_t)rs + nt + b);
 }
 
 // Apex of the block tree (all pairs share one numbering of apex positions).

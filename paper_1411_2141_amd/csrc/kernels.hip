@@ -549,12 +549,16 @@ __device__ __forceinline__ double2 combine_parts(const double2 *red, int o, int 
 // Forward solve, one level of the block tree (supernodal, push form).  Work
 // item = (block, slice).  Every slice of a block computes
 //   t = b_rows - (update entries that descendant blocks wrote for these rows)
-//   y = D^-1 t              (dense inverse, column-major packed, staged in LDS)
+//   y = D^-1 t              (dense inverse, column-major packed)
 // and then its slice of the block's own update entries
-//   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block)).
-// Slice 0 also writes y to ybuf (b stays in x for the other slices).  Each
-// phase spreads its sums over all
-// threads and combines the partial sums in a fixed order (deterministic).
+//   upd[k] = sum_j P[k][j] y_j   for panel rows k of the slice (P = L(below, block),
+//                                 read from its column-major copy).
+// Slice 0 also writes y to ybuf (b stays in x for the other slices).  D and P
+// are read straight from global memory in coalesced order, U loads per thread
+// in flight (each entry is used once, so nothing is staged); only t, y and
+// the partial sums live in LDS, which keeps the workgroup's LDS independent
+// of the block size.  Each phase spreads its sums over all threads and
+// combines the partial sums in a fixed order (deterministic).
 // With FUSED (first level only, no contributions) the workgroup forms b of
 // its rows itself, and the workgroups after the `count` block items assemble
 // the other rows and finish the MSD (AssembleArgs).
@@ -562,9 +566,9 @@ template <int NT, bool FUSED>
 __global__ __launch_bounds__(NT) void k_solve_fwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items, int count,
     const int64_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
-    const double *__restrict__ dcol, const double *__restrict__ prow, double2 *x, double2 *ybuf,
+    const double *__restrict__ dcol, const double *__restrict__ pcol, double2 *x, double2 *ybuf,
     double2 *upd, AssembleArgs A) {
-  extern __shared__ double smem[];
+  extern __shared__ double2 sv[];           // t[b], y[b], red[NT]
   if (FUSED && (int)blockIdx.x >= count) {
     const int g = (int)blockIdx.x - count;
     const int row_groups = (A.n_rows + NT - 1) / NT;
@@ -584,19 +588,26 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   const int b = B.r1 - B.r0;
   if (b == 0) return;
   const int tid = threadIdx.x;
-  const int nd = b * (b + 1) / 2;
+  const int m = B.m;
   const int k0 = it.y * B.rslice;
-  const int kn = max(0, min(B.rslice, B.m - k0));
-  double *D = smem;
-  double *Ps = D + nd;
-  double2 *t = reinterpret_cast<double2 *>(smem + (nd + kn * b + 1) / 2 * 2);
-  double2 *yv = t + b;
-  double2 *red = yv + b;
-  stage_to_lds<NT>(D, dcol + B.doff, nd);
-  stage_to_lds<NT>(Ps, prow + B.poff + (int64_t)k0 * b, kn * b);
+  const int kn = max(0, min(B.rslice, m - k0));
+  double2 *t = sv;
+  double2 *yv = sv + b;
+  double2 *red = sv + 2 * b;
   const int bp = pow2_at_least(b);
   const int np = NT / bp;          // threads per row
   const int r = tid & (bp - 1), part = tid / bp;
+  constexpr int U = 8;
+  // D(r, j), j <= r, at doff + j b - j (j - 1) / 2 + (r - j); the first batch
+  // is in flight during phase 1
+  auto dload = [&](int j) {
+    return (r < b && j <= r)
+               ? dcol[B.doff + (int64_t)j * b - (int64_t)j * (j - 1) / 2 + (r - j)]
+               : 0.0;
+  };
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = dload(part + u * np);
   // phase 1: gathers of the contributions, all loads of a thread in flight
   if (FUSED) {
     if (part == 0 && r < b) {
@@ -608,7 +619,6 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
     if (r < b) {
       const int row = B.r0 + r;
       const int64_t q1 = cptr[row + 1];
-      constexpr int U = 8;
       for (int64_t q = cptr[row] + part; q < q1; q += (int64_t)np * U) {
         int idx[U];
 #pragma unroll
@@ -616,13 +626,13 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
           const int64_t qq = q + (int64_t)u * np;
           idx[u] = qq < q1 ? cidx[qq] : -1;
         }
-        double2 v[U];
+        double2 cv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = idx[u] >= 0 ? upd[idx[u]] : make_double2(0.0, 0.0);
+        for (int u = 0; u < U; ++u) cv[u] = idx[u] >= 0 ? upd[idx[u]] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          ax += v[u].x;
-          ay += v[u].y;
+          ax += cv[u].x;
+          ay += cv[u].y;
         }
       }
     }
@@ -635,16 +645,22 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
     }
   }
   __syncthreads();
-  // phase 2: y_i = sum_{j <= i} D(i, j) t_j, j split over the row's threads
+  // phase 2: y_r = sum_{j <= r} D(r, j) t_j, j = part, part + np, ...
   {
     double ax = 0.0, ay = 0.0;
-    if (r < b) {
-#pragma unroll 8
-      for (int j = part; j <= r; j += np) {
-        // element (r, j) of the packed column-major lower triangle
-        const double v = D[j * b - j * (j - 1) / 2 + (r - j)];
-        ax += v * t[j].x;
-        ay += v * t[j].y;
+    for (int j0 = part; j0 < b; j0 += U * np) {
+      if (j0 != part) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = dload(j0 + u * np);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * np;
+        if (r < b && j <= r) {
+          const double2 tj = t[j];
+          ax += v[u] * tj.x;
+          ay += v[u] * tj.y;
+        }
       }
     }
     red[tid] = make_double2(ax, ay);
@@ -656,38 +672,49 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
     if (it.y == 0) ybuf[B.r0 + r] = y;
   }
   __syncthreads();
-  // phase 3: the slice's update entries, 4 partial sums per panel row
+  // phase 3: the slice's update entries, kParts partial sums per panel row;
+  // P(k0 + kk, j) at poff + j m + k0 + kk
   constexpr int kParts = 4;
   constexpr int kRows = NT / kParts;
   for (int base = 0; base < kn; base += kRows) {
     const int kk = base + tid % kRows;
     const int pp = tid / kRows;
+    const bool on = kk < kn;
     double ax = 0.0, ay = 0.0;
-    if (kk < kn) {
-      const double *Pr = Ps + kk * b;
-#pragma unroll 8
-      for (int j = pp; j < b; j += kParts) {
-        const double v = Pr[j];
-        ax += v * yv[j].x;
-        ay += v * yv[j].y;
+    for (int j0 = pp; j0 < b; j0 += U * kParts) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kParts;
+        v[u] = (on && j < b) ? pcol[B.poff + (int64_t)j * m + k0 + kk] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kParts;
+        if (on && j < b) {
+          const double2 yj = yv[j];
+          ax += v[u] * yj.x;
+          ay += v[u] * yj.y;
+        }
       }
     }
     red[tid] = make_double2(ax, ay);
     __syncthreads();
-    if (pp == 0 && kk < kn) upd[B.boff + k0 + kk] = combine_parts(red, tid, kRows, kParts);
+    if (pp == 0 && on) upd[B.boff + k0 + kk] = combine_parts(red, tid, kRows, kParts);
     __syncthreads();
   }
 }
 
 // Backward solve, one level of the block tree.  Work item = (block, slice);
 // a block is split into B.bslice workgroups, each covering a contiguous run of
-// panel rows that it walks in LDS chunks of B.rslice rows, forming the partial
-// sums s_j = sum_k P[k][j] z(below_k).  A block with one workgroup finishes at
-// once; otherwise each workgroup writes its partials, and the last to arrive
-// (device-scope counter) adds them in slice order.  The finishing workgroup
-// forms t = y_block - s (y from ybuf) and z = D^-T t (row-major packed inverse in LDS),
-// writes z in place and, when `out` is given, scatters it to natural order.
-// The finisher resets the counter.
+// panel rows that it walks in chunks of B.rslice rows (z of the chunk's rows
+// gathered into LDS), forming the partial sums s_j = sum_k P[k][j] z(below_k).
+// A block with one workgroup finishes at once; otherwise each workgroup
+// writes its partials, and the last to arrive (device-scope counter) adds
+// them in slice order.  The finishing workgroup forms t = y_block - s (y from
+// ybuf) and z = D^-T t (row-major packed inverse), writes z in place and,
+// when `out` is given, scatters it to natural order.  The finisher resets the
+// counter.  P and D are read straight from global memory in coalesced order
+// (each entry is used once), U loads per thread in flight.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_solve_bwd(
     const DevBlock *__restrict__ blocks, const int2 *__restrict__ items,
@@ -695,40 +722,51 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
     const double *__restrict__ prow, double2 *x, const double2 *__restrict__ ybuf,
     const int32_t *__restrict__ perm,
     double2 *__restrict__ out, double2 *partials, unsigned *counters) {
-  extern __shared__ double smem[];
+  extern __shared__ double2 sv[];           // zb[cap], red[NT], t[b]
   __shared__ int last;
   const int2 it = items[blockIdx.x];
   const DevBlock B = blocks[it.x];
   const int b = B.r1 - B.r0;
   if (b == 0) return;
   const int tid = threadIdx.x;
-  const int nd = b * (b + 1) / 2;
   const int rs = B.rslice;
   // panel rows [kb, ke) of this workgroup
   const int per = (B.m + B.bslice - 1) / B.bslice;
   const int kb = min(B.m, it.y * per), ke = min(B.m, kb + per);
-  const int cap = min(rs, B.m);   // LDS chunk capacity in panel rows
-  double *Ps = smem;
-  double2 *zb = reinterpret_cast<double2 *>(smem + (cap * b + 1) / 2 * 2);
+  const int cap = min(rs, B.m);   // chunk of panel rows whose z is held in LDS
+  double2 *zb = sv;
   double2 *red = zb + cap;
   double2 *t = red + NT;
-  double *D = reinterpret_cast<double *>(t + b);
-  if (B.bslice == 1) stage_to_lds<NT>(D, drow + B.doff, nd);
   const int bp = pow2_at_least(b);
   const int np = NT / bp;
   const int j = tid & (bp - 1), g = tid / bp;
+  constexpr int U = 8;
+  double v[U];
   double ax = 0.0, ay = 0.0;
   for (int c0 = kb; c0 < ke; c0 += cap) {
     const int kn = min(cap, ke - c0);
-    stage_to_lds<NT>(Ps, prow + B.poff + (int64_t)c0 * b, kn * b);
+    // P(c0 + k, j) at poff + (c0 + k) b + j; the first batch is in flight
+    // during the z gather
+    auto pload = [&](int k) {
+      return (j < b && k < kn) ? prow[B.poff + (int64_t)(c0 + k) * b + j] : 0.0;
+    };
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pload(g + u * np);
     for (int k = tid; k < kn; k += NT) zb[k] = x[below_idx[B.boff + c0 + k]];
     __syncthreads();
-    if (j < b) {
-#pragma unroll 8
-      for (int k = g; k < kn; k += np) {
-        const double v = Ps[k * b + j];
-        ax += v * zb[k].x;
-        ay += v * zb[k].y;
+    for (int q0 = g; q0 < kn; q0 += U * np) {
+      if (q0 != g) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = pload(q0 + u * np);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = q0 + u * np;
+        if (j < b && k < kn) {
+          const double2 zk = zb[k];
+          ax += v[u] * zk.x;
+          ay += v[u] * zk.y;
+        }
       }
     }
     __syncthreads();
@@ -745,7 +783,6 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
     __syncthreads();
     if (!last) return;
     __threadfence();
-    stage_to_lds<NT>(D, drow + B.doff, nd);
     if (g == 0 && j < b) {
       double sx = 0.0, sy = 0.0;
       for (int q = 0; q < B.bslice; ++q) {
@@ -762,16 +799,24 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
     t[j] = make_double2(yy.x - sum.x, yy.y - sum.y);
   }
   __syncthreads();
-  // z_j = sum_{i >= j} D(i, j) t_i, i split over the column's threads
+  // z_j = sum_{i >= j} D(i, j) t_i over i = g, g + np, ...; D(i, j) at
+  // doff + i (i + 1) / 2 + j (a row per step: coalesced over j)
   {
+    auto dload = [&](int i) {
+      return (j < b && i < b && i >= j) ? drow[B.doff + (int64_t)i * (i + 1) / 2 + j] : 0.0;
+    };
     double zx = 0.0, zy = 0.0;
-    if (j < b) {
-#pragma unroll 8
-      for (int i = j + g; i < b; i += np) {
-        // element (i, j) of the packed row-major lower triangle
-        const double v = D[i * (i + 1) / 2 + j];
-        zx += v * t[i].x;
-        zy += v * t[i].y;
+    for (int i0 = g; i0 < b; i0 += U * np) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = dload(i0 + u * np);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * np;
+        if (j < b && i < b && i >= j) {
+          const double2 ti = t[i];
+          zx += v[u] * ti.x;
+          zy += v[u] * ti.y;
+        }
       }
     }
     red[tid] = make_double2(zx, zy);
@@ -1652,7 +1697,7 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
     auto k = nt == 64 ? k_solve_fwd<64, false> : nt == 128 ? k_solve_fwd<128, false>
                                                            : k_solve_fwd<256, false>;
     if (count == 0) return hipSuccess;
-    return launch(k, count, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x,
+    return launch(k, count, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, pcol, x,
                   ybuf, upd, AssembleArgs{});
   }
   auto k = nt == 64 ? k_solve_fwd<64, true> : nt == 128 ? k_solve_fwd<128, true>
@@ -1660,7 +1705,7 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
   const int groups = count + (fuse->n_rows + nt - 1) / nt +
                      (fuse->finish_msd ? (fuse->n_pairs + nt / 64 - 1) / (nt / 64) : 0);
   if (groups == 0) return hipSuccess;
-  return launch(k, groups, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, prow, x,
+  return launch(k, groups, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, pcol, x,
                 ybuf, upd, *fuse);
 }
 
