@@ -109,8 +109,8 @@ typedef struct {
                                   (blocks <= 64 rows, <= 64 KB); 8 or 16 = wavefront per block
                                   with 8 or 16 loads per lane in flight (blocks <= 64 rows);
                                   32 = half wavefront per block (blocks <= 32 rows); these three
-                                  need unsplit backward blocks; 64, 128 or 256 = workgroup per
-                                  block of that size; levels where the choice is not admissible
+                                  need unsplit backward blocks; 64, 128, 256, 512 or 1024 =
+                                  workgroup per block of that size; levels where the choice is not admissible
                                   take the smallest admissible workgroup size.  MR_FLAG_NO_TUNE
                                   with 0 means 256 everywhere. */
 } mr_params;

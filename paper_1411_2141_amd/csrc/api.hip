@@ -141,8 +141,8 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
 // direct LDS staging (blocks of at most 64 rows whose factor data fits 64 KB)
 // or with register batches (blocks of at most 64 rows) (backward: no split
 // blocks), and the workgroup-per-block
-// kernels with 64, 128, 256 threads (at least the level's largest block
-// rounded up to a power of two).  The level kernels only read and write the
+// kernels with 64, 128, 256, 512 or 1024 threads (at least the level's
+// largest block rounded up to a power of two).  The level kernels only read and write the
 // solve scratch vectors, so running them on whatever those hold is harmless.
 bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
   const std::vector<int32_t> &minnt = fwd ? fwd_bp : bwd_bp;
@@ -204,7 +204,7 @@ int mr_ctx::tune(hipStream_t s) {
     }
     return t_min;
   };
-  static const int kCandidates[] = {1, 8, 16, 32, 64, 128, 256};
+  static const int kCandidates[] = {1, 8, 16, 32, 64, 128, 256, 512, 1024};
   // pass 1: every level on its own
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
@@ -788,8 +788,9 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     return fail(MR_EINVAL, "unknown force_mode");
   {
     const int32_t k = params->solve_kernel;
-    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 64 && k != 128 && k != 256)
-      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 64, 128 or 256");
+    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 64 && k != 128 && k != 256 &&
+        k != 512 && k != 1024)
+      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 64, 128, 256, 512 or 1024");
   }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {

@@ -672,9 +672,9 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
     if (it.y == 0) ybuf[B.r0 + r] = y;
   }
   __syncthreads();
-  // phase 3: the slice's update entries, kParts partial sums per panel row;
-  // P(k0 + kk, j) at poff + j m + k0 + kk
-  constexpr int kParts = 4;
+  // phase 3: the slice's update entries, kParts partial sums per panel row
+  // (one pass over a 64-row slice); P(k0 + kk, j) at poff + j m + k0 + kk
+  constexpr int kParts = NT / 64;
   constexpr int kRows = NT / kParts;
   for (int base = 0; base < kn; base += kRows) {
     const int kk = base + tid % kRows;
@@ -1692,16 +1692,22 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
                 : launch(k_wave_fwd<false, 16>, groups, 256, 0, s, blocks, items, count, cptr,
                          cidx, dcol, pcol, x, ybuf, upd, none);
   }
-  nt = nt == 64 || nt == 128 ? nt : 256;
+  nt = nt == 64 || nt == 128 || nt == 512 || nt == 1024 ? nt : 256;
   if (!fuse) {
-    auto k = nt == 64 ? k_solve_fwd<64, false> : nt == 128 ? k_solve_fwd<128, false>
-                                                           : k_solve_fwd<256, false>;
+    auto k = nt == 64    ? k_solve_fwd<64, false>
+             : nt == 128 ? k_solve_fwd<128, false>
+             : nt == 512 ? k_solve_fwd<512, false>
+             : nt == 1024 ? k_solve_fwd<1024, false>
+                          : k_solve_fwd<256, false>;
     if (count == 0) return hipSuccess;
     return launch(k, count, nt, lds_bytes, s, blocks, items, count, cptr, cidx, dcol, pcol, x,
                   ybuf, upd, AssembleArgs{});
   }
-  auto k = nt == 64 ? k_solve_fwd<64, true> : nt == 128 ? k_solve_fwd<128, true>
-                                                        : k_solve_fwd<256, true>;
+  auto k = nt == 64    ? k_solve_fwd<64, true>
+           : nt == 128 ? k_solve_fwd<128, true>
+           : nt == 512 ? k_solve_fwd<512, true>
+           : nt == 1024 ? k_solve_fwd<1024, true>
+                        : k_solve_fwd<256, true>;
   const int groups = count + (fuse->n_rows + nt - 1) / nt +
                      (fuse->finish_msd ? (fuse->n_pairs + nt / 64 - 1) / (nt / 64) : 0);
   if (groups == 0) return hipSuccess;
@@ -1724,9 +1730,14 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   if (nt == 8 || nt == 16)
     return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
                   items, count, below_idx, drow, prow, x, ybuf, perm, out);
-  auto k = nt == 64 ? k_solve_bwd<64> : nt == 128 ? k_solve_bwd<128> : k_solve_bwd<256>;
-  return launch(k, count, nt == 64 || nt == 128 ? nt : 256, lds_bytes, s, blocks, items,
-                below_idx, drow, prow, x, ybuf, perm, out, partials, counters);
+  nt = nt == 64 || nt == 128 || nt == 512 || nt == 1024 ? nt : 256;
+  auto k = nt == 64    ? k_solve_bwd<64>
+           : nt == 128 ? k_solve_bwd<128>
+           : nt == 512 ? k_solve_bwd<512>
+           : nt == 1024 ? k_solve_bwd<1024>
+                        : k_solve_bwd<256>;
+  return launch(k, count, nt, lds_bytes, s, blocks, items, below_idx, drow, prow, x, ybuf, perm,
+                out, partials, counters);
 }
 
 hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acptr,

@@ -1,9 +1,9 @@
 """GPU parity of every solve schedule the library can run.
 
-The autotuner picks, per level, one of seven level kernels (wavefront per
+The autotuner picks, per level, one of nine level kernels (wavefront per
 block with its factor data copied straight into LDS, or with 8 or 16 loads in
 flight per lane, half a wavefront per block of at most 32 rows, or a
-workgroup of 64 / 128 / 256 threads per block);
+workgroup of 64 / 128 / 256 / 512 / 1024 threads per block);
 ``solve_kernel`` forces one of them wherever admissible.
 Each schedule is checked against the FP64 oracle with and without the apex
 (the explicit inverse of the top levels), with split backward panels, on a
@@ -24,7 +24,7 @@ from tests._problems import small_pair
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = (1, 8, 16, 32, 64, 128, 256)
+KERNELS = (1, 8, 16, 32, 64, 128, 256, 512, 1024)
 SOLVE_TOL = 1e-12
 U_TOL = 1e-5
 
