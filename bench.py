@@ -96,16 +96,18 @@ def unit_bytes(ctx, pairs) -> dict:
     }
 
 
-def run_bytes(ub: dict, iters: int, trace: bool) -> dict:
+def run_bytes(ub: dict, iters: int, trace: bool, fused: bool = True) -> dict:
     """Algorithmic bytes per kernel family of one ``step`` of ``iters``
     iterations.  The force assembly runs inside the first forward solve
-    launch (solve family).  With an MSD trace the warp of iterate k's result
-    shares the sample launch of iterate k+1 and its final sum the first solve
-    launch; the last result is warped by one warp + finish pair."""
+    launch (solve family) when ``fused``, else in a launch of its own
+    (assemble family).  With an MSD trace the warp of iterate k's result
+    shares the sample launch of iterate k+1 and its final sum the assembly;
+    the last result is warped by one warp + finish pair."""
     w = max(iters - 1, 0) if trace else 0
+    asm = iters * ub["assemble"] + w * ub["finish"]
     return {"sample": iters * ub["sample"] + w * ub["warp"],
-            "assemble": 0,
-            "solve": iters * (ub["solve"] + ub["assemble"]) + w * ub["finish"],
+            "assemble": 0 if fused else asm,
+            "solve": iters * ub["solve"] + (asm if fused else 0),
             "warp": (ub["warp"] + ub["finish"]) if (trace and iters) else 0}
 
 
@@ -192,7 +194,8 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload) -> dict:
         if not no_profile:
             u.zero_()
             _, roof = profile(ctx, lambda: B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream),
-                              run_bytes(unit_bytes(ctx, pairs), N, False), "diff")
+                              run_bytes(unit_bytes(ctx, pairs), N, False,
+                                        ctx.info(0, "fused_assembly") == 1), "diff")
         ctx.close()
     # the reverse pass recomputes the forward from checkpoints, so one gradient
     # evaluation costs (forward) + (reverse pass)
@@ -319,7 +322,8 @@ def main() -> int:
         if not args.no_profile:
             u.zero_()
             kernels, roof = profile(ctx, lambda: run(K),
-                                    run_bytes(unit_bytes(ctx, [pair]), K, True), "single_pair")
+                                    run_bytes(unit_bytes(ctx, [pair]), K, True,
+                                              ctx.info(0, "fused_assembly") == 1), "single_pair")
             stages = stage_rooflines(ctx, [pair], u)
 
     fwd_bwd = None
@@ -365,7 +369,8 @@ def main() -> int:
                 ub.zero_()
                 bk, broof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, KB, None,
                                                                   side.cuda_stream),
-                                    run_bytes(unit_bytes(bctx, batch), KB, False), "batched")
+                                    run_bytes(unit_bytes(bctx, batch), KB, False,
+                                              bctx.info(0, "fused_assembly") == 1), "batched")
                 bstages = stage_rooflines(bctx, batch, ub)
         batched = {"value": round(nb * KB / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
                    "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),

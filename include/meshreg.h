@@ -77,6 +77,9 @@ enum {
   MR_FLAG_HOST_ONLY = 1, /* build tables, operators and the factor only; no device work */
   MR_FLAG_NO_TUNE = 4,   /* skip the solve-schedule autotuning at init (fixed 256-thread
                             workgroups) */
+  MR_FLAG_SEPARATE_ASSEMBLY = 8, /* the force assembly of an iteration runs in a launch of its
+                            own (otherwise the autotuner chooses between that and assembling
+                            inside the first forward solve launch; untuned: inside) */
   MR_FLAG_GRAPH = 2      /* mesh_reg_step captures its launches in a HIP graph once per
                             (u, n_iter, msd_trace, stream) and replays it on later calls
                             with the same arguments (a NULL stream runs eagerly) */
@@ -193,7 +196,10 @@ enum {
   MR_INFO_SOLVE_DENSE = 12,     /* packed dense-inverse entries per direction */
   MR_INFO_MASS_NNZ = 13,        /* entries of the force operator rows */
   MR_INFO_APEX_ROWS = 14,       /* rows of the apex of the solve (0: none) */
-  MR_INFO_SOLVE_BYTES = 15      /* algorithmic bytes of one solve call (both triangular passes) */
+  MR_INFO_SOLVE_BYTES = 15,     /* algorithmic bytes of one solve call (both triangular passes) */
+  MR_INFO_FUSED_ASSEMBLY = 16   /* context: 1 if an iteration assembles the right-hand side inside
+                                   the first forward solve launch, 0 if in a launch of its own
+                                   (chosen by the autotuner) */
 };
 int mesh_reg_get_info(mr_ctx *ctx, int32_t pair, int32_t key, int64_t *value);
 

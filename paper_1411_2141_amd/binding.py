@@ -19,12 +19,13 @@ MR_FORCE_P1, MR_FORCE_NODAL = 0, 1
 MR_FLAG_HOST_ONLY = 1
 MR_FLAG_GRAPH = 2
 MR_FLAG_NO_TUNE = 4
+MR_FLAG_SEPARATE_ASSEMBLY = 8
 TABLES = {"t1_ptr": 10, "t1_slot": 11, "t2_ptr": 20, "t2_idx": 21, "t3_ptr": 30, "t3_idx": 31,
           "t4": 40, "t5": 50, "t6": 60, "perm": 70}
 INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "bwd_levels": 6,
         "node_offset": 7, "pixel_offset": 8, "n_pairs": 9, "device_bytes": 10,
         "solve_offblock": 11, "solve_dense": 12, "mass_nnz": 13, "apex_rows": 14,
-        "solve_bytes": 15}
+        "solve_bytes": 15, "fused_assembly": 16}
 KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
 EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_warp_msd", "mesh_reg_force",

@@ -205,6 +205,15 @@ int mr_ctx::tune(hipStream_t s) {
     return t_min;
   };
   static const int kCandidates[] = {1, 8, 16, 32, 64, 128, 256, 512, 1024};
+  // The first forward level either assembles the right-hand side itself
+  // (fused) or follows a separate assembly launch; both are candidates unless
+  // the separate launch is requested.
+  const bool separate = (params.flags & MR_FLAG_SEPARATE_ASSEMBLY) != 0;
+  auto first_level = [&](bool fused) -> hipError_t {
+    if (fused) return solve_level(true, 0, d_x.ptr, nullptr, s, &fuse);
+    hipError_t e = assemble(d_x.ptr, nullptr, s);
+    return e == hipSuccess ? solve_level(true, 0, d_x.ptr, nullptr, s, nullptr) : e;
+  };
   // pass 1: every level on its own
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
@@ -212,25 +221,36 @@ int mr_ctx::tune(hipStream_t s) {
     for (size_t lev = 0; lev < choice.size() && rc == MR_OK; ++lev) {
       float best = 1e30f;
       int best_nt = choice[lev];
+      bool best_fused = !separate;
       for (int nt : kCandidates) {
         if (!admissible(fwd, lev, nt)) continue;
         choice[lev] = nt;
-        const float t = time_it([&] {
-          return solve_level(fwd, (int)lev, d_x.ptr, nullptr, s, fwd && lev == 0 ? &fuse : nullptr);
-        });
-        if (t < 0.0f) break;
-        if (t < best) {
-          best = t;
-          best_nt = nt;
+        for (int f = fwd && lev == 0 && separate ? 0 : 1; f >= (fwd && lev == 0 ? 0 : 1); --f) {
+          const float t = time_it([&] {
+            return fwd && lev == 0 ? first_level(f != 0)
+                                   : solve_level(fwd, (int)lev, d_x.ptr, nullptr, s, nullptr);
+          });
+          if (t < 0.0f) break;
+          if (t < best) {
+            best = t;
+            best_nt = nt;
+            best_fused = f != 0;
+          }
         }
+        if (rc != MR_OK) break;
       }
       choice[lev] = best_nt;
+      if (fwd && lev == 0) fuse_first = best_fused;
     }
   }
   // pass 2: one level at a time inside the whole solve (the other levels and
   // the apex evict the caches as in an iteration), keeping a change only when
   // the whole solve gets faster
-  auto whole = [&] { return solve(d_x.ptr, nullptr, s, &fuse); };
+  auto whole = [&]() -> hipError_t {
+    if (fuse_first) return solve(d_x.ptr, nullptr, s, &fuse);
+    hipError_t e = assemble(d_x.ptr, nullptr, s);
+    return e == hipSuccess ? solve(d_x.ptr, nullptr, s, nullptr) : e;
+  };
   float cur = rc == MR_OK ? time_it(whole) : -1.0f;
   for (int dir = 0; dir < 2 && rc == MR_OK; ++dir) {
     const bool fwd = dir == 0;
@@ -239,18 +259,27 @@ int mr_ctx::tune(hipStream_t s) {
     for (size_t lev = 0; lev < choice.size() && rc == MR_OK; ++lev) {
       if (ptr[lev + 1] == ptr[lev] && !(fwd && lev == 0)) continue;
       const int kept = choice[lev];
+      const bool kept_fused = fuse_first;
       int best_nt = kept;
+      bool best_fused = kept_fused;
       for (int nt : kCandidates) {
-        if (nt == kept || !admissible(fwd, lev, nt)) continue;
-        choice[lev] = nt;
-        const float t = time_it(whole);
-        if (t < 0.0f) break;
-        if (t < cur) {
-          cur = t;
-          best_nt = nt;
+        if (!admissible(fwd, lev, nt)) continue;
+        for (int f = fwd && lev == 0 && separate ? 0 : 1; f >= (fwd && lev == 0 ? 0 : 1); --f) {
+          if (nt == kept && (f != 0) == kept_fused) continue;
+          choice[lev] = nt;
+          if (fwd && lev == 0) fuse_first = f != 0;
+          const float t = time_it(whole);
+          if (t < 0.0f) break;
+          if (t < cur) {
+            cur = t;
+            best_nt = nt;
+            best_fused = f != 0;
+          }
         }
+        if (rc != MR_OK) break;
       }
       choice[lev] = best_nt;
+      fuse_first = fwd && lev == 0 ? best_fused : fuse_first;
     }
   }
   hipEventDestroy(a);
@@ -296,7 +325,8 @@ hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, hipStr
                           u,          d_perm.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count,
                           n_pairs,    params.tau,    d_pairs.ptr, d_partials.ptr,
                           msd_now};
-  if (e == hipSuccess) e = solve(d_x.ptr, u, s, &fuse);
+  if (e == hipSuccess && !fuse_first) e = assemble(u, msd_now, s);
+  if (e == hipSuccess) e = solve(d_x.ptr, u, s, fuse_first ? &fuse : nullptr);
   if (e == hipSuccess) *pending = msd_out;
   return e;
 }
@@ -890,6 +920,7 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     delete c;
     return fail(MR_EHIP, std::string("init: ") + hipGetErrorString(e));
   }
+  c->fuse_first = !(params->flags & MR_FLAG_SEPARATE_ASSEMBLY);
   if (params->solve_kernel != 0) {
     c->force_solve_kernel(params->solve_kernel);
   } else if (!(params->flags & MR_FLAG_NO_TUNE) && (rc = c->tune(s)) != MR_OK) {
@@ -1087,6 +1118,10 @@ extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *
   }
   if (key == MR_INFO_DEVICE_BYTES) {
     *value = c->device_bytes();
+    return MR_OK;
+  }
+  if (key == MR_INFO_FUSED_ASSEMBLY) {
+    *value = c->fuse_first ? 1 : 0;
     return MR_OK;
   }
   if (pair < 0 || pair >= c->n_pairs) return fail(MR_EINVAL, "pair out of range");

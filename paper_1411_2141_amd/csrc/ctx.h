@@ -116,6 +116,7 @@ struct mr_ctx {
   hipStream_t graph_stream = nullptr;
 
   bool timing = false;
+  bool fuse_first = true;   // the first forward level assembles b (else a separate launch)
   std::vector<mr::TimedLaunch> pending;
   mr::LaunchTimer timer;
 

@@ -27,7 +27,7 @@ class MeshReg:
     def __init__(self, pairs, tau: float, force_mode: int = B.MR_FORCE_P1,
                  host_only: bool = False, device: str | torch.device = "cuda",
                  apex_rows: int = 0, bwd_split_rows: int = 0, graph: bool = False,
-                 tune: bool = True, solve_kernel: int = 0):
+                 tune: bool = True, solve_kernel: int = 0, separate_assembly: bool = False):
         self.host_only = host_only
         self.device = torch.device(device) if not host_only else torch.device("cpu")
         get = (lambda p, k: p[k]) if isinstance(pairs[0], dict) else (lambda p, k: getattr(p, k))
@@ -48,6 +48,8 @@ class MeshReg:
         flags = B.MR_FLAG_HOST_ONLY if host_only else (B.MR_FLAG_GRAPH if graph else 0)
         if not tune:
             flags |= B.MR_FLAG_NO_TUNE
+        if separate_assembly:
+            flags |= B.MR_FLAG_SEPARATE_ASSEMBLY
         stream = None if host_only else _stream()
         self.ctx = B.mesh_reg_init(specs, tau, force_mode, flags, stream, apex_rows, bwd_split_rows,
                                    solve_kernel)

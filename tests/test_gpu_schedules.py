@@ -120,3 +120,30 @@ def test_invalid_solve_kernel_rejected():
     d = as_dict(make_pair(1))
     with pytest.raises(pkg.binding.MeshRegError):
         pkg.MeshReg([d], tau=0.5, solve_kernel=48)
+
+
+@pytest.mark.parametrize("kernel", [0, 32, 256])
+def test_separate_assembly(batch, kernel):
+    """The force assembly in a launch of its own (MR_FLAG_SEPARATE_ASSEMBLY),
+    autotuned or with a forced level kernel: iterations and the MSD trace
+    match the oracle as in the fused form."""
+    import paper_1411_2141_amd as pkg
+    ds, tau, bs, x_or, u_or = batch
+    say(f"batch of {len(ds)} ragged pairs, separate assembly, solve_kernel={kernel}")
+    ctx = pkg.MeshReg(ds, tau=tau, solve_kernel=kernel, separate_assembly=True)
+    assert ctx.info(0, "fused_assembly") == 0
+    u = ctx.zeros_u()
+    trace = ctx.step(u, 5, record_msd=True).cpu().numpy()
+    ug = u.cpu().numpy()
+    for k, d in enumerate(ds):
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or[k]) < U_TOL, (k, rel(ug[sl], u_or[k]))
+        # the trace holds the MSD of each iterate: against the oracle's MSD of
+        # the same displacements
+        pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau)
+        msd_or = reg.msd(pb, ug[sl])
+        assert abs(trace[4, k] - msd_or) <= 1e-6 * msd_or, (k, trace[4, k], msd_or)
+    ctx.close()
+    fused = pkg.MeshReg(ds, tau=tau, solve_kernel=kernel)
+    assert fused.info(0, "fused_assembly") == 1
+    fused.close()
