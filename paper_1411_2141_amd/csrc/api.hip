@@ -803,9 +803,10 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // Entries of X one level may add to the apex, per pair: moving a level into
 // the apex saves two launches of the whole batch (a fixed latency) and costs
 // streaming its entries of X for every pair, so the budget shrinks with the
-// number of pairs.
+// number of pairs, down to 2^18 (measured on a 256-pair batch: the top levels
+// of the block tree are worth an apex of 1-2 thousand rows per pair).
 static int64_t apex_level_budget(int32_t n_pairs) {
-  return std::max<int64_t>(4096, (int64_t(1) << 21) / std::max(1, n_pairs));
+  return std::max<int64_t>(int64_t(1) << 18, (int64_t(1) << 21) / std::max(1, n_pairs));
 }
 
 extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
