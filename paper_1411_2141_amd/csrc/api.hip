@@ -183,7 +183,7 @@ int mr_ctx::tune(hipStream_t s) {
   int rc = MR_OK;
   // the first forward level runs fused with the force assembly in the
   // iteration, so it is timed that way (on scratch data: u = x)
-  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr, d_perm.ptr,
+  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
                           d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs, params.tau,
                           d_pairs.ptr, d_partials.ptr, nullptr};
   // best of the second and third of three runs, in ms (negative on error)
@@ -211,7 +211,7 @@ int mr_ctx::tune(hipStream_t s) {
   const bool separate = (params.flags & MR_FLAG_SEPARATE_ASSEMBLY) != 0;
   auto first_level = [&](bool fused) -> hipError_t {
     if (fused) return solve_level(true, 0, d_x.ptr, nullptr, s, &fuse);
-    hipError_t e = assemble(d_x.ptr, nullptr, s);
+    hipError_t e = assemble(nullptr, s);
     return e == hipSuccess ? solve_level(true, 0, d_x.ptr, nullptr, s, nullptr) : e;
   };
   // pass 1: every level on its own
@@ -248,7 +248,7 @@ int mr_ctx::tune(hipStream_t s) {
   // the whole solve gets faster
   auto whole = [&]() -> hipError_t {
     if (fuse_first) return solve(d_x.ptr, nullptr, s, &fuse);
-    hipError_t e = assemble(d_x.ptr, nullptr, s);
+    hipError_t e = assemble(nullptr, s);
     return e == hipSuccess ? solve(d_x.ptr, nullptr, s, nullptr) : e;
   };
   float cur = rc == MR_OK ? time_it(whole) : -1.0f;
@@ -287,45 +287,54 @@ int mr_ctx::tune(hipStream_t s) {
   return rc;
 }
 
-// Sample launch at u; with `with_warp` it also writes the warp partials of u.
+// Sample launch at the node displacements in x (solve order; h in solve
+// order); with `with_warp` it also writes the warp partials of u (natural
+// order, the same displacements).
 hipError_t mr_ctx::sample(const double2 *u, bool with_warp, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
-  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr,
-                               d_coef.ptr, d_rho.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
-                               with_warp ? n_tiles : 0, d_tri.ptr, d_tpos.ptr, d_t6.ptr, d_re.ptr,
-                               d_partials.ptr, s);
+  hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, d_x.ptr, d_xy_s.ptr,
+                               d_coef.ptr, d_rho_s.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
+                               with_warp ? n_tiles : 0, u, d_tri.ptr, d_tpos.ptr, d_t6.ptr,
+                               d_re.ptr, d_partials.ptr, s);
   timed_end(s);
   return e;
 }
 
-hipError_t mr_ctx::assemble(const double2 *u, double *finish_msd, hipStream_t s) {
+// Force assembly into x (solve order), in place: u is read from x.
+hipError_t mr_ctx::assemble(double *finish_msd, hipStream_t s) {
   timed_begin(MR_KF_ASSEMBLE, s);
-  hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, u,
-                                 d_perm.ptr, d_x.ptr, params.tau, d_pairs.ptr, n_pairs,
-                                 d_partials.ptr, finish_msd, s);
+  hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
+                                 d_x.ptr, params.tau, d_pairs.ptr, n_pairs, d_partials.ptr,
+                                 finish_msd, s);
   timed_end(s);
   return e;
 }
 
+// h (solve order) and b (solve order, in x) at u (natural order).
 hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
-  hipError_t e = sample(u, false, s);
-  if (e != hipSuccess) return e;
-  return assemble(u, nullptr, s);
+  hipError_t e = launch_to_solve_order((int)n_nodes, u, d_iperm.ptr, d_x.ptr, s);
+  if (e == hipSuccess) e = sample(u, false, s);
+  return e == hipSuccess ? assemble(nullptr, s) : e;
 }
 
-// One iteration u <- S^-1 (u - tau f(u)).  `*pending`, when set, is the MSD
+// One iteration u <- S^-1 (u - tau f(u)).  Sampling and assembly read the
+// displacements in solve order from x, which the previous iteration's
+// backward solve left there; with `x_holds_u` false (the first iteration of
+// a run) u is permuted into x first.  `*pending`, when set, is the MSD
 // output for the current u: its warp shares the sample launch and its final
-// sum the assemble launch.  On return `*pending` is `msd_out` (the MSD of the
-// new u, to be produced by the next iteration or by finish_pending).
-hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, hipStream_t s) {
+// sum the assembly.  On return `*pending` is `msd_out` (the MSD of the new u,
+// to be produced by the next iteration or by finish_pending).
+hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, bool x_holds_u,
+                           hipStream_t s) {
   double *msd_now = *pending;
   *pending = nullptr;
-  hipError_t e = sample(u, msd_now != nullptr, s);
-  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr,    d_mwt.ptr,  d_h.ptr,
-                          u,          d_perm.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count,
-                          n_pairs,    params.tau,    d_pairs.ptr, d_partials.ptr,
-                          msd_now};
-  if (e == hipSuccess && !fuse_first) e = assemble(u, msd_now, s);
+  hipError_t e = hipSuccess;
+  if (!x_holds_u) e = launch_to_solve_order((int)n_nodes, u, d_iperm.ptr, d_x.ptr, s);
+  if (e == hipSuccess) e = sample(u, msd_now != nullptr, s);
+  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr,     d_h.ptr,
+                          d_x.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs,
+                          params.tau, d_pairs.ptr, d_partials.ptr, msd_now};
+  if (e == hipSuccess && !fuse_first) e = assemble(msd_now, s);
   if (e == hipSuccess) e = solve(d_x.ptr, u, s, fuse_first ? &fuse : nullptr);
   if (e == hipSuccess) *pending = msd_out;
   return e;
@@ -466,18 +475,19 @@ int mr_ctx::upload_all(hipStream_t s) {
       iperm[no + i] = no + h.iperm[i];
       perm[no + i] = no + h.perm[i];
     }
-    // force operator rows, in solve order (row k is node perm[k]):
-    // f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j, i.e. the mass row divided by
-    // the lumped mass, with 6 m_i = t5_i
+    // force operator rows and columns in solve order (row k is node perm[k];
+    // h is sampled in solve order): f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j,
+    // i.e. the mass row divided by the lumped mass, with 6 m_i = t5_i; the
+    // columns keep the row order of the natural pattern
     for (int k = 0; k < h.n; ++k) {
       const int i = h.perm[k];
       if (params.force_mode == MR_FORCE_NODAL) {
-        mcol.push_back(no + i);
+        mcol.push_back(no + k);
         mwt.push_back(1.0f);
       } else {
         const double den = 4.0 * (double)h.tab.t5[i];
         for (int64_t q = h.tab.t3_ptr[i]; q < h.tab.t3_ptr[i + 1]; ++q) {
-          mcol.push_back(no + (int32_t)h.tab.t3_idx[q]);
+          mcol.push_back(no + h.iperm[h.tab.t3_idx[q]]);
           mwt.push_back((float)((double)h.mval[q] / den));
         }
       }
@@ -630,6 +640,11 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_node_items, items, s));
   HIP_TRY(upload(d_tiles, tiles, s));
   HIP_TRY(upload(d_xy, xy, s));
+  {
+    std::vector<int2> xy_s(n_nodes);            // node corners in solve order
+    for (int64_t k = 0; k < n_nodes; ++k) xy_s[k] = xy[perm[k]];
+    HIP_TRY(upload(d_xy_s, xy_s, s));
+  }
   HIP_TRY(upload(d_tri, tri, s));
   {
     // triangle corners packed as x | y << 16 (image sides below 65536)
@@ -692,6 +707,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(d_coef.alloc(n_pix));
   HIP_TRY(d_re.alloc(n_pix));
   HIP_TRY(d_rho.alloc(n_nodes));
+  HIP_TRY(d_rho_s.alloc(n_nodes));
   HIP_TRY(d_h.alloc(n_nodes));
   HIP_TRY(d_x.alloc(n_nodes));
   HIP_TRY(d_partials.alloc(std::max(n_tiles, 1)));
@@ -735,7 +751,8 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
 int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
                    d_tri.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
-                   d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_mptr.bytes() +
+                   d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
+                   d_xy_s.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
@@ -910,6 +927,9 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   }
   hipError_t e = launch_sample_rho(c->d_node_items.ptr, c->n_node_items, c->d_pairs.ptr,
                                    c->d_xy.ptr, c->d_re.ptr, c->d_rho.ptr, s);
+  if (e == hipSuccess)                   // the same samples in solve order
+    e = launch_sample_rho(c->d_node_items.ptr, c->n_node_items, c->d_pairs.ptr, c->d_xy_s.ptr,
+                          c->d_re.ptr, c->d_rho_s.ptr, s);
   // the reference pixels themselves replace its coefficients
   for (int p = 0; p < n_pairs && e == hipSuccess; ++p) {
     const DevPair &d = c->dpairs[p];
@@ -937,7 +957,7 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
 int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
   double *pending = nullptr;
   for (int k = 0; k < n_iter; ++k)
-    HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, s));
+    HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, k > 0, s));
   HIP_TRY(finish_pending(u, &pending, s));
   return MR_OK;
 }
@@ -1004,7 +1024,8 @@ extern "C" int mesh_reg_force(mr_ctx *c, const double *u, float *h, double *b, v
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(c->force(reinterpret_cast<const double2 *>(u), s));
-  if (h) HIP_TRY(hipMemcpyAsync(h, c->d_h.ptr, sizeof(float2) * c->n_nodes, hipMemcpyDeviceToDevice, s));
+  if (h) HIP_TRY(launch_h_from_solve_order((int)c->n_nodes, c->d_h.ptr, c->d_iperm.ptr,
+                                           reinterpret_cast<float2 *>(h), s));
   if (b) HIP_TRY(launch_from_solve_order((int)c->n_nodes, c->d_x.ptr, c->d_iperm.ptr,
                                          reinterpret_cast<double2 *>(b), s));
   c->post_flags(s);

@@ -86,12 +86,13 @@ constexpr int kApexMaxRanges = 256;   // ancestor ranges of one apex block (at m
 // workgroups after the block items form b for the other solve rows (`rows`,
 // NT per workgroup), and, when finish_msd is set, the workgroups after those
 // finish the MSD of `partials`.
+// Force assembly inside the first forward solve launch.  Node data in solve
+// order: u and h are indexed by solve row, the operator's columns too.
 struct AssembleArgs {
   const int32_t *mptr, *mcol;
   const float *mwt;
   const float2 *h;
   const double2 *u;
-  const int32_t *perm;          // solve row -> node
   const int32_t *rows;          // solve rows outside the first level
   int32_t n_rows;
   int32_t n_pairs;

@@ -14,16 +14,19 @@ hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp
                             hipStream_t s);
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
-// Sample launch; with n_tiles > 0 it also writes the warp/MSD partials of u.
+// Sample launch (node displacements un with node tables xy, rho and output
+// h, one node order); with n_tiles > 0 it also writes the warp/MSD partials
+// of u (natural order).
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
-                         const double2 *u, const int2 *xy, const float *coef, const float *rho,
+                         const double2 *un, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const int4 *tri, const int4 *tpos, const int32_t *t6, const float *re,
-                         double *partials, hipStream_t s);
-// Assemble launch; with finish_msd it also finishes the MSD of `partials`.
+                         const double2 *u, const int4 *tri, const int4 *tpos, const int32_t *t6,
+                         const float *re, double *partials, hipStream_t s);
+// Assemble launch (solve order; x may be u); with finish_msd it also finishes
+// the MSD of `partials`.
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
-                           const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
-                           double tau, const DevPair *pairs, int n_pairs, const double *partials,
+                           const float2 *h, const double2 *u, double2 *x, double tau,
+                           const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s);
 // One level of the forward / backward block solve; nt = 1 selects the
 // wavefront-per-block kernels with direct global-to-LDS staging (blocks of at
@@ -60,5 +63,7 @@ hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm
                                  hipStream_t s);
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,
                                    hipStream_t s);
+hipError_t launch_h_from_solve_order(int n, const float2 *hs, const int32_t *iperm, float2 *h,
+                                     hipStream_t s);
 
 }  // namespace mr

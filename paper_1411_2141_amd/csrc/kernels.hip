@@ -363,18 +363,22 @@ __device__ __forceinline__ void sample_nodes(const NodeItem (&it)[NT], const Dev
   }
 }
 
-// Node sampling of u (one workgroup per node item).  When `n_tiles` > 0 the
-// workgroups after the node items warp the same u into the MSD partials (one
-// tile each: this launch is short, and a workgroup's latency matters more
-// than overlap), so the MSD of the previous iteration's result shares it.
+// Node sampling (one workgroup per node item) of the node displacements un
+// with the node tables xy, rho and the output h, all in one node order (the
+// iteration uses solve order).  When `n_tiles` > 0 the workgroups after the
+// node items warp the pixel grid by u (natural node order, the same
+// displacements) into the MSD partials (one tile each: this launch is short,
+// and a workgroup's latency matters more than overlap), so the MSD of the
+// previous iteration's result shares it.
 __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ items, int n_items,
                                                 const DevPair *__restrict__ pairs,
-                                                const double2 *__restrict__ u,
+                                                const double2 *__restrict__ un,
                                                 const int2 *__restrict__ xy,
                                                 const float *__restrict__ coef,
                                                 const float *__restrict__ rho,
                                                 float2 *__restrict__ h, unsigned *flags,
                                                 const TileItem *__restrict__ tiles,
+                                                const double2 *__restrict__ u,
                                                 const int4 *__restrict__ tri,
                                                 const int4 *__restrict__ tpos,
                                                 const int32_t *__restrict__ t6,
@@ -388,18 +392,18 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
   const NodeItem it[1] = {items[blockIdx.x]};
   if (it[0].begin + (int)threadIdx.x >= it[0].end) return;
   const DevPair P[1] = {pairs[it[0].pair]};
-  sample_nodes<1>(it, P, u, xy, coef, rho, h, flags);
+  sample_nodes<1>(it, P, un, xy, coef, rho, h, flags);
 }
 
-// b for solve row k (node i): u_i - tau f_i, f_i = sum_q w_q h(col_q) over
-// the force operator row k (FP32 sum in row order), loads issued in batches
-// of U.  Operator rows are stored in solve order.
-__device__ __forceinline__ double2 assemble_b(int k, int i, const int32_t *__restrict__ mptr,
+// b for solve row k: u_k - tau f_k, f_k = sum_q w_q h(col_q) over the force
+// operator row k (FP32 sum in row order), loads issued in batches of U.  Node
+// data in solve order (u, h and the operator's columns).
+__device__ __forceinline__ double2 assemble_b(int k, const int32_t *__restrict__ mptr,
                                               const int32_t *__restrict__ mcol,
                                               const float *__restrict__ mwt,
                                               const float2 *__restrict__ h,
                                               const double2 *__restrict__ u, double tau) {
-  const double2 ui = u[i];
+  const double2 ui = u[k];
   const int q0 = mptr[k], q1 = mptr[k + 1];
   float fx = 0.0f, fy = 0.0f;
   constexpr int U = 8;
@@ -432,19 +436,17 @@ __device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
                                             const int32_t *__restrict__ mcol,
                                             const float *__restrict__ mwt,
                                             const float2 *__restrict__ h,
-                                            const double2 *__restrict__ u,
-                                            const int32_t *__restrict__ perm, double tau,
+                                            const double2 *__restrict__ u, double tau,
                                             double2 out[2]) {
-  int q0[2], q1[2], node[2];
+  int q0[2], q1[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     q0[r] = on[r] ? mptr[k[r]] : 0;
     q1[r] = on[r] ? mptr[k[r] + 1] : 0;
-    node[r] = on[r] ? perm[k[r]] : 0;
   }
   double2 ui[2];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) ui[r] = on[r] ? u[node[r]] : make_double2(0.0, 0.0);
+  for (int r = 0; r < 2; ++r) ui[r] = on[r] ? u[k[r]] : make_double2(0.0, 0.0);
   float fx[2] = {0.0f, 0.0f}, fy[2] = {0.0f, 0.0f};
   constexpr int U = 8;
   const int len = max(q1[0] - q0[0], q1[1] - q0[1]);
@@ -478,16 +480,16 @@ __device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
     out[r] = make_double2(ui[r].x - tau * (double)fx[r], ui[r].y - tau * (double)fy[r]);
 }
 
-// Force assembly (thread per solve row), b written in solve order.  When
-// `finish_msd` is given, the workgroups after the node range finish the MSD of
-// the partials written by the preceding sample launch.
+// Force assembly (a thread per two solve rows), b written in solve order; u
+// and h in solve order too, and x may be u itself (each thread reads its rows
+// of u before writing them).  When `finish_msd` is given, the workgroups after
+// the node range finish the MSD of the partials written by the preceding
+// sample launch.
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
                                                   const int32_t *__restrict__ mcol,
                                                   const float *__restrict__ mwt,
                                                   const float2 *__restrict__ h,
-                                                  const double2 *__restrict__ u,
-                                                  const int32_t *__restrict__ perm,
-                                                  double2 *__restrict__ x, double tau,
+                                                  const double2 *u, double2 *x, double tau,
                                                   const DevPair *__restrict__ pairs, int n_pairs,
                                                   const double *__restrict__ partials,
                                                   double *__restrict__ finish_msd) {
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
   const int k[2] = {k0, k0 + 256};
   const bool on[2] = {true, k0 + 256 < n};
   double2 b[2];
-  assemble_b2(k, on, mptr, mcol, mwt, h, u, perm, tau, b);
+  assemble_b2(k, on, mptr, mcol, mwt, h, u, tau, b);
   x[k0] = b[0];
   if (on[1]) x[k0 + 256] = b[1];
 }
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
       const int k = g * NT + (int)threadIdx.x;
       if (k < A.n_rows) {
         const int row = A.rows[k];
-        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
       }
     } else {
       msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -612,7 +614,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   if (FUSED) {
     if (part == 0 && r < b) {
       const int row = B.r0 + r;
-      t[r] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t[r] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
     }
   } else {
     double ax = 0.0, ay = 0.0;
@@ -893,7 +895,7 @@ __global__ __launch_bounds__(256) void k_wave_fwd(
       if (k < A.n_rows) {
         const int row = A.rows[k];
         // rows outside the first level keep b in x (read by later levels)
-        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
       }
     } else {
       msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -921,7 +923,7 @@ __global__ __launch_bounds__(256) void k_wave_fwd(
   if (lane < b) {
     const int row = B.r0 + lane;
     if (FUSED) {
-      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1061,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_half_fwd(
       const int k = g * 256 + (int)threadIdx.x;
       if (k < A.n_rows) {
         const int row = A.rows[k];
-        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
       }
     } else {
       msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -1097,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_half_fwd(
   if (r < b) {
     const int row = B.r0 + r;
     if (FUSED) {
-      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1272,7 +1274,7 @@ __global__ __launch_bounds__(64) void k_lds_fwd(
       const int k = g * 64 + (int)threadIdx.x;
       if (k < A.n_rows) {
         const int row = A.rows[k];
-        x[row] = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
       }
     } else {
       msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -1293,7 +1295,7 @@ __global__ __launch_bounds__(64) void k_lds_fwd(
   if (lane < b) {
     const int row = B.r0 + lane;
     if (FUSED) {
-      t = assemble_b(row, A.perm[row], A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1611,6 +1613,12 @@ __global__ void k_from_solve_order(int n, const double2 *__restrict__ x,
   if (i < n) dst[i] = x[iperm[i]];
 }
 
+__global__ void k_h_from_solve_order(int n, const float2 *__restrict__ hs,
+                                     const int32_t *__restrict__ iperm, float2 *__restrict__ h) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) h[i] = hs[iperm[i]];
+}
+
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
@@ -1635,21 +1643,21 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
 }
 
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
-                         const double2 *u, const int2 *xy, const float *coef, const float *rho,
+                         const double2 *un, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const int4 *tri, const int4 *tpos, const int32_t *t6, const float *re,
-                         double *partials, hipStream_t s) {
-  return launch(k_sample, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u, xy, coef,
-                rho, h, flags, tiles, tri, tpos, t6, re, partials, n_tiles);
+                         const double2 *u, const int4 *tri, const int4 *tpos, const int32_t *t6,
+                         const float *re, double *partials, hipStream_t s) {
+  return launch(k_sample, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, un, xy,
+                coef, rho, h, flags, tiles, u, tri, tpos, t6, re, partials, n_tiles);
 }
 
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
-                           const float2 *h, const double2 *u, const int32_t *perm, double2 *x,
-                           double tau, const DevPair *pairs, int n_pairs, const double *partials,
+                           const float2 *h, const double2 *u, double2 *x, double tau,
+                           const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, hipStream_t s) {
   const int groups = (n + 511) / 512 + (finish_msd ? (n_pairs + 3) / 4 : 0);
-  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, perm, x, tau, pairs,
-                n_pairs, partials, finish_msd);
+  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, x, tau, pairs, n_pairs,
+                partials, finish_msd);
 }
 
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
@@ -1780,6 +1788,11 @@ hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,
                                    hipStream_t s) {
   return launch(k_from_solve_order, (n + 255) / 256, 256, 0, s, n, x, iperm, dst);
+}
+
+hipError_t launch_h_from_solve_order(int n, const float2 *hs, const int32_t *iperm, float2 *h,
+                                     hipStream_t s) {
+  return launch(k_h_from_solve_order, (n + 255) / 256, 256, 0, s, n, hs, iperm, h);
 }
 
 }  // namespace mr
