@@ -286,7 +286,7 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   if (n_seg > 0) HIP_OK(hipMemcpyAsync(w, u0, nb, hipMemcpyDeviceToDevice, s));
   double *pending = nullptr;
   for (int k = 0; k < n_iter; ++k) {
-    HIP_OK(iterate(w, nullptr, &pending, k > 0, s));
+    HIP_OK(iterate(w, nullptr, &pending, k > 0, true, s));
     if ((k + 1) % ckpt_every == 0 && (k + 1) < n_iter)
       HIP_OK(hipMemcpyAsync(ckpt((k + 1) / ckpt_every), w, nb, hipMemcpyDeviceToDevice, s));
   }
@@ -315,7 +315,7 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
       HIP_OK(hipMemcpyAsync(dst, iterate_at(k), nb, hipMemcpyDeviceToDevice, s));
       // x still holds u^k from the previous recomputed iteration, except at
       // the segment's start (a checkpoint)
-      HIP_OK(iterate(dst, nullptr, &pending, k > k0, s));
+      HIP_OK(iterate(dst, nullptr, &pending, k > k0, true, s));
     }
     for (int k = k1 - 1; k >= k0; --k) {
       // mu = S^-1 lambda^{k+1} (right-hand side in solve order, consumed in place)

@@ -288,13 +288,13 @@ int mr_ctx::tune(hipStream_t s) {
 }
 
 // Sample launch at the node displacements in x (solve order; h in solve
-// order); with `with_warp` it also writes the warp partials of u (natural
-// order, the same displacements).
-hipError_t mr_ctx::sample(const double2 *u, bool with_warp, hipStream_t s) {
+// order); with `with_warp` it also writes the warp partials of the same
+// displacements (triangle corners in solve order).
+hipError_t mr_ctx::sample(bool with_warp, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
   hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, d_x.ptr, d_xy_s.ptr,
                                d_coef.ptr, d_rho_s.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
-                               with_warp ? n_tiles : 0, u, d_tri.ptr, d_tpos.ptr, d_t6.ptr,
+                               with_warp ? n_tiles : 0, d_x.ptr, d_tri_s.ptr, d_tpos.ptr, d_t6.ptr,
                                d_re.ptr, d_partials.ptr, s);
   timed_end(s);
   return e;
@@ -313,29 +313,31 @@ hipError_t mr_ctx::assemble(double *finish_msd, hipStream_t s) {
 // h (solve order) and b (solve order, in x) at u (natural order).
 hipError_t mr_ctx::force(const double2 *u, hipStream_t s) {
   hipError_t e = launch_to_solve_order((int)n_nodes, u, d_iperm.ptr, d_x.ptr, s);
-  if (e == hipSuccess) e = sample(u, false, s);
+  if (e == hipSuccess) e = sample(false, s);
   return e == hipSuccess ? assemble(nullptr, s) : e;
 }
 
-// One iteration u <- S^-1 (u - tau f(u)).  Sampling and assembly read the
-// displacements in solve order from x, which the previous iteration's
-// backward solve left there; with `x_holds_u` false (the first iteration of
-// a run) u is permuted into x first.  `*pending`, when set, is the MSD
-// output for the current u: its warp shares the sample launch and its final
-// sum the assembly.  On return `*pending` is `msd_out` (the MSD of the new u,
-// to be produced by the next iteration or by finish_pending).
+// One iteration u <- S^-1 (u - tau f(u)).  Sampling, assembly and the warp
+// read the displacements in solve order from x, which the previous
+// iteration's backward solve left there; with `x_holds_u` false (the first
+// iteration of a run) u is permuted into x first.  The new displacements go to
+// x and, with `write_u`, also to u (natural order).  `*pending`, when set, is
+// the MSD output for the current displacements: its warp shares the sample
+// launch and its final sum the assembly.  On return `*pending` is `msd_out`
+// (the MSD of the new u, to be produced by the next iteration or by
+// finish_pending, which needs u written).
 hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, bool x_holds_u,
-                           hipStream_t s) {
+                           bool write_u, hipStream_t s) {
   double *msd_now = *pending;
   *pending = nullptr;
   hipError_t e = hipSuccess;
   if (!x_holds_u) e = launch_to_solve_order((int)n_nodes, u, d_iperm.ptr, d_x.ptr, s);
-  if (e == hipSuccess) e = sample(u, msd_now != nullptr, s);
+  if (e == hipSuccess) e = sample(msd_now != nullptr, s);
   const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr,     d_h.ptr,
                           d_x.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs,
                           params.tau, d_pairs.ptr, d_partials.ptr, msd_now};
   if (e == hipSuccess && !fuse_first) e = assemble(msd_now, s);
-  if (e == hipSuccess) e = solve(d_x.ptr, u, s, fuse_first ? &fuse : nullptr);
+  if (e == hipSuccess) e = solve(d_x.ptr, write_u ? u : nullptr, s, fuse_first ? &fuse : nullptr);
   if (e == hipSuccess) *pending = msd_out;
   return e;
 }
@@ -647,6 +649,12 @@ int mr_ctx::upload_all(hipStream_t s) {
   }
   HIP_TRY(upload(d_tri, tri, s));
   {
+    std::vector<int4> tri_s(tri.size());        // triangle corners in solve order
+    for (size_t t = 0; t < tri.size(); ++t)
+      tri_s[t] = make_int4(iperm[tri[t].x], iperm[tri[t].y], iperm[tri[t].z], 0);
+    HIP_TRY(upload(d_tri_s, tri_s, s));
+  }
+  {
     // triangle corners packed as x | y << 16 (image sides below 65536)
     std::vector<int4> tpos(tri.size());
     for (size_t t = 0; t < tri.size(); ++t) {
@@ -750,7 +758,7 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
 
 int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
-                   d_tri.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
+                   d_tri.bytes() + d_tri_s.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
                    d_xy_s.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
@@ -957,7 +965,8 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
 int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
   double *pending = nullptr;
   for (int k = 0; k < n_iter; ++k)
-    HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, k > 0, s));
+    HIP_TRY(iterate(u, msd_trace ? msd_trace + (size_t)k * n_pairs : nullptr, &pending, k > 0,
+                    k + 1 == n_iter, s));
   HIP_TRY(finish_pending(u, &pending, s));
   return MR_OK;
 }

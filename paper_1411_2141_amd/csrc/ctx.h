@@ -56,7 +56,7 @@ struct mr_ctx {
   mr::DevArray<mr::NodeItem> d_node_items;
   mr::DevArray<mr::TileItem> d_tiles;
   mr::DevArray<int2> d_xy, d_xy_s;             // node corners, natural and solve order
-  mr::DevArray<int4> d_tri;
+  mr::DevArray<int4> d_tri, d_tri_s;           // triangle corners, natural and solve order
   mr::DevArray<int4> d_tpos;                    // triangle corners, x | y << 16
   mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
   mr::DevArray<float> d_coef, d_re, d_rho, d_rho_s;   // rho natural and solve order
@@ -129,12 +129,12 @@ struct mr_ctx {
   int prefilter_pair(int p, const float *img, float *coef_out, hipStream_t s);
   int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
   int upload_adjoint_operators(hipStream_t s);
-  hipError_t sample(const double2 *u, bool with_warp, hipStream_t s);
+  hipError_t sample(bool with_warp, hipStream_t s);
   hipError_t assemble(double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
   hipError_t solve(double2 *x, double2 *out, hipStream_t s, const mr::AssembleArgs *fuse);
   hipError_t iterate(double2 *u, double *msd_out, double **pending, bool x_holds_u,
-                     hipStream_t s);
+                     bool write_u, hipStream_t s);
   hipError_t finish_pending(const double2 *u, double **pending, hipStream_t s);
   hipError_t warp(const double2 *u, double *msd, float *warped, hipStream_t s);
   int check_flags();
