@@ -870,7 +870,13 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
   c->host_only = host_only;
   c->host.resize(n_pairs);
   OrderOptions opt;
-  opt.apex_max = params->apex_rows > 0 ? params->apex_rows : params->apex_rows < 0 ? 0 : 1 << 30;
+  // automatic apex: at most 1024 rows per pair in a batch (measured on a
+  // 256-pair batch; a single pair leaves the GPU idle on small levels, so
+  // there only the per-level entry budget limits it)
+  opt.apex_max = params->apex_rows > 0 ? params->apex_rows
+                 : params->apex_rows < 0 ? 0
+                 : n_pairs > 1           ? 1024
+                                         : 1 << 30;
   opt.apex_level_entries = params->apex_rows > 0 ? (int64_t(1) << 40) : apex_level_budget(n_pairs);
   // splitting a backward panel over workgroups costs a device-scope fence per
   // workgroup; it only pays when a single pair leaves most of the GPU idle
