@@ -89,7 +89,7 @@ def unit_bytes(ctx, pairs) -> dict:
         taps += int(np.unique(np.concatenate(idx)).size)
     return {
         "sample": 36 * n + 4 * taps,
-        "assemble": 48 * n + 8 * nnz_m,
+        "assemble": 44 * n + 8 * nnz_m,
         "solve": solve,
         "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
         "finish": 8 * tiles + 8 * len(pairs),
