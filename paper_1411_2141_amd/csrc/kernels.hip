@@ -509,27 +509,6 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
   if (on[1]) x[k0 + 256] = b[1];
 }
 
-// Copies n doubles from global memory to LDS with all of a thread's loads of
-// a batch in flight before the first LDS store (predicated, no serial tail).
-template <int NT>
-__device__ __forceinline__ void stage_to_lds(double *__restrict__ dst, const double *__restrict__ src,
-                                             int n) {
-  constexpr int U = 16;
-  for (int e0 = threadIdx.x; e0 < n; e0 += U * NT) {
-    double v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * NT;
-      v[u] = e < n ? src[e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * NT;
-      if (e < n) dst[e] = v[u];
-    }
-  }
-}
-
 // Smallest power of two >= b (b <= kBlockMax).
 __device__ __forceinline__ int pow2_at_least(int b) {
   int p = 1;
@@ -832,8 +811,8 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront-per-block level kernels: one wavefront solves one block (lane r
-// holds rows r and r + 64), reading the dense inverse and the panel straight
+// Wavefront-per-block level kernels: one wavefront solves one block of at
+// most 64 rows (lane r holds row r), reading the dense inverse and the panel straight
 // from global memory in coalesced order (each entry is used once, so nothing
 // is staged in LDS) and broadcasting the vector entries across lanes.  Four
 // independent wavefronts per workgroup, no barriers.

@@ -32,9 +32,10 @@ __device__ __forceinline__ void bs_weights(float t, float w[4]) {
   w[3] = t3 * (1.0f / 6.0f);
 }
 
-// FP64 weights for the pixel warp: the MSD is a mean of squared differences
-// of nearly equal numbers, so a systematic FP32 weight rounding (at t = 0 the
-// FP32 weights sum to 1 + 3e-8 per axis) would bias it by ~1e-6 relative.
+// FP64 weights (the warp and the adjoint kernels): the MSD is a mean of
+// squared differences of nearly equal numbers, so a systematic FP32 weight
+// rounding (at t = 0 the FP32 weights sum to 1 + 3e-8 per axis) would bias it
+// by ~1e-6 relative.
 __device__ __forceinline__ void bs_weights_d(double t, double w[4]) {
   const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
   w[0] = s * s * s * (1.0 / 6.0);
@@ -152,23 +153,6 @@ __device__ __forceinline__ float spline_value(const float *__restrict__ c, int H
   return v;
 }
 
-// Value with FP32 coefficients, FP64 weights and FP64 accumulation.
-__device__ __forceinline__ double spline_value_d(const float *__restrict__ c, int H, int W,
-                                                 int cx, double fx, int cy, double fy) {
-  double wx[4], wy[4];
-  bs_weights_d(fx, wx);
-  bs_weights_d(fy, wy);
-  float t[4][4];
-  load_taps(c, H, W, cx, cy, t);
-  double v = 0.0;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const double rv = (double)t[m][0] * wx[0] + (double)t[m][1] * wx[1] +
-                      (double)t[m][2] * wx[2] + (double)t[m][3] * wx[3];
-    v += wy[m] * rv;
-  }
-  return v;
-}
 
 // Value and gradient from the 16 taps t (as load_taps gives them).
 __device__ __forceinline__ void spline_value_grad_taps(const float (&t)[4][4], float fx, float fy,
@@ -190,13 +174,6 @@ __device__ __forceinline__ void spline_value_grad_taps(const float (&t)[4][4], f
   }
 }
 
-__device__ __forceinline__ void spline_value_grad(const float *__restrict__ c, int H, int W,
-                                                  int cx, float fx, int cy, float fy, float &val,
-                                                  float &gx, float &gy) {
-  float t[4][4];
-  load_taps(c, H, W, cx, cy, t);
-  spline_value_grad_taps(t, fx, fy, val, gx, gy);
-}
 
 // ---------------------------------------------------------------------------
 // Reductions
