@@ -15,7 +15,9 @@ Extra legs in the same JSON line (same numerator, nodes x iterations):
   large_pair -- one 2048x2048 pair (559k nodes), 50 iterations: plain against
                 forward + reverse pass (checkpoint 10);
   diff_batch -- 64 pairs of 512x512 with per-pair alpha, 100 iterations: plain
-                against forward + reverse pass (checkpoint 10).
+                against forward + reverse pass (checkpoint 10);
+  unstructured -- the 512x512 pair on an unstructured (jittered Delaunay)
+                mesh, 200 iterations with the MSD every iteration.
 Each leg reports its dominant kernel family's roofline (algorithmic bytes per
 launch over the HIP-event launch time).  The FP64 oracle is timed on a
 bounded sample on one host core (``cpu_baseline``).
@@ -94,6 +96,13 @@ def unit_bytes(ctx, pairs) -> dict:
         "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
         "finish": 8 * tiles + 8 * len(pairs),
     }
+
+
+def _as_pair(d: dict):
+    """A mesh + images dict as the attribute view unit_bytes reads."""
+    from types import SimpleNamespace
+    return SimpleNamespace(V=d["V"], T=d["T"], n_nodes=int(d["V"].shape[0]),
+                           height=int(d["te"].shape[0]), width=int(d["te"].shape[1]))
 
 
 def run_bytes(ub: dict, iters: int, trace: bool, fused: bool = True) -> dict:
@@ -248,6 +257,8 @@ def main() -> int:
     ap.add_argument("--diff-batch-pairs", type=int, default=64,
                     help="pairs of the differentiable 512x512 batch leg (0 skips it)")
     ap.add_argument("--diff-batch-iters", type=int, default=100)
+    ap.add_argument("--unstructured-iters", type=int, default=200,
+                    help="0 skips the unstructured-mesh leg")
     ap.add_argument("--gen-procs", type=int, default=0,
                     help="processes generating the batched inputs (0: up to 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -273,6 +284,11 @@ def main() -> int:
     procs = args.gen_procs or min(16, len(os.sched_getaffinity(0)))
     batch = make_pairs(4, args.batched_pairs, processes=procs) if args.batched_pairs else []
     large = make_pair(3) if args.large_iters else None
+    upair = None
+    if args.unstructured_iters:
+        from synth import unstructured_mesh
+        Vu, Tu = unstructured_mesh(pair.te, 1, 32, 0.08, seed=2000)
+        upair = dict(te=pair.te, re=pair.re, V=Vu, T=Tu, alpha=pair.alpha)
     dbatch = make_pairs(5, args.diff_batch_pairs, processes=procs) if args.diff_batch_pairs else []
 
     import torch
@@ -393,6 +409,38 @@ def main() -> int:
                               f"{len(dbatch)} pairs 512x512 12-bit, per-pair alpha log-uniform "
                               f"in [0.02, 0.2]")
 
+    unstructured = None
+    if upair is not None:
+        KU = args.unstructured_iters
+        nu = int(upair["V"].shape[0])
+        with torch.cuda.stream(side):
+            uctx = pkg.MeshReg([upair], tau=tau, graph=True)
+            uu = uctx.zeros_u()
+            utrace = torch.empty((KU, 1), dtype=torch.float64, device="cuda")
+            B.mesh_reg_step(uctx.ctx, uu, KU, utrace, side.cuda_stream)  # capture
+            side.synchronize()
+            uu.zero_()
+            side.synchronize()
+            t0 = time.perf_counter()
+            B.mesh_reg_step(uctx.ctx, uu, KU, utrace, side.cuda_stream)
+            side.synchronize()
+            dtu = time.perf_counter() - t0
+            uroof = None
+            if not args.no_profile:
+                uu.zero_()
+                _, uroof = profile(uctx, lambda: B.mesh_reg_step(uctx.ctx, uu, KU, utrace,
+                                                                 side.cuda_stream),
+                                   run_bytes(unit_bytes(uctx, [_as_pair(upair)]), KU, True,
+                                             uctx.info(0, "fused_assembly") == 1), "unstructured")
+            unstructured = {
+                "workload": "the 512x512 pair on an unstructured mesh (quadtree s=1..32 g=0.08 "
+                            "corners, jittered, Delaunay), warp+MSD every iteration",
+                "nodes": nu, "triangles": int(upair["T"].shape[0]), "iterations": KU,
+                "ms_per_iteration": round(dtu / KU * 1e3, 4),
+                "node_updates_per_s": round(nu * KU / dtu, 1),
+                "final_msd": float(utrace[KU - 1, 0].item()), "roofline": uroof}
+            uctx.close()
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
 
     out = {
@@ -407,7 +455,7 @@ def main() -> int:
                    "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
         "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd, "batched": batched, "large_pair": large_leg,
-        "diff_batch": dbatch_leg,
+        "diff_batch": dbatch_leg, "unstructured": unstructured,
     }
     print(json.dumps(out))
     return 0

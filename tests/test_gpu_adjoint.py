@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import adjoint as oadj, registration as reg
 from synth import make_pair, uniform_mesh
-from tests._problems import small_pair
+from tests._problems import small_pair, unstructured_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -56,12 +56,14 @@ def cases():
         "c1_128": dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=0.1),
         "adaptive_48": dict(te=te, re=re_, V=V, T=T, alpha=0.3),
         "ragged_40x24": dict(te=te2[:24, :40].copy(), re=re2[:24, :40].copy(), V=Vu, T=Tu, alpha=0.2),
+        "unstructured_48": dict(zip(("te", "re", "V", "T"), unstructured_pair(seed=8, side=48)),
+                                alpha=0.2),
     }
 
 
 @pytest.mark.parametrize("case,n_iter,ckpt,force_mode", [
     ("c1_128", 6, 4, 0), ("adaptive_48", 5, 2, 0), ("ragged_40x24", 4, 1, 0), ("adaptive_48", 3, 3, 1),
-    ("c1_128", 3, 10, 0), ("adaptive_48", 0, 10, 0),
+    ("c1_128", 3, 10, 0), ("adaptive_48", 0, 10, 0), ("unstructured_48", 4, 2, 0),
 ])
 def test_gradient_matches_oracle(case, n_iter, ckpt, force_mode):
     say(f"adjoint parity {case} N={n_iter} ckpt={ckpt} mode={force_mode}")

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import registration as reg
 from synth import make_pair, uniform_mesh
-from tests._problems import small_pair, translation_pair
+from tests._problems import small_pair, translation_pair, unstructured_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,8 @@ CASES = {
     "one_leaf_4": lambda: (lambda V, T: dict(
         te=np.arange(16, dtype=np.float32).reshape(4, 4) / 16, re=np.ones((4, 4), np.float32) * 0.3,
         V=V, T=T, alpha=0.5))(*uniform_mesh(4, 4, 4)[:2]),
+    "unstructured_64": lambda: dict(zip(("te", "re", "V", "T"), unstructured_pair(seed=7, side=64)),
+                                    alpha=0.1),
 }
 
 
@@ -223,6 +225,34 @@ def test_batched_pairs_match_single_pair_oracle():
         u_or, msds, _ = reg.run(pb, None, 8, record_msd=True)
         assert rel(ug[ctx.node_offsets[k]:ctx.node_offsets[k + 1]], u_or) < U_TOL, k
         assert abs(trace[-1, k].item() - msds[-1]) <= 1e-4 * msds[-1]
+    ctx.close()
+
+
+def test_unstructured_meshes_run_and_batch_with_quadtrees():
+    """General triangulations through the same ABI: 30 iterations with the
+    MSD every iteration on an unstructured pair, and a batch mixing it with
+    quadtree pairs, against the oracle."""
+    say("unstructured 64x64 pair, 30 iterations; batch with two quadtree pairs")
+    tau = 0.5
+    d = CASES["unstructured_64"]()
+    err, m_gpu, m_or, trace1, msd_or = _run_parity(d, tau, 30, check_trace_every=10)
+    assert err < U_TOL, err
+    assert abs(m_gpu - m_or) <= MSD_TOL * m_or
+    for k, m in msd_or:
+        assert abs(trace1[k] - m) <= 1e-4 * m
+    ds = [CASES["adaptive_48"](), d, as_dict(make_pair(1))]
+    ctx = gpu_ctx(ds, tau)
+    u = ctx.zeros_u()
+    trace = ctx.step(u, 6, record_msd=True)
+    torch.cuda.synchronize()
+    ug = u.cpu().numpy()
+    for k, dk in enumerate(ds):
+        pb = oracle_problem(dk, tau)
+        u_or, msds, _ = reg.run(pb, None, 6, record_msd=True)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or) < U_TOL, (k, rel(ug[sl], u_or))
+        m_or = reg.msd(pb, ug[sl])
+        assert abs(trace[-1, k].item() - m_or) <= MSD_TOL * m_or
     ctx.close()
 
 

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import mesh as omesh
 from synth import make_pair, uniform_mesh
-from tests._problems import small_pair
+from tests._problems import small_pair, unstructured_pair
 
 import paper_1411_2141_amd as pkg
 from paper_1411_2141_amd import binding as B
@@ -46,10 +46,12 @@ def _pairs_for_tables():
     V, T, _ = uniform_mesh(24, 40, 4)     # ragged, non-square
     out.append(dict(te=np.zeros((24, 40), np.float32), re=np.zeros((24, 40), np.float32),
                     V=V, T=T, alpha=0.3))
+    te, re_, V, T = unstructured_pair(seed=9, side=48)     # general triangulation
+    out.append(dict(te=te, re=re_, V=V, T=T, alpha=0.15))
     return out
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_tables_bit_exact_with_oracle(k):
     pair = _pairs_for_tables()[k]
     H, W = pair["te"].shape
@@ -70,7 +72,7 @@ def test_tables_bit_exact_with_oracle(k):
 def test_batched_tables_per_pair():
     pairs = _pairs_for_tables()
     ctx = host_ctx(pairs)
-    assert ctx.info(0, "n_pairs") == 3
+    assert ctx.info(0, "n_pairs") == 4
     for k, pair in enumerate(pairs):
         H, W = pair["te"].shape
         want = omesh.tables(pair["V"], pair["T"], H, W)

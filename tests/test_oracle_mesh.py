@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import mesh
-from synth import quadtree_mesh, uniform_mesh
+from synth import quadtree_mesh, uniform_mesh, unstructured_mesh
 from synth.images import draw_params, make_images
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -178,3 +178,45 @@ def test_validate_rejects_bad_meshes():
         mesh.validate(V, bad, 4, 4)
     with pytest.raises(ValueError):
         mesh.validate(np.vstack([V, [[1, 1]]]), T, 4, 4)   # unreferenced node
+
+
+def test_unstructured_mesh_operators_and_coverage():
+    """General triangulations (irregular valence, edges in all directions):
+    K symmetric with zero row sums and exact energy on linear fields, the
+    mass sums to the image area, T6 covers every pixel and matches the
+    brute-force lowest-id rule, including centres on shared edges."""
+    rng = np.random.default_rng(4)
+    te, _ = make_images(draw_params(rng, 40, 40, 3.0, n_blobs=5))
+    V, T = unstructured_mesh(te, 1, 8, 0.05, seed=4)
+    tb = mesh.tables(V, T, 40, 40)
+    val = np.diff(tb["t2_ptr"])
+    assert val.min() < 4 < val.max()                   # not a quadtree valence pattern
+    P = V[T].astype(np.int64)
+    d = P[:, 1] - P[:, 0]
+    assert np.any((d[:, 0] != 0) & (d[:, 1] != 0) & (np.abs(d[:, 0]) != np.abs(d[:, 1])))
+    K = mesh.stiffness(V, T)
+    Kd = K.toarray()
+    assert np.abs(Kd - Kd.T).max() <= 1e-14 * np.abs(Kd).max()
+    assert np.abs(Kd.sum(1)).max() <= 1e-12 * np.abs(Kd).max()
+    for a in ([1.0, 0.0], [0.3, -0.7]):
+        u = V[:, 0] * a[0] + V[:, 1] * a[1]
+        assert u @ (K @ u) == pytest.approx((a[0] ** 2 + a[1] ** 2) * 40 * 40, rel=1e-12)
+    M = mesh.mass(V, T)
+    one = np.ones(V.shape[0])
+    assert one @ (M @ one) == pytest.approx(40 * 40, rel=1e-14)
+    t6 = tb["t6"]
+    assert t6.min() >= 0
+    V2 = 2 * V.astype(np.int64)
+    ties = 0
+    for i in range(0, 40, 3):
+        for j in range(40):
+            p = np.array([2 * j + 1, 2 * i + 1])
+            hits = []
+            for t in range(T.shape[0]):
+                Q = V2[T[t]]
+                if all((Q[(k + 1) % 3][0] - Q[k][0]) * (p[1] - Q[k][1])
+                       - (Q[(k + 1) % 3][1] - Q[k][1]) * (p[0] - Q[k][0]) >= 0 for k in range(3)):
+                    hits.append(t)
+            assert t6[i, j] == hits[0]
+            ties += len(hits) > 1
+    assert ties > 0                                     # shared-edge centres were exercised
