@@ -141,6 +141,21 @@ int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params
  * MR_ENONFINITE (reported by the call after the one that met it). */
 int mesh_reg_step(mr_ctx *ctx, double *u, int32_t n_iter, double *msd_trace, void *stream);
 
+/* Algorithm 1's loop run to convergence (the paper gives no criterion; this is a
+ * relative-MSD rule), pair by pair: after every check_every (>= 1) iterations each
+ * pair still running compares its MSD m_now with m_prev, the MSD check_every
+ * iterations earlier (MSD(u0) at first), and retires when m_prev <= 0 or
+ * m_prev - m_now < rel_tol * m_prev (an increase retires too), or when max_iter
+ * (>= 0) iterations are done.  A retired pair's work items skip every later
+ * launch, so its u stays as it was at its retirement while the others go on.
+ * u: DEVICE [sum n][2] FP64, in/out.  iters_out: HOST [n_pairs], the iterations
+ * each pair ran (a multiple of check_every, or max_iter).  msd_out: DEVICE
+ * [n_pairs] FP64, each pair's MSD at its final u.  rel_tol: finite, >= 0.
+ * Synchronises `stream` after every chunk (the decision is taken on the host);
+ * every pair is active again on return.  Errors as mesh_reg_step. */
+int mesh_reg_run(mr_ctx *ctx, double *u, int32_t max_iter, int32_t check_every, double rel_tol,
+                 int32_t *iters_out, double *msd_out, void *stream);
+
 /* Warp and MSD (Section 1; Fig. 3): every pixel takes the piecewise-linear
  * displacement of its triangle (T6), the template spline is sampled at the
  * displaced pixel centre and msd[p] = mean over pixels of (W - Re)^2 (FP64,

@@ -12,7 +12,8 @@ Modules:
   interpolation of both images at the nodes).
 * ``mesh``         -- tables T1-T6 (Algorithm 1 pre-computation), P1 element
   gradients (eq. 9), stiffness, mass and lumped mass (eq. 10, Section 2.3).
-* ``registration`` -- the iteration (eq. 3-8, Algorithm 1), warp and MSD.
+* ``registration`` -- the iteration (eq. 3-8, Algorithm 1), warp and MSD, and
+  the loop to convergence (a relative-MSD stopping rule).
 * ``adjoint``      -- reverse-mode gradient of the final MSD.
 
 Pins (see ``tests/test_oracle_*.py``): spline interpolation and quadratic

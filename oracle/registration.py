@@ -180,3 +180,33 @@ def run(pb: Problem, u0: np.ndarray | None, n_iter: int, record_msd: bool = Fals
         if keep_all:
             us.append(u.copy())
     return u, msds, us
+
+
+def run_until(pb: Problem, u0: np.ndarray | None, max_iter: int, check_every: int,
+              rel_tol: float):
+    """Algorithm 1's loop "to convergence" with a relative-MSD stopping rule.
+
+    The paper leaves the criterion open; this reading checks every
+    ``check_every`` iterations: with ``m_prev`` the MSD ``check_every``
+    iterations earlier (``MSD(u0)`` at first) and ``m_now`` the current one,
+    the loop stops when ``m_prev <= 0`` or ``m_prev - m_now < rel_tol m_prev``
+    (an increase stops it too), and after ``max_iter`` iterations at most (the
+    last chunk may be shorter).  Returns ``(u, iters, m_final, checks)`` with
+    ``checks`` the MSDs compared, ``MSD(u0)`` first.
+    """
+    u = np.zeros((pb.V.shape[0], 2)) if u0 is None else np.array(u0, dtype=np.float64)
+    m_prev = msd(pb, u)
+    checks = [m_prev]
+    done = 0
+    while done < max_iter:
+        n = min(check_every, max_iter - done)
+        for _ in range(n):
+            u = step(pb, u)
+        done += n
+        m_now = msd(pb, u)
+        checks.append(m_now)
+        stop = not (m_prev > 0.0) or (m_prev - m_now) < rel_tol * m_prev
+        m_prev = m_now
+        if stop:
+            break
+    return u, done, m_prev, checks

@@ -185,7 +185,7 @@ int mr_ctx::tune(hipStream_t s) {
   // iteration, so it is timed that way (on scratch data: u = x)
   const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
                           d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs, params.tau,
-                          d_pairs.ptr, d_partials.ptr, nullptr};
+                          d_pairs.ptr, d_partials.ptr, nullptr, d_active.ptr};
   // best of the second and third of three runs, in ms (negative on error)
   auto time_it = [&](auto &&run) -> float {
     float t_min = 1e30f;
@@ -305,7 +305,7 @@ hipError_t mr_ctx::assemble(double *finish_msd, hipStream_t s) {
   timed_begin(MR_KF_ASSEMBLE, s);
   hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
                                  d_x.ptr, params.tau, d_pairs.ptr, n_pairs, d_partials.ptr,
-                                 finish_msd, s);
+                                 finish_msd, d_active.ptr, s);
   timed_end(s);
   return e;
 }
@@ -335,7 +335,7 @@ hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, bool x
   if (e == hipSuccess) e = sample(msd_now != nullptr, s);
   const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr,     d_h.ptr,
                           d_x.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs,
-                          params.tau, d_pairs.ptr, d_partials.ptr, msd_now};
+                          params.tau, d_pairs.ptr, d_partials.ptr, msd_now, d_active.ptr};
   if (e == hipSuccess && !fuse_first) e = assemble(msd_now, s);
   if (e == hipSuccess) e = solve(d_x.ptr, write_u ? u : nullptr, s, fuse_first ? &fuse : nullptr);
   if (e == hipSuccess) *pending = msd_out;
@@ -416,12 +416,12 @@ int mr_ctx::upload_all(hipStream_t s) {
     d.tiles_x = (h.width + kTile - 1) / kTile;
     const int ty = (h.height + kTile - 1) / kTile;
     d.n_tiles = d.tiles_x * ty;
-    d.pad0 = 0;
+    d.active = 1;
     for (int y = 0; y < ty; ++y)
-      for (int x = 0; x < d.tiles_x; ++x) tiles.push_back({p, y * kTile, x * kTile, 0});
+      for (int x = 0; x < d.tiles_x; ++x) tiles.push_back({p, y * kTile, x * kTile, 1});
     d.item_off = (int32_t)items.size();
     for (int b = 0; b < h.n; b += kNodeChunk)
-      items.push_back({p, d.node_off + b, d.node_off + std::min(h.n, b + kNodeChunk), 0});
+      items.push_back({p, d.node_off + b, d.node_off + std::min(h.n, b + kNodeChunk), 1});
     d.n_items = (int32_t)items.size() - d.item_off;
     n_nodes += h.n;
     n_tris += h.nt;
@@ -438,6 +438,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int32_t> mptr(n_nodes + 1, 0), mcol;
   std::vector<float> mwt;
   std::vector<DevBlock> blocks;
+  std::vector<int32_t> block_pair;              // pair of each block
   std::vector<int64_t> cptr(n_nodes + 1, 0);
   std::vector<int32_t> cidx, below;
   std::vector<double> dcol, drow, prow;
@@ -514,7 +515,8 @@ int mr_ctx::upload_all(hipStream_t s) {
       const int32_t ns = std::max<int32_t>(1, (m + rs - 1) / rs);
       const int32_t bs = std::max<int32_t>(1, (m + bwd_split_rows - 1) / bwd_split_rows);
       DevBlock db{no + B.r0, no + B.r1, m, B.fwd_group, doff + pl.dense_off[k],
-                  poff + pl.panel_off[k], uoff + pl.below_ptr[k], ns, rs, bs, 0, 0, 0};
+                  poff + pl.panel_off[k], uoff + pl.below_ptr[k], ns, rs, bs, 0, 0, 1};
+      block_pair.push_back(p);
       if (bs > 1) {
         db.part_off = n_partials;
         db.cnt_idx = n_counters++;
@@ -584,7 +586,7 @@ int mr_ctx::upload_all(hipStream_t s) {
             const int32_t g1 = std::min(A.a1, g + kApexRowsPerItem);
             if (g1 - 1 < k0) continue;          // no row of the group reaches the segment
             apex_fitems.push_back({A0 + g, A0 + g1, A0 + k0, A0 + k1, A0 + A.c0,
-                                   pbase + q * nr + (g - A.a0),
+                                   pbase + q * nr + (g - A.a0), p, 1,
                                    apex_xf_base[p] + pl.apex_xf_off[g]});
           }
         }
@@ -604,7 +606,7 @@ int mr_ctx::upload_all(hipStream_t s) {
           const int32_t len = (A.a1 - g) + A.anc_rows;
           if (len > kApexPath) return fail(MR_EINVAL, "apex path longer than the LDS limit");
           apex_path_max = std::max(apex_path_max, len);
-          apex_bitems.push_back({A0 + g, A0 + g1, A0 + A.a1, roff, nrng, len,
+          apex_bitems.push_back({A0 + g, A0 + g1, A0 + A.a1, roff, nrng, len, p, 1,
                                  apex_xb_base[p] + pl.apex_xb_off[g]});
         }
       }
@@ -670,6 +672,13 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_mcol, mcol, s));
   HIP_TRY(upload(d_mwt, mwt, s));
   HIP_TRY(upload(d_blocks, blocks, s));
+  HIP_TRY(upload(d_block_pair, block_pair, s));
+  {
+    // every pair active; the last entry flags that some pair is retired
+    std::vector<int32_t> act(n_pairs + 1, 1);
+    act[n_pairs] = 0;
+    HIP_TRY(upload(d_active, act, s));
+  }
   n_apex_rows = (int64_t)apex_rows_g.size();
   HIP_TRY(upload(d_upper_rows, upper_rows, s));
   HIP_TRY(upload(d_apex_rows, apex_rows_g, s));
@@ -977,6 +986,40 @@ int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
   return MR_OK;
 }
 
+// n_iter iterations, eagerly or replayed from the cached graph (captured on
+// first use for these arguments).
+static int run_iterations(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
+  double2 *u2 = reinterpret_cast<double2 *>(u);
+  // graphs cannot be captured on the legacy default stream
+  const bool use_graph = (c->params.flags & MR_FLAG_GRAPH) && !c->timing && n_iter > 0 && s;
+  if (!use_graph) return c->step(u2, n_iter, msd_trace, s);
+  if (!c->graph_exec || c->graph_u != u || c->graph_trace != msd_trace ||
+      c->graph_iters != n_iter || c->graph_stream != s) {
+    if (c->graph_exec) {
+      hipGraphExecDestroy(c->graph_exec);
+      c->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = c->step(u2, n_iter, msd_trace, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HIP_TRY(e);
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIP_TRY(e);
+    c->graph_u = u;
+    c->graph_trace = msd_trace;
+    c->graph_iters = n_iter;
+    c->graph_stream = s;
+  }
+  HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+  return MR_OK;
+}
+
 extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace,
                              void *stream) {
   int rc = check_ctx(c, true);
@@ -984,37 +1027,93 @@ extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_t
   if (!u || !aligned16(u) || n_iter < 0) return fail(MR_EINVAL, "u must be a 16-byte aligned device pointer; n_iter >= 0");
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
-  double2 *u2 = reinterpret_cast<double2 *>(u);
-  // graphs cannot be captured on the legacy default stream
-  const bool use_graph = (c->params.flags & MR_FLAG_GRAPH) && !c->timing && n_iter > 0 && s;
-  if (!use_graph) {
-    if ((rc = c->step(u2, n_iter, msd_trace, s))) return rc;
-  } else {
-    if (!c->graph_exec || c->graph_u != u || c->graph_trace != msd_trace ||
-        c->graph_iters != n_iter || c->graph_stream != s) {
-      if (c->graph_exec) {
-        hipGraphExecDestroy(c->graph_exec);
-        c->graph_exec = nullptr;
-      }
-      hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      rc = c->step(u2, n_iter, msd_trace, s);
-      hipError_t e = hipStreamEndCapture(s, &g);
-      if (rc) {
-        if (g) hipGraphDestroy(g);
-        return rc;
-      }
-      HIP_TRY(e);
-      e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
-      HIP_TRY(e);
-      c->graph_u = u;
-      c->graph_trace = msd_trace;
-      c->graph_iters = n_iter;
-      c->graph_stream = s;
-    }
-    HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+  if ((rc = run_iterations(c, u, n_iter, msd_trace, s))) return rc;
+  c->post_flags(s);
+  return MR_OK;
+}
+
+// Per-pair activity (1 active, 0 retired; one more entry, nonzero when some
+// pair is retired) into d_active and every work descriptor.
+hipError_t mr_ctx::set_active(const std::vector<int32_t> &flags, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d_active.ptr, flags.data(), sizeof(int32_t) * flags.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = launch_set_active(d_active.ptr, d_pairs.ptr, n_pairs, d_blocks.ptr, d_block_pair.ptr,
+                        (int)d_blocks.count, d_node_items.ptr, n_node_items, d_tiles.ptr, n_tiles,
+                        d_apex_fitems.ptr, (int)d_apex_fitems.count, d_apex_bitems.ptr,
+                        (int)d_apex_bitems.count, s);
+  // the flags were read from pageable host memory: finish before it goes away
+  return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t check_every,
+                            double rel_tol, int32_t *iters_out, double *msd_out, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || max_iter < 0 || check_every < 1 || !iters_out || !msd_out ||
+      !(rel_tol >= 0.0) || !std::isfinite(rel_tol))
+    return fail(MR_EINVAL, "need aligned u, max_iter >= 0, check_every >= 1, finite rel_tol >= 0, "
+                           "iters_out and msd_out");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int np = c->n_pairs;
+  const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(check_every, max_iter));
+  if ((int64_t)c->d_run_trace.count < rows * np) HIP_TRY(c->d_run_trace.alloc((size_t)(rows * np)));
+  // MSD of the starting displacements
+  std::vector<double> prev(np), now(np), final_msd(np);
+  HIP_TRY(c->warp(reinterpret_cast<const double2 *>(u), c->d_run_trace.ptr, nullptr, s));
+  HIP_TRY(hipMemcpyAsync(prev.data(), c->d_run_trace.ptr, sizeof(double) * np,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> active(np, 1);
+  int32_t done = 0, n_active = np;
+  for (int p = 0; p < np; ++p) {
+    final_msd[p] = prev[p];
+    iters_out[p] = 0;
   }
+  while (done < max_iter && n_active > 0) {
+    const int32_t chunk = std::min(check_every, max_iter - done);
+    if ((rc = run_iterations(c, u, chunk, c->d_run_trace.ptr, s))) break;
+    hipError_t e = hipMemcpyAsync(now.data(), c->d_run_trace.ptr + (size_t)(chunk - 1) * np,
+                                  sizeof(double) * np, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = fail(MR_EHIP, std::string("run: ") + hipGetErrorString(e));
+      break;
+    }
+    done += chunk;
+    bool retired = false;
+    for (int p = 0; p < np; ++p) {
+      if (!active[p]) continue;
+      iters_out[p] = done;
+      final_msd[p] = now[p];
+      // relative decrease of the MSD over the chunk below the tolerance
+      // (an increase counts as converged)
+      if (!(prev[p] > 0.0) || (prev[p] - now[p]) < rel_tol * prev[p]) {
+        active[p] = 0;
+        --n_active;
+        retired = true;
+      }
+      prev[p] = now[p];
+    }
+    if (retired && n_active > 0 && done < max_iter) {
+      std::vector<int32_t> flags(active);
+      flags.push_back(1);                     // some pair is retired
+      e = c->set_active(flags, s);
+      if (e != hipSuccess) {
+        rc = fail(MR_EHIP, std::string("run: ") + hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  // every pair active again for later calls
+  std::vector<int32_t> all(np + 1, 1);
+  all[np] = 0;
+  const hipError_t e = c->set_active(all, s);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(MR_EHIP, std::string("run: ") + hipGetErrorString(e));
+  HIP_TRY(hipMemcpyAsync(msd_out, final_msd.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   c->post_flags(s);
   return MR_OK;
 }

@@ -56,6 +56,8 @@ struct mr_ctx {
   mr::DevArray<mr::NodeItem> d_node_items;
   mr::DevArray<mr::TileItem> d_tiles;
   mr::DevArray<int2> d_xy, d_xy_s;             // node corners, natural and solve order
+  mr::DevArray<int32_t> d_block_pair, d_active;   // pair of each block; per-pair activity
+  mr::DevArray<double> d_run_trace;               // mesh_reg_run: MSD of one chunk
   mr::DevArray<int4> d_tri, d_tri_s;           // triangle corners, natural and solve order
   mr::DevArray<int4> d_tpos;                    // triangle corners, x | y << 16
   mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
@@ -130,6 +132,7 @@ struct mr_ctx {
   int prefilter_pair_d(int p, const double *img, float *coef_out, hipStream_t s);
   int upload_adjoint_operators(hipStream_t s);
   hipError_t sample(bool with_warp, hipStream_t s);
+  hipError_t set_active(const std::vector<int32_t> &flags, hipStream_t s);
   hipError_t assemble(double *finish_msd, hipStream_t s);
   hipError_t force(const double2 *u, hipStream_t s);
   hipError_t solve(double2 *x, double2 *out, hipStream_t s, const mr::AssembleArgs *fuse);

@@ -24,7 +24,7 @@ struct DevPair {
   int32_t tile_off, n_tiles;   // warp tiles [tile_off, tile_off + n_tiles)
   int32_t tiles_x;
   int32_t item_off, n_items;   // node work items [item_off, item_off + n_items)
-  int32_t pad0;
+  int32_t active;              // 0: the pair is retired (its work items return at once)
 };
 
 struct DevBlock {
@@ -38,7 +38,7 @@ struct DevBlock {
                           // LDS chunks of rslice)
   int32_t part_off;       // backward partial sums: [bslice][b] double2 from here
   int32_t cnt_idx;        // backward arrival counter of the block
-  int32_t pad;
+  int32_t active;         // the block's pair is active (else its items return at once)
 };
 
 // LDS bytes a forward work item of block size b with kn panel rows needs,
@@ -61,6 +61,7 @@ inline int64_t solve_bwd_lds_bytes(int b, int rs, int nt) {
 // the partial sums of row r go to slot part + (r - a0).
 struct ApexFwdItem {
   int32_t a0, a1, k0, k1, c0, part;
+  int32_t pair, active;         // the item's pair and whether it is active
   int64_t xoff0;
 };
 // Backward work item: rows [a0, a1) of one apex block ending at e; the path
@@ -69,6 +70,7 @@ struct ApexFwdItem {
 // positions r - a0 .. len - 1 and the columns follow each other from xoff0 on.
 struct ApexBwdItem {
   int32_t a0, a1, e, rng_off, n_rng, len;
+  int32_t pair, active;         // the item's pair and whether it is active
   int64_t xoff0;
 };
 // Per apex position: its forward partial slots part + q * stride, q < nseg.
@@ -85,9 +87,8 @@ constexpr int kApexMaxRanges = 256;   // ancestor ranges of one apex block (at m
 // rows of the level's (leaf) blocks is formed by their own workgroups, the
 // workgroups after the block items form b for the other solve rows (`rows`,
 // NT per workgroup), and, when finish_msd is set, the workgroups after those
-// finish the MSD of `partials`.
-// Force assembly inside the first forward solve launch.  Node data in solve
-// order: u and h are indexed by solve row, the operator's columns too.
+// finish the MSD of `partials`.  Node data in solve order: u and h are
+// indexed by solve row, the operator's columns too.
 struct AssembleArgs {
   const int32_t *mptr, *mcol;
   const float *mwt;
@@ -100,16 +101,18 @@ struct AssembleArgs {
   const DevPair *pairs;
   const double *partials;
   double *finish_msd;
+  const int32_t *active;        // per-pair activity, [n_pairs] = any pair retired (or null)
 };
 
-// Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`.
+// Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`
+// (active: the pair is not retired).
 struct NodeItem {
-  int32_t pair, begin, end, pad;
+  int32_t pair, begin, end, active;
 };
 
 // Work item of the pixel-parallel kernels: one kTile x kTile tile.
 struct TileItem {
-  int32_t pair, y0, x0, pad;
+  int32_t pair, y0, x0, active;
 };
 
 }  // namespace mr

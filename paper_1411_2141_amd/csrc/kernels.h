@@ -27,7 +27,7 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, double2 *x, double tau,
                            const DevPair *pairs, int n_pairs, const double *partials,
-                           double *finish_msd, hipStream_t s);
+                           double *finish_msd, const int32_t *active, hipStream_t s);
 // One level of the forward / backward block solve; nt = 1 selects the
 // wavefront-per-block kernels with direct global-to-LDS staging (blocks of at
 // most 64 rows, panels not split), nt = 8 or 16 the wavefront-per-block
@@ -59,6 +59,11 @@ hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPai
                                 float *warped, double *partials, unsigned *flags, hipStream_t s);
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
                              double *msd, hipStream_t s);
+// Per-pair activity flags (1 active, 0 retired) into every work descriptor.
+hipError_t launch_set_active(const int32_t *flags, DevPair *pairs, int n_pairs, DevBlock *blocks,
+                             const int32_t *block_pair, int n_blocks, NodeItem *items,
+                             int n_items, TileItem *tiles, int n_tiles, ApexFwdItem *af, int n_af,
+                             ApexBwdItem *ab, int n_ab, hipStream_t s);
 hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,
                                  hipStream_t s);
 hipError_t launch_from_solve_order(int n, const double2 *x, const int32_t *iperm, double2 *dst,

@@ -158,6 +158,7 @@ __device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pai
   const int p = group * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
   if (p >= n_pairs) return;
   const DevPair Q = pairs[p];
+  if (!Q.active) return;                      // retired pair: its MSD is left as it is
   double s = 0.0;
   for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
   s = wave_sum(s);
@@ -282,7 +283,11 @@ __device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem 
                                            float *__restrict__ warped,
                                            double *__restrict__ partials, unsigned *flags) {
   // NT == 2 without a second tile: the first is evaluated twice (same values,
-  // same writes) and only its sum is kept.
+  // same writes) and only its sum is kept.  Tiles of retired pairs are not
+  // warped (the workgroup returns when all of its tiles are retired).
+  const bool on0 = tiles[tile0].active != 0;
+  const bool on1 = NT == 2 && tile1 >= 0 && tiles[tile1].active != 0;
+  if (!on0 && !on1) return;
   double a[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
@@ -301,8 +306,8 @@ __device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    partials[tile0] = (red[0] + red[1]) + (red[2] + red[3]);
-    if (NT == 2 && tile1 >= 0) partials[tile1] = (red[4] + red[5]) + (red[6] + red[7]);
+    if (on0) partials[tile0] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (on1) partials[tile1] = (red[4] + red[5]) + (red[6] + red[7]);
   }
 }
 
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
     return;
   }
   const NodeItem it[1] = {items[blockIdx.x]};
-  if (it[0].begin + (int)threadIdx.x >= it[0].end) return;
+  if (!it[0].active || it[0].begin + (int)threadIdx.x >= it[0].end) return;
   const DevPair P[1] = {pairs[it[0].pair]};
   sample_nodes<1>(it, P, un, xy, coef, rho, h, flags);
 }
@@ -480,6 +485,41 @@ __device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
     out[r] = make_double2(ui[r].x - tau * (double)fx[r], ui[r].y - tau * (double)fy[r]);
 }
 
+// Whether solve row `row` belongs to an active pair.  active[n_pairs] is
+// nonzero once some pair is retired (until then no lookup is made); the pair
+// is found by bisection over the pairs' first rows (rows are packed pair by
+// pair in solve order).
+__device__ __forceinline__ bool row_active(const DevPair *__restrict__ pairs, int n_pairs,
+                                           const int32_t *__restrict__ active, int row) {
+  if (!active || active[n_pairs] == 0) return true;
+  int lo = 0, hi = n_pairs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pairs[mid].node_off <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  return active[lo] != 0;
+}
+
+// Workgroup g of those after a fused first level's block items: the first
+// ceil(n_rows / blockDim) assemble b of the other solve rows (b stays in x,
+// read by later levels), the rest finish the MSD.  Rows of retired pairs keep
+// their x (the displacement).
+__device__ __forceinline__ void fused_tail(const AssembleArgs &A, double2 *x, int g) {
+  const int nt = (int)blockDim.x;
+  const int row_groups = (A.n_rows + nt - 1) / nt;
+  if (g < row_groups) {
+    const int k = g * nt + (int)threadIdx.x;
+    if (k < A.n_rows) {
+      const int row = A.rows[k];
+      if (row_active(A.pairs, A.n_pairs, A.active, row))
+        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+    }
+  } else {
+    msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
+  }
+}
+
 // Force assembly (a thread per two solve rows), b written in solve order; u
 // and h in solve order too, and x may be u itself (each thread reads its rows
 // of u before writing them).  When `finish_msd` is given, the workgroups after
@@ -492,7 +532,8 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
                                                   const double2 *u, double2 *x, double tau,
                                                   const DevPair *__restrict__ pairs, int n_pairs,
                                                   const double *__restrict__ partials,
-                                                  double *__restrict__ finish_msd) {
+                                                  double *__restrict__ finish_msd,
+                                                  const int32_t *__restrict__ active) {
   const int node_groups = (n + 511) / 512;
   if ((int)blockIdx.x >= node_groups) {
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - node_groups);
@@ -502,10 +543,12 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
   const int k0 = (int)blockIdx.x * 512 + (int)threadIdx.x;
   if (k0 >= n) return;
   const int k[2] = {k0, k0 + 256};
-  const bool on[2] = {true, k0 + 256 < n};
+  // rows of retired pairs keep their x (the displacement)
+  const bool on[2] = {row_active(pairs, n_pairs, active, k0),
+                      k0 + 256 < n && row_active(pairs, n_pairs, active, k0 + 256)};
   double2 b[2];
   assemble_b2(k, on, mptr, mcol, mwt, h, u, tau, b);
-  x[k0] = b[0];
+  if (on[0]) x[k0] = b[0];
   if (on[1]) x[k0 + 256] = b[1];
 }
 
@@ -551,23 +594,13 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
     double2 *upd, AssembleArgs A) {
   extern __shared__ double2 sv[];           // t[b], y[b], red[NT]
   if (FUSED && (int)blockIdx.x >= count) {
-    const int g = (int)blockIdx.x - count;
-    const int row_groups = (A.n_rows + NT - 1) / NT;
-    if (g < row_groups) {
-      const int k = g * NT + (int)threadIdx.x;
-      if (k < A.n_rows) {
-        const int row = A.rows[k];
-        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
-      }
-    } else {
-      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
-    }
+    fused_tail(A, x, (int)blockIdx.x - count);
     return;
   }
   const int2 it = items[blockIdx.x];
   const DevBlock B = blocks[it.x];
   const int b = B.r1 - B.r0;
-  if (b == 0) return;
+  if (b == 0 || !B.active) return;
   const int tid = threadIdx.x;
   const int m = B.m;
   const int k0 = it.y * B.rslice;
@@ -708,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(
   const int2 it = items[blockIdx.x];
   const DevBlock B = blocks[it.x];
   const int b = B.r1 - B.r0;
-  if (b == 0) return;
+  if (b == 0 || !B.active) return;
   const int tid = threadIdx.x;
   const int rs = B.rslice;
   // panel rows [kb, ke) of this workgroup
@@ -867,18 +900,7 @@ __global__ __launch_bounds__(256) void k_wave_fwd(
     double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
   const int item_groups = (count + 3) / 4;
   if (FUSED && (int)blockIdx.x >= item_groups) {
-    const int g = (int)blockIdx.x - item_groups;
-    const int row_groups = (A.n_rows + 255) / 256;
-    if (g < row_groups) {
-      const int k = g * 256 + (int)threadIdx.x;
-      if (k < A.n_rows) {
-        const int row = A.rows[k];
-        // rows outside the first level keep b in x (read by later levels)
-        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
-      }
-    } else {
-      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
-    }
+    fused_tail(A, x, (int)blockIdx.x - item_groups);
     return;
   }
   const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
@@ -886,6 +908,7 @@ __global__ __launch_bounds__(256) void k_wave_fwd(
   const int lane = threadIdx.x & 63;
   const int2 it = items[w];
   const DevBlock B = blocks[it.x];
+  if (!B.active) return;
   const int b = B.r1 - B.r0, m = B.m;
   const int k0 = it.y * B.rslice;
   const int kn = max(0, min(B.rslice, m - k0));
@@ -963,6 +986,7 @@ __global__ __launch_bounds__(256) void k_wave_bwd(
   const int lane = threadIdx.x & 63;
   const int2 it = items[w];
   const DevBlock B = blocks[it.x];
+  if (!B.active) return;
   const int b = B.r1 - B.r0, m = B.m;
   const bool col = lane < b;
   auto pload = [&](int k) { return (k < m && col) ? prow[B.poff + (int64_t)k * b + lane] : 0.0; };
@@ -1036,17 +1060,7 @@ __global__ __launch_bounds__(256) void k_half_fwd(
     double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
   const int item_groups = (count + 7) / 8;
   if (FUSED && (int)blockIdx.x >= item_groups) {
-    const int g = (int)blockIdx.x - item_groups;
-    const int row_groups = (A.n_rows + 255) / 256;
-    if (g < row_groups) {
-      const int k = g * 256 + (int)threadIdx.x;
-      if (k < A.n_rows) {
-        const int row = A.rows[k];
-        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
-      }
-    } else {
-      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
-    }
+    fused_tail(A, x, (int)blockIdx.x - item_groups);
     return;
   }
   __shared__ double2 vec[8][32];
@@ -1058,11 +1072,13 @@ __global__ __launch_bounds__(256) void k_half_fwd(
   if (w < count) {
     const int2 it = items[w];
     B = blocks[it.x];
-    b = B.r1 - B.r0;
-    m = B.m;
-    slice = it.y;
-    k0 = it.y * B.rslice;
-    kn = max(0, min(B.rslice, m - k0));
+    if (B.active) {                            // a retired pair's half idles
+      b = B.r1 - B.r0;
+      m = B.m;
+      slice = it.y;
+      k0 = it.y * B.rslice;
+      kn = max(0, min(B.rslice, m - k0));
+    }
   }
   double2 *v2 = vec[hw];
   // D(r, j), r >= j, at doff + j b - j (j - 1) / 2 + (r - j)
@@ -1146,8 +1162,10 @@ __global__ __launch_bounds__(256) void k_half_bwd(
   int b = 0, m = 0;
   if (w < count) {
     B = blocks[items[w].x];
-    b = B.r1 - B.r0;
-    m = B.m;
+    if (B.active) {                            // a retired pair's half idles
+      b = B.r1 - B.r0;
+      m = B.m;
+    }
   }
   double2 *v2 = vec[hw];
   const bool col = r < b;
@@ -1247,23 +1265,14 @@ __global__ __launch_bounds__(64) void k_lds_fwd(
     double2 *__restrict__ ybuf, double2 *__restrict__ upd, AssembleArgs A) {
   extern __shared__ double smem[];
   if (FUSED && (int)blockIdx.x >= count) {
-    const int g = (int)blockIdx.x - count;
-    const int row_groups = (A.n_rows + 63) / 64;
-    if (g < row_groups) {
-      const int k = g * 64 + (int)threadIdx.x;
-      if (k < A.n_rows) {
-        const int row = A.rows[k];
-        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
-      }
-    } else {
-      msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
-    }
+    fused_tail(A, x, (int)blockIdx.x - count);
     return;
   }
   const int lane = threadIdx.x;
   const int2 it = items[blockIdx.x];
   if (it.y != 0) return;                      // slice 0 takes the whole panel
   const DevBlock B = blocks[it.x];
+  if (!B.active) return;
   const int b = B.r1 - B.r0, m = B.m;
   const int nd = b * (b + 1) / 2;
   double *D = smem;
@@ -1321,6 +1330,7 @@ __global__ __launch_bounds__(64) void k_lds_bwd(
   const int lane = threadIdx.x;
   const int2 it = items[blockIdx.x];
   const DevBlock B = blocks[it.x];
+  if (!B.active) return;
   const int b = B.r1 - B.r0, m = B.m;
   const int nd = b * (b + 1) / 2;
   double *D = smem;
@@ -1438,6 +1448,7 @@ __global__ __launch_bounds__(256) void k_apex_fwd(const ApexFwdItem *__restrict_
                                                   double2 *__restrict__ part) {
   __shared__ double2 tl[kApexSeg];
   const ApexFwdItem it = items[blockIdx.x];
+  if (!it.active) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // rows ra, rb; entries of row r in the segment: columns k0 .. min(k1, r+1)-1,
   // stored from xoff0 + sum_{a0 <= s < r} (s - c0 + 1) + (k0 - c0) on
@@ -1510,6 +1521,7 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
   extern __shared__ double2 yl[];              // the longest path of the launch
   __shared__ int2 rl[kApexMaxRanges];          // the item's ancestor ranges
   const ApexBwdItem it = items[blockIdx.x];
+  if (!it.active) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ra = it.a0 + wave, rb = ra + 4;
   const int qa = ra - it.a0, qb = rb - it.a0;
@@ -1633,10 +1645,10 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
                            const float2 *h, const double2 *u, double2 *x, double tau,
                            const DevPair *pairs, int n_pairs, const double *partials,
-                           double *finish_msd, hipStream_t s) {
+                           double *finish_msd, const int32_t *active, hipStream_t s) {
   const int groups = (n + 511) / 512 + (finish_msd ? (n_pairs + 3) / 4 : 0);
   return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, x, tau, pairs, n_pairs,
-                partials, finish_msd);
+                partials, finish_msd, active);
 }
 
 hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int count,
@@ -1757,6 +1769,36 @@ hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPai
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
                              double *msd, hipStream_t s) {
   return launch(k_msd_finish, (n_pairs + 3) / 4, 256, 0, s, pairs, n_pairs, partials, msd);
+}
+
+// Copies the per-pair activity flags into every work descriptor (pairs,
+// blocks, node items, tiles, apex items): a retired pair's work items return
+// at once in every kernel.
+__global__ void k_set_active(const int32_t *__restrict__ flags, DevPair *pairs, int n_pairs,
+                             DevBlock *blocks, const int32_t *__restrict__ block_pair,
+                             int n_blocks, NodeItem *items, int n_items, TileItem *tiles,
+                             int n_tiles, ApexFwdItem *af, int n_af, ApexBwdItem *ab, int n_ab) {
+  const int stride = (int)(gridDim.x * blockDim.x);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x;; k += stride) {
+    bool any = false;
+    if (k < n_pairs) pairs[k].active = flags[k], any = true;
+    if (k < n_blocks) blocks[k].active = flags[block_pair[k]], any = true;
+    if (k < n_items) items[k].active = flags[items[k].pair], any = true;
+    if (k < n_tiles) tiles[k].active = flags[tiles[k].pair], any = true;
+    if (k < n_af) af[k].active = flags[af[k].pair], any = true;
+    if (k < n_ab) ab[k].active = flags[ab[k].pair], any = true;
+    if (!any) break;
+  }
+}
+
+hipError_t launch_set_active(const int32_t *flags, DevPair *pairs, int n_pairs, DevBlock *blocks,
+                             const int32_t *block_pair, int n_blocks, NodeItem *items,
+                             int n_items, TileItem *tiles, int n_tiles, ApexFwdItem *af, int n_af,
+                             ApexBwdItem *ab, int n_ab, hipStream_t s) {
+  const int n = std::max({n_pairs, n_blocks, n_items, n_tiles, n_af, n_ab});
+  const int groups = std::min(std::max(1, (n + 255) / 256), 4096);
+  return launch(k_set_active, groups, 256, 0, s, flags, pairs, n_pairs, blocks, block_pair,
+                n_blocks, items, n_items, tiles, n_tiles, af, n_af, ab, n_ab);
 }
 
 hipError_t launch_to_solve_order(int n, const double2 *src, const int32_t *iperm, double2 *x,

@@ -89,6 +89,16 @@ class MeshReg:
         B.mesh_reg_step(self.ctx, u, n_iter, trace, _stream())
         return trace
 
+    def run(self, u: torch.Tensor, max_iter: int, check_every: int = 10, rel_tol: float = 1e-3):
+        """Iterates in place until each pair's MSD falls by less than ``rel_tol``
+        (relative) over ``check_every`` iterations, at most ``max_iter``; a pair
+        that stops keeps its u while the others go on.  Returns ``(iters, msd)``:
+        the per-pair iteration counts (list) and the final MSDs (device FP64)."""
+        msd = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device)
+        iters = B.mesh_reg_run(self.ctx, u, max_iter, check_every, rel_tol, self.n_pairs, msd,
+                               _stream())
+        return iters, msd
+
     def warp_msd(self, u: torch.Tensor, return_warped: bool = False):
         msd = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device)
         warped = (torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)

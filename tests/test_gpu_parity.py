@@ -297,3 +297,102 @@ def test_zero_iterations_is_a_no_op():
     torch.cuda.synchronize()
     assert torch.equal(u, u0)
     ctx.close()
+
+
+# Loop to convergence with per-pair retirement.  Four pairs that converge at
+# different rates; the tolerance is chosen from the oracle's own check-point
+# MSDs so that the pairs stop at different iterations and no relative decrease
+# lies within RUN_MARGIN of it (the end-to-end MSD gap between the two
+# trajectories, bounded by 1e-4 relative above, moves a relative decrease by
+# at most about 2e-4).
+RUN_MARGIN = 2.5e-4
+RUN_MAX, RUN_EVERY = 58, 5
+
+
+def _run_cases():
+    return [as_dict(make_pair(1)), CASES["adaptive_48"](), CASES["unstructured_64"](),
+            dict(zip(("te", "re", "V", "T"), small_pair(seed=3, side=32)[:4]), alpha=0.05)]
+
+
+def _pick_tolerance(decreases):
+    best = None
+    for tol in np.linspace(0.012, 0.03, 37):
+        stops, margin = [], np.inf
+        for rd in decreases:
+            below = np.nonzero(rd < tol)[0]
+            c = below[0] if below.size else len(rd) - 1
+            stops.append(c)
+            margin = min(margin, np.abs(rd[:c + 1] - tol).min())
+        if len(set(stops)) >= 3 and (best is None or margin > best[1]):
+            best = (float(tol), margin)
+    return best
+
+
+@pytest.mark.parametrize("variant", ["tuned", "graph", "lds_kernels", "wave_kernels_separate",
+                                     "half_kernels", "block_kernels_separate"])
+def test_run_to_convergence_retires_pairs_like_the_oracle(variant):
+    say(f"run to convergence: 4 ragged pairs, max {RUN_MAX}, check every {RUN_EVERY}, {variant}")
+    tau = 0.5
+    ds = _run_cases()
+    pbs = [oracle_problem(d, tau) for d in ds]
+    decreases = []
+    for pb in pbs:
+        _, _, _, checks = reg.run_until(pb, None, RUN_MAX, RUN_EVERY, 0.0)
+        c = np.asarray(checks)
+        decreases.append((c[:-1] - c[1:]) / c[:-1])
+    tol, margin = _pick_tolerance(decreases)
+    assert margin > RUN_MARGIN, (tol, margin)
+    want = [reg.run_until(pb, None, RUN_MAX, RUN_EVERY, tol) for pb in pbs]
+    assert len({w[1] for w in want}) >= 3
+    kw = dict(graph=variant == "graph",
+              solve_kernel={"lds_kernels": 1, "wave_kernels_separate": 8, "half_kernels": 32,
+                            "block_kernels_separate": 256}.get(variant, 0),
+              separate_assembly=variant.endswith("_separate"))
+    ctx = lib().MeshReg(ds, tau=tau, **kw)
+    u = ctx.zeros_u()
+    iters, msd = ctx.run(u, RUN_MAX, RUN_EVERY, tol)
+    torch.cuda.synchronize()
+    ug, mg = u.cpu().numpy(), msd.cpu().numpy()
+    assert iters == [w[1] for w in want], (iters, [w[1] for w in want], tol)
+    for k, (u_or, it, m_or, _) in enumerate(want):
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or) < U_TOL, (k, rel(ug[sl], u_or))
+        assert abs(mg[k] - m_or) <= 1e-4 * m_or, (k, mg[k], m_or)
+        # the reported MSD is that of the returned displacement
+        m_id = reg.msd(pbs[k], ug[sl])
+        assert abs(mg[k] - m_id) <= MSD_TOL * m_id
+    # every pair is active again: a plain step afterwards matches the oracle
+    u2 = ctx.zeros_u()
+    ctx.step(u2, 3)
+    torch.cuda.synchronize()
+    u2g = u2.cpu().numpy()
+    for k, pb in enumerate(pbs):
+        u_or, _, _ = reg.run(pb, None, 3)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(u2g[sl], u_or) < U_TOL, k
+    ctx.close()
+
+
+def test_run_edge_cases():
+    say("run: zero iterations, a single pair, a tolerance no pair meets")
+    tau = 0.5
+    d = CASES["adaptive_48"]()
+    pb = oracle_problem(d, tau)
+    ctx = gpu_ctx([d], tau)
+    u = ctx.zeros_u()
+    iters, msd = ctx.run(u, 0, 5, 0.01)
+    torch.cuda.synchronize()
+    assert iters == [0] and float(u.abs().max()) == 0.0
+    m0 = reg.msd(pb, np.zeros((d["V"].shape[0], 2)))
+    assert abs(msd.item() - m0) <= MSD_TOL * m0
+    # rel_tol 0: runs to max_iter while the MSD keeps falling (a last chunk of 2)
+    iters, msd = ctx.run(u, 12, 5, 0.0)
+    torch.cuda.synchronize()
+    u_or, it, m_or, _ = reg.run_until(pb, None, 12, 5, 0.0)
+    assert iters == [it] == [12]
+    assert rel(u.cpu().numpy(), u_or) < U_TOL
+    assert abs(msd.item() - m_or) <= 1e-4 * m_or
+    for bad in [(-1, 5, 0.1), (5, 0, 0.1), (5, 5, -1.0), (5, 5, float("nan")), (5, 5, float("inf"))]:
+        with pytest.raises(lib().MeshRegError):
+            ctx.run(u, *bad)
+    ctx.close()

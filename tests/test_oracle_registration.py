@@ -126,3 +126,54 @@ def test_descent_lowers_the_objective_for_small_steps():
         e1 = energy(u)
         assert e1 <= e0 + 1e-15
         e0 = e1
+
+
+def _scan_stop(msds, max_iter, check_every, rel_tol):
+    """Brute force over a recorded MSD trajectory (msds[k] = MSD(u^k)): the
+    first check point whose relative decrease over the last check_every
+    iterations is below rel_tol (or that follows a non-positive MSD)."""
+    prev = 0
+    k = 0
+    while k < max_iter:
+        k = min(k + check_every, max_iter)
+        a, b = msds[prev], msds[k]
+        if not a > 0.0 or a - b < rel_tol * a:
+            return k
+        prev = k
+    return k
+
+
+@pytest.mark.parametrize("rel_tol", [0.0, 0.01, 0.02, 0.03, 1.0])
+def test_run_until_stops_where_a_scan_of_the_trajectory_does(rel_tol):
+    """Stopping rule of the loop to convergence against a scan of the full
+    trajectory: same stop, same u, same final MSD; the last chunk is short
+    (max_iter not a multiple of check_every)."""
+    te, re, V, T, _ = small_pair(seed=3, side=32)
+    pb = reg.setup(te, re, V, T, alpha=0.05, tau=0.5)
+    max_iter, every = 38, 5
+    _, ms, us = reg.run(pb, None, max_iter, record_msd=True, keep_all=True)
+    msds = [reg.msd(pb, us[0])] + ms
+    want = _scan_stop(msds, max_iter, every, rel_tol)
+    u, iters, m_final, checks = reg.run_until(pb, None, max_iter, every, rel_tol)
+    assert iters == want
+    assert np.array_equal(u, us[want])
+    assert m_final == msds[want]
+    points = list(range(0, want, every)) + [want]      # the MSDs compared
+    assert checks == [msds[k] for k in points]
+    if rel_tol == 0.0:
+        assert iters == max_iter          # this problem's MSD decreases throughout
+    if rel_tol == 1.0:
+        assert iters == every             # no chunk removes the whole misfit
+
+
+def test_run_until_special_cases():
+    te, re, V, T, _ = small_pair(seed=3, side=32)
+    pb = reg.setup(te, re, V, T, alpha=0.05, tau=0.5)
+    u0 = np.random.default_rng(1).normal(scale=0.3, size=(V.shape[0], 2))
+    # no iterations: u0 and its MSD come back
+    u, iters, m, checks = reg.run_until(pb, u0, 0, 4, 0.01)
+    assert iters == 0 and np.array_equal(u, u0) and m == reg.msd(pb, u0) and checks == [m]
+    # identical images: zero misfit from the start, so the first check stops
+    pz = reg.setup(te, te, V, T, alpha=0.05, tau=0.5)
+    u, iters, m, _ = reg.run_until(pz, None, 50, 4, 0.01)
+    assert iters == 4 and np.abs(u).max() < 1e-12 and m < 1e-20
