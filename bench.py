@@ -225,6 +225,35 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload) -> dict:
             "roofline": roof}
 
 
+def converge_leg(ctx, pairs, stream, args, s_per_iteration: float) -> dict:
+    """The batch run to convergence: each pair stops at the relative-MSD rule and
+    skips every later launch.  Reported against the same batch stepped in
+    lockstep to the slowest pair's count (the per-iteration time measured above)."""
+    import torch
+    with torch.cuda.stream(stream):
+        u = ctx.zeros_u()
+        ctx.run(u, min(args.converge_every, args.converge_max_iters), args.converge_every,
+                args.converge_tol)                                        # graph capture
+        u.zero_()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        iters, msd = ctx.run(u, args.converge_max_iters, args.converge_every, args.converge_tol)
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+    it = np.asarray(iters)
+    nodes = np.asarray([p.n_nodes for p in pairs], dtype=np.int64)
+    lockstep = s_per_iteration * int(it.max())
+    return {"max_iter": args.converge_max_iters, "check_every": args.converge_every,
+            "rel_tol": args.converge_tol, "seconds": round(dt, 4),
+            "iterations_min_median_max": [int(it.min()), int(np.median(it)), int(it.max())],
+            "pairs_at_max_iter": int((it == args.converge_max_iters).sum()),
+            "node_updates": int((nodes * it).sum()),
+            "node_updates_per_s": round(float((nodes * it).sum()) / dt, 1),
+            "lockstep_seconds": round(lockstep, 4),
+            "speedup_vs_lockstep": round(lockstep / dt, 3),
+            "mean_final_msd": float(msd.mean().item())}
+
+
 def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
     from oracle import registration as reg
     pb = reg.setup(pair.te, pair.re, pair.V, pair.T, pair.alpha, tau)
@@ -259,6 +288,11 @@ def main() -> int:
     ap.add_argument("--diff-batch-iters", type=int, default=100)
     ap.add_argument("--unstructured-iters", type=int, default=200,
                     help="0 skips the unstructured-mesh leg")
+    ap.add_argument("--converge-max-iters", type=int, default=300,
+                    help="batched pairs run to the relative-MSD rule, at most this many "
+                         "iterations (0 skips the leg)")
+    ap.add_argument("--converge-every", type=int, default=10)
+    ap.add_argument("--converge-tol", type=float, default=0.02)
     ap.add_argument("--gen-procs", type=int, default=0,
                     help="processes generating the batched inputs (0: up to 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -397,6 +431,8 @@ def main() -> int:
                    "iterations_per_s": round(KB / dtc, 2), "graph": True,
                    "mean_final_msd": float(msd_b.mean().item()),
                    "kernels": bk, "roofline": broof, "stage_rooflines": bstages}
+        if args.converge_max_iters:
+            batched["converge"] = converge_leg(bctx, batch, side, args, dtc / KB)
         bctx.close()
 
     large_leg = None

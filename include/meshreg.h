@@ -80,9 +80,10 @@ enum {
   MR_FLAG_SEPARATE_ASSEMBLY = 8, /* the force assembly of an iteration runs in a launch of its
                             own (otherwise the autotuner chooses between that and assembling
                             inside the first forward solve launch; untuned: inside) */
-  MR_FLAG_GRAPH = 2      /* mesh_reg_step captures its launches in a HIP graph once per
-                            (u, n_iter, msd_trace, stream) and replays it on later calls
-                            with the same arguments (a NULL stream runs eagerly) */
+  MR_FLAG_GRAPH = 2      /* mesh_reg_step (and each chunk of mesh_reg_run) captures its
+                            launches in a HIP graph once per (u, n_iter, msd_trace, stream)
+                            and replays it on later calls with the same arguments (a NULL
+                            stream runs eagerly) */
 };
 
 /* One registration pair (Algorithm 1, "Inputs"; Section 2.1 for (V, T)). */
@@ -151,8 +152,9 @@ int mesh_reg_step(mr_ctx *ctx, double *u, int32_t n_iter, double *msd_trace, voi
  * u: DEVICE [sum n][2] FP64, in/out.  iters_out: HOST [n_pairs], the iterations
  * each pair ran (a multiple of check_every, or max_iter).  msd_out: DEVICE
  * [n_pairs] FP64, each pair's MSD at its final u.  rel_tol: finite, >= 0.
- * Synchronises `stream` after every chunk (the decision is taken on the host);
- * every pair is active again on return.  Errors as mesh_reg_step. */
+ * The full-pixel warp runs only at the check points.  Synchronises `stream` after
+ * every chunk (the decision is taken on the host); every pair is active again on
+ * return.  Calls on one context must not overlap.  Errors as mesh_reg_step. */
 int mesh_reg_run(mr_ctx *ctx, double *u, int32_t max_iter, int32_t check_every, double rel_tol,
                  int32_t *iters_out, double *msd_out, void *stream);
 

@@ -1057,8 +1057,7 @@ extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t chec
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int np = c->n_pairs;
-  const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(check_every, max_iter));
-  if ((int64_t)c->d_run_trace.count < rows * np) HIP_TRY(c->d_run_trace.alloc((size_t)(rows * np)));
+  if ((int64_t)c->d_run_trace.count < np) HIP_TRY(c->d_run_trace.alloc(np));
   // MSD of the starting displacements
   std::vector<double> prev(np), now(np), final_msd(np);
   HIP_TRY(c->warp(reinterpret_cast<const double2 *>(u), c->d_run_trace.ptr, nullptr, s));
@@ -1073,9 +1072,13 @@ extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t chec
   }
   while (done < max_iter && n_active > 0) {
     const int32_t chunk = std::min(check_every, max_iter - done);
-    if ((rc = run_iterations(c, u, chunk, c->d_run_trace.ptr, s))) break;
-    hipError_t e = hipMemcpyAsync(now.data(), c->d_run_trace.ptr + (size_t)(chunk - 1) * np,
-                                  sizeof(double) * np, hipMemcpyDeviceToHost, s);
+    // the chunk's iterations without the per-iteration warp, then the MSD of
+    // the pairs still running
+    if ((rc = run_iterations(c, u, chunk, nullptr, s))) break;
+    hipError_t e = c->warp(reinterpret_cast<const double2 *>(u), c->d_run_trace.ptr, nullptr, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(now.data(), c->d_run_trace.ptr, sizeof(double) * np,
+                         hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       rc = fail(MR_EHIP, std::string("run: ") + hipGetErrorString(e));

@@ -57,7 +57,7 @@ struct mr_ctx {
   mr::DevArray<mr::TileItem> d_tiles;
   mr::DevArray<int2> d_xy, d_xy_s;             // node corners, natural and solve order
   mr::DevArray<int32_t> d_block_pair, d_active;   // pair of each block; per-pair activity
-  mr::DevArray<double> d_run_trace;               // mesh_reg_run: MSD of one chunk
+  mr::DevArray<double> d_run_trace;               // mesh_reg_run: MSD at a check point
   mr::DevArray<int4> d_tri, d_tri_s;           // triangle corners, natural and solve order
   mr::DevArray<int4> d_tpos;                    // triangle corners, x | y << 16
   mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
