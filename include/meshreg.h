@@ -158,6 +158,26 @@ int mesh_reg_step(mr_ctx *ctx, double *u, int32_t n_iter, double *msd_trace, voi
 int mesh_reg_run(mr_ctx *ctx, double *u, int32_t max_iter, int32_t check_every, double rel_tol,
                  int32_t *iters_out, double *msd_out, void *stream);
 
+/* n_iter >= 0 iterations of Algorithm 1 as printed (explicit, Section 2) on every
+ * pair, in place: with u = u_1^k,
+ *   t_i = s_Te(V_i - 1/2 + u_i), r_i = t_i - s_Re(V_i - 1/2)         eq. 3-4
+ *   g_i = sum_j A_j grad t_Tj / sum_j A_j over i's triangles          eq. 9-10
+ *         (grad t_Tj the linear gradient of t on the triangle's deformed corners
+ *         V + u, A_j its unsigned deformed area; zero-area triangles add nothing)
+ *   u_0 = u - tau r g                                                 eq. 5-6
+ *   u_1^{k+1} = (1 - lambda) u_0 + lambda A^Lap u_0                   eq. 11-14
+ *         (A^Lap: 1/m_i on the m_i nodes of i's 1-ring)
+ * tau: finite, >= 0 (the paper's 0.005 is for 0-255 intensities: 0.005 * 255^2 on
+ * [0, 1] images); lambda: 0 .. 1 (the paper's 0.8).  The context's own tau, alpha
+ * and factor are not used.  u: DEVICE [sum n][2] FP64, natural node order, in/out.
+ * msd_trace: DEVICE [n_iter][n_pairs] FP64 or NULL (MSD(u_1^{k+1}) after
+ * iteration k).  Graph replay as mesh_reg_step.  Timing families: smoothing and
+ * sampling count as "sample", the update as "assemble".  The first call builds
+ * the variant's tables on the device (synchronising `stream`).  Errors as
+ * mesh_reg_step. */
+int mesh_reg_step_explicit(mr_ctx *ctx, double *u, int32_t n_iter, double tau, double lambda,
+                           double *msd_trace, void *stream);
+
 /* Warp and MSD (Section 1; Fig. 3): every pixel takes the piecewise-linear
  * displacement of its triangle (T6), the template spline is sampled at the
  * displaced pixel centre and msd[p] = mean over pixels of (W - Re)^2 (FP64,

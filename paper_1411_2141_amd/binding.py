@@ -28,7 +28,8 @@ INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "
         "solve_bytes": 15, "fused_assembly": 16}
 KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
-EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_run", "mesh_reg_warp_msd", "mesh_reg_force",
+EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_run", "mesh_reg_step_explicit",
+            "mesh_reg_warp_msd", "mesh_reg_force",
             "mesh_reg_solve", "mesh_reg_backward", "mesh_reg_set_alpha", "mesh_reg_set_template",
             "mesh_reg_get_tables", "mesh_reg_get_info", "mesh_reg_enable_timing",
             "mesh_reg_kernel_times", "mesh_reg_set_graph", "mesh_reg_destroy",
@@ -71,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(vp)]),
         "mesh_reg_step": (ctypes.c_int, [vp, vp, i32, vp, vp]),
         "mesh_reg_run": (ctypes.c_int, [vp, vp, i32, i32, dbl, ctypes.POINTER(i32), vp, vp]),
+        "mesh_reg_step_explicit": (ctypes.c_int, [vp, vp, i32, dbl, dbl, vp, vp]),
         "mesh_reg_warp_msd": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mesh_reg_force": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mesh_reg_solve": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -138,6 +140,12 @@ def mesh_reg_run(ctx, u, max_iter: int, check_every: int, rel_tol: float, n_pair
     _check(load_library().mesh_reg_run(ctx, _ptr(u), int(max_iter), int(check_every),
                                        float(rel_tol), iters, _ptr(msd), stream))
     return list(iters)
+
+
+def mesh_reg_step_explicit(ctx, u, n_iter: int, tau: float, lam: float, msd_trace=None,
+                           stream=None) -> None:
+    _check(load_library().mesh_reg_step_explicit(ctx, _ptr(u), int(n_iter), float(tau),
+                                                 float(lam), _ptr(msd_trace), stream))
 
 
 def mesh_reg_warp_msd(ctx, u, msd, warped=None, stream=None) -> None:

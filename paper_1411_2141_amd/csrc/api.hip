@@ -769,6 +769,8 @@ int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
                    d_tri.bytes() + d_tri_s.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
+                   d_x_sptr.bytes() + d_x_slot.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
+                   d_x_u0.bytes() + d_x_t.bytes() +
                    d_xy_s.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
@@ -986,22 +988,25 @@ int mr_ctx::step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
   return MR_OK;
 }
 
-// n_iter iterations, eagerly or replayed from the cached graph (captured on
-// first use for these arguments).
-static int run_iterations(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
-  double2 *u2 = reinterpret_cast<double2 *>(u);
+// Enqueues `enqueue(s)` eagerly, or replays the cached graph of it when
+// MR_FLAG_GRAPH is set (captured on first use for this key: the variant, its
+// step parameters and the arguments).
+template <typename F>
+static int replay(mr_ctx *c, int mode, double tau, double lam, const void *u, int32_t n_iter,
+                  const double *msd_trace, hipStream_t s, F &&enqueue) {
   // graphs cannot be captured on the legacy default stream
   const bool use_graph = (c->params.flags & MR_FLAG_GRAPH) && !c->timing && n_iter > 0 && s;
-  if (!use_graph) return c->step(u2, n_iter, msd_trace, s);
+  if (!use_graph) return enqueue(s);
   if (!c->graph_exec || c->graph_u != u || c->graph_trace != msd_trace ||
-      c->graph_iters != n_iter || c->graph_stream != s) {
+      c->graph_iters != n_iter || c->graph_stream != s || c->graph_mode != mode ||
+      c->graph_tau != tau || c->graph_lam != lam) {
     if (c->graph_exec) {
       hipGraphExecDestroy(c->graph_exec);
       c->graph_exec = nullptr;
     }
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const int rc = c->step(u2, n_iter, msd_trace, s);
+    const int rc = enqueue(s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
       if (g) hipGraphDestroy(g);
@@ -1015,9 +1020,19 @@ static int run_iterations(mr_ctx *c, double *u, int32_t n_iter, double *msd_trac
     c->graph_trace = msd_trace;
     c->graph_iters = n_iter;
     c->graph_stream = s;
+    c->graph_mode = mode;
+    c->graph_tau = tau;
+    c->graph_lam = lam;
   }
   HIP_TRY(hipGraphLaunch(c->graph_exec, s));
   return MR_OK;
+}
+
+// n_iter iterations of the semi-implicit scheme, eagerly or from the graph.
+static int run_iterations(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace, hipStream_t s) {
+  double2 *u2 = reinterpret_cast<double2 *>(u);
+  return replay(c, 0, 0.0, 0.0, u, n_iter, msd_trace, s,
+                [&](hipStream_t st) { return c->step(u2, n_iter, msd_trace, st); });
 }
 
 extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace,
@@ -1044,6 +1059,87 @@ hipError_t mr_ctx::set_active(const std::vector<int32_t> &flags, hipStream_t s) 
                         (int)d_apex_bitems.count, s);
   // the flags were read from pageable host memory: finish before it goes away
   return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+// Node -> triangle slots and 1-ring of every pair with global ids (tables T1
+// and T2), for the explicit variant.
+int mr_ctx::upload_explicit_tables(hipStream_t s) {
+  std::vector<int32_t> sptr(n_nodes + 1, 0), slot, rptr(n_nodes + 1, 0), ridx;
+  for (int p = 0; p < n_pairs; ++p) {
+    const PairHost &h = host[p];
+    const int64_t no = dpairs[p].node_off, to = dpairs[p].tri_off;
+    if ((int64_t)slot.size() + (int64_t)h.tab.t1_slot.size() > INT32_MAX ||
+        (int64_t)ridx.size() + (int64_t)h.tab.t2_idx.size() > INT32_MAX)
+      return fail(MR_EINVAL, "explicit variant: more than 2^31 - 1 table entries");
+    for (int i = 0; i < h.n; ++i) {
+      for (int64_t q = h.tab.t1_ptr[i]; q < h.tab.t1_ptr[i + 1]; ++q)
+        slot.push_back((int32_t)(3 * to + h.tab.t1_slot[q]));
+      for (int64_t q = h.tab.t2_ptr[i]; q < h.tab.t2_ptr[i + 1]; ++q)
+        ridx.push_back((int32_t)(no + h.tab.t2_idx[q]));
+      sptr[no + i + 1] = (int32_t)slot.size();
+      rptr[no + i + 1] = (int32_t)ridx.size();
+    }
+  }
+  HIP_TRY(upload(d_x_sptr, sptr, s));
+  HIP_TRY(upload(d_x_slot, slot, s));
+  HIP_TRY(upload(d_x_rptr, rptr, s));
+  HIP_TRY(upload(d_x_ridx, ridx, s));
+  HIP_TRY(d_x_u0.alloc(n_nodes));
+  HIP_TRY(d_x_t.alloc(n_nodes));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MR_OK;
+}
+
+// n_iter iterations of Algorithm 1 as printed, in place on u (natural order).
+// Iteration k: smooth u_0 into u (not at k = 0) and sample t at u; then the
+// update u_0 = u - tau r g.  After the last iteration one more smoothing
+// leaves u_1^N in u.  MSD(u_1^k) (trace row k - 1) is warped by the update
+// launch of iteration k and finished by the next smoothing launch; the last
+// one by a warp of its own.
+int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, double *msd_trace,
+                          hipStream_t s) {
+  if (n_iter == 0) return MR_OK;
+  double2 *u0 = d_x_u0.ptr;
+  float *t = d_x_t.ptr;
+  for (int k = 0; k <= n_iter; ++k) {
+    // rows of the trace finished here (from the previous update's tiles)
+    double *fin = (msd_trace && k >= 2) ? msd_trace + (size_t)(k - 2) * n_pairs : nullptr;
+    timed_begin(MR_KF_SAMPLE, s);
+    HIP_TRY(launch_explicit_smooth(d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u0, u,
+                                   d_x_rptr.ptr, d_x_ridx.ptr, lam, k > 0, k < n_iter, d_xy.ptr,
+                                   d_coef.ptr, t, d_flags.ptr, d_partials.ptr, fin, s));
+    timed_end(s);
+    if (k == n_iter) break;
+    const int tiles = (msd_trace && k > 0) ? n_tiles : 0;
+    timed_begin(MR_KF_ASSEMBLE, s);
+    HIP_TRY(launch_explicit_update(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr, t,
+                                   d_rho.ptr, d_tri.ptr, d_x_sptr.ptr, d_x_slot.ptr, tau, u0,
+                                   d_flags.ptr, d_tiles.ptr, tiles, d_tpos.ptr, d_t6.ptr,
+                                   d_coef.ptr, d_re.ptr, d_partials.ptr, s));
+    timed_end(s);
+  }
+  if (msd_trace) HIP_TRY(warp(u, msd_trace + (size_t)(n_iter - 1) * n_pairs, nullptr, s));
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_step_explicit(mr_ctx *c, double *u, int32_t n_iter, double tau,
+                                      double lambda, double *msd_trace, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || n_iter < 0 || !std::isfinite(tau) || !(tau >= 0.0) ||
+      !(lambda >= 0.0 && lambda <= 1.0))
+    return fail(MR_EINVAL, "explicit: need aligned u, n_iter >= 0, finite tau >= 0 and "
+                           "0 <= lambda <= 1");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->d_x_sptr.ptr && (rc = c->upload_explicit_tables(s))) return rc;
+  double2 *u2 = reinterpret_cast<double2 *>(u);
+  if ((rc = replay(c, 1, tau, lambda, u, n_iter, msd_trace, s, [&](hipStream_t st) {
+         return c->step_explicit(u2, n_iter, tau, lambda, msd_trace, st);
+       })))
+    return rc;
+  c->post_flags(s);
+  return MR_OK;
 }
 
 extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t check_every,

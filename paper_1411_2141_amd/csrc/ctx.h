@@ -111,11 +111,19 @@ struct mr_ctx {
   mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
   mr::DevArray<int32_t> d_kptr, d_kcol;
 
-  // cached HIP graph of one mesh_reg_step call
+  // explicit variant (allocated by its first call): the node -> triangle slot
+  // list and the 1-ring as CSR with global ids, u_0 and the node samples
+  mr::DevArray<int32_t> d_x_sptr, d_x_slot, d_x_rptr, d_x_ridx;
+  mr::DevArray<double2> d_x_u0;
+  mr::DevArray<float> d_x_t;
+
+  // cached HIP graph of one mesh_reg_step (or mesh_reg_step_explicit) call
   hipGraphExec_t graph_exec = nullptr;
   const void *graph_u = nullptr, *graph_trace = nullptr;
   int32_t graph_iters = -1;
   hipStream_t graph_stream = nullptr;
+  int graph_mode = -1;                       // 0 semi-implicit, 1 explicit variant
+  double graph_tau = 0.0, graph_lam = 0.0;   // the explicit variant's step parameters
 
   bool timing = false;
   bool fuse_first = true;   // the first forward level assembles b (else a separate launch)
@@ -147,6 +155,9 @@ struct mr_ctx {
   hipError_t solve_level(bool fwd, int lev, double2 *x, double2 *out, hipStream_t s,
                          const mr::AssembleArgs *fuse);
   int step(double2 *u, int32_t n_iter, double *msd_trace, hipStream_t s);
+  int upload_explicit_tables(hipStream_t s);
+  int step_explicit(double2 *u, int32_t n_iter, double tau, double lam, double *msd_trace,
+                    hipStream_t s);
   void post_flags(hipStream_t s);
   void timed_begin(int family, hipStream_t s);
   void timed_end(hipStream_t s);

@@ -1771,6 +1771,158 @@ hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *pa
   return launch(k_msd_finish, (n_pairs + 3) / 4, 256, 0, s, pairs, n_pairs, partials, msd);
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 1 as printed: explicit update with the mesh gradient (eq. 5, 6,
+// 9, 10) and umbrella smoothing (eq. 11-14).  Node data in natural order.
+// ---------------------------------------------------------------------------
+
+// Smoothing and sampling (one workgroup per node item).  With `smooth` set,
+// u_i = (1 - lambda) u0_i + lambda * mean of u0 over the 1-ring of i (eq. 14;
+// the 1-ring as CSR r_ptr / r_idx, global node ids, its sum in CSR order);
+// otherwise u is left as it is.  With `sample` set, t_i = s_Te(V_i - 1/2 + u_i)
+// (FP32 spline value, eq. 3).  The workgroups after the node items finish the
+// MSD of `partials` into finish_msd (when given).
+__global__ __launch_bounds__(256) void k_explicit_smooth(
+    const NodeItem *__restrict__ items, int n_items, const DevPair *__restrict__ pairs,
+    int n_pairs, const double2 *__restrict__ u0, double2 *__restrict__ u,
+    const int32_t *__restrict__ r_ptr, const int32_t *__restrict__ r_idx, double lambda,
+    int smooth, int sample, const int2 *__restrict__ xy, const float *__restrict__ coef,
+    float *__restrict__ t, unsigned *flags, const double *__restrict__ partials,
+    double *__restrict__ finish_msd) {
+  if ((int)blockIdx.x >= n_items) {
+    msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - n_items);
+    return;
+  }
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + (int)threadIdx.x;
+  if (i >= it.end) return;
+  double2 ui;
+  if (smooth) {
+    const int q0 = r_ptr[i], q1 = r_ptr[i + 1];
+    double sx = 0.0, sy = 0.0;
+    constexpr int U = 4;
+    for (int q = q0; q < q1; q += U) {
+      int j[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) j[k] = q + k < q1 ? r_idx[q + k] : -1;
+      double2 v[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) v[k] = j[k] >= 0 ? u0[j[k]] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        sx += v[k].x;
+        sy += v[k].y;
+      }
+    }
+    const double2 a = u0[i];
+    const double inv_m = 1.0 / (double)(q1 - q0);
+    ui = make_double2((1.0 - lambda) * a.x + lambda * (sx * inv_m),
+                      (1.0 - lambda) * a.y + lambda * (sy * inv_m));
+    u[i] = ui;
+  } else {
+    ui = u[i];
+  }
+  if (sample) {
+    const DevPair P = pairs[it.pair];
+    const int2 v = xy[i];
+    int cx, cy;
+    float fx, fy;
+    const bool okx = split_coord(v.x, ui.x - 0.5, cx, fx);
+    const bool ok = split_coord(v.y, ui.y - 0.5, cy, fy) && okx;
+    if (!ok) atomicOr(flags, kFlagNonFiniteNode);
+    t[i] = spline_value(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy);
+  }
+}
+
+// Update (one workgroup per node item): the gradient of the nodal samples t
+// on the deformed mesh V + u, eq. 9 per triangle and the area-weighted mean of
+// eq. 10 per node, then u0_i = u_i - tau (t_i - rho_i) g_i (eq. 5-6).  With
+// cr the doubled signed area of a deformed triangle and
+// S = sum_v t_v R(P_{v+2} - P_{v+1}), R(x, y) = (-y, x), the triangle's
+// gradient is S / cr and its area |cr| / 2, so the node's mean is
+// sum sign(cr) S / sum |cr| over its triangles (a zero-area triangle adds
+// nothing; a node with none left gets g = 0).  FP64 throughout.  The
+// triangles of node i come from the slot list s_ptr / s_slot (3 * triangle +
+// corner, global triangle ids, in triangle order).  The workgroups after the
+// node items warp the pixel grid by u into the MSD partials (when n_tiles > 0).
+__global__ __launch_bounds__(256) void k_explicit_update(
+    const NodeItem *__restrict__ items, int n_items, const DevPair *__restrict__ pairs,
+    const double2 *__restrict__ u, const int2 *__restrict__ xy, const float *__restrict__ t,
+    const float *__restrict__ rho, const int4 *__restrict__ tri, const int32_t *__restrict__ s_ptr,
+    const int32_t *__restrict__ s_slot, double tau, double2 *__restrict__ u0, unsigned *flags,
+    const TileItem *__restrict__ tiles, const int4 *__restrict__ tpos,
+    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
+    double *__restrict__ partials, int n_tiles) {
+  if ((int)blockIdx.x >= n_items) {
+    warp_tiles<1>((int)blockIdx.x - n_items, -1, tiles, pairs, u, tpos, tri, t6, coef, re,
+                  nullptr, partials, flags);
+    return;
+  }
+  const NodeItem it = items[blockIdx.x];
+  const int i = it.begin + (int)threadIdx.x;
+  if (i >= it.end) return;
+  const int q0 = s_ptr[i], q1 = s_ptr[i + 1];
+  double nx = 0.0, ny = 0.0, den = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    const int4 c = tri[s_slot[q] / 3];
+    const int id[3] = {c.x, c.y, c.z};
+    double px[3], py[3], f[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const int2 b = xy[id[v]];
+      const double2 w = u[id[v]];
+      px[v] = (double)b.x + w.x;
+      py[v] = (double)b.y + w.y;
+      f[v] = (double)t[id[v]];
+    }
+    const double cr = (px[1] - px[0]) * (py[2] - py[0]) - (py[1] - py[0]) * (px[2] - px[0]);
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const int a = (v + 1) % 3, b = (v + 2) % 3;
+      sx -= f[v] * (py[b] - py[a]);
+      sy += f[v] * (px[b] - px[a]);
+    }
+    if (cr > 0.0) {
+      nx += sx;
+      ny += sy;
+    } else if (cr < 0.0) {
+      nx -= sx;
+      ny -= sy;
+    }
+    den += fabs(cr);
+  }
+  const double gx = den > 0.0 ? nx / den : 0.0;
+  const double gy = den > 0.0 ? ny / den : 0.0;
+  const double r = (double)t[i] - (double)rho[i];
+  const double2 ui = u[i];
+  u0[i] = make_double2(ui.x - tau * r * gx, ui.y - tau * r * gy);
+}
+
+hipError_t launch_explicit_smooth(const NodeItem *items, int n_items, const DevPair *pairs,
+                                  int n_pairs, const double2 *u0, double2 *u,
+                                  const int32_t *r_ptr, const int32_t *r_idx, double lambda,
+                                  bool smooth, bool sample, const int2 *xy, const float *coef,
+                                  float *t, unsigned *flags, const double *partials,
+                                  double *finish_msd, hipStream_t s) {
+  const int groups = n_items + (finish_msd ? (n_pairs + 3) / 4 : 0);
+  return launch(k_explicit_smooth, groups, kNodeChunk, 0, s, items, n_items, pairs, n_pairs, u0, u,
+                r_ptr, r_idx, lambda, (int)smooth, (int)sample, xy, coef, t, flags, partials,
+                finish_msd);
+}
+
+hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevPair *pairs,
+                                  const double2 *u, const int2 *xy, const float *t,
+                                  const float *rho, const int4 *tri, const int32_t *s_ptr,
+                                  const int32_t *s_slot, double tau, double2 *u0, unsigned *flags,
+                                  const TileItem *tiles, int n_tiles, const int4 *tpos,
+                                  const int32_t *t6, const float *coef, const float *re,
+                                  double *partials, hipStream_t s) {
+  return launch(k_explicit_update, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u,
+                xy, t, rho, tri, s_ptr, s_slot, tau, u0, flags, tiles, tpos, t6, coef, re,
+                partials, n_tiles);
+}
+
 // Copies the per-pair activity flags into every work descriptor (pairs,
 // blocks, node items, tiles, apex items): a retired pair's work items return
 // at once in every kernel.

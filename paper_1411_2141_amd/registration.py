@@ -89,6 +89,15 @@ class MeshReg:
         B.mesh_reg_step(self.ctx, u, n_iter, trace, _stream())
         return trace
 
+    def step_explicit(self, u: torch.Tensor, n_iter: int, tau: float, lam: float = 0.8,
+                      record_msd: bool = False):
+        """Algorithm 1 as printed (explicit update with the mesh gradient on the
+        deformed mesh, one umbrella smoothing), ``n_iter`` iterations in place."""
+        trace = (torch.empty((n_iter, self.n_pairs), dtype=torch.float64, device=self.device)
+                 if record_msd else None)
+        B.mesh_reg_step_explicit(self.ctx, u, n_iter, tau, lam, trace, _stream())
+        return trace
+
     def run(self, u: torch.Tensor, max_iter: int, check_every: int = 10, rel_tol: float = 1e-3):
         """Iterates in place until each pair's MSD falls by less than ``rel_tol``
         (relative) over ``check_every`` iterations, at most ``max_iter``; a pair

@@ -1,0 +1,155 @@
+"""GPU parity of Algorithm 1 as printed (explicit update with the mesh
+gradient on the deformed mesh, umbrella smoothing) against the oracle.
+
+Step tau = 20 on [0, 1] images (about 0.0003 on 0-255) and lambda = 0.8: at
+the paper's tau (0.005 on 0-255, i.e. 325 here) these synthetic pairs fold
+triangles in the first iteration and the trajectory becomes chaotic (on the
+CPU, rounding the spline coefficients to FP32 moves u by ~50 % within 20
+iterations), so no parity is defined there.  At tau = 20 the same FP32
+rounding moves u by ~4e-8 (128^2) and ~2e-8 (512^2) relative, so the
+displacement tolerance stays 1e-5 per pair and the MSD at an identical u
+1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import literal as lit, registration as reg
+from synth import make_pair, uniform_mesh
+from tests._problems import small_pair, unstructured_pair
+
+pytestmark = pytest.mark.gpu
+
+TAU, LAM = 20.0, 0.8
+U_TOL, MSD_TOL = 1e-5, 1e-6
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1411_2141_amd  # noqa: F401
+
+
+def lib():
+    import paper_1411_2141_amd as pkg
+    return pkg
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def as_dict(p):
+    return dict(te=p.te, re=p.re, V=p.V, T=p.T, alpha=p.alpha)
+
+
+def problem(d):
+    return reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], 0.5)
+
+
+CASES = {
+    "c1_128": lambda: as_dict(make_pair(1)),
+    "adaptive_48": lambda: dict(zip(("te", "re", "V", "T"), small_pair(seed=1, side=48, s_min=1, s_max=16)[:4]), alpha=0.2),
+    "ragged_40x24": lambda: (lambda V, T: dict(
+        te=small_pair(seed=2, side=48)[0][:24, :40].copy(), re=small_pair(seed=2, side=48)[1][:24, :40].copy(),
+        V=V, T=T, alpha=0.1))(*uniform_mesh(24, 40, 4)[:2]),
+    "one_leaf_4": lambda: (lambda V, T: dict(
+        te=np.arange(16, dtype=np.float32).reshape(4, 4) / 16, re=np.ones((4, 4), np.float32) * 0.3,
+        V=V, T=T, alpha=0.5))(*uniform_mesh(4, 4, 4)[:2]),
+    "unstructured_64": lambda: dict(zip(("te", "re", "V", "T"), unstructured_pair(seed=7, side=64)),
+                                    alpha=0.1),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_explicit_run_matches_the_oracle(case):
+    say(f"explicit variant {case}: 20 iterations, MSD every iteration")
+    d = CASES[case]()
+    pb = problem(d)
+    ctx = lib().MeshReg([d], tau=0.5)
+    u = ctx.zeros_u()
+    trace = ctx.step_explicit(u, 20, TAU, LAM, record_msd=True)
+    torch.cuda.synchronize()
+    u_or, msds = lit.run(pb, None, 20, TAU, LAM, record_msd=True)
+    assert rel(u.cpu().numpy(), u_or) < U_TOL, rel(u.cpu().numpy(), u_or)
+    m_id = ctx.warp_msd(torch.as_tensor(u_or, device="cuda")).item()
+    m_or = reg.msd(pb, u_or)
+    assert abs(m_id - m_or) <= MSD_TOL * m_or
+    tr = trace.cpu().numpy()[:, 0]
+    assert np.all(np.abs(tr - np.asarray(msds)) <= 1e-4 * np.asarray(msds))
+    ctx.close()
+
+
+def test_explicit_one_step_from_a_random_displacement():
+    say("explicit variant: one step from a random u, lambda 0, 0.8 and 1, tau 0")
+    d = CASES["adaptive_48"]()
+    pb = problem(d)
+    ctx = lib().MeshReg([d], tau=0.5)
+    rng = np.random.default_rng(5)
+    u_start = rng.normal(scale=0.3, size=(d["V"].shape[0], 2))
+    for tau, lam in [(TAU, 0.0), (TAU, LAM), (TAU, 1.0), (0.0, LAM)]:
+        u = torch.as_tensor(u_start, device="cuda").contiguous()
+        ctx.step_explicit(u, 1, tau, lam)
+        torch.cuda.synchronize()
+        want = lit.step(pb, u_start, tau, lam)
+        assert rel(u.cpu().numpy(), want) < U_TOL, (tau, lam)
+    ctx.close()
+
+
+def test_explicit_512_pair_50_iterations():
+    say("explicit variant 512^2 12-bit: 50 iterations")
+    d = as_dict(make_pair(2))
+    pb = problem(d)
+    ctx = lib().MeshReg([d], tau=0.5)
+    u = ctx.zeros_u()
+    ctx.step_explicit(u, 50, TAU, LAM)
+    torch.cuda.synchronize()
+    u_or, _ = lit.run(pb, None, 50, TAU, LAM)
+    assert rel(u.cpu().numpy(), u_or) < U_TOL
+    m_id = ctx.warp_msd(torch.as_tensor(u_or, device="cuda")).item()
+    m_or = reg.msd(pb, u_or)
+    assert abs(m_id - m_or) <= MSD_TOL * m_or
+    ctx.close()
+
+
+def test_explicit_batch_graph_and_mixing_with_the_implicit_step():
+    say("explicit variant: 3 ragged pairs, graph replay, then the implicit step")
+    ds = [CASES["adaptive_48"](), CASES["unstructured_64"](), CASES["ragged_40x24"]()]
+    ctx = lib().MeshReg(ds, tau=0.5, graph=True)
+    u = ctx.zeros_u()
+    tr1 = ctx.step_explicit(u, 8, TAU, LAM, record_msd=True)      # capture + replay
+    u_first = u.clone()
+    u.zero_()
+    tr2 = ctx.step_explicit(u, 8, TAU, LAM, record_msd=True)
+    torch.cuda.synchronize()
+    # a second trace buffer means a second capture; both runs are the same work
+    assert torch.equal(u, u_first) and torch.equal(tr1, tr2)
+    ug = u.cpu().numpy()
+    for k, d in enumerate(ds):
+        u_or, msds = lit.run(problem(d), None, 8, TAU, LAM, record_msd=True)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or) < U_TOL, k
+        assert abs(tr2[-1, k].item() - msds[-1]) <= 1e-4 * msds[-1]
+    # the implicit step on the same context still matches its oracle
+    u.zero_()
+    ctx.step(u, 3)
+    torch.cuda.synchronize()
+    ug = u.cpu().numpy()
+    for k, d in enumerate(ds):
+        u_or, _, _ = reg.run(problem(d), None, 3)
+        sl = slice(ctx.node_offsets[k], ctx.node_offsets[k + 1])
+        assert rel(ug[sl], u_or) < U_TOL, k
+    for bad in [(-1, TAU, LAM), (1, -1.0, LAM), (1, float("nan"), LAM), (1, TAU, 1.5),
+                (1, TAU, -0.1)]:
+        with pytest.raises(lib().MeshRegError):
+            ctx.step_explicit(u, *bad)
+    ctx.close()
