@@ -43,6 +43,11 @@ sys.path.insert(0, ROOT)
 METRIC = "node-updates/s per registration iteration, fwd+bwd vs plain; achieved HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# Algorithm 1 as printed: lambda as in the paper; the step is 20 on [0, 1]
+# intensities (the paper's 0.005 on 0-255 is 325 here, where these pairs fold
+# triangles in the first iteration)
+EXPLICIT_TAU = 20.0
+EXPLICIT_LAMBDA = 0.8
 
 
 def source_digest() -> str:
@@ -96,6 +101,74 @@ def unit_bytes(ctx, pairs) -> dict:
         "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
         "finish": 8 * tiles + 8 * len(pairs),
     }
+
+
+def explicit_unit_bytes(pairs) -> dict:
+    """Algorithmic bytes of one iteration of Algorithm 1 as printed: the
+    smoothing part (u_0 and its 1-ring gather, the ring CSR, u written) and
+    the sampling part (node corners, coefficient taps, rho, the 32-byte node
+    record written) of the first launch, and the update launch (slot CSR,
+    triangle corners, node records, u, u_0 written)."""
+    n = sum(p.n_nodes for p in pairs)
+    nt = sum(int(p.T.shape[0]) for p in pairs)
+    ring = 0
+    for p in pairs:                      # 1-ring entries: both directions of every edge
+        T = np.asarray(p.T, dtype=np.int64)
+        e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+        e.sort(axis=1)
+        ring += 2 * int(np.unique(e[:, 0] * (1 << 32) + e[:, 1]).size)
+    taps = 0
+    for p in pairs:
+        H, W = p.height, p.width
+        idx = [np.clip(p.V[:, 1] - 1 + dm, 0, H - 1).astype(np.int64) * W
+               + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)
+               for dm in range(-1, 3) for dn in range(-1, 3)]
+        taps += int(np.unique(np.concatenate(idx)).size)
+    return {"smooth": 36 * n + 4 * ring, "sampling": 44 * n + 4 * taps,
+            "update": 68 * n + 28 * nt, "u": 16 * n}
+
+
+def explicit_leg(pkg, B, pairs, tau, lam, iters, stream, no_profile, workload, leg) -> dict:
+    """Algorithm 1 as printed (explicit update, umbrella smoothing), graph
+    replay, the MSD every iteration."""
+    import torch
+    n = sum(p.n_nodes for p in pairs)
+    with torch.cuda.stream(stream):
+        ctx = pkg.MeshReg(pairs, tau=0.5, graph=True)
+        u = ctx.zeros_u()
+        tr = torch.empty((iters, len(pairs)), dtype=torch.float64, device="cuda")
+
+        def run():
+            B.mesh_reg_step_explicit(ctx.ctx, u, iters, tau, lam, tr, stream.cuda_stream)
+
+        run()                                           # tables, capture, warm-up
+        stream.synchronize()
+        u.zero_()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        run()
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        final = tr[iters - 1].mean().item()
+        kernels, roof = {}, None
+        if not no_profile:
+            u.zero_()
+            xb = explicit_unit_bytes(pairs)
+            ub = unit_bytes(ctx, pairs)
+            # launch k <= iters of the smoothing family: sampling for k < iters
+            # (at k = 0 of u itself), smoothing for k > 0, the MSD sums of
+            # the previous update's tiles for k >= 2; the update family warps
+            # u for k >= 1
+            total = {"sample": iters * (xb["sampling"] + xb["smooth"]) + xb["u"]
+                               + (iters - 1) * ub["finish"],
+                     "assemble": iters * xb["update"] + (iters - 1) * ub["warp"],
+                     "solve": 0, "warp": ub["warp"] + ub["finish"]}
+            kernels, roof = profile(ctx, run, total, leg)
+        ctx.close()
+    return {"workload": workload, "tau": tau, "lambda": lam, "nodes": n, "iterations": iters,
+            "ms_per_iteration": round(dt / iters * 1e3, 4),
+            "node_updates_per_s": round(n * iters / dt, 1),
+            "mean_final_msd": final, "kernels": kernels, "roofline": roof}
 
 
 def _as_pair(d: dict):
@@ -293,6 +366,8 @@ def main() -> int:
                          "iterations (0 skips the leg)")
     ap.add_argument("--converge-every", type=int, default=10)
     ap.add_argument("--converge-tol", type=float, default=0.02)
+    ap.add_argument("--explicit-iters", type=int, default=200,
+                    help="iterations of the explicit (Algorithm 1 as printed) legs (0 skips)")
     ap.add_argument("--gen-procs", type=int, default=0,
                     help="processes generating the batched inputs (0: up to 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -434,6 +509,11 @@ def main() -> int:
         if args.converge_max_iters:
             batched["converge"] = converge_leg(bctx, batch, side, args, dtc / KB)
         bctx.close()
+        if args.explicit_iters:
+            batched["explicit"] = explicit_leg(
+                pkg, B, batch, EXPLICIT_TAU, EXPLICIT_LAMBDA, min(args.explicit_iters, 100),
+                side, args.no_profile, "the same 256 pairs, Algorithm 1 as printed",
+                "explicit_batched")
 
     large_leg = None
     if large is not None:
@@ -477,6 +557,14 @@ def main() -> int:
                 "final_msd": float(utrace[KU - 1, 0].item()), "roofline": uroof}
             uctx.close()
 
+    explicit = None
+    if args.explicit_iters:
+        explicit = explicit_leg(pkg, B, [pair], EXPLICIT_TAU, EXPLICIT_LAMBDA, args.explicit_iters,
+                                side, args.no_profile,
+                                "the 512x512 pair, Algorithm 1 as printed (explicit update with "
+                                "the mesh gradient on the deformed mesh, umbrella smoothing), "
+                                "MSD every iteration", "explicit_single")
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
 
     out = {
@@ -491,7 +579,7 @@ def main() -> int:
                    "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
         "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd, "batched": batched, "large_pair": large_leg,
-        "diff_batch": dbatch_leg, "unstructured": unstructured,
+        "diff_batch": dbatch_leg, "unstructured": unstructured, "explicit": explicit,
     }
     print(json.dumps(out))
     return 0

@@ -770,7 +770,7 @@ int64_t mr_ctx::device_bytes() const {
                    d_tri.bytes() + d_tri_s.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
                    d_x_sptr.bytes() + d_x_slot.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
-                   d_x_u0.bytes() + d_x_t.bytes() +
+                   d_x_u0.bytes() + d_x_rec.bytes() +
                    d_xy_s.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
@@ -1085,7 +1085,7 @@ int mr_ctx::upload_explicit_tables(hipStream_t s) {
   HIP_TRY(upload(d_x_rptr, rptr, s));
   HIP_TRY(upload(d_x_ridx, ridx, s));
   HIP_TRY(d_x_u0.alloc(n_nodes));
-  HIP_TRY(d_x_t.alloc(n_nodes));
+  HIP_TRY(d_x_rec.alloc(n_nodes));
   HIP_TRY(hipStreamSynchronize(s));
   return MR_OK;
 }
@@ -1100,22 +1100,23 @@ int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, do
                           hipStream_t s) {
   if (n_iter == 0) return MR_OK;
   double2 *u0 = d_x_u0.ptr;
-  float *t = d_x_t.ptr;
+  NodeRec *rec = d_x_rec.ptr;
   for (int k = 0; k <= n_iter; ++k) {
     // rows of the trace finished here (from the previous update's tiles)
     double *fin = (msd_trace && k >= 2) ? msd_trace + (size_t)(k - 2) * n_pairs : nullptr;
     timed_begin(MR_KF_SAMPLE, s);
     HIP_TRY(launch_explicit_smooth(d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u0, u,
                                    d_x_rptr.ptr, d_x_ridx.ptr, lam, k > 0, k < n_iter, d_xy.ptr,
-                                   d_coef.ptr, t, d_flags.ptr, d_partials.ptr, fin, s));
+                                   d_coef.ptr, d_rho.ptr, rec, d_flags.ptr, d_partials.ptr, fin,
+                                   s));
     timed_end(s);
     if (k == n_iter) break;
     const int tiles = (msd_trace && k > 0) ? n_tiles : 0;
     timed_begin(MR_KF_ASSEMBLE, s);
-    HIP_TRY(launch_explicit_update(d_node_items.ptr, n_node_items, d_pairs.ptr, u, d_xy.ptr, t,
-                                   d_rho.ptr, d_tri.ptr, d_x_sptr.ptr, d_x_slot.ptr, tau, u0,
-                                   d_flags.ptr, d_tiles.ptr, tiles, d_tpos.ptr, d_t6.ptr,
-                                   d_coef.ptr, d_re.ptr, d_partials.ptr, s));
+    HIP_TRY(launch_explicit_update(d_node_items.ptr, n_node_items, d_pairs.ptr, u, rec, d_tri.ptr,
+                                   d_x_sptr.ptr, d_x_slot.ptr, tau, u0, d_flags.ptr, d_tiles.ptr,
+                                   tiles, d_tpos.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
+                                   d_partials.ptr, s));
     timed_end(s);
   }
   if (msd_trace) HIP_TRY(warp(u, msd_trace + (size_t)(n_iter - 1) * n_pairs, nullptr, s));

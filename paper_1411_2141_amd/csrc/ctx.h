@@ -112,10 +112,10 @@ struct mr_ctx {
   mr::DevArray<int32_t> d_kptr, d_kcol;
 
   // explicit variant (allocated by its first call): the node -> triangle slot
-  // list and the 1-ring as CSR with global ids, u_0 and the node samples
+  // list and the 1-ring as CSR with global ids, u_0 and the node records
   mr::DevArray<int32_t> d_x_sptr, d_x_slot, d_x_rptr, d_x_ridx;
   mr::DevArray<double2> d_x_u0;
-  mr::DevArray<float> d_x_t;
+  mr::DevArray<mr::NodeRec> d_x_rec;
 
   // cached HIP graph of one mesh_reg_step (or mesh_reg_step_explicit) call
   hipGraphExec_t graph_exec = nullptr;

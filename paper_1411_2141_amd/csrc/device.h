@@ -104,6 +104,13 @@ struct AssembleArgs {
   const int32_t *active;        // per-pair activity, [n_pairs] = any pair retired (or null)
 };
 
+// Per-node record of the explicit variant, written by its smoothing launch
+// and gathered (one 32-byte load per triangle corner) by its update launch:
+// the deformed position V + u, the template sample t and r = t - rho.
+struct __align__(32) NodeRec {
+  double px, py, t, r;
+};
+
 // Work item of the node-parallel kernels: nodes [begin, end) of pair `pair`
 // (active: the pair is not retired).
 struct NodeItem {

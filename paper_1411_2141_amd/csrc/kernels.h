@@ -64,15 +64,14 @@ hipError_t launch_explicit_smooth(const NodeItem *items, int n_items, const DevP
                                   int n_pairs, const double2 *u0, double2 *u,
                                   const int32_t *r_ptr, const int32_t *r_idx, double lambda,
                                   bool smooth, bool sample, const int2 *xy, const float *coef,
-                                  float *t, unsigned *flags, const double *partials,
-                                  double *finish_msd, hipStream_t s);
+                                  const float *rho, NodeRec *rec, unsigned *flags,
+                                  const double *partials, double *finish_msd, hipStream_t s);
 hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevPair *pairs,
-                                  const double2 *u, const int2 *xy, const float *t,
-                                  const float *rho, const int4 *tri, const int32_t *s_ptr,
-                                  const int32_t *s_slot, double tau, double2 *u0, unsigned *flags,
-                                  const TileItem *tiles, int n_tiles, const int4 *tpos,
-                                  const int32_t *t6, const float *coef, const float *re,
-                                  double *partials, hipStream_t s);
+                                  const double2 *u, const NodeRec *rec, const int4 *tri,
+                                  const int32_t *s_ptr, const int32_t *s_slot, double tau,
+                                  double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
+                                  const int4 *tpos, const int32_t *t6, const float *coef,
+                                  const float *re, double *partials, hipStream_t s);
 // Per-pair activity flags (1 active, 0 retired) into every work descriptor.
 hipError_t launch_set_active(const int32_t *flags, DevPair *pairs, int n_pairs, DevBlock *blocks,
                              const int32_t *block_pair, int n_blocks, NodeItem *items,

@@ -1780,15 +1780,16 @@ hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *pa
 // u_i = (1 - lambda) u0_i + lambda * mean of u0 over the 1-ring of i (eq. 14;
 // the 1-ring as CSR r_ptr / r_idx, global node ids, its sum in CSR order);
 // otherwise u is left as it is.  With `sample` set, t_i = s_Te(V_i - 1/2 + u_i)
-// (FP32 spline value, eq. 3).  The workgroups after the node items finish the
-// MSD of `partials` into finish_msd (when given).
+// (FP32 spline value, eq. 3) and the node's record (deformed position V + u,
+// t, r = t - rho) is written for the update.  The workgroups after the node
+// items finish the MSD of `partials` into finish_msd (when given).
 __global__ __launch_bounds__(256) void k_explicit_smooth(
     const NodeItem *__restrict__ items, int n_items, const DevPair *__restrict__ pairs,
     int n_pairs, const double2 *__restrict__ u0, double2 *__restrict__ u,
     const int32_t *__restrict__ r_ptr, const int32_t *__restrict__ r_idx, double lambda,
     int smooth, int sample, const int2 *__restrict__ xy, const float *__restrict__ coef,
-    float *__restrict__ t, unsigned *flags, const double *__restrict__ partials,
-    double *__restrict__ finish_msd) {
+    const float *__restrict__ rho, NodeRec *__restrict__ rec, unsigned *flags,
+    const double *__restrict__ partials, double *__restrict__ finish_msd) {
   if ((int)blockIdx.x >= n_items) {
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - n_items);
     return;
@@ -1830,7 +1831,13 @@ __global__ __launch_bounds__(256) void k_explicit_smooth(
     const bool okx = split_coord(v.x, ui.x - 0.5, cx, fx);
     const bool ok = split_coord(v.y, ui.y - 0.5, cy, fy) && okx;
     if (!ok) atomicOr(flags, kFlagNonFiniteNode);
-    t[i] = spline_value(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy);
+    const float tv = spline_value(coef + P.pix_off, P.height, P.width, cx, fx, cy, fy);
+    NodeRec R;
+    R.px = (double)v.x + ui.x;
+    R.py = (double)v.y + ui.y;
+    R.t = (double)tv;
+    R.r = (double)tv - (double)rho[i];
+    rec[i] = R;
   }
 }
 
@@ -1841,14 +1848,15 @@ __global__ __launch_bounds__(256) void k_explicit_smooth(
 // S = sum_v t_v R(P_{v+2} - P_{v+1}), R(x, y) = (-y, x), the triangle's
 // gradient is S / cr and its area |cr| / 2, so the node's mean is
 // sum sign(cr) S / sum |cr| over its triangles (a zero-area triangle adds
-// nothing; a node with none left gets g = 0).  FP64 throughout.  The
+// nothing; a node with none left gets g = 0).  FP64 throughout, from the
+// node records the smoothing launch wrote.  The
 // triangles of node i come from the slot list s_ptr / s_slot (3 * triangle +
 // corner, global triangle ids, in triangle order).  The workgroups after the
 // node items warp the pixel grid by u into the MSD partials (when n_tiles > 0).
 __global__ __launch_bounds__(256) void k_explicit_update(
     const NodeItem *__restrict__ items, int n_items, const DevPair *__restrict__ pairs,
-    const double2 *__restrict__ u, const int2 *__restrict__ xy, const float *__restrict__ t,
-    const float *__restrict__ rho, const int4 *__restrict__ tri, const int32_t *__restrict__ s_ptr,
+    const double2 *__restrict__ u, const NodeRec *__restrict__ rec,
+    const int4 *__restrict__ tri, const int32_t *__restrict__ s_ptr,
     const int32_t *__restrict__ s_slot, double tau, double2 *__restrict__ u0, unsigned *flags,
     const TileItem *__restrict__ tiles, const int4 *__restrict__ tpos,
     const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
@@ -1863,38 +1871,52 @@ __global__ __launch_bounds__(256) void k_explicit_update(
   if (i >= it.end) return;
   const int q0 = s_ptr[i], q1 = s_ptr[i + 1];
   double nx = 0.0, ny = 0.0, den = 0.0;
-  for (int q = q0; q < q1; ++q) {
-    const int4 c = tri[s_slot[q] / 3];
-    const int id[3] = {c.x, c.y, c.z};
-    double px[3], py[3], f[3];
+  // U triangles per batch: their slot, corner and corner-record loads are
+  // issued together (one 32-byte record per corner); the sums run in slot
+  // order
+  constexpr int U = 2;
+  for (int q = q0; q < q1; q += U) {
+    int tr[U];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      const int2 b = xy[id[v]];
-      const double2 w = u[id[v]];
-      px[v] = (double)b.x + w.x;
-      py[v] = (double)b.y + w.y;
-      f[v] = (double)t[id[v]];
-    }
-    const double cr = (px[1] - px[0]) * (py[2] - py[0]) - (py[1] - py[0]) * (px[2] - px[0]);
-    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < U; ++k) tr[k] = q + k < q1 ? s_slot[q + k] / 3 : -1;
+    int id[U][3];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      const int a = (v + 1) % 3, b = (v + 2) % 3;
-      sx -= f[v] * (py[b] - py[a]);
-      sy += f[v] * (px[b] - px[a]);
+    for (int k = 0; k < U; ++k) {
+      const int4 c = tr[k] >= 0 ? tri[tr[k]] : make_int4(i, i, i, 0);
+      id[k][0] = c.x;
+      id[k][1] = c.y;
+      id[k][2] = c.z;
     }
-    if (cr > 0.0) {
-      nx += sx;
-      ny += sy;
-    } else if (cr < 0.0) {
-      nx -= sx;
-      ny -= sy;
+    NodeRec R[U][3];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+      for (int v = 0; v < 3; ++v) R[k][v] = rec[id[k][v]];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (tr[k] < 0) continue;
+      const double cr = (R[k][1].px - R[k][0].px) * (R[k][2].py - R[k][0].py) -
+                        (R[k][1].py - R[k][0].py) * (R[k][2].px - R[k][0].px);
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const int a = (v + 1) % 3, b = (v + 2) % 3;
+        sx -= R[k][v].t * (R[k][b].py - R[k][a].py);
+        sy += R[k][v].t * (R[k][b].px - R[k][a].px);
+      }
+      if (cr > 0.0) {
+        nx += sx;
+        ny += sy;
+      } else if (cr < 0.0) {
+        nx -= sx;
+        ny -= sy;
+      }
+      den += fabs(cr);
     }
-    den += fabs(cr);
   }
   const double gx = den > 0.0 ? nx / den : 0.0;
   const double gy = den > 0.0 ? ny / den : 0.0;
-  const double r = (double)t[i] - (double)rho[i];
+  const double r = rec[i].r;
   const double2 ui = u[i];
   u0[i] = make_double2(ui.x - tau * r * gx, ui.y - tau * r * gy);
 }
@@ -1903,24 +1925,23 @@ hipError_t launch_explicit_smooth(const NodeItem *items, int n_items, const DevP
                                   int n_pairs, const double2 *u0, double2 *u,
                                   const int32_t *r_ptr, const int32_t *r_idx, double lambda,
                                   bool smooth, bool sample, const int2 *xy, const float *coef,
-                                  float *t, unsigned *flags, const double *partials,
-                                  double *finish_msd, hipStream_t s) {
+                                  const float *rho, NodeRec *rec, unsigned *flags,
+                                  const double *partials, double *finish_msd, hipStream_t s) {
   const int groups = n_items + (finish_msd ? (n_pairs + 3) / 4 : 0);
   return launch(k_explicit_smooth, groups, kNodeChunk, 0, s, items, n_items, pairs, n_pairs, u0, u,
-                r_ptr, r_idx, lambda, (int)smooth, (int)sample, xy, coef, t, flags, partials,
-                finish_msd);
+                r_ptr, r_idx, lambda, (int)smooth, (int)sample, xy, coef, rho, rec, flags,
+                partials, finish_msd);
 }
 
 hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevPair *pairs,
-                                  const double2 *u, const int2 *xy, const float *t,
-                                  const float *rho, const int4 *tri, const int32_t *s_ptr,
-                                  const int32_t *s_slot, double tau, double2 *u0, unsigned *flags,
-                                  const TileItem *tiles, int n_tiles, const int4 *tpos,
-                                  const int32_t *t6, const float *coef, const float *re,
-                                  double *partials, hipStream_t s) {
+                                  const double2 *u, const NodeRec *rec, const int4 *tri,
+                                  const int32_t *s_ptr, const int32_t *s_slot, double tau,
+                                  double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
+                                  const int4 *tpos, const int32_t *t6, const float *coef,
+                                  const float *re, double *partials, hipStream_t s) {
   return launch(k_explicit_update, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u,
-                xy, t, rho, tri, s_ptr, s_slot, tau, u0, flags, tiles, tpos, t6, coef, re,
-                partials, n_tiles);
+                rec, tri, s_ptr, s_slot, tau, u0, flags, tiles, tpos, t6, coef, re, partials,
+                n_tiles);
 }
 
 // Copies the per-pair activity flags into every work descriptor (pairs,
