@@ -107,8 +107,9 @@ def explicit_unit_bytes(pairs) -> dict:
     """Algorithmic bytes of one iteration of Algorithm 1 as printed: the
     smoothing part (u_0 and its 1-ring gather, the ring CSR, u written) and
     the sampling part (node corners, coefficient taps, rho, the 32-byte node
-    record written) of the first launch, and the update launch (slot CSR,
-    triangle corners, node records, u, u_0 written)."""
+    record written) of the first launch, and the update launch (per node
+    the list of its triangles' other two corners, node records, u, u_0
+    written)."""
     n = sum(p.n_nodes for p in pairs)
     nt = sum(int(p.T.shape[0]) for p in pairs)
     ring = 0
@@ -125,7 +126,7 @@ def explicit_unit_bytes(pairs) -> dict:
                for dm in range(-1, 3) for dn in range(-1, 3)]
         taps += int(np.unique(np.concatenate(idx)).size)
     return {"smooth": 36 * n + 4 * ring, "sampling": 44 * n + 4 * taps,
-            "update": 68 * n + 28 * nt, "u": 16 * n}
+            "update": 68 * n + 24 * nt, "u": 16 * n}
 
 
 def explicit_leg(pkg, B, pairs, tau, lam, iters, stream, no_profile, workload, leg) -> dict:

@@ -769,7 +769,7 @@ int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
                    d_tri.bytes() + d_tri_s.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
-                   d_x_sptr.bytes() + d_x_slot.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
+                   d_x_sptr.bytes() + d_x_opp.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
                    d_x_u0.bytes() + d_x_rec.bytes() +
                    d_xy_s.bytes() + d_mptr.bytes() +
                    d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
@@ -1061,27 +1061,32 @@ hipError_t mr_ctx::set_active(const std::vector<int32_t> &flags, hipStream_t s) 
   return e == hipSuccess ? hipStreamSynchronize(s) : e;
 }
 
-// Node -> triangle slots and 1-ring of every pair with global ids (tables T1
-// and T2), for the explicit variant.
+// Each node's triangles (table T1: slot 3 t + corner) as their other two
+// corners in cyclic order, and each node's 1-ring (table T2), for every pair
+// with global ids, for the explicit variant.
 int mr_ctx::upload_explicit_tables(hipStream_t s) {
-  std::vector<int32_t> sptr(n_nodes + 1, 0), slot, rptr(n_nodes + 1, 0), ridx;
+  std::vector<int32_t> sptr(n_nodes + 1, 0), rptr(n_nodes + 1, 0), ridx;
+  std::vector<int2> opp;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
-    const int64_t no = dpairs[p].node_off, to = dpairs[p].tri_off;
-    if ((int64_t)slot.size() + (int64_t)h.tab.t1_slot.size() > INT32_MAX ||
+    const int64_t no = dpairs[p].node_off;
+    if ((int64_t)opp.size() + (int64_t)h.tab.t1_slot.size() > INT32_MAX ||
         (int64_t)ridx.size() + (int64_t)h.tab.t2_idx.size() > INT32_MAX)
       return fail(MR_EINVAL, "explicit variant: more than 2^31 - 1 table entries");
     for (int i = 0; i < h.n; ++i) {
-      for (int64_t q = h.tab.t1_ptr[i]; q < h.tab.t1_ptr[i + 1]; ++q)
-        slot.push_back((int32_t)(3 * to + h.tab.t1_slot[q]));
+      for (int64_t q = h.tab.t1_ptr[i]; q < h.tab.t1_ptr[i + 1]; ++q) {
+        const int64_t t = h.tab.t1_slot[q] / 3, a = h.tab.t1_slot[q] % 3;
+        const int32_t *c = &h.tri[3 * t];
+        opp.push_back(make_int2((int32_t)(no + c[(a + 1) % 3]), (int32_t)(no + c[(a + 2) % 3])));
+      }
       for (int64_t q = h.tab.t2_ptr[i]; q < h.tab.t2_ptr[i + 1]; ++q)
         ridx.push_back((int32_t)(no + h.tab.t2_idx[q]));
-      sptr[no + i + 1] = (int32_t)slot.size();
+      sptr[no + i + 1] = (int32_t)opp.size();
       rptr[no + i + 1] = (int32_t)ridx.size();
     }
   }
   HIP_TRY(upload(d_x_sptr, sptr, s));
-  HIP_TRY(upload(d_x_slot, slot, s));
+  HIP_TRY(upload(d_x_opp, opp, s));
   HIP_TRY(upload(d_x_rptr, rptr, s));
   HIP_TRY(upload(d_x_ridx, ridx, s));
   HIP_TRY(d_x_u0.alloc(n_nodes));
@@ -1114,7 +1119,7 @@ int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, do
     const int tiles = (msd_trace && k > 0) ? n_tiles : 0;
     timed_begin(MR_KF_ASSEMBLE, s);
     HIP_TRY(launch_explicit_update(d_node_items.ptr, n_node_items, d_pairs.ptr, u, rec, d_tri.ptr,
-                                   d_x_sptr.ptr, d_x_slot.ptr, tau, u0, d_flags.ptr, d_tiles.ptr,
+                                   d_x_sptr.ptr, d_x_opp.ptr, tau, u0, d_flags.ptr, d_tiles.ptr,
                                    tiles, d_tpos.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
                                    d_partials.ptr, s));
     timed_end(s);

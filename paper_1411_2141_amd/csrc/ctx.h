@@ -111,9 +111,11 @@ struct mr_ctx {
   mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
   mr::DevArray<int32_t> d_kptr, d_kcol;
 
-  // explicit variant (allocated by its first call): the node -> triangle slot
-  // list and the 1-ring as CSR with global ids, u_0 and the node records
-  mr::DevArray<int32_t> d_x_sptr, d_x_slot, d_x_rptr, d_x_ridx;
+  // explicit variant (allocated by its first call): each node's triangles as
+  // their other two corners and the 1-ring, as CSR with global ids, u_0 and
+  // the node records
+  mr::DevArray<int32_t> d_x_sptr, d_x_rptr, d_x_ridx;
+  mr::DevArray<int2> d_x_opp;
   mr::DevArray<double2> d_x_u0;
   mr::DevArray<mr::NodeRec> d_x_rec;
 

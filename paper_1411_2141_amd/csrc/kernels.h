@@ -68,7 +68,7 @@ hipError_t launch_explicit_smooth(const NodeItem *items, int n_items, const DevP
                                   const double *partials, double *finish_msd, hipStream_t s);
 hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevPair *pairs,
                                   const double2 *u, const NodeRec *rec, const int4 *tri,
-                                  const int32_t *s_ptr, const int32_t *s_slot, double tau,
+                                  const int32_t *o_ptr, const int2 *o_jk, double tau,
                                   double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
                                   const int4 *tpos, const int32_t *t6, const float *coef,
                                   const float *re, double *partials, hipStream_t s);

@@ -148,6 +148,16 @@ __global__ __launch_bounds__(256) void k_sample_rho(const NodeItem *__restrict__
 // Hot path
 // ---------------------------------------------------------------------------
 
+// Work item of block b (0 <= b < G) of a launch range whose blocks take one
+// item each: workgroups go to the 8 XCDs round-robin by block id, so blocks
+// b, b + 8, b + 16, ... share an XCD; they take one contiguous run of items
+// (neighbouring items touch the same cache lines, which then stay in that
+// XCD's L2).  A bijection for any G.
+__device__ __forceinline__ int xcd_item(int b, int G) {
+  const int q = G >> 3, r = G & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // Second pass of the MSD: workgroup `group` finishes pairs 4 group .. 4 group + 3,
 // one wavefront per pair summing that pair's tile partials in a fixed order
 // (deterministic) and dividing by its pixel count.
@@ -390,11 +400,11 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
                                                 const float *__restrict__ re,
                                                 double *__restrict__ partials, int n_tiles) {
   if ((int)blockIdx.x >= n_items) {
-    warp_tiles<1>((int)blockIdx.x - n_items, -1, tiles, pairs, u, tpos, tri, t6, coef, re,
-                  nullptr, partials, flags);
+    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), -1, tiles, pairs, u, tpos, tri,
+                  t6, coef, re, nullptr, partials, flags);
     return;
   }
-  const NodeItem it[1] = {items[blockIdx.x]};
+  const NodeItem it[1] = {items[xcd_item((int)blockIdx.x, n_items)]};
   if (!it[0].active || it[0].begin + (int)threadIdx.x >= it[0].end) return;
   const DevPair P[1] = {pairs[it[0].pair]};
   sample_nodes<1>(it, P, un, xy, coef, rho, h, flags);
@@ -1580,7 +1590,7 @@ __global__ __launch_bounds__(256) void k_warp_msd(
     const int4 *__restrict__ tpos, const int4 *__restrict__ tri, const int32_t *__restrict__ t6,
     const float *__restrict__ coef, const float *__restrict__ re, float *__restrict__ warped,
     double *__restrict__ partials, unsigned *flags, int n_tiles) {
-  const int t0 = 2 * (int)blockIdx.x;
+  const int t0 = 2 * xcd_item((int)blockIdx.x, (int)gridDim.x);
   warp_tiles<2>(t0, t0 + 1 < n_tiles ? t0 + 1 : -1, tiles, pairs, u, tpos, tri, t6, coef, re,
                 warped, partials, flags);
 }
@@ -1794,7 +1804,7 @@ __global__ __launch_bounds__(256) void k_explicit_smooth(
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - n_items);
     return;
   }
-  const NodeItem it = items[blockIdx.x];
+  const NodeItem it = items[xcd_item((int)blockIdx.x, n_items)];
   const int i = it.begin + (int)threadIdx.x;
   if (i >= it.end) return;
   double2 ui;
@@ -1849,61 +1859,54 @@ __global__ __launch_bounds__(256) void k_explicit_smooth(
 // gradient is S / cr and its area |cr| / 2, so the node's mean is
 // sum sign(cr) S / sum |cr| over its triangles (a zero-area triangle adds
 // nothing; a node with none left gets g = 0).  FP64 throughout, from the
-// node records the smoothing launch wrote.  The
-// triangles of node i come from the slot list s_ptr / s_slot (3 * triangle +
-// corner, global triangle ids, in triangle order).  The workgroups after the
-// node items warp the pixel grid by u into the MSD partials (when n_tiles > 0).
+// node records the smoothing launch wrote.  Node i's triangles are given by
+// their other two corners (j, k), in the triangle's cyclic order after i, in
+// the list o_ptr / o_jk (global ids, triangle order): one record gather per
+// other corner.  The workgroups after the node items warp the pixel grid by u
+// into the MSD partials (when n_tiles > 0).
 __global__ __launch_bounds__(256) void k_explicit_update(
     const NodeItem *__restrict__ items, int n_items, const DevPair *__restrict__ pairs,
     const double2 *__restrict__ u, const NodeRec *__restrict__ rec,
-    const int4 *__restrict__ tri, const int32_t *__restrict__ s_ptr,
-    const int32_t *__restrict__ s_slot, double tau, double2 *__restrict__ u0, unsigned *flags,
+    const int4 *__restrict__ tri, const int32_t *__restrict__ o_ptr,
+    const int2 *__restrict__ o_jk, double tau, double2 *__restrict__ u0, unsigned *flags,
     const TileItem *__restrict__ tiles, const int4 *__restrict__ tpos,
     const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
     double *__restrict__ partials, int n_tiles) {
   if ((int)blockIdx.x >= n_items) {
-    warp_tiles<1>((int)blockIdx.x - n_items, -1, tiles, pairs, u, tpos, tri, t6, coef, re,
-                  nullptr, partials, flags);
+    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), -1, tiles, pairs, u, tpos, tri,
+                  t6, coef, re, nullptr, partials, flags);
     return;
   }
-  const NodeItem it = items[blockIdx.x];
+  const NodeItem it = items[xcd_item((int)blockIdx.x, n_items)];
   const int i = it.begin + (int)threadIdx.x;
   if (i >= it.end) return;
-  const int q0 = s_ptr[i], q1 = s_ptr[i + 1];
+  const int q0 = o_ptr[i], q1 = o_ptr[i + 1];
+  const NodeRec Ri = rec[i];
   double nx = 0.0, ny = 0.0, den = 0.0;
-  // U triangles per batch: their slot, corner and corner-record loads are
-  // issued together (one 32-byte record per corner); the sums run in slot
-  // order
+  // U triangles per batch, their corner-record gathers issued together; the
+  // sums run in list order
   constexpr int U = 2;
   for (int q = q0; q < q1; q += U) {
-    int tr[U];
+    int2 o[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) tr[k] = q + k < q1 ? s_slot[q + k] / 3 : -1;
-    int id[U][3];
+    for (int k = 0; k < U; ++k) o[k] = q + k < q1 ? o_jk[q + k] : make_int2(i, i);
+    double jx[U], jy[U], jt[U], kx[U], ky[U], kt[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int4 c = tr[k] >= 0 ? tri[tr[k]] : make_int4(i, i, i, 0);
-      id[k][0] = c.x;
-      id[k][1] = c.y;
-      id[k][2] = c.z;
+      const NodeRec Rj = rec[o[k].x], Rk = rec[o[k].y];
+      jx[k] = Rj.px;
+      jy[k] = Rj.py;
+      jt[k] = Rj.t;
+      kx[k] = Rk.px;
+      ky[k] = Rk.py;
+      kt[k] = Rk.t;
     }
-    NodeRec R[U][3];
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-#pragma unroll
-      for (int v = 0; v < 3; ++v) R[k][v] = rec[id[k][v]];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      if (tr[k] < 0) continue;
-      const double cr = (R[k][1].px - R[k][0].px) * (R[k][2].py - R[k][0].py) -
-                        (R[k][1].py - R[k][0].py) * (R[k][2].px - R[k][0].px);
-      double sx = 0.0, sy = 0.0;
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        const int a = (v + 1) % 3, b = (v + 2) % 3;
-        sx -= R[k][v].t * (R[k][b].py - R[k][a].py);
-        sy += R[k][v].t * (R[k][b].px - R[k][a].px);
-      }
+      if (q + k >= q1) continue;
+      const double cr = (jx[k] - Ri.px) * (ky[k] - Ri.py) - (jy[k] - Ri.py) * (kx[k] - Ri.px);
+      const double sx = -(Ri.t * (ky[k] - jy[k]) + jt[k] * (Ri.py - ky[k]) + kt[k] * (jy[k] - Ri.py));
+      const double sy = Ri.t * (kx[k] - jx[k]) + jt[k] * (Ri.px - kx[k]) + kt[k] * (jx[k] - Ri.px);
       if (cr > 0.0) {
         nx += sx;
         ny += sy;
@@ -1916,7 +1919,7 @@ __global__ __launch_bounds__(256) void k_explicit_update(
   }
   const double gx = den > 0.0 ? nx / den : 0.0;
   const double gy = den > 0.0 ? ny / den : 0.0;
-  const double r = rec[i].r;
+  const double r = Ri.r;
   const double2 ui = u[i];
   u0[i] = make_double2(ui.x - tau * r * gx, ui.y - tau * r * gy);
 }
@@ -1935,12 +1938,12 @@ hipError_t launch_explicit_smooth(const NodeItem *items, int n_items, const DevP
 
 hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevPair *pairs,
                                   const double2 *u, const NodeRec *rec, const int4 *tri,
-                                  const int32_t *s_ptr, const int32_t *s_slot, double tau,
+                                  const int32_t *o_ptr, const int2 *o_jk, double tau,
                                   double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
                                   const int4 *tpos, const int32_t *t6, const float *coef,
                                   const float *re, double *partials, hipStream_t s) {
   return launch(k_explicit_update, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u,
-                rec, tri, s_ptr, s_slot, tau, u0, flags, tiles, tpos, t6, coef, re, partials,
+                rec, tri, o_ptr, o_jk, tau, u0, flags, tiles, tpos, t6, coef, re, partials,
                 n_tiles);
 }
 
