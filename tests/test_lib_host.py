@@ -140,6 +140,12 @@ def test_host_only_context_refuses_device_calls():
     with pytest.raises(B.MeshRegError) as ei:
         B.mesh_reg_step(ctx.ctx, None, 1)
     assert ei.value.code in (B.MR_ESTATE, B.MR_EINVAL)
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_run(ctx.ctx, None, 10, 5, 0.01, 1, None)
+    assert ei.value.code == B.MR_ESTATE
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_step_explicit(ctx.ctx, None, 1, 20.0, 0.8)
+    assert ei.value.code == B.MR_ESTATE
     ctx.close()
 
 
