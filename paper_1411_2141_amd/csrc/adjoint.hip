@@ -274,7 +274,7 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   }
   if ((int64_t)d_cbar.count < n_pix) HIP_OK(d_cbar.alloc(n_pix));
   if ((int)d_alpha_part.count < n_node_items) HIP_OK(d_alpha_part.alloc(n_node_items));
-  if (!d_kptr.ptr) {
+  if (!d_mwt_t.ptr) {                         // uploaded last: present after a complete upload
     rc = upload_adjoint_operators(s);
     if (rc) return rc;
   }

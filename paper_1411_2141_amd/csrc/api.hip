@@ -1138,7 +1138,8 @@ extern "C" int mesh_reg_step_explicit(mr_ctx *c, double *u, int32_t n_iter, doub
                            "0 <= lambda <= 1");
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
-  if (!c->d_x_sptr.ptr && (rc = c->upload_explicit_tables(s))) return rc;
+  // the record array is allocated last: present only after a complete upload
+  if (!c->d_x_rec.ptr && (rc = c->upload_explicit_tables(s))) return rc;
   double2 *u2 = reinterpret_cast<double2 *>(u);
   if ((rc = replay(c, 1, tau, lambda, u, n_iter, msd_trace, s, [&](hipStream_t st) {
          return c->step_explicit(u2, n_iter, tau, lambda, msd_trace, st);
