@@ -19,7 +19,11 @@
  *                                                        sparse Cholesky factor
  *
  * and the result is judged by the MSD of the piecewise-linearly warped template
- * against Re (Section 1; Fig. 3; Table 1).
+ * against Re (Section 1; Fig. 3; Table 1).  mesh_reg_run repeats the iteration
+ * until a relative-MSD stopping rule retires each pair (Algorithm 1's loop "to
+ * convergence"); mesh_reg_step_explicit runs Algorithm 1 exactly as printed
+ * (explicit update with the eq. 9-10 mesh gradient on the deformed mesh, then
+ * the eq. 14 umbrella smoothing) on the same context.
  *
  * Conventions
  *   - Pixel (row i, col j) is the unit square [j, j+1) x [i, i+1); the mesh covers
