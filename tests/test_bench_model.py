@@ -1,0 +1,54 @@
+"""The algorithmic byte counts bench.py divides by kernel time, checked against
+the mesh tables they stand for."""
+from types import SimpleNamespace
+
+import numpy as np
+
+import bench
+from oracle import mesh
+from tests._problems import small_pair, unstructured_pair
+
+
+def _pairs():
+    te, re, V, T, _ = small_pair(seed=2, side=48, s_min=1, s_max=16)
+    te2, re2, V2, T2 = unstructured_pair(seed=7, side=32)
+    return [SimpleNamespace(V=V, T=T, n_nodes=V.shape[0], height=48, width=48),
+            SimpleNamespace(V=V2, T=T2, n_nodes=V2.shape[0], height=32, width=32)]
+
+
+def test_explicit_bytes_follow_the_one_ring_and_triangle_counts():
+    pairs = _pairs()
+    xb = bench.explicit_unit_bytes(pairs)
+    n = sum(p.n_nodes for p in pairs)
+    nt = sum(p.T.shape[0] for p in pairs)
+    ring = sum(mesh.table_t2(p.T, p.n_nodes)[1].size for p in pairs)
+    slots = sum(mesh.table_t1(p.T, p.n_nodes)[1].size for p in pairs)
+    assert slots == 3 * nt
+    assert xb["smooth"] == 36 * n + 4 * ring
+    assert xb["update"] == 68 * n + 8 * slots
+    assert xb["u"] == 16 * n
+    # the touched coefficients: the union of every node's 4x4 window at u = 0
+    taps = 0
+    for p in pairs:
+        seen = set()
+        for x, y in p.V:
+            for dm in range(-1, 3):
+                for dn in range(-1, 3):
+                    seen.add((min(max(y - 1 + dm, 0), p.height - 1),
+                              min(max(x - 1 + dn, 0), p.width - 1)))
+        taps += len(seen)
+    assert xb["sampling"] == 44 * n + 4 * taps
+
+
+def test_run_bytes_split_the_assembly_between_families():
+    ub = {"sample": 100, "assemble": 40, "solve": 1000, "warp": 70, "finish": 3}
+    fused = bench.run_bytes(ub, 10, True, fused=True)
+    apart = bench.run_bytes(ub, 10, True, fused=False)
+    assert fused["assemble"] == 0 and apart["assemble"] == 10 * 40 + 9 * 3
+    assert fused["solve"] == 10 * 1000 + 10 * 40 + 9 * 3
+    assert fused["sample"] == apart["sample"] == 10 * 100 + 9 * 70
+    assert fused["warp"] == apart["warp"] == 73
+    assert sum(fused.values()) == sum(apart.values())
+    none = bench.run_bytes(ub, 5, False)
+    assert none["warp"] == 0 and none["sample"] == 500
+    assert np.isclose(sum(none.values()), 5 * (100 + 40 + 1000))
