@@ -247,7 +247,7 @@ def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
     return out
 
 
-def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload) -> dict:
+def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload, leg) -> dict:
     """Plain iterations against forward + checkpointed reverse pass on the same
     pairs: N iterations from u = 0 (graph replay), then the gradient of the
     summed final MSDs w.r.t. u0, every alpha and every template (checkpoint
@@ -278,7 +278,7 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload) -> dict:
             u.zero_()
             _, roof = profile(ctx, lambda: B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream),
                               run_bytes(unit_bytes(ctx, pairs), N, False,
-                                        ctx.info(0, "fused_assembly") == 1), "diff")
+                                        ctx.info(0, "fused_assembly") == 1), leg)
         ctx.close()
     # the reverse pass recomputes the forward from checkpoints, so one gradient
     # evaluation costs (forward) + (reverse pass)
@@ -519,12 +519,13 @@ def main() -> int:
     large_leg = None
     if large is not None:
         large_leg = diff_leg(pkg, B, [large], tau, args.large_iters, side, args.no_profile,
-                             "single pair 2048x2048 FP32, quadtree s=1..32 g=0.08, alpha=0.05")
+                             "single pair 2048x2048 FP32, quadtree s=1..32 g=0.08, alpha=0.05",
+                             "diff_large")
     dbatch_leg = None
     if dbatch:
         dbatch_leg = diff_leg(pkg, B, dbatch, tau, args.diff_batch_iters, side, args.no_profile,
                               f"{len(dbatch)} pairs 512x512 12-bit, per-pair alpha log-uniform "
-                              f"in [0.02, 0.2]")
+                              f"in [0.02, 0.2]", "diff_batch")
 
     unstructured = None
     if upair is not None:
