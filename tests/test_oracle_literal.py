@@ -114,3 +114,32 @@ def test_explicit_run_lowers_the_msd_at_a_stable_step():
     m0 = reg.msd(pb, np.zeros((V.shape[0], 2)))
     _, ms = lit.run(pb, None, 20, 20.0, 0.8, record_msd=True)
     assert ms[-1] < 0.8 * m0
+
+
+def test_division_free_form_of_the_node_gradient_equals_eq9_eq10():
+    """The kernel's form of eq. 9-10: with cr the doubled signed area and
+    S = sum_v t_v R(P_{v+2} - P_{v+1}), R(x, y) = (-y, x), the node mean is
+    sum sign(cr) S / sum |cr|.  Checked against the oracle (eq. 9 as printed,
+    unsigned areas) on a deformed mesh with folded triangles."""
+    te, re, V, T, _ = small_pair(seed=6, side=32)
+    rng = np.random.default_rng(11)
+    P = V + rng.uniform(-1.5, 1.5, size=V.shape)          # large enough to fold some
+    f = np.cos(0.2 * P[:, 0]) + 0.1 * P[:, 1]
+    T = np.asarray(T)
+    Q = P[T]                                              # [nT][3][2]
+    cr = ((Q[:, 1, 0] - Q[:, 0, 0]) * (Q[:, 2, 1] - Q[:, 0, 1])
+          - (Q[:, 1, 1] - Q[:, 0, 1]) * (Q[:, 2, 0] - Q[:, 0, 0]))
+    assert (cr < 0).any() and (cr > 0).any()
+    S = np.zeros((T.shape[0], 2))
+    for v in range(3):
+        a, b = (v + 1) % 3, (v + 2) % 3
+        d = Q[:, b] - Q[:, a]
+        S[:, 0] -= f[T[:, v]] * d[:, 1]
+        S[:, 1] += f[T[:, v]] * d[:, 0]
+    num = np.zeros((V.shape[0], 2))
+    den = np.zeros(V.shape[0])
+    for v in range(3):
+        np.add.at(num, T[:, v], np.sign(cr)[:, None] * S)
+        np.add.at(den, T[:, v], np.abs(cr))
+    g = num / den[:, None]
+    assert np.abs(g - lit.node_gradient(P, T, f)).max() < 1e-9 * max(1.0, np.abs(g).max())
