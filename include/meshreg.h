@@ -198,7 +198,8 @@ int mesh_reg_force(mr_ctx *ctx, const double *u, float *h, double *b, void *stre
  * solves of the Cholesky factor.  b, x: DEVICE [sum n][2]; may alias. */
 int mesh_reg_solve(mr_ctx *ctx, const double *b, double *x, void *stream);
 
-/* Reverse mode through n_iter iterations from u0 followed by the warp + MSD:
+/* Reverse mode of the objective of eq. 1 as unrolled by Algorithm 1 (n_iter
+ * semi-implicit iterations from u0, eq. 3-8, then the warp + MSD of Section 1):
  * with L = sum_p g_msd[p] * MSD_p(u^N), writes dL/du0 (DEVICE [sum n][2] FP64 or
  * NULL), dL/dalpha_p (DEVICE [n_pairs] FP64 or NULL), dL/dTe (DEVICE [sum H*W]
  * FP32 or NULL) and the forward MSDs (DEVICE [n_pairs] FP64 or NULL).
@@ -208,8 +209,12 @@ int mesh_reg_backward(mr_ctx *ctx, const double *u0, int32_t n_iter, int32_t ckp
                       const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
                       double *msd, void *stream);
 
-/* Replace pair `pair`'s alpha: numeric re-factorisation of (I + tau alpha K) with
- * the symbolic analysis reused, then upload.  Synchronises `stream`. */
+/* Replace pair `pair`'s alpha, the regularisation weight of eq. 1 (alpha S[u]):
+ * numeric re-factorisation of (I + tau alpha K) with the symbolic analysis
+ * reused, then upload.  Synchronises `stream`.  Errors: MR_EINVAL (pair out of
+ * range, alpha negative or not finite), MR_ENOTSPD (a pivot overflows or is not
+ * positive), MR_EHIP; on MR_EINVAL and MR_ENOTSPD the pair keeps its old alpha
+ * and factor. */
 int mesh_reg_set_alpha(mr_ctx *ctx, int32_t pair, double alpha, void *stream);
 
 /* Replace pair `pair`'s template (DEVICE [H][W] FP32): recomputes its spline

@@ -10,8 +10,11 @@ the gradients with respect to ``u0`` (``[sum n][2]`` FP64), ``alpha``
 
 ``alpha`` and ``te`` are pushed into the library before the forward pass
 (``mesh_reg_set_alpha`` re-factorises a pair whose alpha changed;
-``mesh_reg_set_template`` re-computes the spline coefficients), so they must
-not be changed between a forward and its backward.
+``mesh_reg_set_template`` re-computes the spline coefficients) and pushed
+again before the backward pass, so each backward differentiates at the values
+its own forward used, also when several applications share one ``MeshReg``
+(with ``alpha=None`` the pairs' alphas at the forward are restored; with
+``te=None`` the backward refuses to run if the template was replaced since).
 """
 from __future__ import annotations
 
@@ -22,13 +25,8 @@ from .registration import MeshReg
 
 def push_parameters(reg: MeshReg, alpha: torch.Tensor | None, te: torch.Tensor | None) -> None:
     if alpha is not None:
-        vals = alpha.detach().to("cpu", torch.float64).tolist()
-        cache = getattr(reg, "_alpha_cache", [None] * reg.n_pairs)
-        for p, a in enumerate(vals):
-            if cache[p] != a:
-                reg.set_alpha(p, a)
-                cache[p] = a
-        reg._alpha_cache = cache
+        for p, a in enumerate(alpha.detach().to("cpu", torch.float64).tolist()):
+            reg.set_alpha(p, a)              # a no-op when the pair already has this alpha
     if te is not None:
         flat = te.detach().to(device=reg.device, dtype=torch.float32).contiguous().view(-1)
         for p in range(reg.n_pairs):
@@ -47,6 +45,11 @@ class MeshRegUnrolled(torch.autograd.Function):
         ctx.ckpt_every = int(ckpt_every)
         ctx.alpha_meta = (alpha.device, alpha.dtype) if alpha is not None else None
         ctx.te_meta = (te.device, te.dtype, te.shape) if te is not None else None
+        # the values this forward ran at, pushed again before its backward
+        ctx.alpha_val = (alpha.detach().clone() if alpha is not None
+                         else torch.tensor(reg.alphas(), dtype=torch.float64))
+        ctx.te_val = te.detach().clone() if te is not None else None
+        ctx.te_version = reg.template_version
         ctx.save_for_backward(u0.detach().to(torch.float64).contiguous())
         return msd
 
@@ -54,6 +57,10 @@ class MeshRegUnrolled(torch.autograd.Function):
     def backward(ctx, grad_msd):
         (u0,) = ctx.saved_tensors
         g = grad_msd.detach().to(device=u0.device, dtype=torch.float64).contiguous()
+        if ctx.te_val is None and ctx.reg.template_version != ctx.te_version:
+            raise RuntimeError("the template was replaced between this forward and its backward; "
+                               "pass te to the apply to differentiate at a template of its own")
+        push_parameters(ctx.reg, ctx.alpha_val, ctx.te_val)
         _, g_u0, g_alpha, g_te = ctx.reg.backward(u0, ctx.n_iter, ctx.ckpt_every, g_msd=g)
         ga = gt = None
         if ctx.alpha_meta is not None:

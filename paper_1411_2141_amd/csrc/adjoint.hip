@@ -266,7 +266,9 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   const int n_ck = n_seg + 1;
   const size_t nb = sizeof(double2) * (size_t)N;
   if ((int64_t)d_ck.count < (int64_t)n_ck * N) HIP_OK(d_ck.alloc((size_t)n_ck * N));
-  if ((int64_t)d_seg.count < (int64_t)ckpt_every * N) HIP_OK(d_seg.alloc((size_t)ckpt_every * N));
+  // recomputed iterates strictly inside a segment: at most min(ckpt_every, n_iter) - 1
+  const int64_t seg_slots = std::max(0, std::min(ckpt_every, n_iter) - 1);
+  if (seg_slots > 0 && (int64_t)d_seg.count < seg_slots * N) HIP_OK(d_seg.alloc((size_t)(seg_slots * N)));
   if ((int64_t)d_lam.count < N) {
     HIP_OK(d_lam.alloc(N));
     HIP_OK(d_lam_s.alloc(N));
@@ -308,10 +310,10 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int k0 = sg * ckpt_every, k1 = std::min(n_iter, k0 + ckpt_every);
     auto iterate_at = [&](int k) -> const double2 * {
-      return k == k0 ? ckpt(sg) : k == k1 ? ckpt(sg + 1) : seg + (size_t)(k - k0) * N;
+      return k == k0 ? ckpt(sg) : k == k1 ? ckpt(sg + 1) : seg + (size_t)(k - k0 - 1) * N;
     };
     for (int k = k0; k + 1 < k1; ++k) {
-      double2 *dst = seg + (size_t)(k - k0 + 1) * N;
+      double2 *dst = seg + (size_t)(k - k0) * N;
       HIP_OK(hipMemcpyAsync(dst, iterate_at(k), nb, hipMemcpyDeviceToDevice, s));
       // x still holds u^k from the previous recomputed iteration, except at
       // the segment's start (a checkpoint)

@@ -1270,19 +1270,30 @@ extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *s
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MR_EINVAL, "alpha must be finite and >= 0");
   PairHost &h = c->host[pair];
   const double old = h.alpha;
+  // on any failure the host factor goes back to the old alpha (the device
+  // copy was never touched), so the context stays as it was
+  auto restore = [&]() {
+    h.alpha = old;
+    bool dummy;
+    refactor(h, c->params.tau, &dummy);
+    fill_dense_inverses(h);
+    fill_panels(h);
+    fill_apex_inverse(h);
+  };
   h.alpha = alpha;
   bool not_spd = false;
   std::string e = refactor(h, c->params.tau, &not_spd);
   if (!e.empty()) {
-    h.alpha = old;
-    bool dummy;
-    refactor(h, c->params.tau, &dummy);
+    restore();
     return fail(not_spd ? MR_ENOTSPD : MR_EINVAL, e);
   }
   fill_dense_inverses(h);
   fill_panels(h);
   e = fill_apex_inverse(h);
-  if (!e.empty()) return fail(MR_EINVAL, e);
+  if (!e.empty()) {
+    restore();
+    return fail(MR_EINVAL, e);
+  }
   if (c->host_only) return MR_OK;
   hipStream_t s = (hipStream_t)stream;
   return c->upload_factor(pair, s);

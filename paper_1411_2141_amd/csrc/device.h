@@ -8,7 +8,6 @@ namespace mr {
 
 constexpr int kBlockMax = 96;      // largest dense diagonal block of the solve
 constexpr int kSolveLdsBudget = 64 * 1024 - 512;  // dynamic LDS per solve workgroup (static use < 512 B)
-constexpr int kSolveThreads = 256;
 constexpr int kTile = 16;          // warp tiles are kTile x kTile pixels
 constexpr int kNodeChunk = 256;    // nodes per sample work item
 

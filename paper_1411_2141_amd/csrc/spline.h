@@ -62,13 +62,6 @@ __device__ __forceinline__ void bs_deriv(float t, float d[4]) {
   d[3] = 0.5f * t2;
 }
 
-__device__ __forceinline__ void bs_deriv2(float t, float e[4]) {
-  e[0] = 1.0f - t;
-  e[1] = 3.0f * t - 2.0f;
-  e[2] = 1.0f - 3.0f * t;
-  e[3] = t;
-}
-
 // Integer cell and fraction of base + off.  Non-finite or absurd offsets are
 // replaced by 0 (so no tap leaves the image) and reported through the result.
 __device__ __forceinline__ bool split_coord(int base, double off, int &cell, float &frac) {

@@ -57,6 +57,8 @@ class MeshReg:
         self.tau = float(tau)
         self.n_pairs = len(pairs)
         self.shapes = [(s["height"], s["width"]) for s in specs]
+        self._alpha = [s["alpha"] for s in specs]       # each pair's alpha in the library
+        self.template_version = 0                         # counts set_template calls
         self.n_nodes = [int(s["V"].shape[0]) for s in specs]
         self.node_offsets = np.concatenate([[0], np.cumsum(self.n_nodes)]).astype(np.int64)
         self.pixel_offsets = np.concatenate(
@@ -141,10 +143,20 @@ class MeshReg:
         return msd, g_u0, g_alpha, g_te
 
     def set_alpha(self, pair: int, alpha: float) -> None:
+        """Re-factorises pair ``pair`` for ``alpha`` (skipped when it already has it)."""
+        alpha = float(alpha)
+        if self._alpha[pair] == alpha:
+            return
         B.mesh_reg_set_alpha(self.ctx, pair, alpha, None if self.host_only else _stream())
+        self._alpha[pair] = alpha
 
     def set_template(self, pair: int, te: torch.Tensor) -> None:
         B.mesh_reg_set_template(self.ctx, pair, te.contiguous(), _stream())
+        self.template_version += 1
+
+    def alphas(self) -> list:
+        """Each pair's alpha as the library holds it."""
+        return list(self._alpha)
 
     # -- introspection -------------------------------------------------------------
     def table(self, pair: int, name: str) -> np.ndarray:

@@ -181,3 +181,32 @@ def test_autograd_function_matches_library_backward():
     pb2 = reg.setup(d["te"], d["re"], d["V"], d["T"], 0.9, 0.6)
     assert abs(m2.item() - reg.msd(pb2, reg.run(pb2, None, 4)[0])) <= 1e-5 * m2.item()
     ctx.close()
+
+
+def test_autograd_two_applies_at_different_alpha_before_one_backward():
+    """(f(a1) + f(a2)).backward(): each backward runs at its own forward's
+    alpha, so the sum of the two gradients equals the oracle's at a1 plus the
+    oracle's at a2; a direct set_alpha afterwards is not undone by a later
+    apply with alpha=None."""
+    say("autograd: two applies at different alpha, one backward")
+    d = cases()["adaptive_48"]
+    ctx = pkg().MeshReg([d], tau=0.6)
+    N = 3
+    u0 = torch.zeros((d["V"].shape[0], 2), dtype=torch.float64, device="cuda", requires_grad=True)
+    a1 = torch.tensor([0.3], dtype=torch.float64, requires_grad=True)
+    a2 = torch.tensor([1.1], dtype=torch.float64, requires_grad=True)
+    loss = pkg().unrolled_msd(ctx, u0, a1, None, n_iter=N) + pkg().unrolled_msd(ctx, u0, a2, None, n_iter=N)
+    loss.sum().backward()
+    torch.cuda.synchronize()
+    want_u = 0.0
+    for a, t in ((0.3, a1), (1.1, a2)):
+        pb = reg.setup(d["te"], d["re"], d["V"], d["T"], a, 0.6)
+        L, gu, ga, _ = oadj.gradient(pb, None, N)
+        assert abs(t.grad.item() - ga) <= G_TOL * abs(ga), (a, t.grad.item(), ga)
+        want_u = want_u + gu
+    assert rel(u0.grad.cpu().numpy(), want_u) < G_TOL
+    ctx.set_alpha(0, 0.5)
+    m = pkg().unrolled_msd(ctx, u0.detach(), None, None, n_iter=N)
+    pb = reg.setup(d["te"], d["re"], d["V"], d["T"], 0.5, 0.6)
+    assert abs(m.item() - reg.msd(pb, reg.run(pb, None, N)[0])) <= 1e-5 * m.item()
+    ctx.close()

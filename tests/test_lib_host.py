@@ -157,3 +157,22 @@ def test_set_alpha_host_only_and_rejects_negative():
         ctx.set_alpha(0, -0.5)
     assert ei.value.code == B.MR_EINVAL
     ctx.close()
+
+
+def test_overflowing_alpha_is_not_positive_definite_and_leaves_the_factor():
+    """tau alpha K overflows the pivots for alpha near the largest double: the
+    factorisation reports MR_ENOTSPD, at init and from set_alpha, and a failed
+    set_alpha leaves the pair usable (a later set_alpha succeeds)."""
+    te, re_, V, T, _ = small_pair(seed=2, side=32)
+    with pytest.raises(B.MeshRegError) as ei:
+        host_ctx([dict(te=te, re=re_, V=V, T=T, alpha=1e308)])
+    assert ei.value.code == B.MR_ENOTSPD
+    ctx = host_ctx([dict(te=te, re=re_, V=V, T=T, alpha=0.1)])
+    nnz = ctx.info(0, "nnz_l")
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_set_alpha(ctx.ctx, 0, 1e308, None)
+    assert ei.value.code == B.MR_ENOTSPD
+    assert ctx.alphas() == [0.1]
+    B.mesh_reg_set_alpha(ctx.ctx, 0, 0.7, None)
+    assert ctx.info(0, "nnz_l") == nnz
+    ctx.close()
