@@ -7,9 +7,11 @@
 // alpha on the host; the GPU only runs the two triangular solves per iteration.
 //
 // Ordering: geometric nested dissection on the node coordinates.  A node set is
-// split at the median coordinate of its wider axis; the separator is the
-// smaller of the two one-sided boundary sets; the halves are ordered first,
-// the separator last.  Small sets become leaf blocks, separators become one or
+// split by a straight cut across one axis, chosen among the positions that
+// leave each side at least a fifth of the set for the smallest separator per
+// pair of halves (not at the median: on adaptive meshes a cut through coarse
+// cells crosses few nodes); the separator is the smaller of the two one-sided
+// boundary sets; the halves are ordered first, the separator last.  Small sets become leaf blocks, separators become one or
 // more chained blocks.  Every block is a contiguous row range of P S P^T and
 // the block tree contains the elimination tree, which is what lets the solve
 // run block-parallel level by level.
@@ -42,33 +44,112 @@ struct NDState {
     return (int32_t)ranges.size() - 1;
   }
 
+  struct Cut {
+    int axis;        // coordinate axis (0: x, 1: y)
+    int32_t value;   // nodes whose coordinate is < value go left
+  };
+
+  // The cut of S.  Candidates: for each coordinate axis, every position c
+  // whose two sides each hold at least a fraction `nd_balance` of S.  Each
+  // is scored by the size of the smaller one-sided boundary set it leaves
+  // (the separator it would give), divided by the product of the two side
+  // sizes (nd_score 1: small separators between large halves) or alone
+  // (nd_score 0), computed for all c at once from per-node intervals: a node
+  // v left of c is on the left boundary iff c <= (largest coordinate among
+  // its neighbours in S), a node right of c is on the right boundary iff
+  // c > (smallest coordinate among its neighbours in S).  The best score
+  // wins, ties going to the more balanced cut, then to axis 0.  On adaptive
+  // meshes the cut moves off the median into coarse regions, where few
+  // nodes lie along it.
+  Cut best_cut(const std::vector<int32_t> &S) {
+    for (int32_t v : S) side[v] = 0;                  // membership of S
+    const auto &ptr = p.tab.t2_ptr;
+    const auto &idx = p.tab.t2_idx;
+    const int64_t ns = (int64_t)S.size();
+    Cut best{0, 0};
+    int64_t best_sep = INT64_MAX, best_imb = INT64_MAX;
+    for (int axis = 0; axis < 2; ++axis) {
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      for (int32_t v : S) {
+        lo = std::min(lo, p.xy[2 * v + axis]);
+        hi = std::max(hi, p.xy[2 * v + axis]);
+      }
+      if (hi == lo) continue;
+      const int32_t len = hi - lo + 2;
+      std::vector<int64_t> below(len + 1, 0), dl(len + 1, 0), dr(len + 1, 0);
+      for (int32_t v : S) {
+        const int32_t cv = p.xy[2 * v + axis] - lo;
+        int32_t mx = cv, mn = cv;
+        for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+          const int32_t w = (int32_t)idx[k];
+          if (side[w] < 0) continue;
+          const int32_t cw = p.xy[2 * w + axis] - lo;
+          mx = std::max(mx, cw);
+          mn = std::min(mn, cw);
+        }
+        below[cv + 1] += 1;               // nodes with coordinate < c, counted from c = cv + 1 on
+        if (mx > cv) {                    // left boundary for cv < c <= mx
+          dl[cv + 1] += 1;
+          dl[mx + 1] -= 1;
+        }
+        if (mn < cv) {                    // right boundary for mn < c <= cv
+          dr[mn + 1] += 1;
+          dr[cv + 1] -= 1;
+        }
+      }
+      int64_t nb = 0, sl = 0, sr = 0;
+      for (int32_t c = 0; c <= len; ++c) {
+        nb += below[c];
+        sl += dl[c];
+        sr += dr[c];
+        if (c == 0 || c > hi - lo) continue;
+        const int64_t left = nb, right = ns - nb;
+        if ((double)std::min(left, right) < opt.nd_balance * (double)ns) continue;
+        int64_t sep = std::min(sl, sr);
+        const int64_t imb = std::abs(left - right);
+        if (opt.nd_score == 1)
+          sep = (int64_t)(1e12 * (double)(sep + 1) / ((double)left * (double)right));
+        if (sep < best_sep || (sep == best_sep && imb < best_imb)) {
+          best_sep = sep;
+          best_imb = imb;
+          best = Cut{axis, lo + c};
+        }
+      }
+    }
+    if (best_sep == INT64_MAX) {
+      // no admissible cut (tiny or degenerate sets): the median of the wider axis
+      int32_t lo[2] = {INT32_MAX, INT32_MAX}, hi[2] = {INT32_MIN, INT32_MIN};
+      for (int32_t v : S)
+        for (int a = 0; a < 2; ++a) {
+          lo[a] = std::min(lo[a], p.xy[2 * v + a]);
+          hi[a] = std::max(hi[a], p.xy[2 * v + a]);
+        }
+      int axis = (hi[0] - lo[0] >= hi[1] - lo[1]) ? 0 : 1;
+      if (hi[axis] == lo[axis]) axis ^= 1;
+      std::vector<int32_t> tmp;
+      for (int32_t v : S) tmp.push_back(p.xy[2 * v + axis]);
+      std::nth_element(tmp.begin(), tmp.begin() + tmp.size() / 2, tmp.end());
+      int32_t c = tmp[tmp.size() / 2];
+      if (c == lo[axis]) {
+        int32_t nxt = INT32_MAX;
+        for (int32_t v : tmp)
+          if (v > lo[axis]) nxt = std::min(nxt, v);
+        c = nxt;
+      }
+      best = Cut{axis, c};
+    }
+    for (int32_t v : S) side[v] = -1;
+    return best;
+  }
+
   // Orders `S` (consumed) and returns the block id of its subtree root.
   int32_t run(std::vector<int32_t> S) {
     if ((int32_t)S.size() <= opt.leaf_max) {
       std::sort(S.begin(), S.end());
       return emit(S);
     }
-    int32_t lo[2] = {INT32_MAX, INT32_MAX}, hi[2] = {INT32_MIN, INT32_MIN};
-    for (int32_t v : S)
-      for (int a = 0; a < 2; ++a) {
-        lo[a] = std::min(lo[a], p.xy[2 * v + a]);
-        hi[a] = std::max(hi[a], p.xy[2 * v + a]);
-      }
-    int axis = (hi[0] - lo[0] >= hi[1] - lo[1]) ? 0 : 1;
-    if (hi[axis] == lo[axis]) axis ^= 1;
-    // split value: the median coordinate, moved up if nothing lies below it
-    std::vector<int32_t> coord(S.size());
-    for (size_t k = 0; k < S.size(); ++k) coord[k] = p.xy[2 * S[k] + axis];
-    std::vector<int32_t> tmp = coord;
-    std::nth_element(tmp.begin(), tmp.begin() + tmp.size() / 2, tmp.end());
-    int32_t c = tmp[tmp.size() / 2];
-    if (c == lo[axis]) {
-      int32_t nxt = INT32_MAX;
-      for (int32_t v : coord)
-        if (v > lo[axis]) nxt = std::min(nxt, v);
-      c = nxt;
-    }
-    for (size_t k = 0; k < S.size(); ++k) side[S[k]] = coord[k] < c ? 0 : 1;
+    const Cut cut = best_cut(S);
+    for (int32_t v : S) side[v] = p.xy[2 * v + cut.axis] < cut.value ? 0 : 1;
     std::vector<int32_t> sepL, sepR;
     const auto &ptr = p.tab.t2_ptr;
     const auto &idx = p.tab.t2_idx;
@@ -95,7 +176,7 @@ struct NDState {
     const int32_t a = A.empty() ? -1 : run(std::move(A));
     const int32_t b = B.empty() ? -1 : run(std::move(B));
     // separator nodes along the cut, then chunked into chained blocks
-    const int other = axis ^ 1;
+    const int other = cut.axis ^ 1;
     std::sort(sep.begin(), sep.end(), [&](int32_t u, int32_t v) {
       const int32_t cu = p.xy[2 * u + other], cv = p.xy[2 * v + other];
       return cu != cv ? cu < cv : u < v;
