@@ -209,6 +209,28 @@ int mesh_reg_backward(mr_ctx *ctx, const double *u0, int32_t n_iter, int32_t ckp
                       const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
                       double *msd, void *stream);
 
+/* The forward pass of the objective of eq. 1 as unrolled by Algorithm 1, keeping
+ * what mesh_reg_backward_ckpt needs: n_iter (>= 0) iterations in place on u
+ * (DEVICE [sum n][2] FP64, in u^0, out u^N) that also write the checkpoints
+ * ckpt[q] = u^{q ckpt_every} for q < n_seg and ckpt[n_seg] = u^N, with
+ * n_seg = ceil(n_iter / ckpt_every) (ckpt: DEVICE [n_seg + 1][sum n][2] FP64,
+ * caller-owned, 16-byte aligned), and the MSD of u^N (msd: DEVICE [n_pairs] FP64
+ * or NULL; Section 1).  The iterates are those of mesh_reg_step bit for bit.
+ * Errors: MR_EINVAL (null or misaligned u or ckpt, n_iter < 0, ckpt_every < 1),
+ * MR_ESTATE, MR_EHIP, MR_ENONFINITE. */
+int mesh_reg_forward_ckpt(mr_ctx *ctx, double *u, int32_t n_iter, int32_t ckpt_every,
+                          double *ckpt, double *msd, void *stream);
+
+/* Reverse mode as mesh_reg_backward, from the checkpoints a mesh_reg_forward_ckpt
+ * call with the same n_iter and ckpt_every wrote (read only; the forward pass is
+ * not run again, only the iterates between checkpoints are recomputed).  The
+ * context's alpha, template and tau must be those of that forward call.
+ * Errors: MR_EINVAL (null or misaligned ckpt or g_u0, null g_msd, n_iter < 0,
+ * ckpt_every < 1), MR_ESTATE, MR_EHIP, MR_ENONFINITE. */
+int mesh_reg_backward_ckpt(mr_ctx *ctx, const double *ckpt, int32_t n_iter, int32_t ckpt_every,
+                           const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
+                           double *msd, void *stream);
+
 /* Replace pair `pair`'s alpha, the regularisation weight of eq. 1 (alpha S[u]):
  * numeric re-factorisation of (I + tau alpha K) with the symbolic analysis
  * reused, then upload.  Synchronises `stream`.  Errors: MR_EINVAL (pair out of

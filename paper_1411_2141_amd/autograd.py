@@ -2,9 +2,10 @@
 
 ``msd = MeshRegUnrolled.apply(reg, u0, alpha, te, n_iter, ckpt_every)`` runs
 ``n_iter`` iterations from ``u0`` on every pair of ``reg`` and returns the
-per-pair MSD of the final warp.  Its backward calls the library's adjoint
-(``mesh_reg_backward``), which recomputes the iterates from checkpoints every
-``ckpt_every`` iterations and reuses each pair's Cholesky factor, and returns
+per-pair MSD of the final warp.  The forward pass writes a checkpoint every
+``ckpt_every`` iterations (``mesh_reg_forward_ckpt``); its backward calls the
+library's adjoint on them (``mesh_reg_backward_ckpt``), which recomputes the
+iterates between checkpoints and reuses each pair's Cholesky factor, and returns
 the gradients with respect to ``u0`` (``[sum n][2]`` FP64), ``alpha``
 (``[n_pairs]`` FP64) and ``te`` (``[sum H*W]`` FP32, pair-major).
 
@@ -38,8 +39,7 @@ class MeshRegUnrolled(torch.autograd.Function):
     def forward(ctx, reg: MeshReg, u0, alpha, te, n_iter: int, ckpt_every: int = 10):
         push_parameters(reg, alpha, te)
         u = u0.detach().to(torch.float64).contiguous().clone()
-        reg.step(u, n_iter)
-        msd = reg.warp_msd(u)
+        msd, ckpt = reg.forward_ckpt(u, n_iter, ckpt_every)
         ctx.reg = reg
         ctx.n_iter = int(n_iter)
         ctx.ckpt_every = int(ckpt_every)
@@ -50,18 +50,18 @@ class MeshRegUnrolled(torch.autograd.Function):
                          else torch.tensor(reg.alphas(), dtype=torch.float64))
         ctx.te_val = te.detach().clone() if te is not None else None
         ctx.te_version = reg.template_version
-        ctx.save_for_backward(u0.detach().to(torch.float64).contiguous())
+        ctx.save_for_backward(ckpt)
         return msd
 
     @staticmethod
     def backward(ctx, grad_msd):
-        (u0,) = ctx.saved_tensors
-        g = grad_msd.detach().to(device=u0.device, dtype=torch.float64).contiguous()
+        (ckpt,) = ctx.saved_tensors
+        g = grad_msd.detach().to(device=ckpt.device, dtype=torch.float64).contiguous()
         if ctx.te_val is None and ctx.reg.template_version != ctx.te_version:
             raise RuntimeError("the template was replaced between this forward and its backward; "
                                "pass te to the apply to differentiate at a template of its own")
         push_parameters(ctx.reg, ctx.alpha_val, ctx.te_val)
-        _, g_u0, g_alpha, g_te = ctx.reg.backward(u0, ctx.n_iter, ctx.ckpt_every, g_msd=g)
+        _, g_u0, g_alpha, g_te = ctx.reg.backward_ckpt(ckpt, ctx.n_iter, ctx.ckpt_every, g_msd=g)
         ga = gt = None
         if ctx.alpha_meta is not None:
             ga = g_alpha.to(device=ctx.alpha_meta[0], dtype=ctx.alpha_meta[1])

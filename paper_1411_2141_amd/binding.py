@@ -30,7 +30,8 @@ KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
 EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_run", "mesh_reg_step_explicit",
             "mesh_reg_warp_msd", "mesh_reg_force",
-            "mesh_reg_solve", "mesh_reg_backward", "mesh_reg_set_alpha", "mesh_reg_set_template",
+            "mesh_reg_solve", "mesh_reg_backward", "mesh_reg_forward_ckpt",
+            "mesh_reg_backward_ckpt", "mesh_reg_set_alpha", "mesh_reg_set_template",
             "mesh_reg_get_tables", "mesh_reg_get_info", "mesh_reg_enable_timing",
             "mesh_reg_kernel_times", "mesh_reg_set_graph", "mesh_reg_destroy",
             "mesh_reg_last_error")
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mesh_reg_force": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mesh_reg_solve": (ctypes.c_int, [vp, vp, vp, vp]),
         "mesh_reg_backward": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "mesh_reg_forward_ckpt": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+        "mesh_reg_backward_ckpt": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "mesh_reg_set_alpha": (ctypes.c_int, [vp, i32, dbl, vp]),
         "mesh_reg_set_template": (ctypes.c_int, [vp, i32, vp, vp]),
         "mesh_reg_get_tables": (ctypes.c_int, [vp, i32, i32, vp, ctypes.POINTER(i64)]),
@@ -165,6 +168,19 @@ def mesh_reg_backward(ctx, u0, n_iter: int, ckpt_every: int, g_msd, g_u0=None, g
     _check(load_library().mesh_reg_backward(ctx, _ptr(u0), int(n_iter), int(ckpt_every),
                                             _ptr(g_msd), _ptr(g_u0), _ptr(g_alpha), _ptr(g_te),
                                             _ptr(msd), stream))
+
+
+def mesh_reg_forward_ckpt(ctx, u, n_iter: int, ckpt_every: int, ckpt, msd=None,
+                          stream=None) -> None:
+    _check(load_library().mesh_reg_forward_ckpt(ctx, _ptr(u), int(n_iter), int(ckpt_every),
+                                                _ptr(ckpt), _ptr(msd), stream))
+
+
+def mesh_reg_backward_ckpt(ctx, ckpt, n_iter: int, ckpt_every: int, g_msd, g_u0=None,
+                           g_alpha=None, g_te=None, msd=None, stream=None) -> None:
+    _check(load_library().mesh_reg_backward_ckpt(ctx, _ptr(ckpt), int(n_iter), int(ckpt_every),
+                                                 _ptr(g_msd), _ptr(g_u0), _ptr(g_alpha),
+                                                 _ptr(g_te), _ptr(msd), stream))
 
 
 def mesh_reg_set_alpha(ctx, pair: int, alpha: float, stream=None) -> None:

@@ -16,6 +16,8 @@
 // The iterates are recomputed from checkpoints every `ckpt_every` iterations
 // (each segment's last iterate is the next checkpoint and is not recomputed)
 // with the forward kernels, so they equal the forward pass bit for bit.  The
+// checkpoints come from a forward pass that writes them as it goes (the
+// caller's, or one the reverse call runs itself).  The
 // adjoint arithmetic is FP64; the scatters into lambda^N and cbar use FP64
 // atomic adds (their summation order is not fixed).
 #include <hip/hip_runtime.h>
@@ -252,20 +254,9 @@ static int bfail(int code, const std::string &msg) { return mr_set_error(code, m
     if (e_ != hipSuccess) return bfail(MR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
-                     double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s) {
-  if (!u0 || !g_msd || n_iter < 0 || ckpt_every < 1 || ((uintptr_t)u0 & 15) ||
-      (g_u0 && ((uintptr_t)g_u0 & 15)))
-    return bfail(MR_EINVAL, "backward: need aligned u0, g_msd, n_iter >= 0, ckpt_every >= 1");
-  int rc = check_flags();
-  if (rc) return rc;
+// Buffers of the reverse sweep (allocated on first use, grown when needed).
+int mr_ctx::reserve_adjoint(int32_t n_iter, int32_t ckpt_every, hipStream_t s) {
   const int64_t N = n_nodes;
-  // checkpoints at every segment boundary: ck[q] = u^{q ckpt_every} for
-  // q < n_seg, ck[n_seg] = u^N
-  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
-  const int n_ck = n_seg + 1;
-  const size_t nb = sizeof(double2) * (size_t)N;
-  if ((int64_t)d_ck.count < (int64_t)n_ck * N) HIP_OK(d_ck.alloc((size_t)n_ck * N));
   // recomputed iterates strictly inside a segment: at most min(ckpt_every, n_iter) - 1
   const int64_t seg_slots = std::max(0, std::min(ckpt_every, n_iter) - 1);
   if (seg_slots > 0 && (int64_t)d_seg.count < seg_slots * N) HIP_OK(d_seg.alloc((size_t)(seg_slots * N)));
@@ -277,28 +268,47 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   if ((int64_t)d_cbar.count < n_pix) HIP_OK(d_cbar.alloc(n_pix));
   if ((int)d_alpha_part.count < n_node_items) HIP_OK(d_alpha_part.alloc(n_node_items));
   if (!d_mwt_t.ptr) {                         // uploaded last: present after a complete upload
-    rc = upload_adjoint_operators(s);
+    const int rc = upload_adjoint_operators(s);
     if (rc) return rc;
   }
-  double2 *ck = d_ck.ptr, *seg = d_seg.ptr;
-  auto ckpt = [&](int q) { return ck + (size_t)q * N; };
-  // forward, iterating in the last checkpoint slot and copying at boundaries
-  double2 *w = ckpt(n_seg);
-  HIP_OK(hipMemcpyAsync(ckpt(0), u0, nb, hipMemcpyDeviceToDevice, s));
-  if (n_seg > 0) HIP_OK(hipMemcpyAsync(w, u0, nb, hipMemcpyDeviceToDevice, s));
+  return MR_OK;
+}
+
+// n_iter iterations from ck[0] (which holds u^0) writing the checkpoints
+// ck[q] = u^{q ckpt_every} for 0 < q < n_seg and ck[n_seg] = u^N; the solve
+// writes u in natural order only at those iterations (the iteration state
+// stays in the solve vector in between).
+hipError_t mr_ctx::forward_ckpt(double2 *ck, int32_t n_iter, int32_t ckpt_every, hipStream_t s) {
+  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  const size_t N = (size_t)n_nodes;
+  hipError_t e = hipSuccess;
+  if (n_iter > 0) e = launch_to_solve_order((int)N, ck, d_iperm.ptr, d_x.ptr, s);
   double *pending = nullptr;
-  for (int k = 0; k < n_iter; ++k) {
-    HIP_OK(iterate(w, nullptr, &pending, k > 0, true, s));
-    if ((k + 1) % ckpt_every == 0 && (k + 1) < n_iter)
-      HIP_OK(hipMemcpyAsync(ckpt((k + 1) / ckpt_every), w, nb, hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k < n_iter && e == hipSuccess; ++k) {
+    const bool last = k + 1 == n_iter, boundary = last || (k + 1) % ckpt_every == 0;
+    double2 *dst = ck + (last ? (size_t)n_seg : (size_t)((k + 1) / ckpt_every)) * N;
+    e = iterate(dst, nullptr, &pending, true, boundary, s);
   }
+  return e;
+}
+
+// Reverse sweep from the checkpoints ck (as forward_ckpt leaves them).
+int mr_ctx::reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
+                    double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s) {
+  const int64_t N = n_nodes;
+  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  const size_t nb = sizeof(double2) * (size_t)N;
+  int rc = reserve_adjoint(n_iter, ckpt_every, s);
+  if (rc) return rc;
+  double2 *seg = d_seg.ptr;
+  auto ckpt = [&](int q) { return ck + (size_t)q * N; };
   // warp adjoint at u^N
   HIP_OK(hipMemsetAsync(d_lam.ptr, 0, nb, s));
   HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
   HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
   timed_begin(MR_KF_WARP, s);
   HIP_OK(launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr, d_pairs.ptr,
-                (const double2 *)ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
+                ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
                 g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr));
   timed_end(s);
   if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));
@@ -306,7 +316,8 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
   // for the first reverse solve; every reverse step writes the next one there
   if (n_iter > 0) HIP_OK(launch_to_solve_order((int)N, d_lam.ptr, d_iperm.ptr, d_lam_s.ptr, s));
   // reverse sweep, one checkpoint segment at a time: u^{k0} and u^{k1} are
-  // checkpoints, the iterates between are recomputed into seg[1 ..]
+  // checkpoints, the iterates between are recomputed into seg[0 ..]
+  double *pending = nullptr;
   for (int sg = n_seg - 1; sg >= 0; --sg) {
     const int k0 = sg * ckpt_every, k1 = std::min(n_iter, k0 + ckpt_every);
     auto iterate_at = [&](int k) -> const double2 * {
@@ -314,10 +325,10 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
     };
     for (int k = k0; k + 1 < k1; ++k) {
       double2 *dst = seg + (size_t)(k - k0) * N;
-      HIP_OK(hipMemcpyAsync(dst, iterate_at(k), nb, hipMemcpyDeviceToDevice, s));
       // x still holds u^k from the previous recomputed iteration, except at
-      // the segment's start (a checkpoint)
-      HIP_OK(iterate(dst, nullptr, &pending, k > k0, true, s));
+      // the segment's start (a checkpoint): permute it in there
+      if (k == k0) HIP_OK(launch_to_solve_order((int)N, ckpt(sg), d_iperm.ptr, d_x.ptr, s));
+      HIP_OK(iterate(dst, nullptr, &pending, true, true, s));
     }
     for (int k = k1 - 1; k >= k0; --k) {
       // mu = S^-1 lambda^{k+1} (right-hand side in solve order, consumed in place)
@@ -343,6 +354,52 @@ int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const
     }
   post_flags(s);
   return MR_OK;
+}
+
+static bool args_ok(int32_t n_iter, int32_t ckpt_every) { return n_iter >= 0 && ckpt_every >= 1; }
+
+int mr_ctx::backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
+                     double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s) {
+  if (!u0 || !g_msd || !args_ok(n_iter, ckpt_every) || ((uintptr_t)u0 & 15) ||
+      (g_u0 && ((uintptr_t)g_u0 & 15)))
+    return bfail(MR_EINVAL, "backward: need aligned u0, g_msd, n_iter >= 0, ckpt_every >= 1");
+  int rc = check_flags();
+  if (rc) return rc;
+  const int64_t N = n_nodes;
+  const int n_ck = (n_iter + ckpt_every - 1) / ckpt_every + 1;
+  if ((int64_t)d_ck.count < (int64_t)n_ck * N) HIP_OK(d_ck.alloc((size_t)n_ck * N));
+  HIP_OK(hipMemcpyAsync(d_ck.ptr, u0, sizeof(double2) * (size_t)N, hipMemcpyDeviceToDevice, s));
+  HIP_OK(forward_ckpt(d_ck.ptr, n_iter, ckpt_every, s));
+  return reverse(d_ck.ptr, n_iter, ckpt_every, g_msd, g_u0, g_alpha, g_te, msd, s);
+}
+
+int mr_ctx::forward_with_ckpt(double *u, int32_t n_iter, int32_t ckpt_every, double *ckpt,
+                              double *msd, hipStream_t s) {
+  if (!u || !ckpt || !args_ok(n_iter, ckpt_every) || ((uintptr_t)u & 15) || ((uintptr_t)ckpt & 15))
+    return bfail(MR_EINVAL, "forward_ckpt: need aligned u and ckpt, n_iter >= 0, ckpt_every >= 1");
+  int rc = check_flags();
+  if (rc) return rc;
+  const size_t nb = sizeof(double2) * (size_t)n_nodes;
+  const int n_seg = (n_iter + ckpt_every - 1) / ckpt_every;
+  double2 *ck = reinterpret_cast<double2 *>(ckpt);
+  HIP_OK(hipMemcpyAsync(ck, u, nb, hipMemcpyDeviceToDevice, s));
+  HIP_OK(forward_ckpt(ck, n_iter, ckpt_every, s));
+  if (n_seg > 0) HIP_OK(hipMemcpyAsync(u, ck + (size_t)n_seg * n_nodes, nb, hipMemcpyDeviceToDevice, s));
+  if (msd) HIP_OK(warp(ck + (size_t)n_seg * n_nodes, msd, nullptr, s));
+  post_flags(s);
+  return MR_OK;
+}
+
+int mr_ctx::backward_from_ckpt(const double *ckpt, int32_t n_iter, int32_t ckpt_every,
+                               const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
+                               double *msd, hipStream_t s) {
+  if (!ckpt || !g_msd || !args_ok(n_iter, ckpt_every) || ((uintptr_t)ckpt & 15) ||
+      (g_u0 && ((uintptr_t)g_u0 & 15)))
+    return bfail(MR_EINVAL, "backward_ckpt: need aligned ckpt, g_msd, n_iter >= 0, ckpt_every >= 1");
+  int rc = check_flags();
+  if (rc) return rc;
+  return reverse(reinterpret_cast<const double2 *>(ckpt), n_iter, ckpt_every, g_msd, g_u0, g_alpha,
+                 g_te, msd, s);
 }
 
 // Stiffness rows (FP64) and the column-normalised mass M_ij / m_j on the

@@ -1455,6 +1455,22 @@ extern "C" int mesh_reg_kernel_times(mr_ctx *c, double *ms, int64_t *launches) {
 
 extern "C" void mesh_reg_destroy(mr_ctx *c) { delete c; }
 
+extern "C" int mesh_reg_forward_ckpt(mr_ctx *c, double *u, int32_t n_iter, int32_t ckpt_every,
+                                     double *ckpt, double *msd, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  return c->forward_with_ckpt(u, n_iter, ckpt_every, ckpt, msd, (hipStream_t)stream);
+}
+
+extern "C" int mesh_reg_backward_ckpt(mr_ctx *c, const double *ckpt, int32_t n_iter,
+                                      int32_t ckpt_every, const double *g_msd, double *g_u0,
+                                      double *g_alpha, float *g_te, double *msd, void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  return c->backward_from_ckpt(ckpt, n_iter, ckpt_every, g_msd, g_u0, g_alpha, g_te, msd,
+                               (hipStream_t)stream);
+}
+
 extern "C" int mesh_reg_backward(mr_ctx *c, const double *u0, int32_t n_iter, int32_t ckpt_every,
                                  const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
                                  double *msd, void *stream) {

@@ -166,6 +166,15 @@ struct mr_ctx {
   int64_t device_bytes() const;
   int backward(const double *u0, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
                double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s);
+  int forward_with_ckpt(double *u, int32_t n_iter, int32_t ckpt_every, double *ckpt, double *msd,
+                        hipStream_t s);
+  int backward_from_ckpt(const double *ckpt, int32_t n_iter, int32_t ckpt_every,
+                         const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
+                         double *msd, hipStream_t s);
+  int reserve_adjoint(int32_t n_iter, int32_t ckpt_every, hipStream_t s);
+  hipError_t forward_ckpt(double2 *ck, int32_t n_iter, int32_t ckpt_every, hipStream_t s);
+  int reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const double *g_msd,
+              double *g_u0, double *g_alpha, float *g_te, double *msd, hipStream_t s);
 };
 
 namespace mr {

@@ -142,6 +142,37 @@ class MeshReg:
                             g_u0, g_alpha, g_te, msd, _stream())
         return msd, g_u0, g_alpha, g_te
 
+    def checkpoints(self, n_iter: int, ckpt_every: int) -> torch.Tensor:
+        """A checkpoint buffer for ``forward_ckpt``: ``[ceil(n_iter / ckpt_every) + 1][sum n][2]``."""
+        n_seg = -(-int(n_iter) // int(ckpt_every))
+        return torch.empty((n_seg + 1, self.total_nodes, 2), dtype=torch.float64, device=self.device)
+
+    def forward_ckpt(self, u: torch.Tensor, n_iter: int, ckpt_every: int = 10, ckpt=None):
+        """``n_iter`` iterations in place on ``u`` that also write the
+        checkpoints the reverse pass needs; returns ``(msd, ckpt)`` with the
+        per-pair MSD of the final ``u``."""
+        if ckpt is None:
+            ckpt = self.checkpoints(n_iter, ckpt_every)
+        msd = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device)
+        B.mesh_reg_forward_ckpt(self.ctx, u, n_iter, ckpt_every, ckpt, msd, _stream())
+        return msd, ckpt
+
+    def backward_ckpt(self, ckpt: torch.Tensor, n_iter: int, ckpt_every: int = 10, g_msd=None,
+                      want_u0: bool = True, want_alpha: bool = True, want_te: bool = True):
+        """Gradients as ``backward`` from the checkpoints ``forward_ckpt`` wrote
+        (no forward pass of its own): ``(msd, g_u0, g_alpha, g_te)``."""
+        if g_msd is None:
+            g_msd = torch.ones(self.n_pairs, dtype=torch.float64, device=self.device)
+        g_u0 = (torch.empty((self.total_nodes, 2), dtype=torch.float64, device=self.device)
+                if want_u0 else None)
+        g_alpha = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device) if want_alpha else None
+        g_te = (torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
+                if want_te else None)
+        msd = torch.empty(self.n_pairs, dtype=torch.float64, device=self.device)
+        B.mesh_reg_backward_ckpt(self.ctx, ckpt, n_iter, ckpt_every, g_msd.contiguous(), g_u0,
+                                 g_alpha, g_te, msd, _stream())
+        return msd, g_u0, g_alpha, g_te
+
     def set_alpha(self, pair: int, alpha: float) -> None:
         """Re-factorises pair ``pair`` for ``alpha`` (skipped when it already has it)."""
         alpha = float(alpha)

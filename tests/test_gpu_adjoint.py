@@ -210,3 +210,62 @@ def test_autograd_two_applies_at_different_alpha_before_one_backward():
     pb = reg.setup(d["te"], d["re"], d["V"], d["T"], 0.5, 0.6)
     assert abs(m.item() - reg.msd(pb, reg.run(pb, None, N)[0])) <= 1e-5 * m.item()
     ctx.close()
+
+
+@pytest.mark.parametrize("n_iter,ckpt", [(7, 3), (6, 6), (5, 1), (4, 10), (0, 10)])
+def test_forward_checkpoints_then_reverse_pass(n_iter, ckpt):
+    """mesh_reg_forward_ckpt: u^N and every checkpoint equal mesh_reg_step's
+    iterates bit for bit, and the MSD equals warp_msd's at u^N;
+    mesh_reg_backward_ckpt from those checkpoints equals mesh_reg_backward
+    (which runs its own forward) and the oracle."""
+    say(f"forward with checkpoints + reverse pass, N={n_iter} ckpt={ckpt}")
+    d = cases()["adaptive_48"]
+    tau = 0.7
+    ctx = pkg().MeshReg([d], tau=tau)
+    u0 = np.random.default_rng(12).normal(scale=0.3, size=(d["V"].shape[0], 2))
+    u = dev(u0)
+    msd_f, ck = ctx.forward_ckpt(u, n_iter, ckpt)
+    torch.cuda.synchronize()
+    n_seg = -(-n_iter // ckpt)
+    assert ck.shape[0] == n_seg + 1
+    for q in range(n_seg + 1):
+        k = min(q * ckpt, n_iter)
+        w = dev(u0)
+        ctx.step(w, k)
+        assert torch.equal(ck[q], w), (q, k)
+    assert torch.equal(ck[n_seg], u)
+    assert msd_f.item() == ctx.warp_msd(u).item()
+    msd_b, gu_b, ga_b, gt_b = ctx.backward_ckpt(ck, n_iter, ckpt)
+    msd_r, gu_r, ga_r, gt_r = ctx.backward(dev(u0), n_iter, ckpt)
+    torch.cuda.synchronize()
+    assert msd_b.item() == msd_r.item()
+    assert torch.equal(gu_b, gu_r) or rel(gu_b.cpu().numpy(), gu_r.cpu().numpy()) < 1e-10
+    assert abs(ga_b.item() - ga_r.item()) <= 1e-10 * abs(ga_r.item()) + 1e-300
+    assert rel(gt_b.cpu().numpy(), gt_r.cpu().numpy()) < 1e-6
+    pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau)
+    L, gu, ga, gt = oadj.gradient(pb, u0, n_iter)
+    assert abs(msd_b.item() - L) <= 1e-5 * L
+    assert rel(gu_b.cpu().numpy(), gu) < G_TOL
+    assert abs(ga_b.item() - ga) <= G_TOL * abs(ga) + 1e-14
+    assert rel(gt_b.cpu().numpy().reshape(d["te"].shape), gt) < G_TOL
+    ctx.close()
+
+
+def test_checkpoint_entry_points_reject_bad_arguments():
+    say("forward/backward checkpoint argument checks")
+    d = cases()["adaptive_48"]
+    ctx = pkg().MeshReg([d], tau=0.5)
+    u = ctx.zeros_u()
+    ck = ctx.checkpoints(4, 2)
+    g = torch.ones(1, dtype=torch.float64, device="cuda")
+    for args in ((u, -1, 2, ck), (u, 4, 0, ck), (None, 4, 2, ck), (u, 4, 2, None)):
+        with pytest.raises(pkg().binding.MeshRegError) as ei:
+            pkg().binding.mesh_reg_forward_ckpt(ctx.ctx, *args)
+        assert ei.value.code == pkg().binding.MR_EINVAL
+    with pytest.raises(pkg().binding.MeshRegError) as ei:
+        pkg().binding.mesh_reg_backward_ckpt(ctx.ctx, ck, 4, 0, g)
+    assert ei.value.code == pkg().binding.MR_EINVAL
+    with pytest.raises(pkg().binding.MeshRegError) as ei:
+        pkg().binding.mesh_reg_backward_ckpt(ctx.ctx, ck, 4, 2, None)
+    assert ei.value.code == pkg().binding.MR_EINVAL
+    ctx.close()

@@ -146,6 +146,12 @@ def test_host_only_context_refuses_device_calls():
     with pytest.raises(B.MeshRegError) as ei:
         B.mesh_reg_step_explicit(ctx.ctx, None, 1, 20.0, 0.8)
     assert ei.value.code == B.MR_ESTATE
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_forward_ckpt(ctx.ctx, None, 4, 2, None)
+    assert ei.value.code == B.MR_ESTATE
+    with pytest.raises(B.MeshRegError) as ei:
+        B.mesh_reg_backward_ckpt(ctx.ctx, None, 4, 2, None)
+    assert ei.value.code == B.MR_ESTATE
     ctx.close()
 
 
