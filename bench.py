@@ -1,26 +1,45 @@
 """Throughput of the registration hot path on one MI355X.
 
-Headline (``value``): one step = one iteration of the method on the 512x512
-12-bit single-pair workload (quadtree mesh s=1..32, g=0.08; alpha=0.05,
-tau=0.5): template sampling at the displaced nodes, P1 force assembly, the
-two FP64 triangular solves of (I + tau alpha K), and the full-pixel warp + MSD
-(every iteration).  The timed region runs exactly ``--steps`` iterations from
-u = 0 with every input already resident in device memory.
+Headline (``value``): the 256-pair ragged batch (sides drawn from
+{128, ..., 1024}, FP32 images, quadtree meshes s=1..32 g=0.10, alpha=0.05,
+tau=0.5; 8.75 M nodes, 86 M pixels), one step = one iteration of the method on
+every pair: template sampling at the displaced nodes, P1 force assembly and
+the two FP64 triangular solves of (I + tau alpha K), all pairs in each launch,
+replayed from a HIP graph.  The timed region runs exactly ``--steps``
+iterations from u = 0 followed by the warp + MSD of the result, with every
+input already resident in device memory.
 
-Extra legs in the same JSON line (same numerator, nodes x iterations):
-  fwd_bwd    -- the same pair, 100 iterations forward plus the checkpointed
-                reverse pass (gradients w.r.t. u0, alpha and the template);
-  batched    -- 256 ragged pairs (sides 128..1024, s=1..32, g=0.10), 100
-                iterations per call, all pairs in every launch, HIP-graph replay;
-  large_pair -- one 2048x2048 pair (559k nodes), 50 iterations: plain against
-                forward + reverse pass (checkpoint 10);
-  diff_batch -- 64 pairs of 512x512 with per-pair alpha, 100 iterations: plain
-                against forward + reverse pass (checkpoint 10);
+``roofline`` is the dominant kernel family's (the solve's) algorithmic bytes
+per launch over its average launch time (events attached to each dispatch),
+against the 8 TB/s HBM peak; algorithmic bytes per iteration are those of the
+method (each datum counted once):
+  sample   36 n + 4 |C|    (u 16, node corner 8, reference sample 4, force
+                            density 8 per node; |C| coefficients touched)
+  assemble 16 n_T + 44 n   (corner slots 12 and weight 4 per triangle; force
+                            density 8, lumped-mass reciprocal 4, u 16, b 16
+                            per node)
+  solve    24 nnz(L) + 64 n (each factor entry, value and index, read once
+                            per triangular pass for both components; b, x in
+                            and out per node)
+  warp     12 P + 16 n     (reference, coefficient and triangle id per pixel;
+                            u per node)
+The library's own layout bytes (dense block inverses, the apex inverse, CSR
+weights) and the HBM traffic the counters measured are reported beside them.
+
+Further legs in the same JSON line (node-updates/s = nodes x iterations / s):
+  single_pair -- one 512x512 12-bit pair, 200 iterations with the warp + MSD
+                 every iteration (graph replay), and its fwd+bwd form;
+  large_pair  -- one 2048x2048 pair (559k nodes), 50 iterations: plain against
+                 forward + reverse pass (checkpoint 10);
+  diff_batch  -- 64 pairs of 512x512 with per-pair alpha, 100 iterations: plain
+                 against forward + reverse pass (checkpoint 10);
   unstructured -- the 512x512 pair on an unstructured (jittered Delaunay)
-                mesh, 200 iterations with the MSD every iteration.
-Each leg reports its dominant kernel family's roofline (algorithmic bytes per
-launch over the HIP-event launch time).  The FP64 oracle is timed on a
-bounded sample on one host core (``cpu_baseline``).
+                 mesh, 200 iterations with the MSD every iteration;
+  explicit    -- Algorithm 1 as printed, on the 512x512 pair and the batch;
+  converge    -- the batch run to the relative-MSD stopping rule.
+``cpu_baseline`` is the FP64 oracle on the host cores: a process pool over a
+labelled subset of the batch (every 8th pair), run before anything touches
+the GPU.
 """
 from __future__ import annotations
 
@@ -78,24 +97,49 @@ def measured_traffic(leg: str, family: str):
     return int(v) if v is not None else None
 
 
+def touched_coefficients(pairs) -> int:
+    """Spline coefficients read by the node samples at u = 0: the union of
+    every node's 4x4 tap window (clamped at the image border), per pair."""
+    taps = 0
+    for p in pairs:
+        H, W = p.height, p.width
+        idx = [np.clip(p.V[:, 1] - 1 + dm, 0, H - 1).astype(np.int64) * W
+               + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)
+               for dm in range(-1, 3) for dn in range(-1, 3)]
+        taps += int(np.unique(np.concatenate(idx)).size)
+    return taps
+
+
+def algorithmic_bytes(ctx, pairs) -> dict:
+    """Bytes one pass of each stage must move over all pairs of the context,
+    each datum counted once (the method's, not the library's layout):
+    sample 36 n + 4 |C|, assemble 16 n_T + 44 n, solve 24 nnz(L) + 64 n,
+    warp 12 P + 16 n."""
+    n = sum(p.n_nodes for p in pairs)
+    nt = sum(int(p.T.shape[0]) for p in pairs)
+    pix = sum(p.height * p.width for p in pairs)
+    nnz_l = sum(ctx.info(k, "nnz_l") for k in range(len(pairs)))
+    return {"sample": 36 * n + 4 * touched_coefficients(pairs),
+            "assemble": 16 * nt + 44 * n,
+            "solve": 24 * nnz_l + 64 * n,
+            "warp": 12 * pix + 16 * n,
+            "finish": 0}
+
+
 def unit_bytes(ctx, pairs) -> dict:
-    """Algorithmic bytes of one pass of each stage over all pairs of the
-    context (each datum counted once)."""
+    """Bytes of one pass of each stage in the library's own data layout (each
+    stored datum the kernels read or write counted once): node streams, CSR
+    force-operator entries (index and weight), the solve's dense block
+    inverses, panels and apex inverse (both passes), the warp's triangle
+    records and tile partials."""
     n = sum(p.n_nodes for p in pairs)
     nt = sum(int(p.T.shape[0]) for p in pairs)
     pix = sum(p.height * p.width for p in pairs)
     tiles = sum(-(-p.height // 16) * -(-p.width // 16) for p in pairs)
     nnz_m = sum(ctx.info(k, "mass_nnz") for k in range(len(pairs)))
     solve = sum(ctx.info(k, "solve_bytes") for k in range(len(pairs)))
-    taps = 0
-    for p in pairs:                      # coefficients touched by node samples at u = 0
-        H, W = p.height, p.width
-        idx = [np.clip(p.V[:, 1] - 1 + dm, 0, H - 1).astype(np.int64) * W
-               + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)
-               for dm in range(-1, 3) for dn in range(-1, 3)]
-        taps += int(np.unique(np.concatenate(idx)).size)
     return {
-        "sample": 36 * n + 4 * taps,
+        "sample": 36 * n + 4 * touched_coefficients(pairs),
         "assemble": 44 * n + 8 * nnz_m,
         "solve": solve,
         "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
@@ -118,13 +162,7 @@ def explicit_unit_bytes(pairs) -> dict:
         e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
         e.sort(axis=1)
         ring += 2 * int(np.unique(e[:, 0] * (1 << 32) + e[:, 1]).size)
-    taps = 0
-    for p in pairs:
-        H, W = p.height, p.width
-        idx = [np.clip(p.V[:, 1] - 1 + dm, 0, H - 1).astype(np.int64) * W
-               + np.clip(p.V[:, 0] - 1 + dn, 0, W - 1)
-               for dm in range(-1, 3) for dn in range(-1, 3)]
-        taps += int(np.unique(np.concatenate(idx)).size)
+    taps = touched_coefficients(pairs)
     return {"smooth": 36 * n + 4 * ring, "sampling": 44 * n + 4 * taps,
             "update": 68 * n + 24 * nt, "u": 16 * n}
 
@@ -155,7 +193,7 @@ def explicit_leg(pkg, B, pairs, tau, lam, iters, stream, no_profile, workload, l
         if not no_profile:
             u.zero_()
             xb = explicit_unit_bytes(pairs)
-            ub = unit_bytes(ctx, pairs)
+            ub = algorithmic_bytes(ctx, pairs)
             # launch k <= iters of the smoothing family: sampling for k < iters
             # (at k = 0 of u itself), smoothing for k > 0, the MSD sums of
             # the previous update's tiles for k >= 2; the update family warps
@@ -194,10 +232,11 @@ def run_bytes(ub: dict, iters: int, trace: bool, fused: bool = True) -> dict:
             "warp": (ub["warp"] + ub["finish"]) if (trace and iters) else 0}
 
 
-def profile(ctx, run, total_bytes: dict, leg: str) -> tuple:
+def profile(ctx, run, total_bytes: dict, leg: str, layout_bytes: dict | None = None) -> tuple:
     """Per-family timing of one run from events attached to each kernel
     dispatch; returns (kernels, roofline of the family with the largest
-    share of GPU time)."""
+    share of GPU time).  ``total_bytes``: algorithmic bytes per family over
+    the run; ``layout_bytes``: the library's own layout bytes (reported)."""
     import torch
     ctx.enable_timing(True)
     run()
@@ -212,22 +251,29 @@ def profile(ctx, run, total_bytes: dict, leg: str) -> tuple:
                             "total_ms": round(ms, 4),
                             "gbs": round(total_bytes[fam] / (ms * 1e-3) / 1e9, 2),
                             "share": round(ms / total, 4)}
+            if layout_bytes is not None:
+                kernels[fam]["layout_gbs"] = round(layout_bytes[fam] / (ms * 1e-3) / 1e9, 2)
     dom = max(kernels, key=lambda f: kernels[f]["share"])
     ach = kernels[dom]["gbs"]
+    launches = kernels[dom]["launches"]
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(leg, dom),
-            "kernel": dom,
-            "bytes_per_launch": int(total_bytes[dom] / kernels[dom]["launches"]),
+            "kernel": dom, "launches": launches,
+            "bytes_per_launch": int(total_bytes[dom] / launches),
             "avg_launch_us": kernels[dom]["avg_us"]}
+    if layout_bytes is not None:
+        roof["layout_bytes_per_launch"] = int(layout_bytes[dom] / launches)
     return kernels, roof
 
 
 def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
     """Sample, assemble and warp each timed on their own (the library's force
     and warp entry points, which launch them unfused), with dispatch-attached
-    events: achieved GB/s on algorithmic bytes against the HBM peak."""
+    events: achieved GB/s on algorithmic bytes against the HBM peak, and the
+    library's layout bytes beside them."""
     import torch
-    ub = unit_bytes(ctx, pairs)
+    ab = algorithmic_bytes(ctx, pairs)
+    lb = unit_bytes(ctx, pairs)
     ctx.enable_timing(True)
     for _ in range(reps):
         ctx.force(u)
@@ -237,28 +283,31 @@ def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
     times = ctx.kernel_times()
     ctx.enable_timing(False)
     out = {}
-    for fam, nbytes in (("sample", ub["sample"]), ("assemble", ub["assemble"]),
-                        ("warp", ub["warp"] + ub["finish"])):
+    for fam in ("sample", "assemble", "warp"):
         ms, cnt = times[fam]
         if cnt:
+            nbytes = ab[fam] + ab["finish"] if fam == "warp" else ab[fam]
+            lbytes = lb[fam] + lb["finish"] if fam == "warp" else lb[fam]
             gbs = reps * nbytes / (ms * 1e-3) / 1e9
             out[fam] = {"us_per_call": round(ms / reps * 1e3, 3), "bytes_per_call": int(nbytes),
-                        "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                        "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "layout_bytes_per_call": int(lbytes),
+                        "traffic_per_call": measured_traffic("stages", fam)}
     return out
 
 
 def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload, leg) -> dict:
     """Plain iterations against forward + checkpointed reverse pass on the same
-    pairs: N iterations from u = 0 (graph replay), then the gradient of the
-    summed final MSDs w.r.t. u0, every alpha and every template (checkpoint
-    every 10 iterations)."""
+    pairs: N iterations from u = 0 (graph replay) + the final warp/MSD, against
+    one gradient evaluation of the summed final MSDs w.r.t. u0, every alpha
+    and every template: N iterations writing a checkpoint every 10 (eager)
+    and the reverse pass from them."""
     import torch
     nb = sum(p.n_nodes for p in pairs)
     with torch.cuda.stream(stream):
         ctx = pkg.MeshReg(pairs, tau=tau, graph=True)
         u = ctx.zeros_u()
         B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream)      # capture + warm-up
-        ctx.backward(ctx.zeros_u(), N, 10)                             # adjoint buffers
         stream.synchronize()
         u.zero_()
         stream.synchronize()
@@ -267,22 +316,27 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload, leg) -> dict:
         msd = ctx.warp_msd(u)
         stream.synchronize()
         dt_plain = time.perf_counter() - t0
-        u0 = ctx.zeros_u()
+        # one gradient evaluation: the forward pass writing its checkpoints,
+        # then the reverse pass from them
+        ck = ctx.checkpoints(N, 10)
+        uf = ctx.zeros_u()
+        ctx.forward_ckpt(uf, N, 10, ck)                                # warm-up
+        ctx.backward_ckpt(ck, N, 10)
+        uf.zero_()
         stream.synchronize()
         t0 = time.perf_counter()
-        msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
+        msd_b, _ = ctx.forward_ckpt(uf, N, 10, ck)
+        _, g_u0, g_alpha, g_te = ctx.backward_ckpt(ck, N, 10)
         stream.synchronize()
-        dt_bwd = time.perf_counter() - t0
+        grad_eval = time.perf_counter() - t0
         roof = None
         if not no_profile:
             u.zero_()
+            fused = ctx.info(0, "fused_assembly") == 1
             _, roof = profile(ctx, lambda: B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream),
-                              run_bytes(unit_bytes(ctx, pairs), N, False,
-                                        ctx.info(0, "fused_assembly") == 1), leg)
+                              run_bytes(algorithmic_bytes(ctx, pairs), N, False, fused), leg,
+                              run_bytes(unit_bytes(ctx, pairs), N, False, fused))
         ctx.close()
-    # the reverse pass recomputes the forward from checkpoints, so one gradient
-    # evaluation costs (forward) + (reverse pass)
-    grad_eval = dt_plain + dt_bwd
     return {"workload": workload, "pairs": len(pairs), "nodes": nb,
             "pixels": int(sum(p.height * p.width for p in pairs)), "iterations": N,
             "ckpt_every": 10,
@@ -328,33 +382,162 @@ def converge_leg(ctx, pairs, stream, args, s_per_iteration: float) -> dict:
             "mean_final_msd": float(msd.mean().item())}
 
 
-def cpu_baseline(pair, tau, n_iter_sample: int) -> dict:
+def cpu_baseline_worker(pairs, tau: float, n_iter: int, barrier, results) -> None:
+    """One process of the CPU baseline: sets up the oracle for its pairs, waits
+    for every process to be ready, then runs ``n_iter`` oracle iterations on
+    each of its pairs and reports (node-updates, seconds)."""
     from oracle import registration as reg
-    pb = reg.setup(pair.te, pair.re, pair.V, pair.T, pair.alpha, tau)
-    u = np.zeros((pair.V.shape[0], 2))
+    pbs = [reg.setup(p.te, p.re, p.V, p.T, p.alpha, tau) for p in pairs]
+    barrier.wait()
     t0 = time.perf_counter()
-    for _ in range(n_iter_sample):
-        u = reg.step(pb, u)
-        reg.msd(pb, u)
-    dt = time.perf_counter() - t0
-    return {"value": round(pair.n_nodes * n_iter_sample / dt, 1), "unit": "node-updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"first {n_iter_sample} iterations (each with warp+MSD) of the same "
-                      f"512x512 pair, FP64 NumPy/SciPy oracle with CG solves, 1 thread, "
-                      f"{dt:.1f} s"}
+    done = 0
+    for pb in pbs:
+        u = np.zeros((pb.V.shape[0], 2))
+        for _ in range(n_iter):
+            u = reg.step(pb, u)
+        done += pb.V.shape[0] * n_iter
+    results.put((done, time.perf_counter() - t0))
+
+
+def cpu_baseline(batch, tau: float, every: int, n_iter: int, procs: int) -> dict:
+    """The FP64 oracle on the host cores over a labelled subset of the batch
+    (every ``every``-th pair), ``n_iter`` iterations per pair, one process per
+    core (BLAS threads pinned to 1), pairs dealt to processes largest first.
+    The rate is the subset's node-updates over the wall time from the moment
+    every process has finished its set-up to the last one's end."""
+    import multiprocessing as mp
+    sub = batch[::every]
+    procs = max(1, min(procs, len(sub)))
+    order = sorted(range(len(sub)), key=lambda k: -sub[k].n_nodes)
+    load, parts = [0] * procs, [[] for _ in range(procs)]
+    for k in order:                              # greedy balance by node count
+        q = int(np.argmin(load))
+        parts[q].append(sub[k])
+        load[q] += sub[k].n_nodes
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(procs + 1)
+    results = ctx.Queue()
+    workers = [ctx.Process(target=cpu_baseline_worker, args=(parts[q], tau, n_iter, barrier, results))
+               for q in range(procs)]
+    for w in workers:
+        w.start()
+    barrier.wait()
+    t0 = time.perf_counter()
+    got = [results.get() for _ in range(procs)]
+    wall = time.perf_counter() - t0
+    for w in workers:
+        w.join()
+    updates = sum(g[0] for g in got)
+    n_sub = sum(p.n_nodes for p in sub)
+    return {"value": round(updates / wall, 1), "unit": "node-updates/s", "cores": procs,
+            "kind": "oracle",
+            "sample": f"every {every}th pair of the same {len(batch)}-pair batch ({len(sub)} pairs, "
+                      f"{n_sub} nodes, sides {min(p.height for p in sub)}..{max(p.height for p in sub)}), "
+                      f"{n_iter} iterations each from u = 0, FP64 NumPy/SciPy oracle with CG solves, "
+                      f"{procs} processes x 1 thread, {wall:.1f} s wall after set-up; a subset rate, "
+                      f"not an extrapolation to the whole batch"}
+
+
+# The paper's own timings: MATLAB on a CPU, Algorithm 1 as printed (explicit
+# update, one umbrella smoothing), brain-CT slices (Section 3.2 Example 1;
+# Section 3.3 and Table 1).  Context only: another method variant, machine
+# and data.
+PAPER_CONTEXT = {
+    "example_1": {"seconds_per_iteration": 0.156, "nodes": 5406, "triangles": 10744,
+                  "node_updates_per_s": round(5406 / 0.156, 1),
+                  "hardware": "not stated for this example", "software": "MATLAB",
+                  "source": "Section 3.2, Example 1"},
+    "example_2": {"total_seconds": 1320, "pairs": "80 slices 512x512 registered consecutively",
+                  "nodes_approx": 3300, "triangles_approx": 6700, "iterations": 100,
+                  "hardware": "Intel Core i7 3.5 GHz, 6 GB RAM", "software": "MATLAB",
+                  "pixel_based_comparison_seconds": 1534,
+                  "source": "Section 3.3, Table 1"},
+}
+
+
+def single_pair_leg(pkg, B, pair, tau, K, warmup, side, no_profile) -> dict:
+    """The 512x512 pair: K iterations with the warp + MSD every iteration
+    (graph replay; eager for comparison), then forward + reverse pass."""
+    import torch
+    n = pair.n_nodes
+    with torch.cuda.stream(side):
+        ctx = pkg.MeshReg([pair], tau=tau, graph=True)
+        u = ctx.zeros_u()
+        trace = torch.empty((K, 1), dtype=torch.float64, device="cuda")
+
+        def run(k):
+            B.mesh_reg_step(ctx.ctx, u, k, trace, side.cuda_stream)
+
+        ctx.set_graph(False)
+        run(warmup)
+        side.synchronize()
+        ctx.set_graph(True)
+        u.zero_()
+        run(K)                                  # capture + first replay
+        side.synchronize()
+        u.zero_()
+        side.synchronize()
+        t0 = time.perf_counter()
+        run(K)
+        side.synchronize()
+        dt = time.perf_counter() - t0
+        final_msd = float(trace[K - 1, 0].item())
+        ctx.set_graph(False)
+        u.zero_()
+        side.synchronize()
+        t0 = time.perf_counter()
+        run(K)
+        side.synchronize()
+        dt_eager = time.perf_counter() - t0
+        kernels, roof, stages = {}, None, None
+        if not no_profile:
+            u.zero_()
+            fused = ctx.info(0, "fused_assembly") == 1
+            kernels, roof = profile(ctx, lambda: run(K),
+                                    run_bytes(algorithmic_bytes(ctx, [pair]), K, True, fused),
+                                    "single_pair", run_bytes(unit_bytes(ctx, [pair]), K, True, fused))
+            stages = stage_rooflines(ctx, [pair], u)
+        N = 100
+        ck = ctx.checkpoints(N, 10)
+        uu = ctx.zeros_u()
+        ctx.forward_ckpt(uu, N, 10, ck)         # warm-up (allocates the adjoint buffers)
+        ctx.backward_ckpt(ck, N, 10)
+        uu.zero_()
+        side.synchronize()
+        t0 = time.perf_counter()
+        ctx.forward_ckpt(uu, N, 10, ck)         # forward writing checkpoints, then the reverse pass
+        ctx.backward_ckpt(ck, N, 10)
+        side.synchronize()
+        dtb = time.perf_counter() - t0
+        ctx.close()
+    value = n * K / dt
+    return {"workload": "single pair 512x512 12-bit blobs+disk, sine warp A=8, quadtree s=1..32 "
+                        "g=0.08, alpha=0.05 tau=0.5, warp+MSD every iteration, graph replay",
+            "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": pair.height * pair.width,
+            "iterations": K, "ms_per_iteration": round(dt / K * 1e3, 5),
+            "node_updates_per_s": round(value, 1), "ms_per_iteration_eager": round(dt_eager / K * 1e3, 5),
+            "final_msd": final_msd, "kernels": kernels, "roofline": roof, "stage_rooflines": stages,
+            "fwd_bwd": {"node_updates_per_s": round(n * N / dtb, 1), "iterations": N, "ckpt_every": 10,
+                        "ms_per_iteration": round(dtb / N * 1e3, 4),
+                        "vs_plain": round(n * N / dtb / value, 4),
+                        "grad_evals_per_s": round(1.0 / dtb, 3),
+                        "note": "forward N iterations writing a checkpoint every 10 + warp/MSD, "
+                                "then the reverse pass from them (segment recompute + adjoint)"}}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations timed on the host")
+    ap.add_argument("--steps", type=int, default=100,
+                    help="iterations of the 256-pair batch in the timed region")
+    ap.add_argument("--warmup", type=int, default=10, help="eager iterations before the graph capture")
+    ap.add_argument("--batched-pairs", type=int, default=256)
+    ap.add_argument("--cpu-every", type=int, default=8, help="CPU baseline: every k-th pair of the batch")
+    ap.add_argument("--cpu-iters", type=int, default=20, help="CPU baseline: oracle iterations per pair")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--fwdbwd-iters", type=int, default=100, help="0 skips the fwd+bwd leg")
-    ap.add_argument("--batched-pairs", type=int, default=256, help="0 skips the batched leg")
-    ap.add_argument("--batched-iters", type=int, default=100)
+    ap.add_argument("--single-iters", type=int, default=200,
+                    help="iterations of the 512x512 leg (0 skips it)")
     ap.add_argument("--large-iters", type=int, default=50,
                     help="iterations of the 2048x2048 differentiable leg (0 skips it)")
     ap.add_argument("--diff-batch-pairs", type=int, default=64,
@@ -370,7 +553,8 @@ def main() -> int:
     ap.add_argument("--explicit-iters", type=int, default=200,
                     help="iterations of the explicit (Algorithm 1 as printed) legs (0 skips)")
     ap.add_argument("--gen-procs", type=int, default=0,
-                    help="processes generating the batched inputs (0: up to 16)")
+                    help="processes generating the batched inputs and running the CPU baseline "
+                         "(0: the host's cores, at most 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -389,10 +573,12 @@ def main() -> int:
         return 2
 
     from synth import make_pair, make_pairs
-    # inputs first, before anything touches the GPU
-    pair = make_pair(2)
+    # inputs and the CPU baseline first, before anything touches the GPU (the
+    # process pools start fresh interpreters)
     procs = args.gen_procs or min(16, len(os.sched_getaffinity(0)))
-    batch = make_pairs(4, args.batched_pairs, processes=procs) if args.batched_pairs else []
+    tau = 0.5
+    batch = make_pairs(4, args.batched_pairs, processes=procs)
+    pair = make_pair(2) if (args.single_iters or args.unstructured_iters or args.explicit_iters) else None
     large = make_pair(3) if args.large_iters else None
     upair = None
     if args.unstructured_iters:
@@ -400,122 +586,60 @@ def main() -> int:
         Vu, Tu = unstructured_mesh(pair.te, 1, 32, 0.08, seed=2000)
         upair = dict(te=pair.te, re=pair.re, V=Vu, T=Tu, alpha=pair.alpha)
     dbatch = make_pairs(5, args.diff_batch_pairs, processes=procs) if args.diff_batch_pairs else []
+    cpu = None if args.no_cpu_baseline else cpu_baseline(batch, tau, args.cpu_every, args.cpu_iters,
+                                                         procs)
 
     import torch
     import paper_1411_2141_amd as pkg
     B = pkg.binding
 
-    tau = 0.5
-    n = pair.n_nodes
     K = args.steps
     side = torch.cuda.Stream()
+    nb = sum(p.n_nodes for p in batch)
     with torch.cuda.stream(side):
-        ctx = pkg.MeshReg([pair], tau=tau, graph=True)
-        u = ctx.zeros_u()
-        trace = torch.empty((K, 1), dtype=torch.float64, device="cuda")
-
-        def run(k):
-            B.mesh_reg_step(ctx.ctx, u, k, trace, side.cuda_stream)
-
-        # warm-up: W eager iterations, then the K-iteration graph is captured
-        # and replayed once
-        ctx.set_graph(False)
-        run(args.warmup)
+        # the force assembly in its own launch: what the autotuner picks on
+        # this workload in most runs (within ~3 % of the fused form), fixed
+        # so that counter runs and timed runs execute the same launches
+        bctx = pkg.MeshReg(batch, tau=tau, graph=True, separate_assembly=True)
+        ub = bctx.zeros_u()
+        bctx.set_graph(False)
+        if args.warmup:
+            B.mesh_reg_step(bctx.ctx, ub, args.warmup, None, side.cuda_stream)
+        bctx.set_graph(True)
+        ub.zero_()
+        B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # capture + first replay
         side.synchronize()
-        ctx.set_graph(True)
-        u.zero_()
-        run(K)
-        side.synchronize()
-        u.zero_()
-        side.synchronize()
+        ub.zero_()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        run(K)                                  # graph replay: K iterations, MSD every iteration
+        B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # graph replay: K iterations
+        msd_b = bctx.warp_msd(ub)
         side.synchronize()
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        final_msd = float(trace[K - 1, 0].item())
-        value = n * K / dt
-
-        # the same K iterations launched eagerly (no graph), for comparison
-        ctx.set_graph(False)
-        u.zero_()
-        side.synchronize()
-        t0 = time.perf_counter()
-        run(K)
-        side.synchronize()
-        dt_eager = time.perf_counter() - t0
-
+        value = nb * K / dt
         kernels, roof, stages = {}, None, None
         if not args.no_profile:
-            u.zero_()
-            kernels, roof = profile(ctx, lambda: run(K),
-                                    run_bytes(unit_bytes(ctx, [pair]), K, True,
-                                              ctx.info(0, "fused_assembly") == 1), "single_pair")
-            stages = stage_rooflines(ctx, [pair], u)
-
-    fwd_bwd = None
-    if args.fwdbwd_iters:
-        N = args.fwdbwd_iters
-        with torch.cuda.stream(side):
-            u0 = ctx.zeros_u()
-            ctx.backward(u0, N, 10)             # warm-up (allocates the adjoint buffers)
-            side.synchronize()
-            t0 = time.perf_counter()
-            uu = u0.clone()
-            B.mesh_reg_step(ctx.ctx, uu, N, None, side.cuda_stream)     # eager (graph off)
-            ctx.warp_msd(uu)
-            msd_b, g_u0, g_alpha, g_te = ctx.backward(u0, N, 10)
-            side.synchronize()
-            dtb = time.perf_counter() - t0
-        fwd_bwd = {"value": round(n * N / dtb, 1), "unit": "node-updates/s",
-                   "iterations": N, "ckpt_every": 10, "ms_per_iteration": round(dtb / N * 1e3, 4),
-                   "vs_plain": round(n * N / dtb / value, 4),
-                   "grad_evals_per_s": round(1.0 / dtb, 3),
-                   "note": "forward N iterations + warp/MSD, then the checkpointed reverse pass "
-                           "(recompute + adjoint), same 512x512 pair"}
-    ctx.close()
-
-    batched = None
-    if batch:
-        nb = sum(p.n_nodes for p in batch)
-        with torch.cuda.stream(side):
-            # the force assembly in its own launch: what the autotuner picks on
-            # this workload in most runs (within ~3 % of the fused form), fixed
-            # so that counter runs and timed runs execute the same launches
-            bctx = pkg.MeshReg(batch, tau=tau, graph=True, separate_assembly=True)
-            ub = bctx.zeros_u()
-            KB = args.batched_iters
-            B.mesh_reg_step(bctx.ctx, ub, KB, None, side.cuda_stream)     # capture + warm-up
-            side.synchronize()
             ub.zero_()
-            side.synchronize()
-            t0 = time.perf_counter()
-            B.mesh_reg_step(bctx.ctx, ub, KB, None, side.cuda_stream)
-            msd_b = bctx.warp_msd(ub)
-            side.synchronize()
-            dtc = time.perf_counter() - t0
-            bk, broof, bstages = {}, None, None
-            if not args.no_profile:
-                ub.zero_()
-                bk, broof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, KB, None,
+            fused = bctx.info(0, "fused_assembly") == 1
+            kernels, roof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, K, None,
                                                                   side.cuda_stream),
-                                    run_bytes(unit_bytes(bctx, batch), KB, False,
-                                              bctx.info(0, "fused_assembly") == 1), "batched")
-                bstages = stage_rooflines(bctx, batch, ub)
-        batched = {"value": round(nb * KB / dtc, 1), "unit": "node-updates/s", "pairs": len(batch),
-                   "nodes": nb, "pixels": int(sum(p.height * p.width for p in batch)),
-                   "iterations": KB, "ms_per_iteration": round(dtc / KB * 1e3, 4),
-                   "iterations_per_s": round(KB / dtc, 2), "graph": True,
-                   "mean_final_msd": float(msd_b.mean().item()),
-                   "kernels": bk, "roofline": broof, "stage_rooflines": bstages}
-        if args.converge_max_iters:
-            batched["converge"] = converge_leg(bctx, batch, side, args, dtc / KB)
-        bctx.close()
-        if args.explicit_iters:
-            batched["explicit"] = explicit_leg(
-                pkg, B, batch, EXPLICIT_TAU, EXPLICIT_LAMBDA, min(args.explicit_iters, 100),
-                side, args.no_profile, "the same 256 pairs, Algorithm 1 as printed",
-                "explicit_batched")
+                                    run_bytes(algorithmic_bytes(bctx, batch), K, False, fused),
+                                    "batched", run_bytes(unit_bytes(bctx, batch), K, False, fused))
+            stages = stage_rooflines(bctx, batch, ub)
+        nnz_l = sum(bctx.info(k, "nnz_l") for k in range(len(batch)))
+        levels = max(bctx.info(k, "fwd_levels") for k in range(len(batch)))
+    converge = converge_leg(bctx, batch, side, args, dt / K) if args.converge_max_iters else None
+    bctx.close()
+    explicit_b = None
+    if args.explicit_iters:
+        explicit_b = explicit_leg(
+            pkg, B, batch, EXPLICIT_TAU, EXPLICIT_LAMBDA, min(args.explicit_iters, 100),
+            side, args.no_profile, "the same 256 pairs, Algorithm 1 as printed", "explicit_batched")
 
+    single = None
+    if args.single_iters:
+        single = single_pair_leg(pkg, B, pair, tau, args.single_iters, 20, side, args.no_profile)
     large_leg = None
     if large is not None:
         large_leg = diff_leg(pkg, B, [large], tau, args.large_iters, side, args.no_profile,
@@ -546,10 +670,12 @@ def main() -> int:
             uroof = None
             if not args.no_profile:
                 uu.zero_()
+                fused = uctx.info(0, "fused_assembly") == 1
+                up = [_as_pair(upair)]
                 _, uroof = profile(uctx, lambda: B.mesh_reg_step(uctx.ctx, uu, KU, utrace,
                                                                  side.cuda_stream),
-                                   run_bytes(unit_bytes(uctx, [_as_pair(upair)]), KU, True,
-                                             uctx.info(0, "fused_assembly") == 1), "unstructured")
+                                   run_bytes(algorithmic_bytes(uctx, up), KU, True, fused),
+                                   "unstructured", run_bytes(unit_bytes(uctx, up), KU, True, fused))
             unstructured = {
                 "workload": "the 512x512 pair on an unstructured mesh (quadtree s=1..32 g=0.08 "
                             "corners, jittered, Delaunay), warp+MSD every iteration",
@@ -567,21 +693,27 @@ def main() -> int:
                                 "the mesh gradient on the deformed mesh, umbrella smoothing), "
                                 "MSD every iteration", "explicit_single")
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(pair, tau, args.cpu_iters)
-
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "node-updates/s", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": round(dt / K * 1e3, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "single pair 512x512 12-bit blobs+disk, sine warp A=8, quadtree "
-                               "s=1..32 g=0.08, alpha=0.05 tau=0.5, warp+MSD every iteration",
-                   "nodes": n, "triangles": int(pair.T.shape[0]), "pixels": pair.height * pair.width,
-                   "iterations": K, "parallelism": "single GPU", "graph": True,
-                   "final_msd": final_msd, "ms_per_step_eager": round(dt_eager / K * 1e3, 5)},
+        "config": {"workload": f"{len(batch)} ragged pairs, sides uniform in {{128..1024}}, FP32 "
+                               "blobs+disk, sine warp A=6, quadtree s=1..32 g=0.10, alpha=0.05 "
+                               "tau=0.5, all pairs in every launch, graph replay; timed: K "
+                               "iterations from u=0 then the warp+MSD of the result",
+                   "pairs": len(batch), "nodes": nb,
+                   "triangles": int(sum(p.T.shape[0] for p in batch)),
+                   "pixels": int(sum(p.height * p.width for p in batch)),
+                   "nnz_l": int(nnz_l), "solve_levels_max": int(levels),
+                   "iterations": K, "iterations_per_s": round(K / dt, 2),
+                   "parallelism": "single GPU", "graph": True,
+                   "mean_final_msd": float(msd_b.mean().item())},
         "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
-        "fwd_bwd": fwd_bwd, "batched": batched, "large_pair": large_leg,
-        "diff_batch": dbatch_leg, "unstructured": unstructured, "explicit": explicit,
+        "paper_context": PAPER_CONTEXT,
+        "single_pair": single, "large_pair": large_leg, "diff_batch": dbatch_leg,
+        "unstructured": unstructured, "explicit": explicit, "explicit_batched": explicit_b,
+        "converge": converge,
     }
     print(json.dumps(out))
     return 0

@@ -52,3 +52,23 @@ def test_run_bytes_split_the_assembly_between_families():
     none = bench.run_bytes(ub, 5, False)
     assert none["warp"] == 0 and none["sample"] == 500
     assert np.isclose(sum(none.values()), 5 * (100 + 40 + 1000))
+
+
+def test_algorithmic_bytes_follow_the_method_counts():
+    """sample 36 n + 4 |C|, assemble 16 n_T + 44 n, solve 24 nnz(L) + 64 n,
+    warp 12 P + 16 n, with n_T and the touched coefficients from the mesh and
+    nnz(L) the factor's (host-only contexts, no GPU)."""
+    import paper_1411_2141_amd as pkg
+    for p in _pairs():
+        te = np.zeros((p.height, p.width), dtype=np.float32)
+        ctx = pkg.MeshReg([dict(te=te, re=te, V=p.V, T=p.T, alpha=0.05)], tau=0.5, host_only=True)
+        ab = bench.algorithmic_bytes(ctx, [p])
+        n, nt, P = p.n_nodes, p.T.shape[0], p.height * p.width
+        nnz_l = ctx.info(0, "nnz_l")
+        assert n <= nnz_l <= n * (n + 1) // 2
+        assert ab["assemble"] == 16 * nt + 44 * n
+        assert ab["solve"] == 24 * nnz_l + 64 * n
+        assert ab["warp"] == 12 * P + 16 * n
+        assert ab["sample"] == 36 * n + 4 * bench.touched_coefficients([p])
+        assert bench.touched_coefficients([p]) <= P
+        ctx.close()

@@ -1,6 +1,7 @@
 """The HIP path and the oracle share no code: no file of the library or of the
 input generators imports the oracle, the oracle imports neither of them, and
-bench.py reaches the oracle only inside its CPU-baseline leg."""
+bench.py reaches the oracle only inside its CPU-baseline leg (the pool and its
+worker processes)."""
 import ast
 import os
 
@@ -49,6 +50,6 @@ def test_bench_uses_the_oracle_only_in_its_cpu_baseline():
     for fn in [n for n in tree.body if isinstance(n, ast.FunctionDef)]:
         uses = any(isinstance(n, ast.ImportFrom) and n.module and n.module.startswith("oracle")
                    for n in ast.walk(fn))
-        assert not uses or fn.name == "cpu_baseline", fn.name
+        assert not uses or fn.name in ("cpu_baseline", "cpu_baseline_worker"), fn.name
     top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
     assert all("oracle" not in ast.dump(n) for n in top)
