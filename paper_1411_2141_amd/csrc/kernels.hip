@@ -175,11 +175,31 @@ __device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pai
   if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
 }
 
+// FP32 cubic B-spline weights of fraction t in [0, 1); w[2] is formed from the
+// other three so the four sum to 1 up to the last rounding (no systematic
+// scaling of the sample, which would bias a mean of squared differences).
+__device__ __forceinline__ void bs_weights_unit(float t, float w[4]) {
+  const float s = 1.0f - t, t2 = t * t, s2 = s * s;
+  w[0] = s2 * (s * (1.0f / 6.0f));
+  w[3] = t2 * (t * (1.0f / 6.0f));
+  w[1] = fmaf(t2, fmaf(t, 0.5f, -1.0f), 2.0f / 3.0f);
+  w[2] = ((1.0f - w[0]) - w[1]) - w[3];
+}
+
+// Element at byte offset `off` (unsigned 32-bit, cannot overflow) of an array
+// at a workgroup-uniform base: the load takes the scalar base plus a 32-bit
+// vector offset, with no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T load_at(const T *__restrict__ base, unsigned off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // Squared differences of NT pixels, the thread's position in each of NT
 // tiles (0 for positions outside the image): each pixel takes the
-// piecewise-linear displacement of its triangle (barycentric weights from
+// piecewise-linear displacement of its triangle (FP64 barycentric weights from
 // exact cross products in doubled integer coordinates) and the template
-// spline is sampled at the displaced pixel centre (FP64 weights and sums).
+// spline is sampled at the displaced pixel centre (FP32 weights with the
+// partition of unity kept and FP32 tap sums; the squared difference in FP64).
 // The NT pixels go through each step together so their dependent load chains
 // overlap; positions outside the image are clamped to its last row / column
 // for the loads and count 0.  Offsets within a pair's image are 32-bit (fewer
@@ -209,21 +229,21 @@ __device__ __forceinline__ void warp_pixels(const TileItem (&it)[NT], const DevP
   }
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    tt[q] = P[q].tri_off + (t6 + P[q].pix_off)[po[q]];
-    rv[q] = (re + P[q].pix_off)[po[q]];
+    tt[q] = load_at(t6 + P[q].pix_off, po[q] << 2);
+    rv[q] = load_at(re + P[q].pix_off, po[q] << 2);
   }
   int4 nd[NT], ps[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    nd[q] = tri[tt[q]];
-    ps[q] = tpos[tt[q]];                        // corners as x | y << 16
+    nd[q] = load_at(tri + P[q].tri_off, (unsigned)tt[q] << 4);
+    ps[q] = load_at(tpos + P[q].tri_off, (unsigned)tt[q] << 4);   // corners as x | y << 16
   }
   double2 ua[NT], ub[NT], uc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    ua[q] = u[nd[q].x];
-    ub[q] = u[nd[q].y];
-    uc[q] = u[nd[q].z];
+    ua[q] = load_at(u, (unsigned)nd[q].x << 4);
+    ub[q] = load_at(u, (unsigned)nd[q].y << 4);
+    uc[q] = load_at(u, (unsigned)nd[q].z << 4);
   }
   int qx[NT], qy[NT];
   double fx[NT], fy[NT];
@@ -238,8 +258,11 @@ __device__ __forceinline__ void warp_pixels(const TileItem (&it)[NT], const DevP
     const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
     const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
     const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-    const double inv = 1.0 / (ca + cb + cc);
-    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+    // 1 / (ca + cb + cc), an integer: the FP32 estimate and one Newton step
+    const double den = ca + cb + cc;
+    double inv = (double)__frcp_rn((float)den);
+    inv = fma(inv, fma(-den, inv, 1.0), inv);
+    const double wa = ca * inv, wb = cb * inv, wc = (1.0 - wa) - wb;
     const double dx = wa * ua[q].x + wb * ub[q].x + wc * uc[q].x;
     const double dy = wa * ua[q].y + wb * ub[q].y + wc * uc[q].y;
     const bool okx = split_coord_d(J[q], dx, qx[q], fx[q]);
@@ -260,19 +283,18 @@ __device__ __forceinline__ void warp_pixels(const TileItem (&it)[NT], const DevP
   }
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    double wx[4], wy[4];
-    bs_weights6_d(fx[q], wx);
-    bs_weights6_d(fy[q], wy);
-    double w = 0.0;
+    float wx[4], wy[4];
+    bs_weights_unit((float)fx[q], wx);
+    bs_weights_unit((float)fy[q], wy);
+    float w = 0.0f;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const double rs = (double)tap[q][m][0] * wx[0] + (double)tap[q][m][1] * wx[1] +
-                        (double)tap[q][m][2] * wx[2] + (double)tap[q][m][3] * wx[3];
+      const float rs = tap[q][m][0] * wx[0] + tap[q][m][1] * wx[1] + tap[q][m][2] * wx[2] +
+                       tap[q][m][3] * wx[3];
       w += wy[m] * rs;
     }
-    w *= 1.0 / 36.0;
-    if (warped && in[q]) (warped + P[q].pix_off)[po[q]] = (float)w;
-    const double e = w - (double)rv[q];
+    if (warped && in[q]) (warped + P[q].pix_off)[po[q]] = w;
+    const double e = (double)(w - rv[q]);
     sq[q] = in[q] ? e * e : 0.0;
   }
 }

@@ -32,26 +32,13 @@ __device__ __forceinline__ void bs_weights(float t, float w[4]) {
   w[3] = t3 * (1.0f / 6.0f);
 }
 
-// FP64 weights (the warp and the adjoint kernels): the MSD is a mean of
-// squared differences of nearly equal numbers, so a systematic FP32 weight
-// rounding (at t = 0 the FP32 weights sum to 1 + 3e-8 per axis) would bias it
-// by ~1e-6 relative.
+// FP64 weights (the adjoint kernels).
 __device__ __forceinline__ void bs_weights_d(double t, double w[4]) {
   const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
   w[0] = s * s * s * (1.0 / 6.0);
   w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) * (1.0 / 6.0);
   w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) * (1.0 / 6.0);
   w[3] = t3 * (1.0 / 6.0);
-}
-
-// Six times the FP64 weights (the caller divides by 6 per axis, or by 36
-// once for a 2-D sample): no scaling per weight.
-__device__ __forceinline__ void bs_weights6_d(double t, double w[4]) {
-  const double s = 1.0 - t, t2 = t * t, t3 = t2 * t;
-  w[0] = s * s * s;
-  w[1] = 3.0 * t3 - 6.0 * t2 + 4.0;
-  w[2] = -3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0;
-  w[3] = t3;
 }
 
 __device__ __forceinline__ void bs_deriv(float t, float d[4]) {

@@ -165,12 +165,15 @@ def test_c3_gradient_against_oracle_50_iterations(c3):
 
 
 def test_c3_central_differences_against_oracle_64_directions(c3):
-    """Central differences of the GPU forward (FP32 sampling) along the 64
-    seeded directions against the oracle's directional derivatives.  The
-    forward's FP32 rounding bounds how closely a difference quotient at h =
-    1e-3 px can agree (two losses of ~4e-3 differing by ~1e-6 in their
-    seventh digit), so the bound is the difference quotient's, not the
-    gradient's."""
+    """Central differences of the GPU forward along the 64 seeded directions
+    against the oracle's directional derivatives.  The forward samples and
+    warps in FP32, so a difference quotient at h = 1e-3 px carries an absolute
+    noise floor: each warped pixel W_p is rounded to ~delta = 2^-22 (FP32 tap
+    sums of coefficients of magnitude ~1), and the loss difference
+    (2/P) sum_p e_p (W_p(+h) - W_p(-h)) then carries ~2 e_rms delta / sqrt(P),
+    i.e. eta = 2 sqrt(MSD) delta / (sqrt(P) 2h) in the quotient.  Each
+    direction must agree to 5e-3 relative plus 5 eta, and the 64 together to
+    5e-3 normwise."""
     p, ctx = c3
     rec = golden("full_size_2048.json")
     check_inputs(rec, p)
@@ -186,11 +189,13 @@ def test_c3_central_differences_against_oracle_64_directions(c3):
     fd = np.array([(loss(h * d) - loss(-h * d)) / (2 * h)
                    for d in random_directions(p.n_nodes, 64, rec["direction_seed"])])
     want = np.asarray(rec["projections"])
-    errs = np.abs(fd - want) / np.abs(want)
-    say(f"c3 FD vs oracle: normwise {rel(fd, want):.2e}, per direction median {np.median(errs):.2e} "
-        f"max {errs.max():.2e}")
+    eta = 2.0 * np.sqrt(rec["msd"]) * 2.0 ** -22 / (np.sqrt(p.height * p.width) * 2 * h)
+    err = np.abs(fd - want)
+    say(f"c3 FD vs oracle: normwise {rel(fd, want):.2e}, per direction median "
+        f"{np.median(err / np.abs(want)):.2e}, worst (err - 5e-3 |p|) / eta "
+        f"{np.max((err - 5e-3 * np.abs(want)) / eta):.2f} (eta {eta:.2e})")
     assert rel(fd, want) < 5e-3
-    assert np.median(errs) < 5e-3 and errs.max() < 5e-2
+    assert np.all(err <= 5e-3 * np.abs(want) + 5 * eta)
 
 
 def test_c5_batched_gradients_on_four_pairs():
