@@ -189,6 +189,18 @@ int mesh_reg_step_explicit(mr_ctx *ctx, double *u, int32_t n_iter, double tau, d
  * warped: DEVICE [sum H*W] FP32 or NULL. */
 int mesh_reg_warp_msd(mr_ctx *ctx, const double *u, double *msd, float *warped, void *stream);
 
+/* mesh_reg_warp_msd for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and results, with the per-tile partial sums in a static device
+ * array of the library (2^19 tiles of 16 x 16 pixels, 4 MiB per GPU, held until
+ * the process ends) instead of the context's buffer; the call allocates nothing.
+ * Calls on one GPU share that array, so calls that overlap on one GPU race.
+ * Errors: as mesh_reg_warp_msd, plus MR_EINVAL when the context has more pixel
+ * tiles than the array holds, MR_ESTATE when mesh_reg_init did not run on this
+ * GPU. */
+int mesh_reg_warp_msd_noalloc(mr_ctx *ctx, const double *u, double *msd, float *warped,
+                              void *stream);
+
 /* The force of one iteration (eq. 4-6 and eq. 10) for the given u:
  * h: DEVICE [sum n][2] FP32 or NULL (h_i = r_i g_i); b: DEVICE [sum n][2] FP64 or
  * NULL (b = u - tau f, natural node order). */

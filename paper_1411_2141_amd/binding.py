@@ -29,7 +29,7 @@ INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "
 KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
 EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_run", "mesh_reg_step_explicit",
-            "mesh_reg_warp_msd", "mesh_reg_force",
+            "mesh_reg_warp_msd", "mesh_reg_warp_msd_noalloc", "mesh_reg_force",
             "mesh_reg_solve", "mesh_reg_backward", "mesh_reg_forward_ckpt",
             "mesh_reg_backward_ckpt", "mesh_reg_set_alpha", "mesh_reg_set_template",
             "mesh_reg_get_tables", "mesh_reg_get_info", "mesh_reg_enable_timing",
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mesh_reg_run": (ctypes.c_int, [vp, vp, i32, i32, dbl, ctypes.POINTER(i32), vp, vp]),
         "mesh_reg_step_explicit": (ctypes.c_int, [vp, vp, i32, dbl, dbl, vp, vp]),
         "mesh_reg_warp_msd": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "mesh_reg_warp_msd_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mesh_reg_force": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mesh_reg_solve": (ctypes.c_int, [vp, vp, vp, vp]),
         "mesh_reg_backward": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -153,6 +154,11 @@ def mesh_reg_step_explicit(ctx, u, n_iter: int, tau: float, lam: float, msd_trac
 
 def mesh_reg_warp_msd(ctx, u, msd, warped=None, stream=None) -> None:
     _check(load_library().mesh_reg_warp_msd(ctx, _ptr(u), _ptr(msd), _ptr(warped), stream))
+
+def mesh_reg_warp_msd_noalloc(ctx, u, msd, warped=None, stream=None) -> None:
+    """mesh_reg_warp_msd with its partial sums in the library's static device
+    scratch (no allocation; calls on one GPU must not overlap)."""
+    _check(load_library().mesh_reg_warp_msd_noalloc(ctx, _ptr(u), _ptr(msd), _ptr(warped), stream))
 
 
 def mesh_reg_force(ctx, u, h=None, b=None, stream=None) -> None:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <thread>
 #include <cstdio>
@@ -28,6 +29,37 @@ int mr_set_error(int code, const std::string &msg) {
 }
 
 static int fail(int code, const std::string &msg) { return mr_set_error(code, msg); }
+
+// Static device scratch of mesh_reg_warp_msd_noalloc: the per-tile FP64
+// partial sums of the warp + MSD, 2^19 tiles of 16 x 16 pixels (4 MiB, images
+// of up to 2^27 pixels in all).  Each GPU the library runs on holds its own
+// copy until the process ends; its device address is looked up once per
+// device by mesh_reg_init (hipGetSymbolAddress with that device current) and
+// only that address is used on the host (the array's name is a host-side
+// stand-in).  Calls on one GPU share it: overlapping calls race.
+constexpr size_t kScratchDoubles = size_t(1) << 19;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+static int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(MR_EINVAL, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MR_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MR_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<double *>(ptr);
+  return MR_OK;
+}
+
+static double *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -937,6 +969,10 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     delete c;
     return fail(MR_EHIP, "no HIP device available");
   }
+  if ((rc = resolve_scratch(c->device)) != MR_OK) {
+    delete c;
+    return rc;
+  }
   if ((rc = c->upload_all(s)) != MR_OK || (rc = c->upload_prefilter_tables(s)) != MR_OK) {
     delete c;
     return rc;
@@ -1232,6 +1268,33 @@ extern "C" int mesh_reg_warp_msd(mr_ctx *c, const double *u, double *msd, float 
   if ((rc = c->check_flags())) return rc;
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(c->warp(reinterpret_cast<const double2 *>(u), msd, warped, s));
+  c->post_flags(s);
+  return MR_OK;
+}
+
+extern "C" int mesh_reg_warp_msd_noalloc(mr_ctx *c, const double *u, double *msd, float *warped,
+                                         void *stream) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  if (!u || !aligned16(u) || !msd) return fail(MR_EINVAL, "need aligned u and msd");
+  if ((int64_t)c->n_tiles > (int64_t)kScratchDoubles)
+    return fail(MR_EINVAL, "warp_msd_noalloc: " + std::to_string(c->n_tiles) +
+                               " pixel tiles exceed the static scratch of " +
+                               std::to_string(kScratchDoubles) + " tiles (" +
+                               std::to_string(kScratchDoubles * kTile * kTile) + " pixels)");
+  double *partials = scratch_ptr(c->device);
+  if (!partials) return fail(MR_ESTATE, "warp_msd_noalloc: no scratch address for this device");
+  if ((rc = c->check_flags())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // every tile of an active pair writes its own partial before the finish
+  // reads it (all pairs are active outside mesh_reg_run), so nothing needs
+  // clearing; no kernel timing here (it would create events)
+  hipError_t e = launch_warp_partials(c->d_tiles.ptr, c->n_tiles, c->d_pairs.ptr,
+                                      reinterpret_cast<const double2 *>(u), c->d_tpos.ptr,
+                                      c->d_tri.ptr, c->d_t6.ptr, c->d_coef.ptr, c->d_re.ptr, warped,
+                                      partials, c->d_flags.ptr, s);
+  if (e == hipSuccess) e = launch_msd_finish(c->d_pairs.ptr, c->n_pairs, partials, msd, s);
+  HIP_TRY(e);
   c->post_flags(s);
   return MR_OK;
 }
