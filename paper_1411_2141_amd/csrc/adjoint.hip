@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <string>
 #include <vector>
 
@@ -61,85 +62,170 @@ __device__ __forceinline__ void spline_vg_d(const float *__restrict__ c, int H, 
   }
 }
 
-// Adds cv beta(x) beta(y) + cgx beta'(x) beta(y) + cgy beta(x) beta'(y) to the
-// 16 taps of the point in cbar (one pair's [H][W] FP64 array).
-__device__ __forceinline__ void scatter_taps(double *__restrict__ cbar, int H, int W, int cx,
-                                             double fx, int cy, double fy, double cv, double cgx,
-                                             double cgy) {
+// Coefficient-adjoint contributions of a wavefront's nodes: node (lane) adds
+// cv beta(x) beta(y) + cgx beta'(x) beta(y) + cgy beta(x) beta'(y) at its 16
+// taps (cell cx, cy; fractions fx, fy) into cbar (one pair's [H][W] FP64
+// array).  When the taps of the wavefront's nodes fit a box of at most
+// kAdjBox coefficients, they are first summed in `box` (this wavefront's LDS,
+// FP64 LDS atomics) and the box is then added to cbar with one global atomic
+// per touched coefficient; otherwise each tap is a global atomic.  Every
+// wavefront of the workgroup must call this once (it holds two workgroup
+// barriers); lanes with `on` false add nothing.
+constexpr int kAdjBox = 512;
+__device__ __forceinline__ void scatter_taps_wave(double *__restrict__ cbar, int H, int W, bool on,
+                                                  int cx, double fx, int cy, double fy, double cv,
+                                                  double cgx, double cgy, double *box) {
+  const int lane = (int)threadIdx.x & 63;
+  int mnx = on ? cx : INT_MAX, mxx = on ? cx : INT_MIN;
+  int mny = on ? cy : INT_MAX, mxy = on ? cy : INT_MIN;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mnx = min(mnx, __shfl_xor(mnx, off));
+    mxx = max(mxx, __shfl_xor(mxx, off));
+    mny = min(mny, __shfl_xor(mny, off));
+    mxy = max(mxy, __shfl_xor(mxy, off));
+  }
+  const bool any = mxx >= mnx;                      // uniform in the wavefront
+  const int bx0 = mnx - 1, by0 = mny - 1;
+  const int bw = any ? mxx - mnx + 4 : 0, bh = any ? mxy - mny + 4 : 0;
+  const bool staged = any && bw <= 64 && bw * bh <= kAdjBox;
+  if (staged)
+    for (int e = lane; e < bw * bh; e += 64) box[e] = 0.0;
+  __syncthreads();
   double wx[4], dx[4], wy[4], dy[4];
   bs_weights_d(fx, wx);
   bs_deriv_d(fx, dx);
   bs_weights_d(fy, wy);
   bs_deriv_d(fy, dy);
-  unsigned col[4], row[4];
-  if (cx >= 1 && cx + 2 < W && cy >= 1 && cy + 2 < H) {
+  if (on && staged) {
+    double *b = box + (cy - 1 - by0) * bw + (cx - 1 - bx0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      col[k] = (unsigned)(cx - 1 + k);
-      row[k] = (unsigned)(cy - 1 + k) * (unsigned)W;
-    }
-  } else {
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        atomicAdd(b + m * bw + n, cv * wy[m] * wx[n] + cgx * wy[m] * dx[n] + cgy * dy[m] * wx[n]);
+  } else if (on) {
+    unsigned col[4], row[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       col[k] = (unsigned)fold_index(cx - 1 + k, W);
       row[k] = (unsigned)fold_index(cy - 1 + k, H) * (unsigned)W;
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        unsafeAtomicAdd(cbar + (row[m] + col[n]),
+                        cv * wy[m] * wx[n] + cgx * wy[m] * dx[n] + cgy * dy[m] * wx[n]);
   }
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const double v = cv * wy[m] * wx[n] + cgx * wy[m] * dx[n] + cgy * dy[m] * wx[n];
-      unsafeAtomicAdd(cbar + (row[m] + col[n]), v);
-    }
+  __syncthreads();
+  if (staged) {
+    // box rows, 64 / (32 or 64) rows per pass
+    const int per = bw <= 32 ? 32 : 64, rpp = 64 / per, c = lane % per;
+    for (int r = lane / per; r < bh; r += rpp)
+      if (c < bw) {
+        const double v = box[r * bw + c];
+        if (v != 0.0)
+          unsafeAtomicAdd(cbar + ((unsigned)fold_index(by0 + r, H) * (unsigned)W +
+                                  (unsigned)fold_index(bx0 + c, W)),
+                          v);
+      }
+  }
 }
 
-// Warp adjoint (and the forward MSD partials of the same pixels).
+// Adds (ax, ay) to lam[node] for every lane with `on`: the wavefront first
+// sums equal nodes in an LDS table of kLamSlots (node, value) slots (linear
+// probing, at most kLamProbes probes; a node that finds no slot goes straight
+// to global memory), then adds each occupied slot to lam with global atomics.
+// Every wavefront of the workgroup must call this once (two workgroup
+// barriers).
+constexpr int kLamSlots = 128, kLamProbes = 8;
+__device__ __forceinline__ void add_lambda_wave(double2 *lam, bool on, int node, double ax,
+                                                double ay, int *keys, double2 *vals) {
+  const int lane = (int)threadIdx.x & 63;
+  for (int e = lane; e < kLamSlots; e += 64) {
+    keys[e] = -1;
+    vals[e] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (on) {
+    int h = (int)(((unsigned)node * 2654435761u) >> 25);     // 7 bits
+    bool done = false;
+    for (int p = 0; p < kLamProbes && !done; ++p) {
+      const int old = atomicCAS(keys + h, -1, node);
+      if (old == -1 || old == node) {
+        atomicAdd(&vals[h].x, ax);
+        atomicAdd(&vals[h].y, ay);
+        done = true;
+      }
+      h = (h + 1) & (kLamSlots - 1);
+    }
+    if (!done) {
+      unsafeAtomicAdd(&lam[node].x, ax);
+      unsafeAtomicAdd(&lam[node].y, ay);
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < kLamSlots; e += 64) {
+    const int nd = keys[e];
+    if (nd >= 0) {
+      unsafeAtomicAdd(&lam[nd].x, vals[e].x);
+      unsafeAtomicAdd(&lam[nd].y, vals[e].y);
+    }
+  }
+}
+
+// Warp adjoint (and the forward MSD partials of the same pixels), one 16 x 16
+// tile per workgroup: lambda^N of the three corners of each pixel's triangle
+// and the coefficient adjoint of the pixel's sample, both pre-summed per
+// wavefront in LDS (add_lambda_wave, scatter_taps_wave) before the global
+// atomics.
 __global__ __launch_bounds__(256) void k_warp_adjoint(
     const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs,
     const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
     const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
     const double *__restrict__ g_msd, double2 *lam, double *cbar, double *__restrict__ partials) {
+  __shared__ double box[4][kAdjBox];
+  __shared__ int keys[4][kLamSlots];
+  __shared__ double2 vals[4][kLamSlots];
+  const int wave = (int)threadIdx.x >> 6;
   const TileItem it = tiles[blockIdx.x];
   const DevPair P = pairs[it.pair];
   const int i = it.y0 + (int)(threadIdx.x / kTile);
   const int j = it.x0 + (int)(threadIdx.x % kTile);
-  double acc = 0.0;
-  if (i < P.height && j < P.width) {
-    const size_t pix = (size_t)P.pix_off + (size_t)i * P.width + j;
-    const int4 nd = tri[P.tri_off + t6[pix]];
-    const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
-    const double px = 2.0 * j + 1.0, py = 2.0 * i + 1.0;
-    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
-    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
-    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
-    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-    const double inv = 1.0 / (ca + cb + cc);
-    const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
-    const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
-    const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
-    const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
-    int qx, qy;
-    double fx, fy;
-    split_coord_d(j, dx, qx, fx);
-    split_coord_d(i, dy, qy, fy);
-    const float *cp = coef + P.pix_off;
-    double val, gx, gy;
-    spline_vg_d(cp, P.height, P.width, qx, fx, qy, fy, val, gx, gy);
-    const double e = val - (double)re[pix];
-    acc = e * e;
-    const double s = 2.0 * g_msd[it.pair] / ((double)P.height * (double)P.width) * e;
-    unsafeAtomicAdd(&lam[nd.x].x, s * wa * gx);
-    unsafeAtomicAdd(&lam[nd.x].y, s * wa * gy);
-    unsafeAtomicAdd(&lam[nd.y].x, s * wb * gx);
-    unsafeAtomicAdd(&lam[nd.y].y, s * wb * gy);
-    unsafeAtomicAdd(&lam[nd.z].x, s * wc * gx);
-    unsafeAtomicAdd(&lam[nd.z].y, s * wc * gy);
-    scatter_taps(cbar + P.pix_off, P.height, P.width, qx, fx, qy, fy, s, 0.0, 0.0);
-  }
+  const bool in = i < P.height && j < P.width;
+  const int I = min(i, P.height - 1), J = min(j, P.width - 1);
+  const size_t pix = (size_t)P.pix_off + (size_t)I * P.width + J;
+  const int4 nd = tri[P.tri_off + t6[pix]];
+  const int2 a = xy[nd.x], b = xy[nd.y], c = xy[nd.z];
+  const double px = 2.0 * J + 1.0, py = 2.0 * I + 1.0;
+  const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
+  const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
+  const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
+  const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
+  const double inv = 1.0 / (ca + cb + cc);
+  const double wa = ca * inv, wb = cb * inv, wc = cc * inv;
+  const double2 ua = u[nd.x], ub = u[nd.y], uc = u[nd.z];
+  const double dx = wa * ua.x + wb * ub.x + wc * uc.x;
+  const double dy = wa * ua.y + wb * ub.y + wc * uc.y;
+  int qx, qy;
+  double fx, fy;
+  split_coord_d(J, dx, qx, fx);
+  split_coord_d(I, dy, qy, fy);
+  const float *cp = coef + P.pix_off;
+  double val, gx, gy;
+  spline_vg_d(cp, P.height, P.width, qx, fx, qy, fy, val, gx, gy);
+  const double e = val - (double)re[pix];
+  const double acc = in ? e * e : 0.0;
+  const double s = in ? 2.0 * g_msd[it.pair] / ((double)P.height * (double)P.width) * e : 0.0;
+  add_lambda_wave(lam, in, nd.x, s * wa * gx, s * wa * gy, keys[wave], vals[wave]);
+  add_lambda_wave(lam, in, nd.y, s * wb * gx, s * wb * gy, keys[wave], vals[wave]);
+  add_lambda_wave(lam, in, nd.z, s * wc * gx, s * wc * gy, keys[wave], vals[wave]);
+  scatter_taps_wave(cbar + P.pix_off, P.height, P.width, in, qx, fx, qy, fy, s, 0.0, 0.0,
+                    box[wave]);
   __shared__ double red[4];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  const double sum = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[wave] = sum;
   __syncthreads();
   if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
@@ -150,6 +236,9 @@ __global__ __launch_bounds__(256) void k_warp_adjoint(
 //   lambda^k_i = mu_i + (g_i . eta_i) g_i + r_i H_i eta_i at u^k, written in natural
 //   and in solve order (the right-hand side of the next step's solve),
 //   and the coefficient adjoint of the force density scattered into cbar.
+// The stiffness / mass row is read in batches of 4 entries (indices and
+// weights, then the gathers of u^{k+1} and mu), the template taps at u^k in
+// the same batch as the row's first indices.
 __global__ __launch_bounds__(256) void k_adjoint_step(
     const NodeItem *__restrict__ items, const DevPair *__restrict__ pairs,
     const int32_t *__restrict__ kptr, const int32_t *__restrict__ kcol,
@@ -158,70 +247,89 @@ __global__ __launch_bounds__(256) void k_adjoint_step(
     const int2 *__restrict__ xy, const float *__restrict__ coef, const float *__restrict__ rho,
     const int32_t *__restrict__ iperm, double2 *__restrict__ lam, double2 *__restrict__ lam_solve,
     double *cbar, double *__restrict__ alpha_part, double tau, int nodal) {
+  __shared__ double box[4][kAdjBox];
   const NodeItem it = items[blockIdx.x];
   const int i = it.begin + threadIdx.x;
-  double da = 0.0;
-  if (i < it.end) {
-    const DevPair P = pairs[it.pair];
-    double kx = 0.0, ky = 0.0, ex = 0.0, ey = 0.0;
-    for (int q = kptr[i]; q < kptr[i + 1]; ++q) {
-      const int jn = kcol[q];
-      const double2 uj = u1[jn];
-      kx += kval[q] * uj.x;
-      ky += kval[q] * uj.y;
-      if (!nodal) {
-        const double2 mj = mu[jn];
-        ex += mwt_t[q] * mj.x;
-        ey += mwt_t[q] * mj.y;
-      }
-    }
-    const double2 mi = mu[i];
-    da = mi.x * kx + mi.y * ky;
-    const double2 et = nodal ? make_double2(-tau * mi.x, -tau * mi.y)
-                             : make_double2(-tau * ex, -tau * ey);
-    // spline value, gradient and Hessian of the template at u^k
-    const double2 ui = u[i];
-    const int2 v = xy[i];
-    int cx, cy;
-    double fx, fy;
-    split_coord_d(v.x, ui.x - 0.5, cx, fx);
-    split_coord_d(v.y, ui.y - 0.5, cy, fy);
-    double wx[4], dx[4], exw[4], wy[4], dy[4], eyw[4];
-    bs_weights_d(fx, wx);
-    bs_deriv_d(fx, dx);
-    bs_deriv2_d(fx, exw);
-    bs_weights_d(fy, wy);
-    bs_deriv_d(fy, dy);
-    bs_deriv2_d(fy, eyw);
-    const float *c = coef + P.pix_off;
-    float t[4][4];
-    load_taps(c, P.height, P.width, cx, cy, t);
-    double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+  const bool on = i < it.end;
+  const int ii = on ? i : it.begin;               // idle lanes read a valid node
+  const DevPair P = pairs[it.pair];
+  const double2 ui = u[ii];
+  const int2 v = xy[ii];
+  const double2 mi = mu[ii];
+  const float rh = rho[ii];
+  const int q0 = kptr[ii], q1 = kptr[ii + 1];
+  int cx, cy;
+  double fx, fy;
+  split_coord_d(v.x, ui.x - 0.5, cx, fx);
+  split_coord_d(v.y, ui.y - 0.5, cy, fy);
+  const float *c = coef + P.pix_off;
+  float t[4][4];
+  load_taps(c, P.height, P.width, cx, cy, t);
+  double kx = 0.0, ky = 0.0, ex = 0.0, ey = 0.0;
+  constexpr int U = 4;
+  for (int q = q0; q < q1; q += U) {
+    int jn[U];
+    double kv[U], mw[U];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      double rv = 0.0, rd = 0.0, re2 = 0.0;
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const double cv = (double)t[m][n];
-        rv += cv * wx[n];
-        rd += cv * dx[n];
-        re2 += cv * exw[n];
-      }
-      val += wy[m] * rv;
-      gx += wy[m] * rd;
-      gy += dy[m] * rv;
-      hxx += wy[m] * re2;
-      hxy += dy[m] * rd;
-      hyy += eyw[m] * rv;
+    for (int k = 0; k < U; ++k) {
+      const bool in = q + k < q1;
+      jn[k] = in ? kcol[q + k] : ii;
+      kv[k] = in ? kval[q + k] : 0.0;
+      mw[k] = (in && !nodal) ? mwt_t[q + k] : 0.0;
     }
-    const double r = val - (double)rho[i];
-    const double ge = gx * et.x + gy * et.y;
+    double2 uj[U], mj[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      uj[k] = u1[jn[k]];
+      mj[k] = nodal ? make_double2(0.0, 0.0) : mu[jn[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      kx += kv[k] * uj[k].x;
+      ky += kv[k] * uj[k].y;
+      ex += mw[k] * mj[k].x;
+      ey += mw[k] * mj[k].y;
+    }
+  }
+  double da = on ? mi.x * kx + mi.y * ky : 0.0;
+  const double2 et = nodal ? make_double2(-tau * mi.x, -tau * mi.y)
+                           : make_double2(-tau * ex, -tau * ey);
+  // spline value, gradient and Hessian of the template at u^k
+  double wx[4], dx[4], exw[4], wy[4], dy[4], eyw[4];
+  bs_weights_d(fx, wx);
+  bs_deriv_d(fx, dx);
+  bs_deriv2_d(fx, exw);
+  bs_weights_d(fy, wy);
+  bs_deriv_d(fy, dy);
+  bs_deriv2_d(fy, eyw);
+  double val = 0.0, gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double rv = 0.0, rd = 0.0, re2 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const double cv = (double)t[m][n];
+      rv += cv * wx[n];
+      rd += cv * dx[n];
+      re2 += cv * exw[n];
+    }
+    val += wy[m] * rv;
+    gx += wy[m] * rd;
+    gy += dy[m] * rv;
+    hxx += wy[m] * re2;
+    hxy += dy[m] * rd;
+    hyy += eyw[m] * rv;
+  }
+  const double r = val - (double)rh;
+  const double ge = gx * et.x + gy * et.y;
+  if (on) {
     const double2 l = make_double2(mi.x + ge * gx + r * (hxx * et.x + hxy * et.y),
                                    mi.y + ge * gy + r * (hxy * et.x + hyy * et.y));
     lam[i] = l;
     lam_solve[iperm[i]] = l;
-    scatter_taps(cbar + P.pix_off, P.height, P.width, cx, fx, cy, fy, ge, r * et.x, r * et.y);
   }
+  scatter_taps_wave(cbar + P.pix_off, P.height, P.width, on, cx, fx, cy, fy, ge, r * et.x,
+                    r * et.y, box[threadIdx.x >> 6]);
   __shared__ double red[4];
   da = wave_sum(da);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = da;
