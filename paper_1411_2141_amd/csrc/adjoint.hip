@@ -455,11 +455,11 @@ int mr_ctx::reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const
     HIP_OK(launch(k_alpha_finish, 1, 256, 0, s, d_pairs.ptr, n_pairs, d_alpha_part.ptr,
                   g_alpha));
   }
+  // gbar_Te = B^-1 cbar for every pair in two launches (cbar is overwritten)
   if (g_te)
-    for (int p = 0; p < n_pairs; ++p) {
-      rc = prefilter_pair_d(p, d_cbar.ptr + dpairs[p].pix_off, g_te + dpairs[p].pix_off, s);
-      if (rc) return rc;
-    }
+    HIP_OK(launch_prefilter_all(d_pref_rows.ptr, (int)d_pref_rows.count, d_pref_cols.ptr,
+                                (int)d_pref_cols.count, d_pairs.ptr, d_cbar.ptr, g_te,
+                                d_thomas.ptr, s));
   post_flags(s);
   return MR_OK;
 }

@@ -169,7 +169,7 @@ hipError_t mr_ctx::solve(double2 *x, double2 *out, hipStream_t s, const Assemble
 // Autotuner: for every solve level, times each admissible kernel on the
 // context's own data (first each level alone, then each level inside the
 // whole solve) and keeps the fastest: the half-wavefront-per-block kernels
-// (blocks of at most 32 rows), the wavefront-per-block kernels with
+// (blocks of at most 32 rows; 8 or 16 loads per lane in flight), the wavefront-per-block kernels with
 // direct LDS staging (blocks of at most 64 rows whose factor data fits 64 KB)
 // or with register batches (blocks of at most 64 rows) (backward: no split
 // blocks), and the workgroup-per-block
@@ -181,7 +181,8 @@ bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
   if (nt == 1)
     return minnt[lev] <= 64 && (fwd ? fwd_direct[lev] : bwd_direct[lev]) <= 64 * 1024 &&
            (fwd || !bwd_split[lev]);
-  if (nt == 32) return (fwd ? fwd_maxb[lev] : bwd_maxb[lev]) <= 32 && (fwd || !bwd_split[lev]);
+  if (nt == 32 || nt == 33)
+    return (fwd ? fwd_maxb[lev] : bwd_maxb[lev]) <= 32 && (fwd || !bwd_split[lev]);
   if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
   return nt >= minnt[lev];
 }
@@ -236,7 +237,7 @@ int mr_ctx::tune(hipStream_t s) {
     }
     return t_min;
   };
-  static const int kCandidates[] = {1, 8, 16, 32, 64, 128, 256, 512, 1024};
+  static const int kCandidates[] = {1, 8, 16, 32, 33, 64, 128, 256, 512, 1024};
   // The first forward level either assembles the right-hand side itself
   // (fused) or follows a separate assembly launch; both are candidates unless
   // the separate launch is requested.
@@ -834,6 +835,17 @@ int mr_ctx::upload_prefilter_tables(hipStream_t s) {
   }
   HIP_TRY(upload(d_thomas, all, s));
   HIP_TRY(d_prefilter_tmp.alloc(max_pix));
+  // work items of the batched passes: 64 rows / columns of one pair each
+  std::vector<PrefItem> rows, cols;
+  for (int p = 0; p < n_pairs; ++p) {
+    const DevPair &d = dpairs[p];
+    const int32_t tw = (int32_t)thomas_off.at(d.width), th = (int32_t)thomas_off.at(d.height);
+    for (int32_t r = 0; r < d.height; r += 64) rows.push_back(PrefItem{p, r, tw, th});
+    for (int32_t c = 0; c < d.width; c += 64) cols.push_back(PrefItem{p, c, tw, th});
+  }
+  HIP_TRY(upload(d_pref_rows, rows, s));
+  HIP_TRY(upload(d_pref_cols, cols, s));
+  HIP_TRY(hipStreamSynchronize(s));            // the host vectors go out of scope
   return MR_OK;
 }
 
@@ -887,9 +899,9 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     return fail(MR_EINVAL, "unknown force_mode");
   {
     const int32_t k = params->solve_kernel;
-    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 64 && k != 128 && k != 256 &&
-        k != 512 && k != 1024)
-      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 64, 128, 256, 512 or 1024");
+    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 33 && k != 64 && k != 128 &&
+        k != 256 && k != 512 && k != 1024)
+      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 33, 64, 128, 256, 512 or 1024");
   }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {

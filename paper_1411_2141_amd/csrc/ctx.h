@@ -82,6 +82,7 @@ struct mr_ctx {
   std::vector<int32_t> fwd_maxb, bwd_maxb;      // per level: rows of its largest block
   mr::DevArray<double2> d_thomas;                // prefilter tables of every image side
   std::map<int32_t, int64_t> thomas_off;         // side -> offset into d_thomas
+  mr::DevArray<mr::PrefItem> d_pref_rows, d_pref_cols;  // batched prefilter work items
   mr::DevArray<double> d_prefilter_tmp;          // prefilter scratch (largest pair)
   mr::DevArray<int32_t> d_upper_rows;           // solve rows outside the first forward level
   int64_t n_apex_rows = 0;

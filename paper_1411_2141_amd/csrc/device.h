@@ -116,6 +116,13 @@ struct NodeItem {
   int32_t pair, begin, end, active;
 };
 
+// Work item of the batched prefilter: 64 consecutive rows (row pass) or
+// columns (column pass) of pair `pair`, from `first` on; tab_w / tab_h are the
+// offsets of the Thomas tables of the pair's width and height.
+struct PrefItem {
+  int32_t pair, first, tab_w, tab_h;
+};
+
 // Work item of the pixel-parallel kernels: one kTile x kTile tile.
 struct TileItem {
   int32_t pair, y0, x0, active;

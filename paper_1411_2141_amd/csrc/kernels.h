@@ -53,6 +53,11 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
                              const ApexBwdItem *bitems, int n_bitems, const int2 *rng, int bwd_lds,
                              const double *xb, const int32_t *perm, double2 *out, hipStream_t s);
 // Warp partials of u; tpos holds each triangle's corners packed as x | y << 16.
+// B^-1 along rows then columns of every pair of a context (img: FP64, all
+// pairs' pixels, overwritten by the row pass; out: FP32 coefficients).
+hipError_t launch_prefilter_all(const PrefItem *row_items, int n_row_items,
+                                const PrefItem *col_items, int n_col_items, const DevPair *pairs,
+                                double *img, float *out, const double2 *tab, hipStream_t s);
 hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
                                 const double2 *u, const int4 *tpos, const int4 *tri,
                                 const int32_t *t6, const float *coef, const float *re,

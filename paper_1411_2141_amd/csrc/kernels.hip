@@ -130,6 +130,113 @@ __global__ void k_prefilter_cols(double *__restrict__ tmp, float *__restrict__ o
   }
 }
 
+// The two passes for every pair of a context at once (work items of 64 rows
+// or columns of one pair); FP64 in, the row pass may run in place
+// (src == tmp: each batch of loads is issued before its writes, later
+// batches read only positions not yet written), FP32 coefficients out.
+__global__ __launch_bounds__(64) void k_prefilter_rows_all(const PrefItem *__restrict__ items,
+                                                           const DevPair *__restrict__ pairs,
+                                                           const double *src, double *tmp,
+                                                           const double2 *__restrict__ tab) {
+  const PrefItem it = items[blockIdx.x];
+  const DevPair P = pairs[it.pair];
+  const int r = it.first + (int)threadIdx.x;
+  if (r >= P.height) return;
+  const int W = P.width;
+  const double *s = src + P.pix_off + (size_t)r * W;
+  double *d = tmp + P.pix_off + (size_t)r * W;
+  const double2 *tw = tab + it.tab_w;
+  if (W == 1) {
+    d[0] = s[0];
+    return;
+  }
+  const double off = 1.0 / 6.0;
+  constexpr int U = 8;
+  double prev = 0.0;
+  for (int k0 = 0; k0 < W; k0 += U) {
+    double sv[U], mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      sv[u] = k < W ? s[k] : 0.0;
+      mv[u] = k < W ? tw[k].y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < W) {
+        prev = (sv[u] - off * prev) * mv[u];
+        d[k0 + u] = prev;
+      }
+  }
+  for (int k1 = W - 2; k1 >= 0; k1 -= U) {
+    double yv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k1 - u;
+      yv[u] = k >= 0 ? d[k] : 0.0;
+      cv[u] = k >= 0 ? tw[k].x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k1 - u >= 0) {
+        prev = yv[u] - cv[u] * prev;
+        d[k1 - u] = prev;
+      }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_prefilter_cols_all(const PrefItem *__restrict__ items,
+                                                           const DevPair *__restrict__ pairs,
+                                                           double *tmp, float *__restrict__ out,
+                                                           const double2 *__restrict__ tab) {
+  const PrefItem it = items[blockIdx.x];
+  const DevPair P = pairs[it.pair];
+  const int col = it.first + (int)threadIdx.x;
+  if (col >= P.width) return;
+  const int H = P.height, W = P.width;
+  double *d = tmp + P.pix_off + col;
+  float *o = out + P.pix_off + col;
+  const double2 *th = tab + it.tab_h;
+  if (H == 1) {
+    o[0] = (float)d[0];
+    return;
+  }
+  const double off = 1.0 / 6.0;
+  constexpr int U = 8;
+  double prev = 0.0;
+  for (int k0 = 0; k0 < H; k0 += U) {
+    double sv[U], mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      sv[u] = k < H ? d[(size_t)k * W] : 0.0;
+      mv[u] = k < H ? th[k].y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < H) {
+        prev = (sv[u] - off * prev) * mv[u];
+        d[(size_t)(k0 + u) * W] = prev;
+      }
+  }
+  o[(size_t)(H - 1) * W] = (float)prev;
+  for (int k1 = H - 2; k1 >= 0; k1 -= U) {
+    double yv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k1 - u;
+      yv[u] = k >= 0 ? d[(size_t)k * W] : 0.0;
+      cv[u] = k >= 0 ? th[k].x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k1 - u >= 0) {
+        prev = yv[u] - cv[u] * prev;
+        o[(size_t)(k1 - u) * W] = (float)prev;
+      }
+  }
+}
+
 // Reference spline at the undisplaced nodes: rho_i = s_Re(V_i - 1/2).
 __global__ __launch_bounds__(256) void k_sample_rho(const NodeItem *__restrict__ items,
                                                     const DevPair *__restrict__ pairs,
@@ -1660,6 +1767,16 @@ hipError_t launch_prefilter(const float *src_f, const double *src_d, double *tmp
   return launch(k_prefilter_cols, (W + tb - 1) / tb, tb, 0, s, tmp, out, H, W, tab_h);
 }
 
+hipError_t launch_prefilter_all(const PrefItem *row_items, int n_row_items,
+                                const PrefItem *col_items, int n_col_items, const DevPair *pairs,
+                                double *img, float *out, const double2 *tab, hipStream_t s) {
+  if (n_row_items == 0 || n_col_items == 0) return hipSuccess;
+  hipError_t e = launch(k_prefilter_rows_all, n_row_items, 64, 0, s, row_items, pairs,
+                        (const double *)img, img, tab);
+  if (e != hipSuccess) return e;
+  return launch(k_prefilter_cols_all, n_col_items, 64, 0, s, col_items, pairs, img, out, tab);
+}
+
 hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *pairs,
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s) {
   return launch(k_sample_rho, n_items, kNodeChunk, 0, s, items, pairs, xy, coef_re, rho);
@@ -1697,11 +1814,17 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
                 : launch(k_lds_fwd<false>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
                          cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
   }
-  if (nt == 32) {                             // half-wavefront per block (at most 32 rows)
+  if (nt == 32 || nt == 33) {                 // half-wavefront per block (at most 32 rows),
+                                              // 8 (32) or 16 (33) loads per batch
     int groups = (count + 7) / 8;
     if (fuse)
       groups += (fuse->n_rows + 255) / 256 + (fuse->finish_msd ? (fuse->n_pairs + 3) / 4 : 0);
     if (groups == 0) return hipSuccess;
+    if (nt == 33)
+      return fuse ? launch(k_half_fwd<true, 16>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, *fuse)
+                  : launch(k_half_fwd<false, 16>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
     return fuse ? launch(k_half_fwd<true, 8>, groups, 256, 0, s, blocks, items, count, cptr, cidx,
                          dcol, pcol, x, ybuf, upd, *fuse)
                 : launch(k_half_fwd<false, 8>, groups, 256, 0, s, blocks, items, count, cptr,
@@ -1755,9 +1878,9 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   if (nt == 1)
     return launch(k_lds_bwd, count, 64, lds_bytes, s, blocks, items, count, below_idx, drow, prow,
                   x, ybuf, perm, out);
-  if (nt == 32)
-    return launch(k_half_bwd<8>, (count + 7) / 8, 256, 0, s, blocks, items, count, below_idx,
-                  drow, prow, x, ybuf, perm, out);
+  if (nt == 32 || nt == 33)
+    return launch(nt == 32 ? k_half_bwd<8> : k_half_bwd<16>, (count + 7) / 8, 256, 0, s, blocks,
+                  items, count, below_idx, drow, prow, x, ybuf, perm, out);
   if (nt == 8 || nt == 16)
     return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
                   items, count, below_idx, drow, prow, x, ybuf, perm, out);
