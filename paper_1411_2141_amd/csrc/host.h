@@ -111,7 +111,7 @@ constexpr int32_t kApexPathMax = 2048;
 struct OrderOptions {
   int32_t leaf_max = 32;                   // nested-dissection leaf size
   int32_t block_max = 96;                  // largest dense diagonal block
-  double nd_balance = 0.2;                 // nested dissection: smallest side fraction of a cut
+  double nd_balance = 0.3;                 // nested dissection: smallest side fraction of a cut
   int32_t nd_score = 1;                    // nested dissection cut score: 0 separator size,
                                            // 1 separator size / (left x right)
   int32_t apex_max = 1 << 30;              // most apex rows (0: no apex)

@@ -8,7 +8,7 @@
 //
 // Ordering: geometric nested dissection on the node coordinates.  A node set is
 // split by a straight cut across one axis, chosen among the positions that
-// leave each side at least a fifth of the set for the smallest separator per
+// leave each side at least 30 % of the set for the smallest separator per
 // pair of halves (not at the median: on adaptive meshes a cut through coarse
 // cells crosses few nodes); the separator is the smaller of the two one-sided
 // boundary sets; the halves are ordered first, the separator last.  Small sets become leaf blocks, separators become one or

@@ -153,3 +153,32 @@ def test_explicit_batch_graph_and_mixing_with_the_implicit_step():
         with pytest.raises(lib().MeshRegError):
             ctx.step_explicit(u, *bad)
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg,n_iter", [(1, 3), (2, 5)])
+def test_explicit_at_the_papers_step(cfg, n_iter):
+    """The paper's own step (eq. 5: tau = 0.005 on 0-255 intensities, i.e.
+    0.005 * 255^2 on [0, 1] images) with lambda = 0.8, for the first
+    iterations, where the trajectory is still well defined: on the CPU,
+    rounding the spline coefficients to FP32 moves u by <= 4.4e-7 (128^2, 3
+    iterations) and <= 1e-7 (512^2, 5 iterations) relative, while the deformed
+    mesh folds from the first iteration on (here checked to be so), so the
+    kernels' handling of folded triangles (unsigned areas) is exercised."""
+    tau = 0.005 * 255.0 ** 2
+    d = as_dict(make_pair(cfg))
+    say(f"explicit variant at the paper's step tau={tau}: config {cfg}, {n_iter} iterations")
+    pb = problem(d)
+    ctx = lib().MeshReg([d], tau=0.5)
+    u = ctx.zeros_u()
+    ctx.step_explicit(u, n_iter, tau, LAM)
+    torch.cuda.synchronize()
+    u_or, _ = lit.run(pb, None, n_iter, tau, LAM)
+    err = rel(u.cpu().numpy(), u_or)
+    P = d["V"] + u_or
+    T = d["T"]
+    cr = ((P[T[:, 1], 0] - P[T[:, 0], 0]) * (P[T[:, 2], 1] - P[T[:, 0], 1])
+          - (P[T[:, 1], 1] - P[T[:, 0], 1]) * (P[T[:, 2], 0] - P[T[:, 0], 0]))
+    say(f"paper's step: |du|/|u| {err:.2e}, folded triangles {int((cr <= 0).sum())} of {len(T)}")
+    assert (cr <= 0).sum() > 0
+    assert err < U_TOL
+    ctx.close()
