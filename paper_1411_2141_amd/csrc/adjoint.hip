@@ -415,10 +415,11 @@ int mr_ctx::reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const
   HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
   HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
   timed_begin(MR_KF_WARP, s);
-  HIP_OK(launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr, d_pairs.ptr,
-                ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
-                g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr));
-  timed_end(s);
+  const hipError_t ew = launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr,
+                               d_pairs.ptr, ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr,
+                               d_re.ptr, g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr);
+  timed_end(s);          // before any return, so no timer stays attached to the thread
+  HIP_OK(ew);
   if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));
   // lambda^N in solve order (its own buffer: the recomputed iterations use x)
   // for the first reverse solve; every reverse step writes the next one there
@@ -442,12 +443,14 @@ int mr_ctx::reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const
       // mu = S^-1 lambda^{k+1} (right-hand side in solve order, consumed in place)
       HIP_OK(solve(d_lam_s.ptr, d_mu.ptr, s, nullptr));
       timed_begin(MR_KF_ASSEMBLE, s);
-      HIP_OK(launch(k_adjoint_step, n_node_items, kNodeChunk, 0, s, d_node_items.ptr, d_pairs.ptr,
-                    d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, (const double2 *)d_mu.ptr,
-                    iterate_at(k + 1), iterate_at(k), d_xy.ptr, d_coef.ptr, d_rho.ptr,
-                    d_iperm.ptr, d_lam.ptr, d_lam_s.ptr, d_cbar.ptr, d_alpha_part.ptr, params.tau,
-                    params.force_mode == MR_FORCE_NODAL ? 1 : 0));
+      const hipError_t ea =
+          launch(k_adjoint_step, n_node_items, kNodeChunk, 0, s, d_node_items.ptr, d_pairs.ptr,
+                 d_kptr.ptr, d_kcol.ptr, d_kval.ptr, d_mwt_t.ptr, (const double2 *)d_mu.ptr,
+                 iterate_at(k + 1), iterate_at(k), d_xy.ptr, d_coef.ptr, d_rho.ptr, d_iperm.ptr,
+                 d_lam.ptr, d_lam_s.ptr, d_cbar.ptr, d_alpha_part.ptr, params.tau,
+                 params.force_mode == MR_FORCE_NODAL ? 1 : 0);
       timed_end(s);
+      HIP_OK(ea);
     }
   }
   if (g_u0) HIP_OK(hipMemcpyAsync(g_u0, d_lam.ptr, nb, hipMemcpyDeviceToDevice, s));

@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/meshreg.h"
 #include "device.h"
 #include "host.h"
@@ -29,6 +31,15 @@ int mr_set_error(int code, const std::string &msg) {
 }
 
 static int fail(int code, const std::string &msg) { return mr_set_error(code, msg); }
+
+// A roctx range around an entry point (named after it), so that profiler
+// traces group each call's kernel launches; a no-op without a profiler.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Static device scratch of mesh_reg_warp_msd_noalloc: the per-tile FP64
 // partial sums of the warp + MSD, 2^19 tiles of 16 x 16 pixels (4 MiB, images
@@ -891,6 +902,7 @@ static int64_t apex_level_budget(int32_t n_pairs) {
 
 extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_params *params,
                              void *stream, mr_ctx **out) {
+  const TraceRange range_("mesh_reg_init");
   if (!out) return fail(MR_EINVAL, "out is null");
   *out = nullptr;
   if (!pairs || n_pairs < 1 || !params) return fail(MR_EINVAL, "need pairs, n_pairs >= 1 and params");
@@ -1085,6 +1097,7 @@ static int run_iterations(mr_ctx *c, double *u, int32_t n_iter, double *msd_trac
 
 extern "C" int mesh_reg_step(mr_ctx *c, double *u, int32_t n_iter, double *msd_trace,
                              void *stream) {
+  const TraceRange range_("mesh_reg_step");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!u || !aligned16(u) || n_iter < 0) return fail(MR_EINVAL, "u must be a 16-byte aligned device pointer; n_iter >= 0");
@@ -1158,19 +1171,21 @@ int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, do
     // rows of the trace finished here (from the previous update's tiles)
     double *fin = (msd_trace && k >= 2) ? msd_trace + (size_t)(k - 2) * n_pairs : nullptr;
     timed_begin(MR_KF_SAMPLE, s);
-    HIP_TRY(launch_explicit_smooth(d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u0, u,
-                                   d_x_rptr.ptr, d_x_ridx.ptr, lam, k > 0, k < n_iter, d_xy.ptr,
-                                   d_coef.ptr, d_rho.ptr, rec, d_flags.ptr, d_partials.ptr, fin,
-                                   s));
-    timed_end(s);
+    const hipError_t es = launch_explicit_smooth(
+        d_node_items.ptr, n_node_items, d_pairs.ptr, n_pairs, u0, u, d_x_rptr.ptr, d_x_ridx.ptr,
+        lam, k > 0, k < n_iter, d_xy.ptr, d_coef.ptr, d_rho.ptr, rec, d_flags.ptr, d_partials.ptr,
+        fin, s);
+    timed_end(s);          // before any return, so no timer stays attached to the thread
+    HIP_TRY(es);
     if (k == n_iter) break;
     const int tiles = (msd_trace && k > 0) ? n_tiles : 0;
     timed_begin(MR_KF_ASSEMBLE, s);
-    HIP_TRY(launch_explicit_update(d_node_items.ptr, n_node_items, d_pairs.ptr, u, rec, d_tri.ptr,
-                                   d_x_sptr.ptr, d_x_opp.ptr, tau, u0, d_flags.ptr, d_tiles.ptr,
-                                   tiles, d_tpos.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
-                                   d_partials.ptr, s));
+    const hipError_t eu = launch_explicit_update(
+        d_node_items.ptr, n_node_items, d_pairs.ptr, u, rec, d_tri.ptr, d_x_sptr.ptr, d_x_opp.ptr,
+        tau, u0, d_flags.ptr, d_tiles.ptr, tiles, d_tpos.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
+        d_partials.ptr, s);
     timed_end(s);
+    HIP_TRY(eu);
   }
   if (msd_trace) HIP_TRY(warp(u, msd_trace + (size_t)(n_iter - 1) * n_pairs, nullptr, s));
   return MR_OK;
@@ -1178,6 +1193,7 @@ int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, do
 
 extern "C" int mesh_reg_step_explicit(mr_ctx *c, double *u, int32_t n_iter, double tau,
                                       double lambda, double *msd_trace, void *stream) {
+  const TraceRange range_("mesh_reg_step_explicit");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!u || !aligned16(u) || n_iter < 0 || !std::isfinite(tau) || !(tau >= 0.0) ||
@@ -1199,6 +1215,7 @@ extern "C" int mesh_reg_step_explicit(mr_ctx *c, double *u, int32_t n_iter, doub
 
 extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t check_every,
                             double rel_tol, int32_t *iters_out, double *msd_out, void *stream) {
+  const TraceRange range_("mesh_reg_run");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!u || !aligned16(u) || max_iter < 0 || check_every < 1 || !iters_out || !msd_out ||
@@ -1274,6 +1291,7 @@ extern "C" int mesh_reg_run(mr_ctx *c, double *u, int32_t max_iter, int32_t chec
 
 extern "C" int mesh_reg_warp_msd(mr_ctx *c, const double *u, double *msd, float *warped,
                                  void *stream) {
+  const TraceRange range_("mesh_reg_warp_msd");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!u || !aligned16(u) || !msd) return fail(MR_EINVAL, "need aligned u and msd");
@@ -1312,6 +1330,7 @@ extern "C" int mesh_reg_warp_msd_noalloc(mr_ctx *c, const double *u, double *msd
 }
 
 extern "C" int mesh_reg_force(mr_ctx *c, const double *u, float *h, double *b, void *stream) {
+  const TraceRange range_("mesh_reg_force");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!u || !aligned16(u) || (b && !aligned16(b)) || (h && ((uintptr_t)h & 7u)))
@@ -1328,6 +1347,7 @@ extern "C" int mesh_reg_force(mr_ctx *c, const double *u, float *h, double *b, v
 }
 
 extern "C" int mesh_reg_solve(mr_ctx *c, const double *b, double *x, void *stream) {
+  const TraceRange range_("mesh_reg_solve");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (!b || !x || !aligned16(b) || !aligned16(x)) return fail(MR_EINVAL, "need aligned b and x");
@@ -1339,6 +1359,7 @@ extern "C" int mesh_reg_solve(mr_ctx *c, const double *b, double *x, void *strea
 }
 
 extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *stream) {
+  const TraceRange range_("mesh_reg_set_alpha");
   int rc = check_ctx(c, false);
   if (rc) return rc;
   if (pair < 0 || pair >= c->n_pairs) return fail(MR_EINVAL, "pair out of range");
@@ -1375,6 +1396,7 @@ extern "C" int mesh_reg_set_alpha(mr_ctx *c, int32_t pair, double alpha, void *s
 }
 
 extern "C" int mesh_reg_set_template(mr_ctx *c, int32_t pair, const float *te, void *stream) {
+  const TraceRange range_("mesh_reg_set_template");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   if (pair < 0 || pair >= c->n_pairs || !te) return fail(MR_EINVAL, "bad pair or null te");
@@ -1532,6 +1554,7 @@ extern "C" void mesh_reg_destroy(mr_ctx *c) { delete c; }
 
 extern "C" int mesh_reg_forward_ckpt(mr_ctx *c, double *u, int32_t n_iter, int32_t ckpt_every,
                                      double *ckpt, double *msd, void *stream) {
+  const TraceRange range_("mesh_reg_forward_ckpt");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   return c->forward_with_ckpt(u, n_iter, ckpt_every, ckpt, msd, (hipStream_t)stream);
@@ -1540,6 +1563,7 @@ extern "C" int mesh_reg_forward_ckpt(mr_ctx *c, double *u, int32_t n_iter, int32
 extern "C" int mesh_reg_backward_ckpt(mr_ctx *c, const double *ckpt, int32_t n_iter,
                                       int32_t ckpt_every, const double *g_msd, double *g_u0,
                                       double *g_alpha, float *g_te, double *msd, void *stream) {
+  const TraceRange range_("mesh_reg_backward_ckpt");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   return c->backward_from_ckpt(ckpt, n_iter, ckpt_every, g_msd, g_u0, g_alpha, g_te, msd,
@@ -1549,6 +1573,7 @@ extern "C" int mesh_reg_backward_ckpt(mr_ctx *c, const double *ckpt, int32_t n_i
 extern "C" int mesh_reg_backward(mr_ctx *c, const double *u0, int32_t n_iter, int32_t ckpt_every,
                                  const double *g_msd, double *g_u0, double *g_alpha, float *g_te,
                                  double *msd, void *stream) {
+  const TraceRange range_("mesh_reg_backward");
   int rc = check_ctx(c, true);
   if (rc) return rc;
   return c->backward(u0, n_iter, ckpt_every, g_msd, g_u0, g_alpha, g_te, msd, (hipStream_t)stream);
