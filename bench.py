@@ -130,19 +130,21 @@ def unit_bytes(ctx, pairs) -> dict:
     """Bytes of one pass of each stage in the library's own data layout (each
     stored datum the kernels read or write counted once): node streams, CSR
     force-operator entries (index and weight), the solve's dense block
-    inverses, panels and apex inverse (both passes), the warp's triangle
-    records and tile partials."""
+    inverses, panels and apex inverse (both passes), the warp's per-pixel
+    slot byte, per-tile triangle entries (24 bytes), tile records and
+    partials."""
     n = sum(p.n_nodes for p in pairs)
     nt = sum(int(p.T.shape[0]) for p in pairs)
     pix = sum(p.height * p.width for p in pairs)
     tiles = sum(-(-p.height // 16) * -(-p.width // 16) for p in pairs)
+    entries = sum(ctx.info(k, "tile_entries") for k in range(len(pairs)))
     nnz_m = sum(ctx.info(k, "mass_nnz") for k in range(len(pairs)))
     solve = sum(ctx.info(k, "solve_bytes") for k in range(len(pairs)))
     return {
         "sample": 36 * n + 4 * touched_coefficients(pairs),
         "assemble": 44 * n + 8 * nnz_m,
         "solve": solve,
-        "warp": 12 * pix + 24 * n + 16 * nt + 8 * tiles,
+        "warp": 9 * pix + 16 * n + 24 * entries + 48 * tiles,
         "finish": 8 * tiles + 8 * len(pairs),
     }
 

@@ -279,9 +279,11 @@ enum {
   MR_INFO_MASS_NNZ = 13,        /* entries of the force operator rows */
   MR_INFO_APEX_ROWS = 14,       /* rows of the apex of the solve (0: none) */
   MR_INFO_SOLVE_BYTES = 15,     /* algorithmic bytes of one solve call (both triangular passes) */
-  MR_INFO_FUSED_ASSEMBLY = 16   /* context: 1 if an iteration assembles the right-hand side inside
+  MR_INFO_FUSED_ASSEMBLY = 16,  /* context: 1 if an iteration assembles the right-hand side inside
                                    the first forward solve launch, 0 if in a launch of its own
                                    (chosen by the autotuner) */
+  MR_INFO_TILE_ENTRIES = 17     /* distinct triangles of T6 summed over the pair's 16 x 16 pixel
+                                   tiles (the warp's per-tile triangle lists) */
 };
 int mesh_reg_get_info(mr_ctx *ctx, int32_t pair, int32_t key, int64_t *value);
 

@@ -25,7 +25,7 @@ TABLES = {"t1_ptr": 10, "t1_slot": 11, "t2_ptr": 20, "t2_idx": 21, "t3_ptr": 30,
 INFO = {"n_nodes": 1, "n_tris": 2, "nnz_l": 3, "n_blocks": 4, "fwd_levels": 5, "bwd_levels": 6,
         "node_offset": 7, "pixel_offset": 8, "n_pairs": 9, "device_bytes": 10,
         "solve_offblock": 11, "solve_dense": 12, "mass_nnz": 13, "apex_rows": 14,
-        "solve_bytes": 15, "fused_assembly": 16}
+        "solve_bytes": 15, "fused_assembly": 16, "tile_entries": 17}
 KERNEL_FAMILIES = ("sample", "assemble", "solve", "warp")
 
 EXPORTED = ("mesh_reg_init", "mesh_reg_step", "mesh_reg_run", "mesh_reg_step_explicit",

@@ -338,8 +338,8 @@ hipError_t mr_ctx::sample(bool with_warp, hipStream_t s) {
   timed_begin(MR_KF_SAMPLE, s);
   hipError_t e = launch_sample(d_node_items.ptr, n_node_items, d_pairs.ptr, d_x.ptr, d_xy_s.ptr,
                                d_coef.ptr, d_rho_s.ptr, d_h.ptr, d_flags.ptr, d_tiles.ptr,
-                               with_warp ? n_tiles : 0, d_x.ptr, d_tri_s.ptr, d_tpos.ptr, d_t6.ptr,
-                               d_re.ptr, d_partials.ptr, s);
+                               with_warp ? n_tiles : 0, d_x.ptr, d_tile_nodes_s.ptr,
+                               d_tile_pbc.ptr, d_tile_loc.ptr, d_re.ptr, d_partials.ptr, s);
   timed_end(s);
   return e;
 }
@@ -395,9 +395,9 @@ hipError_t mr_ctx::finish_pending(const double2 *u, double **pending, hipStream_
 
 hipError_t mr_ctx::warp(const double2 *u, double *msd, float *warped, hipStream_t s) {
   timed_begin(MR_KF_WARP, s);
-  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, d_pairs.ptr, u, d_tpos.ptr,
-                                      d_tri.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr, warped,
-                                      d_partials.ptr, d_flags.ptr, s);
+  hipError_t e = launch_warp_partials(d_tiles.ptr, n_tiles, u, d_tile_nodes.ptr,
+                                      d_tile_pbc.ptr, d_tile_loc.ptr, d_coef.ptr,
+                                      d_re.ptr, warped, d_partials.ptr, d_flags.ptr, s);
   if (e == hipSuccess) e = launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s);
   timed_end(s);
   return e;
@@ -446,6 +446,8 @@ int mr_ctx::upload_all(hipStream_t s) {
   dpairs.resize(n_pairs);
   std::vector<NodeItem> items;
   std::vector<TileItem> tiles;
+  std::vector<int32_t> tile_tri;
+  std::vector<uint8_t> tile_loc;
   for (int p = 0; p < n_pairs; ++p) {
     const PairHost &h = host[p];
     DevPair &d = dpairs[p];
@@ -462,7 +464,31 @@ int mr_ctx::upload_all(hipStream_t s) {
     d.n_tiles = d.tiles_x * ty;
     d.active = 1;
     for (int y = 0; y < ty; ++y)
-      for (int x = 0; x < d.tiles_x; ++x) tiles.push_back({p, y * kTile, x * kTile, 1});
+      for (int x = 0; x < d.tiles_x; ++x) {
+        // the tile's distinct triangles (T6 over its pixels inside the image),
+        // ascending, and each pixel's position among them
+        const int y0 = y * kTile, x0 = x * kTile;
+        int32_t ids[kTile * kTile];
+        int n_ids = 0;
+        for (int r = y0; r < std::min(h.height, y0 + kTile); ++r)
+          for (int c = x0; c < std::min(h.width, x0 + kTile); ++c)
+            ids[n_ids++] = h.tab.t6[(size_t)r * h.width + c];
+        std::sort(ids, ids + n_ids);
+        const int n_ent = (int)(std::unique(ids, ids + n_ids) - ids);
+        if ((int64_t)tile_tri.size() + n_ent >= (int64_t)INT32_MAX)
+          return fail(MR_EINVAL, "too many pixel-tile triangle entries");
+        tiles.push_back({p, y0, x0, 1, (int32_t)tile_tri.size(), n_ent, h.height, h.width,
+                         d.pix_off});
+        tile_tri.insert(tile_tri.end(), ids, ids + n_ent);
+        const size_t lo = tile_loc.size();
+        tile_loc.resize(lo + kTile * kTile, 0);
+        for (int r = y0; r < std::min(h.height, y0 + kTile); ++r)
+          for (int c = x0; c < std::min(h.width, x0 + kTile); ++c) {
+            const int32_t t = h.tab.t6[(size_t)r * h.width + c];
+            tile_loc[lo + (r - y0) * kTile + (c - x0)] =
+                (uint8_t)(std::lower_bound(ids, ids + n_ent, t) - ids);
+          }
+      }
     d.item_off = (int32_t)items.size();
     for (int b = 0; b < h.n; b += kNodeChunk)
       items.push_back({p, d.node_off + b, d.node_off + std::min(h.n, b + kNodeChunk), 1});
@@ -687,6 +713,7 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_pairs, dpairs, s));
   HIP_TRY(upload(d_node_items, items, s));
   HIP_TRY(upload(d_tiles, tiles, s));
+  HIP_TRY(upload(d_tile_loc, tile_loc, s));
   HIP_TRY(upload(d_xy, xy, s));
   {
     std::vector<int2> xy_s(n_nodes);            // node corners in solve order
@@ -695,19 +722,22 @@ int mr_ctx::upload_all(hipStream_t s) {
   }
   HIP_TRY(upload(d_tri, tri, s));
   {
-    std::vector<int4> tri_s(tri.size());        // triangle corners in solve order
-    for (size_t t = 0; t < tri.size(); ++t)
-      tri_s[t] = make_int4(iperm[tri[t].x], iperm[tri[t].y], iperm[tri[t].z], 0);
-    HIP_TRY(upload(d_tri_s, tri_s, s));
-  }
-  {
-    // triangle corners packed as x | y << 16 (image sides below 65536)
-    std::vector<int4> tpos(tri.size());
-    for (size_t t = 0; t < tri.size(); ++t) {
-      auto pk = [&](int node) { return (int)((uint32_t)xy[node].x | ((uint32_t)xy[node].y << 16)); };
-      tpos[t] = make_int4(pk(tri[t].x), pk(tri[t].y), pk(tri[t].z), 0);
-    }
-    HIP_TRY(upload(d_tpos, tpos, s));
+    // per pixel-tile triangle entry: the corner nodes (natural and solve
+    // order) with the first corner's coordinates, and the other two corners'
+    // coordinates, packed as x | y << 16 (image sides below 65536)
+    auto pk = [&](int node) { return (int)((uint32_t)xy[node].x | ((uint32_t)xy[node].y << 16)); };
+    std::vector<int4> tn(tile_tri.size()), tns(tile_tri.size());
+    std::vector<int2> tpbc(tile_tri.size());
+    for (const TileItem &ti : tiles)
+      for (int32_t k = ti.ent_off; k < ti.ent_off + ti.n_ent; ++k) {
+        const int4 c = tri[dpairs[ti.pair].tri_off + tile_tri[k]];
+        tn[k] = make_int4(c.x, c.y, c.z, pk(c.x));
+        tns[k] = make_int4(iperm[c.x], iperm[c.y], iperm[c.z], pk(c.x));
+        tpbc[k] = make_int2(pk(c.y), pk(c.z));
+      }
+    HIP_TRY(upload(d_tile_nodes, tn, s));
+    HIP_TRY(upload(d_tile_nodes_s, tns, s));
+    HIP_TRY(upload(d_tile_pbc, tpbc, s));
   }
   HIP_TRY(upload(d_t6, t6, s));
   HIP_TRY(upload(d_iperm, iperm, s));
@@ -811,7 +841,8 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
 
 int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
-                   d_tri.bytes() + d_tri_s.bytes() + d_tpos.bytes() + d_t6.bytes() + d_iperm.bytes() + d_perm.bytes() +
+                   d_tri.bytes() + d_t6.bytes() + d_tile_nodes.bytes() +
+                   d_tile_nodes_s.bytes() + d_tile_pbc.bytes() + d_tile_loc.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
                    d_x_sptr.bytes() + d_x_opp.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
                    d_x_u0.bytes() + d_x_rec.bytes() +
@@ -1182,8 +1213,8 @@ int mr_ctx::step_explicit(double2 *u, int32_t n_iter, double tau, double lam, do
     timed_begin(MR_KF_ASSEMBLE, s);
     const hipError_t eu = launch_explicit_update(
         d_node_items.ptr, n_node_items, d_pairs.ptr, u, rec, d_tri.ptr, d_x_sptr.ptr, d_x_opp.ptr,
-        tau, u0, d_flags.ptr, d_tiles.ptr, tiles, d_tpos.ptr, d_t6.ptr, d_coef.ptr, d_re.ptr,
-        d_partials.ptr, s);
+        tau, u0, d_flags.ptr, d_tiles.ptr, tiles, d_tile_nodes.ptr, d_tile_pbc.ptr, d_tile_loc.ptr,
+        d_coef.ptr, d_re.ptr, d_partials.ptr, s);
     timed_end(s);
     HIP_TRY(eu);
   }
@@ -1319,10 +1350,11 @@ extern "C" int mesh_reg_warp_msd_noalloc(mr_ctx *c, const double *u, double *msd
   // every tile of an active pair writes its own partial before the finish
   // reads it (all pairs are active outside mesh_reg_run), so nothing needs
   // clearing; no kernel timing here (it would create events)
-  hipError_t e = launch_warp_partials(c->d_tiles.ptr, c->n_tiles, c->d_pairs.ptr,
-                                      reinterpret_cast<const double2 *>(u), c->d_tpos.ptr,
-                                      c->d_tri.ptr, c->d_t6.ptr, c->d_coef.ptr, c->d_re.ptr, warped,
-                                      partials, c->d_flags.ptr, s);
+  hipError_t e = launch_warp_partials(c->d_tiles.ptr, c->n_tiles,
+                                      reinterpret_cast<const double2 *>(u), c->d_tile_nodes.ptr,
+                                      c->d_tile_pbc.ptr, c->d_tile_loc.ptr,
+                                      c->d_coef.ptr, c->d_re.ptr, warped, partials,
+                                      c->d_flags.ptr, s);
   if (e == hipSuccess) e = launch_msd_finish(c->d_pairs.ptr, c->n_pairs, partials, msd, s);
   HIP_TRY(e);
   c->post_flags(s);
@@ -1458,6 +1490,22 @@ static int64_t solve_bytes(const PairHost &h) {
   return b;
 }
 
+// Distinct triangles of T6 summed over the pair's kTile x kTile pixel tiles.
+static int64_t tile_entries(const PairHost &h) {
+  int64_t total = 0;
+  int32_t ids[kTile * kTile];
+  for (int y0 = 0; y0 < h.height; y0 += kTile)
+    for (int x0 = 0; x0 < h.width; x0 += kTile) {
+      int n = 0;
+      for (int r = y0; r < std::min(h.height, y0 + kTile); ++r)
+        for (int c = x0; c < std::min(h.width, x0 + kTile); ++c)
+          ids[n++] = h.tab.t6[(size_t)r * h.width + c];
+      std::sort(ids, ids + n);
+      total += std::unique(ids, ids + n) - ids;
+    }
+  return total;
+}
+
 extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
@@ -1488,6 +1536,7 @@ extern "C" int mesh_reg_get_info(mr_ctx *c, int32_t pair, int32_t key, int64_t *
       break;
     case MR_INFO_APEX_ROWS: *value = (int64_t)h.plan.apex_rows.size(); break;
     case MR_INFO_SOLVE_BYTES: *value = solve_bytes(h); break;
+    case MR_INFO_TILE_ENTRIES: *value = tile_entries(h); break;
     case MR_INFO_FWD_LEVELS: *value = h.plan.n_fwd_levels; break;
     case MR_INFO_BWD_LEVELS: *value = h.plan.n_bwd_levels; break;
     case MR_INFO_NODE_OFFSET: {

@@ -58,9 +58,13 @@ struct mr_ctx {
   mr::DevArray<int2> d_xy, d_xy_s;             // node corners, natural and solve order
   mr::DevArray<int32_t> d_block_pair, d_active;   // pair of each block; per-pair activity
   mr::DevArray<double> d_run_trace;               // mesh_reg_run: MSD at a check point
-  mr::DevArray<int4> d_tri, d_tri_s;           // triangle corners, natural and solve order
-  mr::DevArray<int4> d_tpos;                    // triangle corners, x | y << 16
+  mr::DevArray<int4> d_tri;                     // triangle corners, natural order
   mr::DevArray<int32_t> d_t6, d_iperm, d_perm;
+  // per pixel-tile triangle entry (TileItem): corner nodes in natural and in
+  // solve order, each with the packed first corner, and the other corners
+  mr::DevArray<int4> d_tile_nodes, d_tile_nodes_s;
+  mr::DevArray<int2> d_tile_pbc;
+  mr::DevArray<uint8_t> d_tile_loc;             // per tile pixel: its entry in the tile's list
   mr::DevArray<float> d_coef, d_re, d_rho, d_rho_s;   // rho natural and solve order
   mr::DevArray<int32_t> d_mptr, d_mcol;
   mr::DevArray<float> d_mwt;

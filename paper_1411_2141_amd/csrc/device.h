@@ -123,9 +123,17 @@ struct PrefItem {
   int32_t pair, first, tab_w, tab_h;
 };
 
-// Work item of the pixel-parallel kernels: one kTile x kTile tile.
+// Work item of the pixel-parallel kernels: one kTile x kTile tile of pair
+// `pair` (whose image size and pixel offset it repeats).  The
+// tile's distinct triangles (those of T6 over its pixels inside the image,
+// ascending, pair-local ids) are tile_tri[ent_off .. ent_off + n_ent), and
+// tile_loc[tile * kTile^2 + pixel] is each pixel's position in that list
+// (pixels row by row; 0 outside the image).
 struct TileItem {
   int32_t pair, y0, x0, active;
+  int32_t ent_off, n_ent;
+  int32_t height, width;  // the pair's image
+  int64_t pix_off;
 };
 
 }  // namespace mr

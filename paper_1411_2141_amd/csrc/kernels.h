@@ -16,12 +16,13 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
                              const int2 *xy, const float *coef_re, float *rho, hipStream_t s);
 // Sample launch (node displacements un with node tables xy, rho and output
 // h, one node order); with n_tiles > 0 it also writes the warp/MSD partials
-// of u (natural order).
+// of u (in the node order of tile_nodes).
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *un, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const double2 *u, const int4 *tri, const int4 *tpos, const int32_t *t6,
-                         const float *re, double *partials, hipStream_t s);
+                         const double2 *u, const int4 *tile_nodes, const int2 *tile_pbc,
+                         const uint8_t *tile_loc, const float *re, double *partials,
+                         hipStream_t s);
 // Assemble launch (solve order; x may be u); with finish_msd it also finishes
 // the MSD of `partials`.
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
@@ -58,10 +59,11 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
 hipError_t launch_prefilter_all(const PrefItem *row_items, int n_row_items,
                                 const PrefItem *col_items, int n_col_items, const DevPair *pairs,
                                 double *img, float *out, const double2 *tab, hipStream_t s);
-hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                const double2 *u, const int4 *tpos, const int4 *tri,
-                                const int32_t *t6, const float *coef, const float *re,
-                                float *warped, double *partials, unsigned *flags, hipStream_t s);
+hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const double2 *u,
+                                const int4 *tile_nodes, const int2 *tile_pbc,
+                                const uint8_t *tile_loc, const float *coef, const float *re,
+                                float *warped, double *partials, unsigned *flags,
+                                hipStream_t s);
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
                              double *msd, hipStream_t s);
 // Algorithm 1 as printed (explicit update, umbrella smoothing), natural node order.
@@ -75,8 +77,9 @@ hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevP
                                   const double2 *u, const NodeRec *rec, const int4 *tri,
                                   const int32_t *o_ptr, const int2 *o_jk, double tau,
                                   double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
-                                  const int4 *tpos, const int32_t *t6, const float *coef,
-                                  const float *re, double *partials, hipStream_t s);
+                                  const int4 *tile_nodes, const int2 *tile_pbc,
+                                  const uint8_t *tile_loc, const float *coef, const float *re,
+                                  double *partials, hipStream_t s);
 // Per-pair activity flags (1 active, 0 retired) into every work descriptor.
 hipError_t launch_set_active(const int32_t *flags, DevPair *pairs, int n_pairs, DevBlock *blocks,
                              const int32_t *block_pair, int n_blocks, NodeItem *items,

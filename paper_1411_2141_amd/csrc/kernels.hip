@@ -10,11 +10,12 @@
 //   k_solve_fwd / k_solve_bwd
 //               block-level-scheduled FP64 triangular solves with the Cholesky
 //               factor of I + tau alpha K (eq. 7-8 made implicit, solved directly)
-//   warp tiles  pixel-tile-parallel: piecewise-linear displacement of each
-//               pixel's triangle, template sample at the displaced pixel centre,
-//               squared error, deterministic FP64 reduction to the MSD; run in
-//               the next iteration's sample launch (both read the same u), the
-//               final sum in its assemble launch
+//   warp tiles  pixel-tile-parallel: the affine displacement map of each
+//               triangle of a tile (once per triangle, into LDS), the template
+//               sample at each displaced pixel centre, squared error,
+//               deterministic FP64 reduction to the MSD; run in the next
+//               iteration's sample launch (both read the same u), the final sum
+//               in its assemble launch
 // All node-, tile- and block-parallel launches cover every pair of a batch
 // through work lists, so one launch per kernel family advances all pairs.
 #include <hip/hip_runtime.h>
@@ -301,152 +302,219 @@ __device__ __forceinline__ T load_at(const T *__restrict__ base, unsigned off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
 
-// Squared differences of NT pixels, the thread's position in each of NT
-// tiles (0 for positions outside the image): each pixel takes the
-// piecewise-linear displacement of its triangle (FP64 barycentric weights from
-// exact cross products in doubled integer coordinates) and the template
-// spline is sampled at the displaced pixel centre (FP32 weights with the
-// partition of unity kept and FP32 tap sums; the squared difference in FP64).
-// The NT pixels go through each step together so their dependent load chains
-// overlap; positions outside the image are clamped to its last row / column
-// for the loads and count 0.  Offsets within a pair's image are 32-bit (fewer
-// than 2^31 pixels).
+// Warp + MSD of NT kTile x kTile pixel tiles, tile0 .. tile0 + NT - 1 (those
+// below n_tiles), with a workgroup of kTile^2 threads, the thread taking the
+// same pixel position in each tile.
+//
+// Every pixel of a triangle has the same affine displacement map (P1
+// interpolation), so the work is split in two stages.  First each distinct
+// triangle of a tile (the tile's list, built at init from T6: corner node ids
+// in tile_nodes, in the node order of u, and packed corner coordinates) gets
+// its map in the tile's frame, one thread per triangle, into LDS: for the
+// pixel at tile position r = (rx, ry) the sampling position in spline
+// coordinates is (x0, y0) + c + G' r, with G' = I + grad d and c the displaced
+// position of the tile origin's pixel (FP64; the map is formed from the
+// corners' exact integer coordinates and displacements).  Then each pixel
+// reads its triangle's slot (a byte per pixel) and samples the template
+// spline there (FP32 weights with the partition of unity kept and FP32 tap
+// sums).  A triangle with a non-finite displacement, or one of 10^6 pixels or
+// more, at a corner raises the flag and is warped with zero displacement.
+// Windows wholly inside the image take four row loads per pixel; a wavefront
+// with a lane whose window crosses the border folds its taps one by one.
+// Each tile's FP64 sum of squared differences (a fixed order over the
+// workgroup's threads) goes to partials[tile].  Offsets within a pair's image
+// are 32-bit (fewer than 2^31 pixels).
 template <int NT>
-__device__ __forceinline__ void warp_pixels(const TileItem (&it)[NT], const DevPair (&P)[NT],
-                                            const double2 *__restrict__ u,
-                                            const int4 *__restrict__ tpos,
-                                            const int4 *__restrict__ tri,
-                                            const int32_t *__restrict__ t6,
-                                            const float *__restrict__ coef,
-                                            const float *__restrict__ re,
-                                            float *__restrict__ warped, unsigned *flags,
-                                            double (&sq)[NT]) {
-  int I[NT], J[NT], tt[NT];
-  unsigned po[NT];
-  bool in[NT];
-  float rv[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int i = it[q].y0 + (int)(threadIdx.x / kTile);
-    const int j = it[q].x0 + (int)(threadIdx.x % kTile);
-    in[q] = i < P[q].height && j < P[q].width;
-    I[q] = min(i, P[q].height - 1);
-    J[q] = min(j, P[q].width - 1);
-    po[q] = (unsigned)I[q] * (unsigned)P[q].width + (unsigned)J[q];
-  }
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    tt[q] = load_at(t6 + P[q].pix_off, po[q] << 2);
-    rv[q] = load_at(re + P[q].pix_off, po[q] << 2);
-  }
-  int4 nd[NT], ps[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    nd[q] = load_at(tri + P[q].tri_off, (unsigned)tt[q] << 4);
-    ps[q] = load_at(tpos + P[q].tri_off, (unsigned)tt[q] << 4);   // corners as x | y << 16
-  }
-  double2 ua[NT], ub[NT], uc[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    ua[q] = load_at(u, (unsigned)nd[q].x << 4);
-    ub[q] = load_at(u, (unsigned)nd[q].y << 4);
-    uc[q] = load_at(u, (unsigned)nd[q].z << 4);
-  }
-  int qx[NT], qy[NT];
-  double fx[NT], fy[NT];
-  bool inside = true;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int2 a = make_int2(ps[q].x & 0xffff, (int)((unsigned)ps[q].x >> 16));
-    const int2 b = make_int2(ps[q].y & 0xffff, (int)((unsigned)ps[q].y >> 16));
-    const int2 c = make_int2(ps[q].z & 0xffff, (int)((unsigned)ps[q].z >> 16));
-    const double px = 2.0 * J[q] + 1.0, py = 2.0 * I[q] + 1.0;
-    const double ax = 2.0 * a.x - px, ay = 2.0 * a.y - py;
-    const double bx = 2.0 * b.x - px, by = 2.0 * b.y - py;
-    const double cx = 2.0 * c.x - px, cy = 2.0 * c.y - py;
-    const double ca = bx * cy - by * cx, cb = cx * ay - cy * ax, cc = ax * by - ay * bx;
-    // 1 / (ca + cb + cc), an integer: the FP32 estimate and one Newton step
-    const double den = ca + cb + cc;
-    double inv = (double)__frcp_rn((float)den);
-    inv = fma(inv, fma(-den, inv, 1.0), inv);
-    const double wa = ca * inv, wb = cb * inv, wc = (1.0 - wa) - wb;
-    const double dx = wa * ua[q].x + wb * ub[q].x + wc * uc[q].x;
-    const double dy = wa * ua[q].y + wb * ub[q].y + wc * uc[q].y;
-    const bool okx = split_coord_d(J[q], dx, qx[q], fx[q]);
-    const bool ok = split_coord_d(I[q], dy, qy[q], fy[q]) && okx;
-    if (in[q] && !ok) atomicOr(flags, kFlagNonFinitePixel);
-    inside = inside && taps_inside(P[q].height, P[q].width, qx[q], qy[q]);
-  }
-  float tap[NT][4][4];
-  if (inside) {
-    // every window inside its image: four 16-byte row loads per pixel
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-      load_taps_inside(coef + P[q].pix_off, P[q].width, qx[q], qy[q], tap[q]);
-  } else {
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-      load_taps(coef + P[q].pix_off, P[q].height, P[q].width, qx[q], qy[q], tap[q]);
-  }
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    float wx[4], wy[4];
-    bs_weights_unit((float)fx[q], wx);
-    bs_weights_unit((float)fy[q], wy);
-    float w = 0.0f;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const float rs = tap[q][m][0] * wx[0] + tap[q][m][1] * wx[1] + tap[q][m][2] * wx[2] +
-                       tap[q][m][3] * wx[3];
-      w += wy[m] * rs;
-    }
-    if (warped && in[q]) (warped + P[q].pix_off)[po[q]] = w;
-    const double e = (double)(w - rv[q]);
-    sq[q] = in[q] ? e * e : 0.0;
-  }
-}
-
-// Warp + MSD of NT (1 or 2) kTile x kTile pixel tiles, tile0 and tile1
-// (tile1 < 0: none), one after the other: every thread takes the same pixel
-// position in both.  Each tile's FP64 sum of squared differences (wavefront
-// sums, then the four wavefronts in order) goes to partials[tile].
-template <int NT>
-__device__ __forceinline__ void warp_tiles(int tile0, int tile1, const TileItem *__restrict__ tiles,
-                                           const DevPair *__restrict__ pairs,
+__device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileItem *__restrict__ tiles,
                                            const double2 *__restrict__ u,
-                                           const int4 *__restrict__ tpos,
-                                           const int4 *__restrict__ tri,
-                                           const int32_t *__restrict__ t6,
+                                           const int4 *__restrict__ tile_nodes,
+                                           const int2 *__restrict__ tile_pbc,
+                                           const uint8_t *__restrict__ tile_loc,
                                            const float *__restrict__ coef,
                                            const float *__restrict__ re,
                                            float *__restrict__ warped,
                                            double *__restrict__ partials, unsigned *flags) {
-  // NT == 2 without a second tile: the first is evaluated twice (same values,
-  // same writes) and only its sum is kept.  Tiles of retired pairs are not
-  // warped (the workgroup returns when all of its tiles are retired).
-  const bool on0 = tiles[tile0].active != 0;
-  const bool on1 = NT == 2 && tile1 >= 0 && tiles[tile1].active != 0;
-  if (!on0 && !on1) return;
-  double a[NT];
+  constexpr int kPix = kTile * kTile;
+  // maps of up to kPix triangles at a time: c, (G'xx, G'xy), (G'yx, G'yy)
+  __shared__ double2 map[3][kPix];
+  const int tid = (int)threadIdx.x;
+  int tl[NT];
+  TileItem it[NT];
+  bool on[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    const TileItem it[1] = {tiles[q == 0 || tile1 < 0 ? tile0 : tile1]};
-    const DevPair P[1] = {pairs[it[0].pair]};
-    double sq[1];
-    warp_pixels<1>(it, P, u, tpos, tri, t6, coef, re, warped, flags, sq);
-    a[q] = sq[0];
+    const bool valid = tile0 + q < n_tiles;
+    tl[q] = valid ? tile0 + q : tile0;
+    it[q] = tiles[tl[q]];
+    on[q] = valid && it[q].active != 0;
   }
-  __shared__ double red[2 * 4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // Tiles of retired pairs are not warped (the workgroup returns when all of
+  // its tiles are retired).
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) any = any || on[q];
+  if (!any) return;
+  int base[NT], total = 0;
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    a[q] = wave_sum(a[q]);
-    if (lane == 0) red[4 * q + wave] = a[q];
+    base[q] = total;
+    total += on[q] ? it[q].n_ent : 0;
   }
+
+  // The pixels' slots and reference samples do not depend on the maps:
+  // their loads go out first.
+  const int rx = tid % kTile, ry = tid / kTile;
+  int slot[NT];
+  float rv[NT];
+  unsigned po[NT];
+  bool in[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int i = it[q].y0 + ry, j = it[q].x0 + rx;
+    in[q] = on[q] && i < it[q].height && j < it[q].width;
+    po[q] = __umul24((unsigned)min(i, it[q].height - 1), (unsigned)it[q].width) +
+            (unsigned)min(j, it[q].width - 1);
+    slot[q] = base[q] + (int)tile_loc[(size_t)tl[q] * kPix + tid];
+    rv[q] = load_at(re + it[q].pix_off, po[q] << 2);
+  }
+  const double rxd = (double)rx, ryd = (double)ry;
+  double sq[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
+
+  // The tiles' triangles in rounds of up to kPix (one round unless two dense
+  // tiles share the workgroup); each pixel is evaluated in its slot's round.
+  for (int r0 = 0; r0 < total; r0 += kPix) {
+    const int r1 = min(total, r0 + kPix);
+    if (r0 > 0) __syncthreads();                  // the previous round's maps are read
+    // Stage 1: the displacement maps of the round's triangles.
+    const int e = r0 + tid;
+    if (e < r1) {
+      // the entry's tile: the last with base <= e (off tiles have no entries)
+      int x0 = it[0].x0, y0 = it[0].y0, k = it[0].ent_off + e;
+#pragma unroll
+      for (int q = 1; q < NT; ++q)
+        if (e >= base[q]) {
+          x0 = it[q].x0;
+          y0 = it[q].y0;
+          k = it[q].ent_off - base[q] + e;
+        }
+      const int4 nd = tile_nodes[k];               // corner nodes, packed first corner
+      const int2 pbc = tile_pbc[k];                // packed other corners
+      double2 ua = load_at(u, (unsigned)nd.x << 4);
+      const double2 ub = load_at(u, (unsigned)nd.y << 4);
+      const double2 uc = load_at(u, (unsigned)nd.z << 4);
+      // corners relative to the tile origin (exact)
+      const int ax = (nd.w & 0xffff) - x0, ay = (int)((unsigned)nd.w >> 16) - y0;
+      const double e1x = (double)((pbc.x & 0xffff) - x0 - ax);
+      const double e1y = (double)((int)((unsigned)pbc.x >> 16) - y0 - ay);
+      const double e2x = (double)((pbc.y & 0xffff) - x0 - ax);
+      const double e2y = (double)((int)((unsigned)pbc.y >> 16) - y0 - ay);
+      const double det = e1x * e2y - e1y * e2x;    // twice the area: exact, positive
+      // 1 / det: the FP32 estimate and two Newton steps
+      double inv = (double)__builtin_amdgcn_rcpf((float)det);
+      inv = fma(inv, fma(-det, inv, 1.0), inv);
+      inv = fma(inv, fma(-det, inv, 1.0), inv);
+      const bool ok = fabs(ua.x) < 1.0e6 && fabs(ua.y) < 1.0e6 && fabs(ub.x) < 1.0e6 &&
+                      fabs(ub.y) < 1.0e6 && fabs(uc.x) < 1.0e6 && fabs(uc.y) < 1.0e6;
+      double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
+      if (ok) {
+        const double d1x = ub.x - ua.x, d1y = ub.y - ua.y, d2x = uc.x - ua.x, d2y = uc.y - ua.y;
+        gxx = (d1x * e2y - d2x * e1y) * inv;
+        gxy = (d2x * e1x - d1x * e2x) * inv;
+        gyx = (d1y * e2y - d2y * e1y) * inv;
+        gyy = (d2y * e1x - d1y * e2x) * inv;
+      } else {
+        ua = make_double2(0.0, 0.0);
+        atomicOr(flags, kFlagNonFinitePixel);
+      }
+      // displacement at the origin pixel's centre, (1/2, 1/2) in the tile frame
+      const double ox = 0.5 - (double)ax, oy = 0.5 - (double)ay;
+      map[0][tid] = make_double2(ua.x + gxx * ox + gxy * oy, ua.y + gyx * ox + gyy * oy);
+      map[1][tid] = make_double2(1.0 + gxx, gxy);
+      map[2][tid] = make_double2(gyx, 1.0 + gyy);
+    }
+    __syncthreads();
+
+    // Stage 2: the pixels of the round, both tiles' loads issued together.
+    int qx[NT], qy[NT];
+    float fx[NT], fy[NT];
+    bool act[NT], inside = true;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      act[q] = slot[q] >= r0 && slot[q] < r1;
+      const int sl = act[q] ? slot[q] - r0 : 0;
+      const double2 c = map[0][sl], gx = map[1][sl], gy = map[2][sl];
+      const double vx = fma(gx.x, rxd, fma(gx.y, ryd, c.x));
+      const double vy = fma(gy.x, rxd, fma(gy.y, ryd, c.y));
+      const double flx = floor(vx), fly = floor(vy);
+      qx[q] = it[q].x0 + (int)flx;
+      qy[q] = it[q].y0 + (int)fly;
+      fx[q] = (float)(vx - flx);
+      fy[q] = (float)(vy - fly);
+      // positions outside the image or the round take the window of cell
+      // (1, 1) (inside the image when both sides are at least 4)
+      if (!(in[q] && act[q])) {
+        qx[q] = qy[q] = 1;
+        fx[q] = fy[q] = 0.0f;
+      }
+      inside = inside && taps_inside(it[q].height, it[q].width, qx[q], qy[q]);
+    }
+    float tap[NT][4][4];
+    if (__all(inside)) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        load_taps_inside(coef + it[q].pix_off, it[q].width, qx[q], qy[q], tap[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        load_taps(coef + it[q].pix_off, it[q].height, it[q].width, qx[q], qy[q], tap[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      float wx[4], wy[4];
+      bs_weights_unit(fx[q], wx);
+      bs_weights_unit(fy[q], wy);
+      float w = 0.0f;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float rs = tap[q][m][0] * wx[0] + tap[q][m][1] * wx[1] + tap[q][m][2] * wx[2] +
+                         tap[q][m][3] * wx[3];
+        w += wy[m] * rs;
+      }
+      if (act[q]) {
+        if (warped && in[q]) (warped + it[q].pix_off)[po[q]] = w;
+        const double d = (double)(w - rv[q]);
+        sq[q] = in[q] ? d * d : 0.0;
+      }
+    }
+  }
+
+  // Tile sums in a fixed order: the threads' values through LDS (the maps'
+  // storage), then one wavefront adds kPix / (64 / NT) of them per lane and
+  // reduces within its 64 / NT lanes.
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (on0) partials[tile0] = (red[0] + red[1]) + (red[2] + red[3]);
-    if (on1) partials[tile1] = (red[4] + red[5]) + (red[6] + red[7]);
+  double *red = reinterpret_cast<double *>(&map[0][0]);
+#pragma unroll
+  for (int q = 0; q < NT; ++q) red[q * kPix + tid] = sq[q];
+  __syncthreads();
+  if (tid < 64) {
+    constexpr int kLanes = 64 / NT;
+    const int q = tid / kLanes, j = tid % kLanes;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPix / kLanes; ++k) s += red[q * kPix + j + k * kLanes];
+#pragma unroll
+    for (int off = kLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    bool onq = on[0];
+    int tq = tl[0];
+#pragma unroll
+    for (int p = 1; p < NT; ++p)
+      if (q == p) {
+        onq = on[p];
+        tq = tl[p];
+      }
+    if (j == 0 && onq) partials[tq] = s;
   }
 }
 
@@ -523,14 +591,14 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
                                                 float2 *__restrict__ h, unsigned *flags,
                                                 const TileItem *__restrict__ tiles,
                                                 const double2 *__restrict__ u,
-                                                const int4 *__restrict__ tri,
-                                                const int4 *__restrict__ tpos,
-                                                const int32_t *__restrict__ t6,
+                                                const int4 *__restrict__ tile_nodes,
+                                                const int2 *__restrict__ tile_pbc,
+                                                const uint8_t *__restrict__ tile_loc,
                                                 const float *__restrict__ re,
                                                 double *__restrict__ partials, int n_tiles) {
   if ((int)blockIdx.x >= n_items) {
-    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), -1, tiles, pairs, u, tpos, tri,
-                  t6, coef, re, nullptr, partials, flags);
+    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), n_tiles, tiles, u, tile_nodes,
+                  tile_pbc, tile_loc, coef, re, nullptr, partials, flags);
     return;
   }
   const NodeItem it[1] = {items[xcd_item((int)blockIdx.x, n_items)]};
@@ -1714,14 +1782,17 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
   }
 }
 
+// Two tiles per workgroup: their loads overlap, and the launch's workgroups
+// stay within the LDS and register budget of seven per CU.
 __global__ __launch_bounds__(256) void k_warp_msd(
-    const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs, const double2 *__restrict__ u,
-    const int4 *__restrict__ tpos, const int4 *__restrict__ tri, const int32_t *__restrict__ t6,
-    const float *__restrict__ coef, const float *__restrict__ re, float *__restrict__ warped,
-    double *__restrict__ partials, unsigned *flags, int n_tiles) {
+    const TileItem *__restrict__ tiles, const double2 *__restrict__ u,
+    const int4 *__restrict__ tile_nodes, const int2 *__restrict__ tile_pbc,
+    const uint8_t *__restrict__ tile_loc, const float *__restrict__ coef,
+    const float *__restrict__ re, float *__restrict__ warped, double *__restrict__ partials,
+    unsigned *flags, int n_tiles) {
   const int t0 = 2 * xcd_item((int)blockIdx.x, (int)gridDim.x);
-  warp_tiles<2>(t0, t0 + 1 < n_tiles ? t0 + 1 : -1, tiles, pairs, u, tpos, tri, t6, coef, re,
-                warped, partials, flags);
+  warp_tiles<2>(t0, n_tiles, tiles, u, tile_nodes, tile_pbc, tile_loc, coef, re, warped, partials,
+                flags);
 }
 
 __global__ __launch_bounds__(256) void k_msd_finish(const DevPair *__restrict__ pairs, int n_pairs,
@@ -1785,10 +1856,12 @@ hipError_t launch_sample_rho(const NodeItem *items, int n_items, const DevPair *
 hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pairs,
                          const double2 *un, const int2 *xy, const float *coef, const float *rho,
                          float2 *h, unsigned *flags, const TileItem *tiles, int n_tiles,
-                         const double2 *u, const int4 *tri, const int4 *tpos, const int32_t *t6,
-                         const float *re, double *partials, hipStream_t s) {
+                         const double2 *u, const int4 *tile_nodes, const int2 *tile_pbc,
+                         const uint8_t *tile_loc, const float *re, double *partials,
+                         hipStream_t s) {
   return launch(k_sample, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, un, xy,
-                coef, rho, h, flags, tiles, u, tri, tpos, t6, re, partials, n_tiles);
+                coef, rho, h, flags, tiles, u, tile_nodes, tile_pbc, tile_loc, re, partials,
+                n_tiles);
 }
 
 hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
@@ -1912,13 +1985,14 @@ hipError_t launch_apex_solve(int n_rows, const int32_t *rows, const int64_t *acp
   return e;
 }
 
-hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const DevPair *pairs,
-                                const double2 *u, const int4 *tpos, const int4 *tri,
-                                const int32_t *t6, const float *coef, const float *re,
-                                float *warped, double *partials, unsigned *flags, hipStream_t s) {
+hipError_t launch_warp_partials(const TileItem *tiles, int n_tiles, const double2 *u,
+                                const int4 *tile_nodes, const int2 *tile_pbc,
+                                const uint8_t *tile_loc, const float *coef, const float *re,
+                                float *warped, double *partials, unsigned *flags,
+                                hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  return launch(k_warp_msd, (n_tiles + 1) / 2, kTile * kTile, 0, s, tiles, pairs, u, tpos, tri, t6,
-                coef, re, warped, partials, flags, n_tiles);
+  return launch(k_warp_msd, (n_tiles + 1) / 2, kTile * kTile, 0, s, tiles, u, tile_nodes, tile_pbc,
+                tile_loc, coef, re, warped, partials, flags, n_tiles);
 }
 
 hipError_t launch_msd_finish(const DevPair *pairs, int n_pairs, const double *partials,
@@ -2014,12 +2088,13 @@ __global__ __launch_bounds__(256) void k_explicit_update(
     const double2 *__restrict__ u, const NodeRec *__restrict__ rec,
     const int4 *__restrict__ tri, const int32_t *__restrict__ o_ptr,
     const int2 *__restrict__ o_jk, double tau, double2 *__restrict__ u0, unsigned *flags,
-    const TileItem *__restrict__ tiles, const int4 *__restrict__ tpos,
-    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
+    const TileItem *__restrict__ tiles, const int4 *__restrict__ tile_nodes,
+    const int2 *__restrict__ tile_pbc, const uint8_t *__restrict__ tile_loc,
+    const float *__restrict__ coef, const float *__restrict__ re,
     double *__restrict__ partials, int n_tiles) {
   if ((int)blockIdx.x >= n_items) {
-    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), -1, tiles, pairs, u, tpos, tri,
-                  t6, coef, re, nullptr, partials, flags);
+    warp_tiles<1>(xcd_item((int)blockIdx.x - n_items, n_tiles), n_tiles, tiles, u, tile_nodes,
+                  tile_pbc, tile_loc, coef, re, nullptr, partials, flags);
     return;
   }
   const NodeItem it = items[xcd_item((int)blockIdx.x, n_items)];
@@ -2085,11 +2160,12 @@ hipError_t launch_explicit_update(const NodeItem *items, int n_items, const DevP
                                   const double2 *u, const NodeRec *rec, const int4 *tri,
                                   const int32_t *o_ptr, const int2 *o_jk, double tau,
                                   double2 *u0, unsigned *flags, const TileItem *tiles, int n_tiles,
-                                  const int4 *tpos, const int32_t *t6, const float *coef,
-                                  const float *re, double *partials, hipStream_t s) {
+                                  const int4 *tile_nodes, const int2 *tile_pbc,
+                                  const uint8_t *tile_loc, const float *coef, const float *re,
+                                  double *partials, hipStream_t s) {
   return launch(k_explicit_update, n_items + n_tiles, kNodeChunk, 0, s, items, n_items, pairs, u,
-                rec, tri, o_ptr, o_jk, tau, u0, flags, tiles, tpos, t6, coef, re, partials,
-                n_tiles);
+                rec, tri, o_ptr, o_jk, tau, u0, flags, tiles, tile_nodes, tile_pbc, tile_loc, coef,
+                re, partials, n_tiles);
 }
 
 // Copies the per-pair activity flags into every work descriptor (pairs,

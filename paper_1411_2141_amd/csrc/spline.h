@@ -18,6 +18,9 @@ namespace mr {
 
 __device__ __forceinline__ int fold_index(int n, int N) {
   if ((unsigned)n < (unsigned)N) return n;
+  // one reflection covers -N <= n < 2N
+  const int r = n < 0 ? -1 - n : 2 * N - 1 - n;
+  if ((unsigned)r < (unsigned)N) return r;
   const int P = 2 * N;
   int m = n % P;
   if (m < 0) m += P;
@@ -90,9 +93,18 @@ __device__ __forceinline__ bool taps_inside(int H, int W, int cx, int cy) {
 }
 __device__ __forceinline__ void load_taps_inside(const float *__restrict__ c, int W, int cx, int cy,
                                                  float (&t)[4][4]) {
-  const unsigned o = (unsigned)(cy - 1) * (unsigned)W + (unsigned)(cx - 1);
+  // byte offsets from c (sides below 2^16, so the 24-bit product is exact)
+  const unsigned o = (__umul24((unsigned)(cy - 1), (unsigned)W) + (unsigned)(cx - 1)) << 2;
+  const unsigned row = (unsigned)W << 2;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) load_row4(c + (o + (unsigned)m * (unsigned)W), t[m]);
+  for (int m = 0; m < 4; ++m) {
+    const float4_a4 q = *reinterpret_cast<const float4_a4 *>(
+        reinterpret_cast<const char *>(c) + (o + (unsigned)m * row));
+    t[m][0] = q.x;
+    t[m][1] = q.y;
+    t[m][2] = q.z;
+    t[m][3] = q.w;
+  }
 }
 
 // The 4x4 coefficient taps around cell (cx, cy), t[m][n] = c(cy - 1 + m,

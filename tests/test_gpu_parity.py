@@ -78,6 +78,12 @@ CASES = {
         V=V, T=T, alpha=0.5))(*uniform_mesh(4, 4, 4)[:2]),
     "unstructured_64": lambda: dict(zip(("te", "re", "V", "T"), unstructured_pair(seed=7, side=64)),
                                     alpha=0.1),
+    # unit cells: every pixel of a 16 x 16 tile has its own triangle, so two
+    # tiles of a warp workgroup hold more triangles than one round of maps
+    "unit_cells_40": lambda: (lambda V, T: dict(
+        te=small_pair(seed=4, side=48)[0][:40, :40].copy(),
+        re=small_pair(seed=4, side=48)[1][:40, :40].copy(), V=V, T=T,
+        alpha=0.1))(*uniform_mesh(40, 40, 1)[:2]),
 }
 
 

@@ -69,6 +69,19 @@ def test_tables_bit_exact_with_oracle(k):
     ctx.close()
 
 
+def test_tile_entries_count_distinct_triangles_per_pixel_tile():
+    """MR_INFO_TILE_ENTRIES: the warp's per-tile triangle lists hold the
+    distinct T6 triangles of each 16 x 16 pixel tile (T6 from the oracle)."""
+    for pair in _pairs_for_tables():
+        H, W = pair["te"].shape
+        t6 = omesh.tables(pair["V"], pair["T"], H, W)["t6"]
+        want = sum(len(np.unique(t6[y:y + 16, x:x + 16]))
+                   for y in range(0, H, 16) for x in range(0, W, 16))
+        ctx = host_ctx([pair])
+        assert ctx.info(0, "tile_entries") == want
+        ctx.close()
+
+
 def test_batched_tables_per_pair():
     pairs = _pairs_for_tables()
     ctx = host_ctx(pairs)
