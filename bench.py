@@ -128,8 +128,10 @@ def algorithmic_bytes(ctx, pairs) -> dict:
 
 def unit_bytes(ctx, pairs) -> dict:
     """Bytes of one pass of each stage in the library's own data layout (each
-    stored datum the kernels read or write counted once): node streams, CSR
-    force-operator entries (index and weight), the solve's dense block
+    stored datum the kernels read or write counted once): node streams, the
+    force operator's one-word entries (column offset and integer numerator;
+    the few two-word rows counted as one word per entry) and per-row
+    pointer and 1 / m, the solve's dense block
     inverses, panels and apex inverse (both passes), the warp's per-pixel
     slot byte, per-tile triangle entries (24 bytes), tile records and
     partials."""
@@ -142,7 +144,7 @@ def unit_bytes(ctx, pairs) -> dict:
     solve = sum(ctx.info(k, "solve_bytes") for k in range(len(pairs)))
     return {
         "sample": 36 * n + 4 * touched_coefficients(pairs),
-        "assemble": 44 * n + 8 * nnz_m,
+        "assemble": 48 * n + 4 * nnz_m,
         "solve": solve,
         "warp": 9 * pix + 16 * n + 24 * entries + 48 * tiles,
         "finish": 8 * tiles + 8 * len(pairs),

@@ -227,7 +227,7 @@ int mr_ctx::tune(hipStream_t s) {
   int rc = MR_OK;
   // the first forward level runs fused with the force assembly in the
   // iteration, so it is timed that way (on scratch data: u = x)
-  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
+  const AssembleArgs fuse{d_mptr.ptr, d_ment.ptr, d_minv.ptr, d_h.ptr, d_x.ptr,
                           d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs, params.tau,
                           d_pairs.ptr, d_partials.ptr, nullptr, d_active.ptr};
   // best of the second and third of three runs, in ms (negative on error)
@@ -347,7 +347,7 @@ hipError_t mr_ctx::sample(bool with_warp, hipStream_t s) {
 // Force assembly into x (solve order), in place: u is read from x.
 hipError_t mr_ctx::assemble(double *finish_msd, hipStream_t s) {
   timed_begin(MR_KF_ASSEMBLE, s);
-  hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_mcol.ptr, d_mwt.ptr, d_h.ptr, d_x.ptr,
+  hipError_t e = launch_assemble((int)n_nodes, d_mptr.ptr, d_ment.ptr, d_minv.ptr, d_h.ptr, d_x.ptr,
                                  d_x.ptr, params.tau, d_pairs.ptr, n_pairs, d_partials.ptr,
                                  finish_msd, d_active.ptr, s);
   timed_end(s);
@@ -377,7 +377,7 @@ hipError_t mr_ctx::iterate(double2 *u, double *msd_out, double **pending, bool x
   hipError_t e = hipSuccess;
   if (!x_holds_u) e = launch_to_solve_order((int)n_nodes, u, d_iperm.ptr, d_x.ptr, s);
   if (e == hipSuccess) e = sample(msd_now != nullptr, s);
-  const AssembleArgs fuse{d_mptr.ptr, d_mcol.ptr, d_mwt.ptr,     d_h.ptr,
+  const AssembleArgs fuse{d_mptr.ptr, d_ment.ptr, d_minv.ptr,    d_h.ptr,
                           d_x.ptr,    d_upper_rows.ptr, (int32_t)d_upper_rows.count, n_pairs,
                           params.tau, d_pairs.ptr, d_partials.ptr, msd_now, d_active.ptr};
   if (e == hipSuccess && !fuse_first) e = assemble(msd_now, s);
@@ -505,8 +505,9 @@ int mr_ctx::upload_all(hipStream_t s) {
   std::vector<int2> xy(n_nodes);
   std::vector<int4> tri(n_tris);
   std::vector<int32_t> t6(n_pix), iperm(n_nodes), perm(n_nodes);
-  std::vector<int32_t> mptr(n_nodes + 1, 0), mcol;
-  std::vector<float> mwt;
+  std::vector<int32_t> mptr(n_nodes + 1, 0);
+  std::vector<uint32_t> ment;
+  std::vector<float> minv(n_nodes);
   std::vector<DevBlock> blocks;
   std::vector<int32_t> block_pair;              // pair of each block
   std::vector<int64_t> cptr(n_nodes + 1, 0);
@@ -549,23 +550,47 @@ int mr_ctx::upload_all(hipStream_t s) {
       perm[no + i] = no + h.perm[i];
     }
     // force operator rows and columns in solve order (row k is node perm[k];
-    // h is sampled in solve order): f_i = sum_j (24 M_ij) / (4 * 6 m_i) h_j,
+    // h is sampled in solve order): f_i = sum_j (24 M_ij) h_j / (4 * 6 m_i),
     // i.e. the mass row divided by the lumped mass, with 6 m_i = t5_i; the
-    // columns keep the row order of the natural pattern
+    // columns keep the row order of the natural pattern.  An entry is one
+    // word, the column's offset from the row (16 bits, signed) above the
+    // integer numerator 24 M_ij (16 bits); a row with an entry outside those
+    // ranges (a separator node far from a neighbour in solve order) stores
+    // each entry as two words, the column and the numerator as FP32, and is
+    // flagged by bit 31 of its mptr.
+    std::vector<std::pair<int32_t, int64_t>> ent;     // one row's (column, numerator)
     for (int k = 0; k < h.n; ++k) {
       const int i = h.perm[k];
+      const int32_t row = no + k;
+      ent.clear();
+      double den = 1.0;
       if (params.force_mode == MR_FORCE_NODAL) {
-        mcol.push_back(no + k);
-        mwt.push_back(1.0f);
+        ent.push_back({row, 1});
       } else {
-        const double den = 4.0 * (double)h.tab.t5[i];
-        for (int64_t q = h.tab.t3_ptr[i]; q < h.tab.t3_ptr[i + 1]; ++q) {
-          mcol.push_back(no + h.iperm[h.tab.t3_idx[q]]);
-          mwt.push_back((float)((double)h.mval[q] / den));
+        den = 4.0 * (double)h.tab.t5[i];
+        for (int64_t q = h.tab.t3_ptr[i]; q < h.tab.t3_ptr[i + 1]; ++q)
+          ent.push_back({no + h.iperm[h.tab.t3_idx[q]], h.mval[q]});
+      }
+      minv[row] = (float)(1.0 / den);
+      bool narrow = true;
+      for (const auto &e : ent)
+        narrow = narrow && std::abs(e.first - row) <= 32767 && e.second >= 0 && e.second < 65536;
+      if ((int64_t)ment.size() + 2 * (int64_t)ent.size() >= (int64_t)INT32_MAX)
+        return fail(MR_EINVAL, "force operator too large");
+      mptr[row] = (int32_t)ment.size() | (narrow ? 0 : (int32_t)0x80000000u);
+      for (const auto &e : ent) {
+        if (narrow) {
+          ment.push_back(((uint32_t)(uint16_t)(int16_t)(e.first - row) << 16) | (uint32_t)e.second);
+        } else {
+          const float num = (float)e.second;
+          uint32_t bits;
+          std::memcpy(&bits, &num, sizeof bits);
+          ment.push_back((uint32_t)e.first);
+          ment.push_back(bits);
         }
       }
-      mptr[no + k + 1] = (int32_t)mcol.size();
     }
+    mptr[no + h.n] = (int32_t)ment.size();
     // solve plan, shifted to global rows
     const SolvePlan &pl = h.plan;
     const int64_t doff = (int64_t)dcol.size();
@@ -685,7 +710,6 @@ int mr_ctx::upload_all(hipStream_t s) {
     for (int r = 0; r < h.n; ++r) cptr[no + r + 1] = co + pl.cptr[r + 1];
     for (int32_t k : pl.cidx) cidx.push_back((int32_t)(uoff + k));
   }
-  if (mcol.size() >= (size_t)INT32_MAX) return fail(MR_EINVAL, "operator too large");
   std::vector<int2> fwd_items, bwd_items;
   fwd_ptr.assign(1, 0);
   bwd_ptr.assign(1, 0);
@@ -743,8 +767,8 @@ int mr_ctx::upload_all(hipStream_t s) {
   HIP_TRY(upload(d_iperm, iperm, s));
   HIP_TRY(upload(d_perm, perm, s));
   HIP_TRY(upload(d_mptr, mptr, s));
-  HIP_TRY(upload(d_mcol, mcol, s));
-  HIP_TRY(upload(d_mwt, mwt, s));
+  HIP_TRY(upload(d_ment, ment, s));
+  HIP_TRY(upload(d_minv, minv, s));
   HIP_TRY(upload(d_blocks, blocks, s));
   HIP_TRY(upload(d_block_pair, block_pair, s));
   {
@@ -847,7 +871,7 @@ int64_t mr_ctx::device_bytes() const {
                    d_x_sptr.bytes() + d_x_opp.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
                    d_x_u0.bytes() + d_x_rec.bytes() +
                    d_xy_s.bytes() + d_mptr.bytes() +
-                   d_mcol.bytes() + d_mwt.bytes() + d_h.bytes() + d_x.bytes() +
+                   d_ment.bytes() + d_minv.bytes() + d_h.bytes() + d_x.bytes() +
                    d_blocks.bytes() + d_fwd_items.bytes() + d_bwd_items.bytes() + d_cptr.bytes() +
                    d_cidx.bytes() + d_below.bytes() + d_partials2.bytes() + d_prow.bytes() +
                    d_upd.bytes() + d_dcol.bytes() + d_drow.bytes() + d_partials.bytes() +

@@ -66,8 +66,9 @@ struct mr_ctx {
   mr::DevArray<int2> d_tile_pbc;
   mr::DevArray<uint8_t> d_tile_loc;             // per tile pixel: its entry in the tile's list
   mr::DevArray<float> d_coef, d_re, d_rho, d_rho_s;   // rho natural and solve order
-  mr::DevArray<int32_t> d_mptr, d_mcol;
-  mr::DevArray<float> d_mwt;
+  mr::DevArray<int32_t> d_mptr;                 // force operator rows (bit 31: two-word entries)
+  mr::DevArray<uint32_t> d_ment;                // its entries (column offset | numerator)
+  mr::DevArray<float> d_minv;                   // per row 1 / (4 * 6 m_i)
   mr::DevArray<float2> d_h;
   mr::DevArray<double2> d_x;
   mr::DevArray<mr::DevBlock> d_blocks;

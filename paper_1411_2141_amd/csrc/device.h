@@ -89,8 +89,9 @@ constexpr int kApexMaxRanges = 256;   // ancestor ranges of one apex block (at m
 // finish the MSD of `partials`.  Node data in solve order: u and h are
 // indexed by solve row, the operator's columns too.
 struct AssembleArgs {
-  const int32_t *mptr, *mcol;
-  const float *mwt;
+  const int32_t *mptr;
+  const uint32_t *ment;
+  const float *minv;
   const float2 *h;
   const double2 *u;
   const int32_t *rows;          // solve rows outside the first level

@@ -25,7 +25,7 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
                          hipStream_t s);
 // Assemble launch (solve order; x may be u); with finish_msd it also finishes
 // the MSD of `partials`.
-hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
+hipError_t launch_assemble(int n, const int32_t *mptr, const uint32_t *ment, const float *minv,
                            const float2 *h, const double2 *u, double2 *x, double tau,
                            const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, const int32_t *active, hipStream_t s);

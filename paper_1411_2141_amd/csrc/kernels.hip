@@ -607,89 +607,117 @@ __global__ __launch_bounds__(256) void k_sample(const NodeItem *__restrict__ ite
   sample_nodes<1>(it, P, un, xy, coef, rho, h, flags);
 }
 
-// b for solve row k: u_k - tau f_k, f_k = sum_q w_q h(col_q) over the force
-// operator row k (FP32 sum in row order), loads issued in batches of U.  Node
-// data in solve order (u, h and the operator's columns).
+// Entry q of a one-word force-operator row of solve row k: its column (k plus
+// the signed 16-bit offset in the high half) and its integer numerator.
+__device__ __forceinline__ int ment_col(uint32_t e, int k) { return k + ((int32_t)e >> 16); }
+__device__ __forceinline__ float ment_num(uint32_t e) { return (float)(e & 0xffffu); }
+
+// b for solve row k: u_k - tau f_k, f_k = (sum_q a_q h(col_q)) / (4 * 6 m_k)
+// over the force operator row k (integer numerators a_q; FP32 sum in row
+// order), loads issued in batches of U.  Node data in solve order (u, h and
+// the operator's columns).  Rows flagged by bit 31 of mptr hold two words per
+// entry (column, FP32 numerator).
 __device__ __forceinline__ double2 assemble_b(int k, const int32_t *__restrict__ mptr,
-                                              const int32_t *__restrict__ mcol,
-                                              const float *__restrict__ mwt,
+                                              const uint32_t *__restrict__ ment,
+                                              const float *__restrict__ minv,
                                               const float2 *__restrict__ h,
                                               const double2 *__restrict__ u, double tau) {
   const double2 ui = u[k];
-  const int q0 = mptr[k], q1 = mptr[k + 1];
+  const int32_t p0 = mptr[k];
+  const int q0 = p0 & 0x7fffffff, q1 = mptr[k + 1] & 0x7fffffff;
+  const float inv = minv[k];
   float fx = 0.0f, fy = 0.0f;
   constexpr int U = 8;
-  for (int q = q0; q < q1; q += U) {
-    int c[U];
-    float w[U];
+  if (p0 >= 0) {
+    for (int q = q0; q < q1; q += U) {
+      uint32_t e[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      c[k] = q + k < q1 ? mcol[q + k] : -1;
-      w[k] = q + k < q1 ? mwt[q + k] : 0.0f;
+      for (int j = 0; j < U; ++j) e[j] = q + j < q1 ? ment[q + j] : 0u;
+      float2 hv[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) hv[j] = h[ment_col(e[j], k)];
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (q + j < q1) {
+          fx += ment_num(e[j]) * hv[j].x;
+          fy += ment_num(e[j]) * hv[j].y;
+        }
     }
-    float2 hv[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) hv[k] = c[k] >= 0 ? h[c[k]] : make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (q + k < q1) {
-        fx += w[k] * hv[k].x;
-        fy += w[k] * hv[k].y;
-      }
+  } else {
+    for (int q = q0; q < q1; q += 2) {
+      const int c = (int)ment[q];
+      const float a = __uint_as_float(ment[q + 1]);
+      const float2 hv = h[c];
+      fx += a * hv.x;
+      fy += a * hv.y;
+    }
   }
-  return make_double2(ui.x - tau * (double)fx, ui.y - tau * (double)fy);
+  return make_double2(ui.x - tau * (double)(fx * inv), ui.y - tau * (double)(fy * inv));
 }
 
 // assemble_b for two rows at once (rows with on[r] false are skipped): both
 // rows' loads are issued together, so their gather chains overlap.  Same
-// arithmetic, in the same order, as assemble_b.
+// arithmetic, in the same order, as assemble_b; a two-word row takes
+// assemble_b itself.
 __device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
                                             const int32_t *__restrict__ mptr,
-                                            const int32_t *__restrict__ mcol,
-                                            const float *__restrict__ mwt,
+                                            const uint32_t *__restrict__ ment,
+                                            const float *__restrict__ minv,
                                             const float2 *__restrict__ h,
                                             const double2 *__restrict__ u, double tau,
                                             double2 out[2]) {
+  int32_t p0[2];
   int q0[2], q1[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    q0[r] = on[r] ? mptr[k[r]] : 0;
-    q1[r] = on[r] ? mptr[k[r] + 1] : 0;
+    p0[r] = on[r] ? mptr[k[r]] : 0;
+    q0[r] = p0[r] & 0x7fffffff;
+    q1[r] = on[r] ? mptr[k[r] + 1] & 0x7fffffff : q0[r];
+  }
+  if (p0[0] < 0 || p0[1] < 0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      if (on[r]) out[r] = assemble_b(k[r], mptr, ment, minv, h, u, tau);
+    return;
   }
   double2 ui[2];
+  float inv[2];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) ui[r] = on[r] ? u[k[r]] : make_double2(0.0, 0.0);
+  for (int r = 0; r < 2; ++r) {
+    ui[r] = on[r] ? u[k[r]] : make_double2(0.0, 0.0);
+    inv[r] = on[r] ? minv[k[r]] : 0.0f;
+  }
   float fx[2] = {0.0f, 0.0f}, fy[2] = {0.0f, 0.0f};
   constexpr int U = 8;
   const int len = max(q1[0] - q0[0], q1[1] - q0[1]);
   for (int d = 0; d < len; d += U) {
-    int c[2][U];
-    float w[2][U];
+    uint32_t e[2][U];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int q = q0[r] + d + k;
-        c[r][k] = q < q1[r] ? mcol[q] : -1;
-        w[r][k] = q < q1[r] ? mwt[q] : 0.0f;
+      for (int j = 0; j < U; ++j) {
+        const int q = q0[r] + d + j;
+        e[r][j] = q < q1[r] ? ment[q] : 0u;
       }
     float2 hv[2][U];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int k = 0; k < U; ++k) hv[r][k] = c[r][k] >= 0 ? h[c[r][k]] : make_float2(0.0f, 0.0f);
+      for (int j = 0; j < U; ++j) hv[r][j] = h[ment_col(e[r][j], on[r] ? k[r] : k[0])];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int k = 0; k < U; ++k)
-        if (q0[r] + d + k < q1[r]) {
-          fx[r] += w[r][k] * hv[r][k].x;
-          fy[r] += w[r][k] * hv[r][k].y;
+      for (int j = 0; j < U; ++j)
+        if (q0[r] + d + j < q1[r]) {
+          fx[r] += ment_num(e[r][j]) * hv[r][j].x;
+          fy[r] += ment_num(e[r][j]) * hv[r][j].y;
         }
   }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    out[r] = make_double2(ui[r].x - tau * (double)fx[r], ui[r].y - tau * (double)fy[r]);
+    if (on[r])
+      out[r] = make_double2(ui[r].x - tau * (double)(fx[r] * inv[r]),
+                            ui[r].y - tau * (double)(fy[r] * inv[r]));
 }
 
 // Whether solve row `row` belongs to an active pair.  active[n_pairs] is
@@ -720,7 +748,7 @@ __device__ __forceinline__ void fused_tail(const AssembleArgs &A, double2 *x, in
     if (k < A.n_rows) {
       const int row = A.rows[k];
       if (row_active(A.pairs, A.n_pairs, A.active, row))
-        x[row] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+        x[row] = assemble_b(row, A.mptr, A.ment, A.minv, A.h, A.u, A.tau);
     }
   } else {
     msd_finish_group(A.pairs, A.n_pairs, A.partials, A.finish_msd, g - row_groups);
@@ -733,8 +761,8 @@ __device__ __forceinline__ void fused_tail(const AssembleArgs &A, double2 *x, in
 // the node range finish the MSD of the partials written by the preceding
 // sample launch.
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
-                                                  const int32_t *__restrict__ mcol,
-                                                  const float *__restrict__ mwt,
+                                                  const uint32_t *__restrict__ ment,
+                                                  const float *__restrict__ minv,
                                                   const float2 *__restrict__ h,
                                                   const double2 *u, double2 *x, double tau,
                                                   const DevPair *__restrict__ pairs, int n_pairs,
@@ -754,7 +782,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
   const bool on[2] = {row_active(pairs, n_pairs, active, k0),
                       k0 + 256 < n && row_active(pairs, n_pairs, active, k0 + 256)};
   double2 b[2];
-  assemble_b2(k, on, mptr, mcol, mwt, h, u, tau, b);
+  assemble_b2(k, on, mptr, ment, minv, h, u, tau, b);
   if (on[0]) x[k0] = b[0];
   if (on[1]) x[k0 + 256] = b[1];
 }
@@ -833,7 +861,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(
   if (FUSED) {
     if (part == 0 && r < b) {
       const int row = B.r0 + r;
-      t[r] = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t[r] = assemble_b(row, A.mptr, A.ment, A.minv, A.h, A.u, A.tau);
     }
   } else {
     double ax = 0.0, ay = 0.0;
@@ -1132,7 +1160,7 @@ __global__ __launch_bounds__(256) void k_wave_fwd(
   if (lane < b) {
     const int row = B.r0 + lane;
     if (FUSED) {
-      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.ment, A.minv, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1301,7 +1329,7 @@ __global__ __launch_bounds__(256) void k_half_fwd(
   if (r < b) {
     const int row = B.r0 + r;
     if (FUSED) {
-      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.ment, A.minv, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1490,7 +1518,7 @@ __global__ __launch_bounds__(64) void k_lds_fwd(
   if (lane < b) {
     const int row = B.r0 + lane;
     if (FUSED) {
-      t = assemble_b(row, A.mptr, A.mcol, A.mwt, A.h, A.u, A.tau);
+      t = assemble_b(row, A.mptr, A.ment, A.minv, A.h, A.u, A.tau);
     } else {
       const double2 c = gather_updates(cptr[row], cptr[row + 1], cidx, upd);
       const double2 bb = x[row];
@@ -1864,12 +1892,12 @@ hipError_t launch_sample(const NodeItem *items, int n_items, const DevPair *pair
                 n_tiles);
 }
 
-hipError_t launch_assemble(int n, const int32_t *mptr, const int32_t *mcol, const float *mwt,
+hipError_t launch_assemble(int n, const int32_t *mptr, const uint32_t *ment, const float *minv,
                            const float2 *h, const double2 *u, double2 *x, double tau,
                            const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, const int32_t *active, hipStream_t s) {
   const int groups = (n + 511) / 512 + (finish_msd ? (n_pairs + 3) / 4 : 0);
-  return launch(k_assemble, groups, 256, 0, s, n, mptr, mcol, mwt, h, u, x, tau, pairs, n_pairs,
+  return launch(k_assemble, groups, 256, 0, s, n, mptr, ment, minv, h, u, x, tau, pairs, n_pairs,
                 partials, finish_msd, active);
 }
 
