@@ -581,7 +581,8 @@ def main() -> int:
     # process pools start fresh interpreters)
     procs = args.gen_procs or min(16, len(os.sched_getaffinity(0)))
     tau = 0.5
-    batch = make_pairs(4, args.batched_pairs, processes=procs)
+    # --batched-pairs 0 skips the headline leg (counter runs of the other legs)
+    batch = make_pairs(4, args.batched_pairs, processes=procs) if args.batched_pairs else []
     pair = make_pair(2) if (args.single_iters or args.unstructured_iters or args.explicit_iters) else None
     large = make_pair(3) if args.large_iters else None
     upair = None
@@ -590,8 +591,8 @@ def main() -> int:
         Vu, Tu = unstructured_mesh(pair.te, 1, 32, 0.08, seed=2000)
         upair = dict(te=pair.te, re=pair.re, V=Vu, T=Tu, alpha=pair.alpha)
     dbatch = make_pairs(5, args.diff_batch_pairs, processes=procs) if args.diff_batch_pairs else []
-    cpu = None if args.no_cpu_baseline else cpu_baseline(batch, tau, args.cpu_every, args.cpu_iters,
-                                                         procs)
+    cpu = None if (args.no_cpu_baseline or not batch) else cpu_baseline(
+        batch, tau, args.cpu_every, args.cpu_iters, procs)
 
     import torch
     import paper_1411_2141_amd as pkg
@@ -600,46 +601,48 @@ def main() -> int:
     K = args.steps
     side = torch.cuda.Stream()
     nb = sum(p.n_nodes for p in batch)
-    with torch.cuda.stream(side):
-        # the force assembly in its own launch: what the autotuner picks on
-        # this workload in most runs (within ~3 % of the fused form), fixed
-        # so that counter runs and timed runs execute the same launches
-        bctx = pkg.MeshReg(batch, tau=tau, graph=True, separate_assembly=True)
-        ub = bctx.zeros_u()
-        bctx.set_graph(False)
-        if args.warmup:
-            B.mesh_reg_step(bctx.ctx, ub, args.warmup, None, side.cuda_stream)
-        bctx.set_graph(True)
-        ub.zero_()
-        B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # capture + first replay
-        side.synchronize()
-        ub.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # graph replay: K iterations
-        msd_b = bctx.warp_msd(ub)
-        side.synchronize()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        value = nb * K / dt
-        kernels, roof, stages = {}, None, None
-        if not args.no_profile:
+    value = dt = msd_b = None
+    kernels, roof, stages, converge, explicit_b = {}, None, None, None, None
+    nnz_l = levels = 0
+    if batch:
+        with torch.cuda.stream(side):
+            # the force assembly in its own launch: what the autotuner picks on
+            # this workload in most runs (within ~3 % of the fused form), fixed
+            # so that counter runs and timed runs execute the same launches
+            bctx = pkg.MeshReg(batch, tau=tau, graph=True, separate_assembly=True)
+            ub = bctx.zeros_u()
+            bctx.set_graph(False)
+            if args.warmup:
+                B.mesh_reg_step(bctx.ctx, ub, args.warmup, None, side.cuda_stream)
+            bctx.set_graph(True)
             ub.zero_()
-            fused = bctx.info(0, "fused_assembly") == 1
-            kernels, roof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, K, None,
-                                                                  side.cuda_stream),
-                                    run_bytes(algorithmic_bytes(bctx, batch), K, False, fused),
-                                    "batched", run_bytes(unit_bytes(bctx, batch), K, False, fused))
-            stages = stage_rooflines(bctx, batch, ub)
-        nnz_l = sum(bctx.info(k, "nnz_l") for k in range(len(batch)))
-        levels = max(bctx.info(k, "fwd_levels") for k in range(len(batch)))
-    converge = converge_leg(bctx, batch, side, args, dt / K) if args.converge_max_iters else None
-    bctx.close()
-    explicit_b = None
-    if args.explicit_iters:
-        explicit_b = explicit_leg(
-            pkg, B, batch, EXPLICIT_TAU, EXPLICIT_LAMBDA, min(args.explicit_iters, 100),
-            side, args.no_profile, "the same 256 pairs, Algorithm 1 as printed", "explicit_batched")
+            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # capture + first replay
+            side.synchronize()
+            ub.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.mesh_reg_step(bctx.ctx, ub, K, None, side.cuda_stream)      # graph replay: K iterations
+            msd_b = bctx.warp_msd(ub)
+            side.synchronize()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            value = nb * K / dt
+            if not args.no_profile:
+                ub.zero_()
+                fused = bctx.info(0, "fused_assembly") == 1
+                kernels, roof = profile(bctx, lambda: B.mesh_reg_step(bctx.ctx, ub, K, None,
+                                                                      side.cuda_stream),
+                                        run_bytes(algorithmic_bytes(bctx, batch), K, False, fused),
+                                        "batched", run_bytes(unit_bytes(bctx, batch), K, False, fused))
+                stages = stage_rooflines(bctx, batch, ub)
+            nnz_l = sum(bctx.info(k, "nnz_l") for k in range(len(batch)))
+            levels = max(bctx.info(k, "fwd_levels") for k in range(len(batch)))
+        converge = converge_leg(bctx, batch, side, args, dt / K) if args.converge_max_iters else None
+        bctx.close()
+        if args.explicit_iters:
+            explicit_b = explicit_leg(
+                pkg, B, batch, EXPLICIT_TAU, EXPLICIT_LAMBDA, min(args.explicit_iters, 100),
+                side, args.no_profile, "the same 256 pairs, Algorithm 1 as printed", "explicit_batched")
 
     single = None
     if args.single_iters:
@@ -698,8 +701,9 @@ def main() -> int:
                                 "MSD every iteration", "explicit_single")
 
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "node-updates/s", "n_gpus": 1,
-        "steps": K, "warmup": args.warmup, "ms_per_step": round(dt / K * 1e3, 5),
+        "metric": METRIC, "value": round(value, 1) if batch else None, "unit": "node-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(dt / K * 1e3, 5) if batch else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{len(batch)} ragged pairs, sides uniform in {{128..1024}}, FP32 "
@@ -710,9 +714,9 @@ def main() -> int:
                    "triangles": int(sum(p.T.shape[0] for p in batch)),
                    "pixels": int(sum(p.height * p.width for p in batch)),
                    "nnz_l": int(nnz_l), "solve_levels_max": int(levels),
-                   "iterations": K, "iterations_per_s": round(K / dt, 2),
+                   "iterations": K, "iterations_per_s": round(K / dt, 2) if batch else None,
                    "parallelism": "single GPU", "graph": True,
-                   "mean_final_msd": float(msd_b.mean().item())},
+                   "mean_final_msd": float(msd_b.mean().item()) if batch else None},
         "kernels": kernels, "roofline": roof, "stage_rooflines": stages, "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
         "single_pair": single, "large_pair": large_leg, "diff_batch": dbatch_leg,
