@@ -80,6 +80,15 @@ CASES = {
                                     alpha=0.1),
     # unit cells: every pixel of a 16 x 16 tile has its own triangle, so two
     # tiles of a warp workgroup hold more triangles than one round of maps
+    # three rows: no spline window lies inside the image, every sample folds
+    # its taps (the reference cropped three pixels down and right, so the MSD
+    # is not that of two near-equal crops, where on so few pixels the FP32
+    # coefficients' rounding alone reaches the relative bound: 1.1e-6 on a
+    # 3 x 5 crop at u = 0, reproduced by an FP32 emulation on the CPU)
+    "tiny_3x40": lambda: (lambda V, T: dict(
+        te=small_pair(seed=6, side=48)[0][:3, :40].copy(),
+        re=small_pair(seed=6, side=48)[1][3:6, 3:43].copy(), V=V, T=T,
+        alpha=0.1))(*uniform_mesh(3, 40, 1)[:2]),
     "unit_cells_40": lambda: (lambda V, T: dict(
         te=small_pair(seed=4, side=48)[0][:40, :40].copy(),
         re=small_pair(seed=4, side=48)[1][:40, :40].copy(), V=V, T=T,
