@@ -117,8 +117,8 @@ typedef struct {
                                   block with the block's factor data copied straight into LDS
                                   (blocks <= 64 rows, <= 64 KB); 8 or 16 = wavefront per block
                                   with 8 or 16 loads per lane in flight (blocks <= 64 rows);
-                                  32 or 33 = half wavefront per block (blocks <= 32 rows) with 8
-                                  or 16 loads per lane in flight; these four
+                                  32, 33 or 34 = half wavefront per block (blocks <= 32 rows)
+                                  with 8, 16 or 4 loads per lane in flight; these five
                                   need unsplit backward blocks; 64, 128, 256, 512 or 1024 =
                                   workgroup per block of that size; levels where the choice is not admissible
                                   take the smallest admissible workgroup size.  MR_FLAG_NO_TUNE

@@ -192,7 +192,7 @@ bool mr_ctx::admissible(bool fwd, size_t lev, int nt) const {
   if (nt == 1)
     return minnt[lev] <= 64 && (fwd ? fwd_direct[lev] : bwd_direct[lev]) <= 64 * 1024 &&
            (fwd || !bwd_split[lev]);
-  if (nt == 32 || nt == 33)
+  if (nt == 32 || nt == 33 || nt == 34)
     return (fwd ? fwd_maxb[lev] : bwd_maxb[lev]) <= 32 && (fwd || !bwd_split[lev]);
   if (nt < 64) return minnt[lev] <= 64 && (fwd || !bwd_split[lev]);
   return nt >= minnt[lev];
@@ -248,7 +248,7 @@ int mr_ctx::tune(hipStream_t s) {
     }
     return t_min;
   };
-  static const int kCandidates[] = {1, 8, 16, 32, 33, 64, 128, 256, 512, 1024};
+  static const int kCandidates[] = {1, 8, 16, 32, 33, 34, 64, 128, 256, 512, 1024};
   // The first forward level either assembles the right-hand side itself
   // (fused) or follows a separate assembly launch; both are candidates unless
   // the separate launch is requested.
@@ -966,9 +966,10 @@ extern "C" int mesh_reg_init(const mr_pair *pairs, int32_t n_pairs, const mr_par
     return fail(MR_EINVAL, "unknown force_mode");
   {
     const int32_t k = params->solve_kernel;
-    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 33 && k != 64 && k != 128 &&
-        k != 256 && k != 512 && k != 1024)
-      return fail(MR_EINVAL, "solve_kernel must be 0, 1, 8, 16, 32, 33, 64, 128, 256, 512 or 1024");
+    if (k != 0 && k != 1 && k != 8 && k != 16 && k != 32 && k != 33 && k != 34 && k != 64 &&
+        k != 128 && k != 256 && k != 512 && k != 1024)
+      return fail(MR_EINVAL,
+                  "solve_kernel must be 0, 1, 8, 16, 32, 33, 34, 64, 128, 256, 512 or 1024");
   }
   const bool host_only = (params->flags & MR_FLAG_HOST_ONLY) != 0;
   for (int p = 0; p < n_pairs; ++p) {

@@ -1915,8 +1915,8 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
                 : launch(k_lds_fwd<false>, groups, 64, lds_bytes, s, blocks, items, count, cptr,
                          cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
   }
-  if (nt == 32 || nt == 33) {                 // half-wavefront per block (at most 32 rows),
-                                              // 8 (32) or 16 (33) loads per batch
+  if (nt == 32 || nt == 33 || nt == 34) {     // half-wavefront per block (at most 32 rows),
+                                              // 8 (32), 16 (33) or 4 (34) loads per batch
     int groups = (count + 7) / 8;
     if (fuse)
       groups += (fuse->n_rows + 255) / 256 + (fuse->finish_msd ? (fuse->n_pairs + 3) / 4 : 0);
@@ -1925,6 +1925,11 @@ hipError_t launch_solve_fwd_level(const DevBlock *blocks, const int2 *items, int
       return fuse ? launch(k_half_fwd<true, 16>, groups, 256, 0, s, blocks, items, count, cptr,
                            cidx, dcol, pcol, x, ybuf, upd, *fuse)
                   : launch(k_half_fwd<false, 16>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
+    if (nt == 34)
+      return fuse ? launch(k_half_fwd<true, 4>, groups, 256, 0, s, blocks, items, count, cptr,
+                           cidx, dcol, pcol, x, ybuf, upd, *fuse)
+                  : launch(k_half_fwd<false, 4>, groups, 256, 0, s, blocks, items, count, cptr,
                            cidx, dcol, pcol, x, ybuf, upd, AssembleArgs{});
     return fuse ? launch(k_half_fwd<true, 8>, groups, 256, 0, s, blocks, items, count, cptr, cidx,
                          dcol, pcol, x, ybuf, upd, *fuse)
@@ -1979,9 +1984,10 @@ hipError_t launch_solve_bwd_level(const DevBlock *blocks, const int2 *items, int
   if (nt == 1)
     return launch(k_lds_bwd, count, 64, lds_bytes, s, blocks, items, count, below_idx, drow, prow,
                   x, ybuf, perm, out);
-  if (nt == 32 || nt == 33)
-    return launch(nt == 32 ? k_half_bwd<8> : k_half_bwd<16>, (count + 7) / 8, 256, 0, s, blocks,
-                  items, count, below_idx, drow, prow, x, ybuf, perm, out);
+  if (nt == 32 || nt == 33 || nt == 34)
+    return launch(nt == 32 ? k_half_bwd<8> : nt == 33 ? k_half_bwd<16> : k_half_bwd<4>,
+                  (count + 7) / 8, 256, 0, s, blocks, items, count, below_idx, drow, prow, x,
+                  ybuf, perm, out);
   if (nt == 8 || nt == 16)
     return launch(nt == 8 ? k_wave_bwd<8> : k_wave_bwd<16>, (count + 3) / 4, 256, 0, s, blocks,
                   items, count, below_idx, drow, prow, x, ybuf, perm, out);

@@ -24,7 +24,7 @@ from tests._problems import small_pair
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = (1, 8, 16, 32, 33, 64, 128, 256, 512, 1024)
+KERNELS = (1, 8, 16, 32, 33, 34, 64, 128, 256, 512, 1024)
 SOLVE_TOL = 1e-12
 U_TOL = 1e-5
 
