@@ -655,71 +655,6 @@ __device__ __forceinline__ double2 assemble_b(int k, const int32_t *__restrict__
   return make_double2(ui.x - tau * (double)(fx * inv), ui.y - tau * (double)(fy * inv));
 }
 
-// assemble_b for two rows at once (rows with on[r] false are skipped): both
-// rows' loads are issued together, so their gather chains overlap.  Same
-// arithmetic, in the same order, as assemble_b; a two-word row takes
-// assemble_b itself.
-__device__ __forceinline__ void assemble_b2(const int k[2], const bool on[2],
-                                            const int32_t *__restrict__ mptr,
-                                            const uint32_t *__restrict__ ment,
-                                            const float *__restrict__ minv,
-                                            const float2 *__restrict__ h,
-                                            const double2 *__restrict__ u, double tau,
-                                            double2 out[2]) {
-  int32_t p0[2];
-  int q0[2], q1[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    p0[r] = on[r] ? mptr[k[r]] : 0;
-    q0[r] = p0[r] & 0x7fffffff;
-    q1[r] = on[r] ? mptr[k[r] + 1] & 0x7fffffff : q0[r];
-  }
-  if (p0[0] < 0 || p0[1] < 0) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-      if (on[r]) out[r] = assemble_b(k[r], mptr, ment, minv, h, u, tau);
-    return;
-  }
-  double2 ui[2];
-  float inv[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    ui[r] = on[r] ? u[k[r]] : make_double2(0.0, 0.0);
-    inv[r] = on[r] ? minv[k[r]] : 0.0f;
-  }
-  float fx[2] = {0.0f, 0.0f}, fy[2] = {0.0f, 0.0f};
-  constexpr int U = 8;
-  const int len = max(q1[0] - q0[0], q1[1] - q0[1]);
-  for (int d = 0; d < len; d += U) {
-    uint32_t e[2][U];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const int q = q0[r] + d + j;
-        e[r][j] = q < q1[r] ? ment[q] : 0u;
-      }
-    float2 hv[2][U];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int j = 0; j < U; ++j) hv[r][j] = h[ment_col(e[r][j], on[r] ? k[r] : k[0])];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int j = 0; j < U; ++j)
-        if (q0[r] + d + j < q1[r]) {
-          fx[r] += ment_num(e[r][j]) * hv[r][j].x;
-          fy[r] += ment_num(e[r][j]) * hv[r][j].y;
-        }
-  }
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-    if (on[r])
-      out[r] = make_double2(ui[r].x - tau * (double)(fx[r] * inv[r]),
-                            ui[r].y - tau * (double)(fy[r] * inv[r]));
-}
-
 // Whether solve row `row` belongs to an active pair.  active[n_pairs] is
 // nonzero once some pair is retired (until then no lookup is made); the pair
 // is found by bisection over the pairs' first rows (rows are packed pair by
@@ -755,9 +690,10 @@ __device__ __forceinline__ void fused_tail(const AssembleArgs &A, double2 *x, in
   }
 }
 
-// Force assembly (a thread per two solve rows), b written in solve order; u
-// and h in solve order too, and x may be u itself (each thread reads its rows
-// of u before writing them).  When `finish_msd` is given, the workgroups after
+// Force assembly (a thread per solve row: at 38 VGPRs the workgroups fill
+// the CUs, which beat two rows per thread with their gathers interleaved at
+// 76), b written in solve order; u and h in solve order too, and x may be u
+// itself (each thread reads its row of u before writing it).  When `finish_msd` is given, the workgroups after
 // the node range finish the MSD of the partials written by the preceding
 // sample launch.
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ mptr,
@@ -769,22 +705,15 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
                                                   const double *__restrict__ partials,
                                                   double *__restrict__ finish_msd,
                                                   const int32_t *__restrict__ active) {
-  const int node_groups = (n + 511) / 512;
+  const int node_groups = (n + 255) / 256;
   if ((int)blockIdx.x >= node_groups) {
     msd_finish_group(pairs, n_pairs, partials, finish_msd, (int)blockIdx.x - node_groups);
     return;
   }
-  // rows k and k + 256 of the workgroup's 512
-  const int k0 = (int)blockIdx.x * 512 + (int)threadIdx.x;
-  if (k0 >= n) return;
-  const int k[2] = {k0, k0 + 256};
+  const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
   // rows of retired pairs keep their x (the displacement)
-  const bool on[2] = {row_active(pairs, n_pairs, active, k0),
-                      k0 + 256 < n && row_active(pairs, n_pairs, active, k0 + 256)};
-  double2 b[2];
-  assemble_b2(k, on, mptr, ment, minv, h, u, tau, b);
-  if (on[0]) x[k0] = b[0];
-  if (on[1]) x[k0 + 256] = b[1];
+  if (k < n && row_active(pairs, n_pairs, active, k))
+    x[k] = assemble_b(k, mptr, ment, minv, h, u, tau);
 }
 
 // Smallest power of two >= b (b <= kBlockMax).
@@ -1896,7 +1825,7 @@ hipError_t launch_assemble(int n, const int32_t *mptr, const uint32_t *ment, con
                            const float2 *h, const double2 *u, double2 *x, double tau,
                            const DevPair *pairs, int n_pairs, const double *partials,
                            double *finish_msd, const int32_t *active, hipStream_t s) {
-  const int groups = (n + 511) / 512 + (finish_msd ? (n_pairs + 3) / 4 : 0);
+  const int groups = (n + 255) / 256 + (finish_msd ? (n_pairs + 3) / 4 : 0);
   return launch(k_assemble, groups, 256, 0, s, n, mptr, ment, minv, h, u, x, tau, pairs, n_pairs,
                 partials, finish_msd, active);
 }
