@@ -324,6 +324,191 @@ __device__ __forceinline__ T load_at(const T *__restrict__ base, unsigned off) {
 // Each tile's FP64 sum of squared differences (a fixed order over the
 // workgroup's threads) goes to partials[tile].  Offsets within a pair's image
 // are 32-bit (fewer than 2^31 pixels).
+// The records of NT consecutive tiles from tile0 (a tile past the end or of a
+// retired pair is off and has no entries); the group's triangle entries are
+// numbered tile after tile, tile q's from base[q] on, total in all.
+template <int NT>
+struct WarpGroup {
+  TileItem it[NT];
+  int tl[NT], base[NT], total;
+  bool on[NT];
+};
+
+template <int NT>
+__device__ __forceinline__ void warp_group(WarpGroup<NT> &g, int tile0, int n_tiles,
+                                           const TileItem *__restrict__ tiles) {
+  g.total = 0;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const bool valid = tile0 + q < n_tiles;
+    g.tl[q] = valid ? tile0 + q : tile0;
+    g.it[q] = tiles[g.tl[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const bool valid = tile0 + q < n_tiles;
+    g.on[q] = valid & (g.it[q].active != 0);
+    g.base[q] = g.total;
+    g.total += g.on[q] ? g.it[q].n_ent : 0;
+  }
+}
+
+// The thread's pixel (rx, ry) of each tile: its triangle's slot in the group's
+// entry numbering, its offset in the pair's image, whether it lies inside the
+// image and its reference sample.  None of it depends on the maps.
+template <int NT>
+struct WarpPixels {
+  int slot[NT];
+  float rv[NT];
+  unsigned po[NT];
+  bool in[NT];
+};
+
+template <int NT>
+__device__ __forceinline__ void warp_pixels(WarpPixels<NT> &p, const WarpGroup<NT> &g, int tid,
+                                            int rx, int ry, const uint8_t *__restrict__ tile_loc,
+                                            const float *__restrict__ re) {
+  constexpr int kPix = kTile * kTile;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int i = g.it[q].y0 + ry, j = g.it[q].x0 + rx;
+    p.in[q] = g.on[q] && i < g.it[q].height && j < g.it[q].width;
+    p.po[q] = __umul24((unsigned)min(i, g.it[q].height - 1), (unsigned)g.it[q].width) +
+              (unsigned)min(j, g.it[q].width - 1);
+    p.slot[q] = g.base[q] + (int)tile_loc[(size_t)g.tl[q] * kPix + tid];
+    p.rv[q] = load_at(re + g.it[q].pix_off, p.po[q] << 2);
+  }
+}
+
+// Stage 1: the maps of the group's entries [r0, r1) (at most kTile^2), entry e
+// by thread e - r0, into map[.][e - r0].
+template <int NT>
+__device__ __forceinline__ void warp_maps(const WarpGroup<NT> &g, int r0, int r1, int tid,
+                                          const double2 *__restrict__ u,
+                                          const int4 *__restrict__ tile_nodes,
+                                          const int2 *__restrict__ tile_pbc, unsigned *flags,
+                                          double2 (*map)[kTile * kTile]) {
+  const int e = r0 + tid;
+  if (e >= r1) return;
+  // the entry's tile: the last with base <= e (off tiles have no entries)
+  int x0 = g.it[0].x0, y0 = g.it[0].y0, k = g.it[0].ent_off + e;
+#pragma unroll
+  for (int q = 1; q < NT; ++q)
+    if (e >= g.base[q]) {
+      x0 = g.it[q].x0;
+      y0 = g.it[q].y0;
+      k = g.it[q].ent_off - g.base[q] + e;
+    }
+  const int4 nd = tile_nodes[k];               // corner nodes, packed first corner
+  const int2 pbc = tile_pbc[k];                // packed other corners
+  double2 ua = load_at(u, (unsigned)nd.x << 4);
+  const double2 ub = load_at(u, (unsigned)nd.y << 4);
+  const double2 uc = load_at(u, (unsigned)nd.z << 4);
+  // corners relative to the tile origin (exact)
+  const int ax = (nd.w & 0xffff) - x0, ay = (int)((unsigned)nd.w >> 16) - y0;
+  const double e1x = (double)((pbc.x & 0xffff) - x0 - ax);
+  const double e1y = (double)((int)((unsigned)pbc.x >> 16) - y0 - ay);
+  const double e2x = (double)((pbc.y & 0xffff) - x0 - ax);
+  const double e2y = (double)((int)((unsigned)pbc.y >> 16) - y0 - ay);
+  const double det = e1x * e2y - e1y * e2x;    // twice the area: exact, positive
+  // 1 / det: the FP32 estimate and two Newton steps
+  double inv = (double)__builtin_amdgcn_rcpf((float)det);
+  inv = fma(inv, fma(-det, inv, 1.0), inv);
+  inv = fma(inv, fma(-det, inv, 1.0), inv);
+  const bool ok = fabs(ua.x) < 1.0e6 && fabs(ua.y) < 1.0e6 && fabs(ub.x) < 1.0e6 &&
+                  fabs(ub.y) < 1.0e6 && fabs(uc.x) < 1.0e6 && fabs(uc.y) < 1.0e6;
+  // formed unconditionally (a branch around them would sink the corner
+  // coordinate load behind the displacement loads)
+  const double d1x = ub.x - ua.x, d1y = ub.y - ua.y, d2x = uc.x - ua.x, d2y = uc.y - ua.y;
+  double gxx = (d1x * e2y - d2x * e1y) * inv;
+  double gxy = (d2x * e1x - d1x * e2x) * inv;
+  double gyx = (d1y * e2y - d2y * e1y) * inv;
+  double gyy = (d2y * e1x - d1y * e2x) * inv;
+  if (!ok) {
+    gxx = gxy = gyx = gyy = 0.0;
+    ua = make_double2(0.0, 0.0);
+    atomicOr(flags, kFlagNonFinitePixel);
+  }
+  // displacement at the origin pixel's centre, (1/2, 1/2) in the tile frame
+  const double ox = 0.5 - (double)ax, oy = 0.5 - (double)ay;
+  map[0][tid] = make_double2(ua.x + gxx * ox + gxy * oy, ua.y + gyx * ox + gyy * oy);
+  map[1][tid] = make_double2(1.0 + gxx, gxy);
+  map[2][tid] = make_double2(gyx, 1.0 + gyy);
+}
+
+// Stage 2, first half: the pixels whose slots lie in the round [r0, r1)
+// evaluate their map and issue their coefficient loads (both tiles' together).
+template <int NT>
+struct WarpTaps {
+  float tap[NT][4][4];
+  float fx[NT], fy[NT];
+  bool act[NT];
+};
+
+template <int NT>
+__device__ __forceinline__ void warp_taps(WarpTaps<NT> &t, const WarpGroup<NT> &g,
+                                          const WarpPixels<NT> &p, int r0, int r1, double rxd,
+                                          double ryd, const double2 (*map)[kTile * kTile],
+                                          const float *__restrict__ coef) {
+  int qx[NT], qy[NT];
+  bool inside = true;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    t.act[q] = p.slot[q] >= r0 && p.slot[q] < r1;
+    const int sl = t.act[q] ? p.slot[q] - r0 : 0;
+    const double2 c = map[0][sl], gx = map[1][sl], gy = map[2][sl];
+    const double vx = fma(gx.x, rxd, fma(gx.y, ryd, c.x));
+    const double vy = fma(gy.x, rxd, fma(gy.y, ryd, c.y));
+    const double flx = floor(vx), fly = floor(vy);
+    qx[q] = g.it[q].x0 + (int)flx;
+    qy[q] = g.it[q].y0 + (int)fly;
+    t.fx[q] = (float)(vx - flx);
+    t.fy[q] = (float)(vy - fly);
+    // positions outside the image or the round take the window of cell
+    // (1, 1) (inside the image when both sides are at least 4)
+    if (!(p.in[q] && t.act[q])) {
+      qx[q] = qy[q] = 1;
+      t.fx[q] = t.fy[q] = 0.0f;
+    }
+    inside = inside && taps_inside(g.it[q].height, g.it[q].width, qx[q], qy[q]);
+  }
+  if (__all(inside)) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps_inside(coef + g.it[q].pix_off, g.it[q].width, qx[q], qy[q], t.tap[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      load_taps(coef + g.it[q].pix_off, g.it[q].height, g.it[q].width, qx[q], qy[q], t.tap[q]);
+  }
+}
+
+// Stage 2, second half: the samples of the round's pixels, the warped image
+// and the squared differences (each pixel is in exactly one round).
+template <int NT>
+__device__ __forceinline__ void warp_samples(const WarpTaps<NT> &t, const WarpGroup<NT> &g,
+                                             const WarpPixels<NT> &p, float *__restrict__ warped,
+                                             double (&sq)[NT]) {
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    float wx[4], wy[4];
+    bs_weights_unit(t.fx[q], wx);
+    bs_weights_unit(t.fy[q], wy);
+    float w = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float rs = t.tap[q][m][0] * wx[0] + t.tap[q][m][1] * wx[1] +
+                       t.tap[q][m][2] * wx[2] + t.tap[q][m][3] * wx[3];
+      w += wy[m] * rs;
+    }
+    if (t.act[q]) {
+      if (warped && p.in[q]) (warped + g.it[q].pix_off)[p.po[q]] = w;
+      const double d = (double)(w - p.rv[q]);
+      sq[q] = p.in[q] ? d * d : 0.0;
+    }
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileItem *__restrict__ tiles,
                                            const double2 *__restrict__ u,
@@ -338,45 +523,20 @@ __device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileIte
   // maps of up to kPix triangles at a time: c, (G'xx, G'xy), (G'yx, G'yy)
   __shared__ double2 map[3][kPix];
   const int tid = (int)threadIdx.x;
-  int tl[NT];
-  TileItem it[NT];
-  bool on[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const bool valid = tile0 + q < n_tiles;
-    tl[q] = valid ? tile0 + q : tile0;
-    it[q] = tiles[tl[q]];
-    on[q] = valid && it[q].active != 0;
-  }
+  WarpGroup<NT> g;
+  warp_group(g, tile0, n_tiles, tiles);
   // Tiles of retired pairs are not warped (the workgroup returns when all of
   // its tiles are retired).
   bool any = false;
 #pragma unroll
-  for (int q = 0; q < NT; ++q) any = any || on[q];
+  for (int q = 0; q < NT; ++q) any = any || g.on[q];
   if (!any) return;
-  int base[NT], total = 0;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    base[q] = total;
-    total += on[q] ? it[q].n_ent : 0;
-  }
 
   // The pixels' slots and reference samples do not depend on the maps:
   // their loads go out first.
   const int rx = tid % kTile, ry = tid / kTile;
-  int slot[NT];
-  float rv[NT];
-  unsigned po[NT];
-  bool in[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int i = it[q].y0 + ry, j = it[q].x0 + rx;
-    in[q] = on[q] && i < it[q].height && j < it[q].width;
-    po[q] = __umul24((unsigned)min(i, it[q].height - 1), (unsigned)it[q].width) +
-            (unsigned)min(j, it[q].width - 1);
-    slot[q] = base[q] + (int)tile_loc[(size_t)tl[q] * kPix + tid];
-    rv[q] = load_at(re + it[q].pix_off, po[q] << 2);
-  }
+  WarpPixels<NT> p;
+  warp_pixels(p, g, tid, rx, ry, tile_loc, re);
   const double rxd = (double)rx, ryd = (double)ry;
   double sq[NT];
 #pragma unroll
@@ -384,110 +544,14 @@ __device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileIte
 
   // The tiles' triangles in rounds of up to kPix (one round unless two dense
   // tiles share the workgroup); each pixel is evaluated in its slot's round.
-  for (int r0 = 0; r0 < total; r0 += kPix) {
-    const int r1 = min(total, r0 + kPix);
+  for (int r0 = 0; r0 < g.total; r0 += kPix) {
+    const int r1 = min(g.total, r0 + kPix);
     if (r0 > 0) __syncthreads();                  // the previous round's maps are read
-    // Stage 1: the displacement maps of the round's triangles.
-    const int e = r0 + tid;
-    if (e < r1) {
-      // the entry's tile: the last with base <= e (off tiles have no entries)
-      int x0 = it[0].x0, y0 = it[0].y0, k = it[0].ent_off + e;
-#pragma unroll
-      for (int q = 1; q < NT; ++q)
-        if (e >= base[q]) {
-          x0 = it[q].x0;
-          y0 = it[q].y0;
-          k = it[q].ent_off - base[q] + e;
-        }
-      const int4 nd = tile_nodes[k];               // corner nodes, packed first corner
-      const int2 pbc = tile_pbc[k];                // packed other corners
-      double2 ua = load_at(u, (unsigned)nd.x << 4);
-      const double2 ub = load_at(u, (unsigned)nd.y << 4);
-      const double2 uc = load_at(u, (unsigned)nd.z << 4);
-      // corners relative to the tile origin (exact)
-      const int ax = (nd.w & 0xffff) - x0, ay = (int)((unsigned)nd.w >> 16) - y0;
-      const double e1x = (double)((pbc.x & 0xffff) - x0 - ax);
-      const double e1y = (double)((int)((unsigned)pbc.x >> 16) - y0 - ay);
-      const double e2x = (double)((pbc.y & 0xffff) - x0 - ax);
-      const double e2y = (double)((int)((unsigned)pbc.y >> 16) - y0 - ay);
-      const double det = e1x * e2y - e1y * e2x;    // twice the area: exact, positive
-      // 1 / det: the FP32 estimate and two Newton steps
-      double inv = (double)__builtin_amdgcn_rcpf((float)det);
-      inv = fma(inv, fma(-det, inv, 1.0), inv);
-      inv = fma(inv, fma(-det, inv, 1.0), inv);
-      const bool ok = fabs(ua.x) < 1.0e6 && fabs(ua.y) < 1.0e6 && fabs(ub.x) < 1.0e6 &&
-                      fabs(ub.y) < 1.0e6 && fabs(uc.x) < 1.0e6 && fabs(uc.y) < 1.0e6;
-      double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
-      if (ok) {
-        const double d1x = ub.x - ua.x, d1y = ub.y - ua.y, d2x = uc.x - ua.x, d2y = uc.y - ua.y;
-        gxx = (d1x * e2y - d2x * e1y) * inv;
-        gxy = (d2x * e1x - d1x * e2x) * inv;
-        gyx = (d1y * e2y - d2y * e1y) * inv;
-        gyy = (d2y * e1x - d1y * e2x) * inv;
-      } else {
-        ua = make_double2(0.0, 0.0);
-        atomicOr(flags, kFlagNonFinitePixel);
-      }
-      // displacement at the origin pixel's centre, (1/2, 1/2) in the tile frame
-      const double ox = 0.5 - (double)ax, oy = 0.5 - (double)ay;
-      map[0][tid] = make_double2(ua.x + gxx * ox + gxy * oy, ua.y + gyx * ox + gyy * oy);
-      map[1][tid] = make_double2(1.0 + gxx, gxy);
-      map[2][tid] = make_double2(gyx, 1.0 + gyy);
-    }
+    warp_maps(g, r0, r1, tid, u, tile_nodes, tile_pbc, flags, map);
     __syncthreads();
-
-    // Stage 2: the pixels of the round, both tiles' loads issued together.
-    int qx[NT], qy[NT];
-    float fx[NT], fy[NT];
-    bool act[NT], inside = true;
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      act[q] = slot[q] >= r0 && slot[q] < r1;
-      const int sl = act[q] ? slot[q] - r0 : 0;
-      const double2 c = map[0][sl], gx = map[1][sl], gy = map[2][sl];
-      const double vx = fma(gx.x, rxd, fma(gx.y, ryd, c.x));
-      const double vy = fma(gy.x, rxd, fma(gy.y, ryd, c.y));
-      const double flx = floor(vx), fly = floor(vy);
-      qx[q] = it[q].x0 + (int)flx;
-      qy[q] = it[q].y0 + (int)fly;
-      fx[q] = (float)(vx - flx);
-      fy[q] = (float)(vy - fly);
-      // positions outside the image or the round take the window of cell
-      // (1, 1) (inside the image when both sides are at least 4)
-      if (!(in[q] && act[q])) {
-        qx[q] = qy[q] = 1;
-        fx[q] = fy[q] = 0.0f;
-      }
-      inside = inside && taps_inside(it[q].height, it[q].width, qx[q], qy[q]);
-    }
-    float tap[NT][4][4];
-    if (__all(inside)) {
-#pragma unroll
-      for (int q = 0; q < NT; ++q)
-        load_taps_inside(coef + it[q].pix_off, it[q].width, qx[q], qy[q], tap[q]);
-    } else {
-#pragma unroll
-      for (int q = 0; q < NT; ++q)
-        load_taps(coef + it[q].pix_off, it[q].height, it[q].width, qx[q], qy[q], tap[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      float wx[4], wy[4];
-      bs_weights_unit(fx[q], wx);
-      bs_weights_unit(fy[q], wy);
-      float w = 0.0f;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const float rs = tap[q][m][0] * wx[0] + tap[q][m][1] * wx[1] + tap[q][m][2] * wx[2] +
-                         tap[q][m][3] * wx[3];
-        w += wy[m] * rs;
-      }
-      if (act[q]) {
-        if (warped && in[q]) (warped + it[q].pix_off)[po[q]] = w;
-        const double d = (double)(w - rv[q]);
-        sq[q] = in[q] ? d * d : 0.0;
-      }
-    }
+    WarpTaps<NT> t;
+    warp_taps(t, g, p, r0, r1, rxd, ryd, map, coef);
+    warp_samples(t, g, p, warped, sq);
   }
 
   // Tile sums in a fixed order: the threads' values through LDS (the maps'
@@ -506,13 +570,13 @@ __device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileIte
     for (int k = 0; k < kPix / kLanes; ++k) s += red[q * kPix + j + k * kLanes];
 #pragma unroll
     for (int off = kLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    bool onq = on[0];
-    int tq = tl[0];
+    bool onq = g.on[0];
+    int tq = g.tl[0];
 #pragma unroll
-    for (int p = 1; p < NT; ++p)
-      if (q == p) {
-        onq = on[p];
-        tq = tl[p];
+    for (int p2 = 1; p2 < NT; ++p2)
+      if (q == p2) {
+        onq = g.on[p2];
+        tq = g.tl[p2];
       }
     if (j == 0 && onq) partials[tq] = s;
   }
@@ -1236,13 +1300,14 @@ __global__ __launch_bounds__(256) void k_half_fwd(
   if (w < count) {
     const int2 it = items[w];
     B = blocks[it.x];
-    if (B.active) {                            // a retired pair's half idles
-      b = B.r1 - B.r0;
-      m = B.m;
-      slice = it.y;
-      k0 = it.y * B.rslice;
-      kn = max(0, min(B.rslice, m - k0));
-    }
+    // a retired pair's half idles; selects rather than a branch, so that the
+    // record's fields and the item arrive in one round of loads
+    const bool on = B.active != 0;
+    b = on ? B.r1 - B.r0 : 0;
+    m = on ? B.m : 1;
+    slice = on ? it.y : 1;
+    k0 = on ? it.y * B.rslice : 0;
+    kn = on ? max(0, min(B.rslice, m - k0)) : 0;
   }
   double2 *v2 = vec[hw];
   // D(r, j), r >= j, at doff + j b - j (j - 1) / 2 + (r - j)
@@ -1326,10 +1391,9 @@ __global__ __launch_bounds__(256) void k_half_bwd(
   int b = 0, m = 0;
   if (w < count) {
     B = blocks[items[w].x];
-    if (B.active) {                            // a retired pair's half idles
-      b = B.r1 - B.r0;
-      m = B.m;
-    }
+    const bool on = B.active != 0;             // a retired pair's half idles
+    b = on ? B.r1 - B.r0 : 0;
+    m = on ? B.m : 0;
   }
   double2 *v2 = vec[hw];
   const bool col = r < b;
