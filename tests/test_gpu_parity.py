@@ -302,6 +302,40 @@ def test_non_finite_displacement_is_reported():
     ctx.close()
 
 
+def test_non_finite_pixel_displacement_is_reported():
+    """The warp's own check: a triangle with a non-finite or out-of-range
+    (10^6 pixels or more) corner displacement raises the flag (reported by the
+    next call) and is warped with zero displacement; the pixels of the other
+    triangles keep the oracle's values, and the call after the report is
+    exact again."""
+    say("non-finite pixel displacement flag")
+    d = CASES["adaptive_48"]()
+    pb = oracle_problem(d, 0.5)
+    ctx = gpu_ctx([d], 0.5)
+    u = np.random.default_rng(8).normal(scale=0.8, size=(d["V"].shape[0], 2))
+    bad = u.copy()
+    bad[3, 0] = float("nan")
+    bad[7, 1] = 1.0e7
+    _, warped = ctx.warp_msd(to_dev(bad), return_warped=True)     # no fault
+    torch.cuda.synchronize()
+    H, W = d["te"].shape
+    T = np.asarray(d["T"])
+    hit = np.isin(T, [3, 7]).any(axis=1)[pb.t6.ravel()].reshape(H, W)
+    assert hit.any() and not hit.all()
+    W_or = reg.warp(pb, u)
+    got = warped.cpu().numpy().reshape(H, W)
+    assert np.isfinite(got).all()
+    assert np.abs(got[~hit] - W_or[~hit]).max() < 2e-6 * max(1.0, np.abs(W_or).max())
+    with pytest.raises(lib().MeshRegError) as ei:
+        ctx.warp_msd(to_dev(u))
+    assert ei.value.code == lib().binding.MR_ENONFINITE
+    msd = ctx.warp_msd(to_dev(u))              # the flag was cleared
+    torch.cuda.synchronize()
+    m_or = reg.msd(pb, u)
+    assert abs(msd.item() - m_or) <= MSD_TOL * m_or + 1e-14
+    ctx.close()
+
+
 def test_zero_iterations_is_a_no_op():
     say("n_iter = 0")
     d = CASES["adaptive_48"]()
