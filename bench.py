@@ -270,11 +270,12 @@ def profile(ctx, run, total_bytes: dict, leg: str, layout_bytes: dict | None = N
     return kernels, roof
 
 
-def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
+def stage_rooflines(ctx, pairs, u, reps: int = 20, leg: str = "stages") -> dict:
     """Sample, assemble and warp each timed on their own (the library's force
     and warp entry points, which launch them unfused), with dispatch-attached
     events: achieved GB/s on algorithmic bytes against the HBM peak, and the
-    library's layout bytes beside them."""
+    library's layout bytes beside them (and the counter traffic recorded for
+    `leg`, if any)."""
     import torch
     ab = algorithmic_bytes(ctx, pairs)
     lb = unit_bytes(ctx, pairs)
@@ -296,7 +297,7 @@ def stage_rooflines(ctx, pairs, u, reps: int = 20) -> dict:
             out[fam] = {"us_per_call": round(ms / reps * 1e3, 3), "bytes_per_call": int(nbytes),
                         "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                         "layout_bytes_per_call": int(lbytes),
-                        "traffic_per_call": measured_traffic("stages", fam)}
+                        "traffic_per_call": measured_traffic(leg, fam)}
     return out
 
 
@@ -333,13 +334,15 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload, leg) -> dict:
         _, g_u0, g_alpha, g_te = ctx.backward_ckpt(ck, N, 10)
         stream.synchronize()
         grad_eval = time.perf_counter() - t0
-        roof = None
+        roof = stages = None
         if not no_profile:
             u.zero_()
             fused = ctx.info(0, "fused_assembly") == 1
             _, roof = profile(ctx, lambda: B.mesh_reg_step(ctx.ctx, u, N, None, stream.cuda_stream),
                               run_bytes(algorithmic_bytes(ctx, pairs), N, False, fused), leg,
                               run_bytes(unit_bytes(ctx, pairs), N, False, fused))
+            # the stages at the iterate the plain run ends on
+            stages = stage_rooflines(ctx, pairs, u, leg=leg + "_stages")
         ctx.close()
     return {"workload": workload, "pairs": len(pairs), "nodes": nb,
             "pixels": int(sum(p.height * p.width for p in pairs)), "iterations": N,
@@ -354,7 +357,7 @@ def diff_leg(pkg, B, pairs, tau, N, stream, no_profile, workload, leg) -> dict:
                         "vs_plain": round(dt_plain / grad_eval, 4),
                         "mean_final_msd": float(msd_b.mean().item()),
                         "g_alpha_norm": float(torch.linalg.vector_norm(g_alpha).item())},
-            "roofline": roof}
+            "roofline": roof, "stage_rooflines": stages}
 
 
 def converge_leg(ctx, pairs, stream, args, s_per_iteration: float) -> dict:

@@ -343,9 +343,7 @@ __global__ void k_alpha_finish(const DevPair *__restrict__ pairs, int n_pairs,
   const int lane = threadIdx.x & 63;
   for (int p = threadIdx.x >> 6; p < n_pairs; p += blockDim.x >> 6) {
     const DevPair Q = pairs[p];
-    double s = 0.0;
-    for (int k = lane; k < Q.n_items; k += 64) s += alpha_part[Q.item_off + k];
-    s = wave_sum(s);
+    const double s = wave_sum(lane_strided_sum(alpha_part + Q.item_off, Q.n_items, lane));
     if (lane == 0) g_alpha[p] = s;
   }
 }

@@ -277,9 +277,7 @@ __device__ __forceinline__ void msd_finish_group(const DevPair *__restrict__ pai
   if (p >= n_pairs) return;
   const DevPair Q = pairs[p];
   if (!Q.active) return;                      // retired pair: its MSD is left as it is
-  double s = 0.0;
-  for (int k = lane; k < Q.n_tiles; k += 64) s += partials[Q.tile_off + k];
-  s = wave_sum(s);
+  const double s = wave_sum(lane_strided_sum(partials + Q.tile_off, Q.n_tiles, lane));
   if (lane == 0) msd[p] = s / ((double)Q.height * (double)Q.width);
 }
 

@@ -177,6 +177,24 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Lane `lane`'s share of a wavefront's sum over a[0 .. n): a[lane],
+// a[lane + 64], ... added in that order, with sixteen loads in flight at a
+// time (the order, and so the result, does not depend on the batching).
+__device__ __forceinline__ double lane_strided_sum(const double *__restrict__ a, int n, int lane) {
+  constexpr int U = 16;
+  double s = 0.0;
+  int k = lane;
+  for (; k + (U - 1) * 64 < n; k += U * 64) {
+    double v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = a[k + j * 64];
+#pragma unroll
+    for (int j = 0; j < U; ++j) s += v[j];
+  }
+  for (; k < n; k += 64) s += a[k];
+  return s;
+}
+
 
 // FP64 first and second derivative weights (adjoint kernels).
 __device__ __forceinline__ void bs_deriv_d(double t, double d[4]) {
