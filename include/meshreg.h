@@ -108,9 +108,10 @@ typedef struct {
   int32_t flags;               /* MR_FLAG_* */
   int32_t apex_rows;           /* solve schedule: most rows per pair in the apex (the top levels
                                   of the block tree, solved with the explicit inverse of their
-                                  factor block); 0 = automatic (a level joins while the inverse
-                                  entries it adds stay within max(2^21 / n_pairs, 2^18), up to
-                                  1024 rows per pair when there are several pairs), -1 = none */
+                                  factor block); 0 = automatic (several pairs: a level joins
+                                  while the inverse entries it adds stay within
+                                  max(2^21 / n_pairs, 2^18), up to 1024 rows per pair; one pair:
+                                  up to 16384 rows), -1 = none */
   int32_t bwd_split_rows;      /* solve schedule: panel rows per backward workgroup; 0 = automatic
                                   (128 for one pair, unsplit for a batch) */
   int32_t solve_kernel;        /* solve schedule: 0 = autotuned per level; 1 = wavefront per

@@ -5,8 +5,14 @@ pre-computation behind the C ABI of ``include/meshreg.h``).  Importing this
 package loads that library and fails if it has not been built
 (``python -m paper_1411_2141_amd.build``); there is no fallback path.
 """
-from . import binding
-from .binding import MeshRegError, load_library
+# torch first: it carries its own HIP runtime, and the library must bind to
+# that same runtime (loaded first, the library would pull in the system's,
+# and the process would hold two runtimes that do not share devices, streams
+# or memory)
+import torch  # noqa: F401,E402
+
+from . import binding  # noqa: E402
+from .binding import MeshRegError, load_library  # noqa: E402
 
 load_library()
 
