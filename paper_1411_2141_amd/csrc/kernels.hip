@@ -1337,13 +1337,16 @@ __global__ __launch_bounds__(256) void k_half_fwd(
 #pragma unroll
       for (int u = 0; u < C; ++u) v[u] = dload(j0 + u);
     }
+    // no guard on j0 + u < b: the slot holds t_j = 0 and D(r, j) = 0 past
+    // the block (j0 + u < 32), so all C reads go out together
+    double2 tj[C];
 #pragma unroll
-    for (int u = 0; u < C; ++u)
-      if (j0 + u < b) {
-        const double2 tj = v2[j0 + u];
-        y.x += v[u] * tj.x;
-        y.y += v[u] * tj.y;
-      }
+    for (int u = 0; u < C; ++u) tj[u] = v2[j0 + u];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      y.x += v[u] * tj[u].x;
+      y.y += v[u] * tj[u].y;
+    }
   }
   __builtin_amdgcn_wave_barrier();
   v2[r] = y;
@@ -1357,13 +1360,14 @@ __global__ __launch_bounds__(256) void k_half_fwd(
 #pragma unroll
       for (int u = 0; u < C; ++u)
         v[u] = (j0 + u < b && on) ? pcol[B.poff + (int64_t)(j0 + u) * m + kk] : 0.0;
+      double2 yj[C];                 // y_j = 0 and P(k, j) = 0 past the block
 #pragma unroll
-      for (int u = 0; u < C; ++u)
-        if (j0 + u < b) {
-          const double2 yj = v2[j0 + u];
-          acc.x += v[u] * yj.x;
-          acc.y += v[u] * yj.y;
-        }
+      for (int u = 0; u < C; ++u) yj[u] = v2[j0 + u];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        acc.x += v[u] * yj[u].x;
+        acc.y += v[u] * yj[u].y;
+      }
     }
     if (on) upd[B.boff + kk] = acc;
   }
@@ -1411,13 +1415,14 @@ __global__ __launch_bounds__(256) void k_half_bwd(
 #pragma unroll
         for (int u = 0; u < C; ++u) v[u] = pload(kc + k0 + u);
       }
+      double2 zk[C];                 // z = 0 and P(k, j) = 0 past the panel
 #pragma unroll
-      for (int u = 0; u < C; ++u)
-        if (k0 + u < kend) {
-          const double2 zk = v2[k0 + u];
-          s.x += v[u] * zk.x;
-          s.y += v[u] * zk.y;
-        }
+      for (int u = 0; u < C; ++u) zk[u] = v2[k0 + u];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        s.x += v[u] * zk[u].x;
+        s.y += v[u] * zk[u].y;
+      }
     }
   }
   double2 t = make_double2(0.0, 0.0);
@@ -1436,13 +1441,14 @@ __global__ __launch_bounds__(256) void k_half_bwd(
       const int i = i0 + u;
       v[u] = (i < b && r <= i && col) ? drow[B.doff + (int64_t)i * (i + 1) / 2 + r] : 0.0;
     }
+    double2 ti[C];                   // t_i = 0 and D(i, j) = 0 past the block
 #pragma unroll
-    for (int u = 0; u < C; ++u)
-      if (i0 + u < b) {
-        const double2 ti = v2[i0 + u];
-        z.x += v[u] * ti.x;
-        z.y += v[u] * ti.y;
-      }
+    for (int u = 0; u < C; ++u) ti[u] = v2[i0 + u];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      z.x += v[u] * ti[u].x;
+      z.y += v[u] * ti[u].y;
+    }
   }
   if (col) {
     x[B.r0 + r] = z;
