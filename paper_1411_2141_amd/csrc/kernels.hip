@@ -300,28 +300,6 @@ __device__ __forceinline__ T load_at(const T *__restrict__ base, unsigned off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
 
-// Warp + MSD of NT kTile x kTile pixel tiles, tile0 .. tile0 + NT - 1 (those
-// below n_tiles), with a workgroup of kTile^2 threads, the thread taking the
-// same pixel position in each tile.
-//
-// Every pixel of a triangle has the same affine displacement map (P1
-// interpolation), so the work is split in two stages.  First each distinct
-// triangle of a tile (the tile's list, built at init from T6: corner node ids
-// in tile_nodes, in the node order of u, and packed corner coordinates) gets
-// its map in the tile's frame, one thread per triangle, into LDS: for the
-// pixel at tile position r = (rx, ry) the sampling position in spline
-// coordinates is (x0, y0) + c + G' r, with G' = I + grad d and c the displaced
-// position of the tile origin's pixel (FP64; the map is formed from the
-// corners' exact integer coordinates and displacements).  Then each pixel
-// reads its triangle's slot (a byte per pixel) and samples the template
-// spline there (FP32 weights with the partition of unity kept and FP32 tap
-// sums).  A triangle with a non-finite displacement, or one of 10^6 pixels or
-// more, at a corner raises the flag and is warped with zero displacement.
-// Windows wholly inside the image take four row loads per pixel; a wavefront
-// with a lane whose window crosses the border folds its taps one by one.
-// Each tile's FP64 sum of squared differences (a fixed order over the
-// workgroup's threads) goes to partials[tile].  Offsets within a pair's image
-// are 32-bit (fewer than 2^31 pixels).
 // The records of NT consecutive tiles from tile0 (a tile past the end or of a
 // retired pair is off and has no entries); the group's triangle entries are
 // numbered tile after tile, tile q's from base[q] on, total in all.
@@ -507,6 +485,28 @@ __device__ __forceinline__ void warp_samples(const WarpTaps<NT> &t, const WarpGr
   }
 }
 
+// Warp + MSD of NT kTile x kTile pixel tiles, tile0 .. tile0 + NT - 1 (those
+// below n_tiles), with a workgroup of kTile^2 threads, the thread taking the
+// same pixel position in each tile.
+//
+// Every pixel of a triangle has the same affine displacement map (P1
+// interpolation), so the work is split in two stages.  First each distinct
+// triangle of a tile (the tile's list, built at init from T6: corner node ids
+// in tile_nodes, in the node order of u, and packed corner coordinates) gets
+// its map in the tile's frame, one thread per triangle, into LDS: for the
+// pixel at tile position r = (rx, ry) the sampling position in spline
+// coordinates is (x0, y0) + c + G' r, with G' = I + grad d and c the displaced
+// position of the tile origin's pixel (FP64; the map is formed from the
+// corners' exact integer coordinates and displacements).  Then each pixel
+// reads its triangle's slot (a byte per pixel) and samples the template
+// spline there (FP32 weights with the partition of unity kept and FP32 tap
+// sums).  A triangle with a non-finite displacement, or one of 10^6 pixels or
+// more, at a corner raises the flag and is warped with zero displacement.
+// Windows wholly inside the image take four row loads per pixel; a wavefront
+// with a lane whose window crosses the border folds its taps one by one.
+// Each tile's FP64 sum of squared differences (a fixed order over the
+// workgroup's threads) goes to partials[tile].  Offsets within a pair's image
+// are 32-bit (fewer than 2^31 pixels).
 template <int NT>
 __device__ __forceinline__ void warp_tiles(int tile0, int n_tiles, const TileItem *__restrict__ tiles,
                                            const double2 *__restrict__ u,
@@ -1808,7 +1808,7 @@ __global__ __launch_bounds__(256) void k_apex_bwd(const ApexBwdItem *__restrict_
 }
 
 // Two tiles per workgroup: their loads overlap, and the launch's workgroups
-// stay within the LDS and register budget of seven per CU.
+// stay within the LDS and register budget of eight per CU (64 VGPRs).
 __global__ __launch_bounds__(256) void k_warp_msd(
     const TileItem *__restrict__ tiles, const double2 *__restrict__ u,
     const int4 *__restrict__ tile_nodes, const int2 *__restrict__ tile_pbc,
