@@ -30,9 +30,9 @@ Further legs in the same JSON line (node-updates/s = nodes x iterations / s):
   single_pair -- one 512x512 12-bit pair, 200 iterations with the warp + MSD
                  every iteration (graph replay), and its fwd+bwd form;
   large_pair  -- one 2048x2048 pair (559k nodes), 50 iterations: plain against
-                 forward + reverse pass (checkpoint 10);
+                 forward + reverse pass (checkpoint 10), and its stages;
   diff_batch  -- 64 pairs of 512x512 with per-pair alpha, 100 iterations: plain
-                 against forward + reverse pass (checkpoint 10);
+                 against forward + reverse pass (checkpoint 10), and its stages;
   unstructured -- the 512x512 pair on an unstructured (jittered Delaunay)
                  mesh, 200 iterations with the MSD every iteration;
   explicit    -- Algorithm 1 as printed, on the 512x512 pair and the batch;
