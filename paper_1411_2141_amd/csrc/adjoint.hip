@@ -18,8 +18,9 @@
 // with the forward kernels, so they equal the forward pass bit for bit.  The
 // checkpoints come from a forward pass that writes them as it goes (the
 // caller's, or one the reverse call runs itself).  The
-// adjoint arithmetic is FP64; the scatters into lambda^N and cbar use FP64
-// atomic adds (their summation order is not fixed).
+// adjoint arithmetic is FP64; lambda^N is summed in a fixed order (per tile
+// entry, then per node), the scatter into cbar uses FP64 atomic adds (its
+// summation order is not fixed).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -133,66 +134,31 @@ __device__ __forceinline__ void scatter_taps_wave(double *__restrict__ cbar, int
   }
 }
 
-// Adds (ax, ay) to lam[node] for every lane with `on`: the wavefront first
-// sums equal nodes in an LDS table of kLamSlots (node, value) slots (linear
-// probing, at most kLamProbes probes; a node that finds no slot goes straight
-// to global memory), then adds each occupied slot to lam with global atomics.
-// Every wavefront of the workgroup must call this once (two workgroup
-// barriers).
-constexpr int kLamSlots = 128, kLamProbes = 8;
-__device__ __forceinline__ void add_lambda_wave(double2 *lam, bool on, int node, double ax,
-                                                double ay, int *keys, double2 *vals) {
-  const int lane = (int)threadIdx.x & 63;
-  for (int e = lane; e < kLamSlots; e += 64) {
-    keys[e] = -1;
-    vals[e] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  if (on) {
-    int h = (int)(((unsigned)node * 2654435761u) >> 25);     // 7 bits
-    bool done = false;
-    for (int p = 0; p < kLamProbes && !done; ++p) {
-      const int old = atomicCAS(keys + h, -1, node);
-      if (old == -1 || old == node) {
-        atomicAdd(&vals[h].x, ax);
-        atomicAdd(&vals[h].y, ay);
-        done = true;
-      }
-      h = (h + 1) & (kLamSlots - 1);
-    }
-    if (!done) {
-      unsafeAtomicAdd(&lam[node].x, ax);
-      unsafeAtomicAdd(&lam[node].y, ay);
-    }
-  }
-  __syncthreads();
-  for (int e = lane; e < kLamSlots; e += 64) {
-    const int nd = keys[e];
-    if (nd >= 0) {
-      unsafeAtomicAdd(&lam[nd].x, vals[e].x);
-      unsafeAtomicAdd(&lam[nd].y, vals[e].y);
-    }
-  }
-}
-
 // Warp adjoint (and the forward MSD partials of the same pixels), one 16 x 16
-// tile per workgroup: lambda^N of the three corners of each pixel's triangle
-// and the coefficient adjoint of the pixel's sample, both pre-summed per
-// wavefront in LDS (add_lambda_wave, scatter_taps_wave) before the global
-// atomics.
+// tile per workgroup: the coefficient adjoint of each pixel's sample
+// (pre-summed per wavefront in LDS before the global atomics,
+// scatter_taps_wave) and, for lambda^N, each pixel's contributions to the
+// three corners of its triangle summed per entry of the tile's triangle list
+// in pixel order (thread e adds the pixels whose slot is e) into
+// lam_part[3 (ent_off + e) + corner]; k_lambda_gather then adds each node's
+// entries in a fixed order, so lambda^N does not depend on the order in
+// which workgroups run.
 __global__ __launch_bounds__(256) void k_warp_adjoint(
     const TileItem *__restrict__ tiles, const DevPair *__restrict__ pairs,
     const double2 *__restrict__ u, const int2 *__restrict__ xy, const int4 *__restrict__ tri,
-    const int32_t *__restrict__ t6, const float *__restrict__ coef, const float *__restrict__ re,
-    const double *__restrict__ g_msd, double2 *lam, double *cbar, double *__restrict__ partials) {
+    const int32_t *__restrict__ t6, const uint8_t *__restrict__ tile_loc,
+    const float *__restrict__ coef, const float *__restrict__ re,
+    const double *__restrict__ g_msd, double2 *__restrict__ lam_part, double *cbar,
+    double *__restrict__ partials) {
+  constexpr int kPix = kTile * kTile;
   __shared__ double box[4][kAdjBox];
-  __shared__ int keys[4][kLamSlots];
-  __shared__ double2 vals[4][kLamSlots];
-  const int wave = (int)threadIdx.x >> 6;
+  __shared__ double2 cont[3][kPix];
+  __shared__ uint8_t slot[kPix];
+  const int tid = (int)threadIdx.x, wave = tid >> 6;
   const TileItem it = tiles[blockIdx.x];
   const DevPair P = pairs[it.pair];
-  const int i = it.y0 + (int)(threadIdx.x / kTile);
-  const int j = it.x0 + (int)(threadIdx.x % kTile);
+  const int i = it.y0 + tid / kTile;
+  const int j = it.x0 + tid % kTile;
   const bool in = i < P.height && j < P.width;
   const int I = min(i, P.height - 1), J = min(j, P.width - 1);
   const size_t pix = (size_t)P.pix_off + (size_t)I * P.width + J;
@@ -218,16 +184,52 @@ __global__ __launch_bounds__(256) void k_warp_adjoint(
   const double e = val - (double)re[pix];
   const double acc = in ? e * e : 0.0;
   const double s = in ? 2.0 * g_msd[it.pair] / ((double)P.height * (double)P.width) * e : 0.0;
-  add_lambda_wave(lam, in, nd.x, s * wa * gx, s * wa * gy, keys[wave], vals[wave]);
-  add_lambda_wave(lam, in, nd.y, s * wb * gx, s * wb * gy, keys[wave], vals[wave]);
-  add_lambda_wave(lam, in, nd.z, s * wc * gx, s * wc * gy, keys[wave], vals[wave]);
+  // the pixel's entry in the tile's triangle list (the triangle of T6 above)
+  slot[tid] = tile_loc[(size_t)blockIdx.x * kPix + tid];
+  cont[0][tid] = in ? make_double2(s * wa * gx, s * wa * gy) : make_double2(0.0, 0.0);
+  cont[1][tid] = in ? make_double2(s * wb * gx, s * wb * gy) : make_double2(0.0, 0.0);
+  cont[2][tid] = in ? make_double2(s * wc * gx, s * wc * gy) : make_double2(0.0, 0.0);
+  // (its barriers also make slot and cont visible to the whole workgroup)
   scatter_taps_wave(cbar + P.pix_off, P.height, P.width, in, qx, fx, qy, fy, s, 0.0, 0.0,
                     box[wave]);
+  if (tid < it.n_ent) {
+    double2 sa = make_double2(0.0, 0.0), sb = sa, sc = sa;
+    for (int q = 0; q < kPix; ++q)
+      if (slot[q] == tid) {
+        sa.x += cont[0][q].x;
+        sa.y += cont[0][q].y;
+        sb.x += cont[1][q].x;
+        sb.y += cont[1][q].y;
+        sc.x += cont[2][q].x;
+        sc.y += cont[2][q].y;
+      }
+    double2 *o = lam_part + 3 * ((int64_t)it.ent_off + tid);
+    o[0] = sa;
+    o[1] = sb;
+    o[2] = sc;
+  }
   __shared__ double red[4];
   const double sum = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[wave] = sum;
+  if ((tid & 63) == 0) red[wave] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// lambda^N of node v: its (tile entry, corner) sums lam_part[lidx[q]],
+// q = lptr[v] .. lptr[v + 1] - 1, added in that (ascending) order.
+__global__ __launch_bounds__(256) void k_lambda_gather(int n, const int32_t *__restrict__ lptr,
+                                                       const int32_t *__restrict__ lidx,
+                                                       const double2 *__restrict__ lam_part,
+                                                       double2 *__restrict__ lam) {
+  const int v = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (v >= n) return;
+  double sx = 0.0, sy = 0.0;
+  for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
+    const double2 c = lam_part[lidx[q]];
+    sx += c.x;
+    sy += c.y;
+  }
+  lam[v] = make_double2(sx, sy);
 }
 
 // One reverse step per node i, given mu = S^-1 lambda^{k+1}:
@@ -372,6 +374,7 @@ int mr_ctx::reserve_adjoint(int32_t n_iter, int32_t ckpt_every, hipStream_t s) {
     HIP_OK(d_mu.alloc(N));
   }
   if ((int64_t)d_cbar.count < n_pix) HIP_OK(d_cbar.alloc(n_pix));
+  if (d_lam_part.count < 3 * d_tile_nodes.count) HIP_OK(d_lam_part.alloc(3 * d_tile_nodes.count));
   if ((int)d_alpha_part.count < n_node_items) HIP_OK(d_alpha_part.alloc(n_node_items));
   if (!d_mwt_t.ptr) {                         // uploaded last: present after a complete upload
     const int rc = upload_adjoint_operators(s);
@@ -408,14 +411,16 @@ int mr_ctx::reverse(const double2 *ck, int32_t n_iter, int32_t ckpt_every, const
   if (rc) return rc;
   double2 *seg = d_seg.ptr;
   auto ckpt = [&](int q) { return ck + (size_t)q * N; };
-  // warp adjoint at u^N
-  HIP_OK(hipMemsetAsync(d_lam.ptr, 0, nb, s));
+  // warp adjoint at u^N: lambda^N per (tile entry, corner), then per node
   HIP_OK(hipMemsetAsync(d_cbar.ptr, 0, sizeof(double) * n_pix, s));
   HIP_OK(hipMemsetAsync(d_alpha_part.ptr, 0, sizeof(double) * n_node_items, s));
   timed_begin(MR_KF_WARP, s);
-  const hipError_t ew = launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr,
-                               d_pairs.ptr, ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_coef.ptr,
-                               d_re.ptr, g_msd, d_lam.ptr, d_cbar.ptr, d_partials.ptr);
+  hipError_t ew = launch(k_warp_adjoint, n_tiles, kTile * kTile, 0, s, d_tiles.ptr, d_pairs.ptr,
+                         ckpt(n_seg), d_xy.ptr, d_tri.ptr, d_t6.ptr, d_tile_loc.ptr, d_coef.ptr,
+                         d_re.ptr, g_msd, d_lam_part.ptr, d_cbar.ptr, d_partials.ptr);
+  if (ew == hipSuccess && N > 0)
+    ew = launch(k_lambda_gather, (int)((N + 255) / 256), 256, 0, s, (int)N, d_lam_ptr.ptr,
+                d_lam_idx.ptr, (const double2 *)d_lam_part.ptr, d_lam.ptr);
   timed_end(s);          // before any return, so no timer stays attached to the thread
   HIP_OK(ew);
   if (msd) HIP_OK(launch_msd_finish(d_pairs.ptr, n_pairs, d_partials.ptr, msd, s));

@@ -762,6 +762,26 @@ int mr_ctx::upload_all(hipStream_t s) {
     HIP_TRY(upload(d_tile_nodes, tn, s));
     HIP_TRY(upload(d_tile_nodes_s, tns, s));
     HIP_TRY(upload(d_tile_pbc, tpbc, s));
+    // per node, the slots 3 k + corner of the tile entries k it is a corner
+    // of, ascending (the warp adjoint sums lambda^N in this order)
+    if (3 * (int64_t)tn.size() >= (int64_t)INT32_MAX) return fail(MR_EINVAL, "too many tile entries");
+    std::vector<int32_t> lptr(n_nodes + 1, 0), lidx(3 * tn.size());
+    for (const int4 &t : tn) {
+      ++lptr[t.x + 1];
+      ++lptr[t.y + 1];
+      ++lptr[t.z + 1];
+    }
+    for (int64_t v = 0; v < n_nodes; ++v) lptr[v + 1] += lptr[v];
+    {
+      std::vector<int32_t> cur(lptr.begin(), lptr.end() - 1);
+      for (size_t k = 0; k < tn.size(); ++k) {
+        lidx[cur[tn[k].x]++] = (int32_t)(3 * k);
+        lidx[cur[tn[k].y]++] = (int32_t)(3 * k + 1);
+        lidx[cur[tn[k].z]++] = (int32_t)(3 * k + 2);
+      }
+    }
+    HIP_TRY(upload(d_lam_ptr, lptr, s));
+    HIP_TRY(upload(d_lam_idx, lidx, s));
   }
   HIP_TRY(upload(d_t6, t6, s));
   HIP_TRY(upload(d_iperm, iperm, s));
@@ -866,7 +886,8 @@ int mr_ctx::upload_factor(int p, hipStream_t s) {
 int64_t mr_ctx::device_bytes() const {
   return (int64_t)(d_pairs.bytes() + d_node_items.bytes() + d_tiles.bytes() + d_xy.bytes() +
                    d_tri.bytes() + d_t6.bytes() + d_tile_nodes.bytes() +
-                   d_tile_nodes_s.bytes() + d_tile_pbc.bytes() + d_tile_loc.bytes() + d_iperm.bytes() + d_perm.bytes() +
+                   d_tile_nodes_s.bytes() + d_tile_pbc.bytes() + d_tile_loc.bytes() + d_lam_ptr.bytes() +
+                   d_lam_idx.bytes() + d_iperm.bytes() + d_perm.bytes() +
                    d_coef.bytes() + d_re.bytes() + d_rho.bytes() + d_rho_s.bytes() +
                    d_x_sptr.bytes() + d_x_opp.bytes() + d_x_rptr.bytes() + d_x_ridx.bytes() +
                    d_x_u0.bytes() + d_x_rec.bytes() +

@@ -65,6 +65,8 @@ struct mr_ctx {
   mr::DevArray<int4> d_tile_nodes, d_tile_nodes_s;
   mr::DevArray<int2> d_tile_pbc;
   mr::DevArray<uint8_t> d_tile_loc;             // per tile pixel: its entry in the tile's list
+  mr::DevArray<int32_t> d_lam_ptr, d_lam_idx;   // per node its (tile entry, corner) slots
+                                                // 3 entry + corner, ascending
   mr::DevArray<float> d_coef, d_re, d_rho, d_rho_s;   // rho natural and solve order
   mr::DevArray<int32_t> d_mptr;                 // force operator rows (bit 31: two-word entries)
   mr::DevArray<uint32_t> d_ment;                // its entries (column offset | numerator)
@@ -114,6 +116,7 @@ struct mr_ctx {
 
   // adjoint (allocated by the first backward call)
   mr::DevArray<double2> d_ck, d_seg, d_lam, d_lam_s, d_mu;  // d_lam_s: lambda in solve order
+  mr::DevArray<double2> d_lam_part;             // lambda^N per (tile entry, corner)
   mr::DevArray<double> d_cbar, d_alpha_part, d_kval, d_mwt_t;
   mr::DevArray<int32_t> d_kptr, d_kcol;
 

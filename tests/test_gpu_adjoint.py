@@ -112,12 +112,15 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     d = cases()["c1_128"]
     ctx = pkg().MeshReg([d], tau=0.5)
     u0 = dev(np.zeros((d["V"].shape[0], 2)))
-    outs = [ctx.backward(u0, 7, k) for k in (1, 3, 7)]
+    outs = [ctx.backward(u0, 7, k) for k in (1, 3, 7, 3)]
     torch.cuda.synchronize()
     ref = outs[0]
     for o in outs[1:]:
-        assert rel(o[1].cpu().numpy(), ref[1].cpu().numpy()) < 1e-10
-        assert abs(o[2].item() - ref[2].item()) <= 1e-10 * abs(ref[2].item())
+        # lambda^N is summed per node in a fixed order and every reverse step
+        # writes its lambda per node, so the displacement and alpha gradients
+        # are the same bit for bit; the template's goes through FP64 atomics
+        assert torch.equal(o[1], ref[1])
+        assert o[2].item() == ref[2].item()
         assert rel(o[3].cpu().numpy(), ref[3].cpu().numpy()) < 1e-6
     ctx.close()
 
@@ -239,8 +242,8 @@ def test_forward_checkpoints_then_reverse_pass(n_iter, ckpt):
     msd_r, gu_r, ga_r, gt_r = ctx.backward(dev(u0), n_iter, ckpt)
     torch.cuda.synchronize()
     assert msd_b.item() == msd_r.item()
-    assert torch.equal(gu_b, gu_r) or rel(gu_b.cpu().numpy(), gu_r.cpu().numpy()) < 1e-10
-    assert abs(ga_b.item() - ga_r.item()) <= 1e-10 * abs(ga_r.item()) + 1e-300
+    assert torch.equal(gu_b, gu_r)
+    assert ga_b.item() == ga_r.item()
     assert rel(gt_b.cpu().numpy(), gt_r.cpu().numpy()) < 1e-6
     pb = reg.setup(d["te"], d["re"], d["V"], d["T"], d["alpha"], tau)
     L, gu, ga, gt = oadj.gradient(pb, u0, n_iter)
