@@ -503,7 +503,7 @@ def single_pair_leg(pkg, B, pair, tau, K, warmup, side, no_profile) -> dict:
             kernels, roof = profile(ctx, lambda: run(K),
                                     run_bytes(algorithmic_bytes(ctx, [pair]), K, True, fused),
                                     "single_pair", run_bytes(unit_bytes(ctx, [pair]), K, True, fused))
-            stages = stage_rooflines(ctx, [pair], u)
+            stages = stage_rooflines(ctx, [pair], u, leg="single_pair_stages")
         N = 100
         ck = ctx.checkpoints(N, 10)
         uu = ctx.zeros_u()
